@@ -1,0 +1,222 @@
+/*
+ * htsvt.h -- C ABI of the MI355X randomized high-order t-SVT library.
+ *
+ * The library computes, on one GPU, the randomized approximation of the
+ * GNHTSVT operator D_{Phi,tau}(A, L) (Def. 4.3 of the paper; the operator that
+ * solves  argmin_G tau*||G||_{Phi,L} + ||G - A||_F^2 / 2, Thm. 4.1) for an
+ * order-d real tensor under invertible transforms L along modes 3..d
+ * (eq. defining L and its inverse), and the per-iteration update of the pure
+ * low-rank-prior ADMM solvers for completion and robust completion that call
+ * it once per iteration (Sec. V, ADMM updates of L, E, the multiplier and mu).
+ *
+ * Conventions
+ *  - Tensors are dense, real, stored in Fortran order: element (i1,...,id)
+ *    (0-based) lives at i1 + n1*(i2 + n2*(i3 + ...)).  Face slice j
+ *    (j = i3 + n3*(i4 + ...), the slice index of Sec. II) is therefore the
+ *    contiguous column-major n1 x n2 block starting at j*n1*n2.
+ *  - All tensor arguments are DEVICE pointers owned by the caller.  The library
+ *    never frees them and never keeps them past the call.
+ *  - Work is enqueued on the caller's stream (hipStream_t passed as void*;
+ *    NULL = the null stream).  Calls return after enqueueing; they do not
+ *    synchronize unless stated.  Calls on one plan must not overlap in time
+ *    on different host threads.
+ *  - Scratch memory is a caller-provided device workspace of at least the
+ *    size reported by the matching *_workspace_size call; the library does not
+ *    allocate per call.  Plans own small device tables (transform matrices).
+ *  - Return value: HT_OK (0) or a negative HT_ERR_* code.  A human-readable
+ *    message for the last failure on the calling thread is available from
+ *    ht_last_error().  No exception crosses the ABI.
+ *  - Numerical breakdowns inside the method (rank-deficient sketches handled
+ *    by deflation) are not errors.
+ */
+#ifndef HTSVT_H
+#define HTSVT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define HT_MAX_ORDER 8
+#define HT_MAX_WIDTH 80    /* largest sketch width l = min(r + p, n1, n2) */
+#define HT_MAX_MODE 64     /* largest n_k of a transformed mode */
+
+enum {
+  HT_OK = 0,
+  HT_ERR_INVALID_ARG = -1,
+  HT_ERR_UNSUPPORTED = -2,
+  HT_ERR_NONFINITE = -3,
+  HT_ERR_WORKSPACE = -4,
+  HT_ERR_HIP = -5,
+  HT_ERR_ALLOC = -6
+};
+
+/* Transform of one mode k = 3..d (the matrices U_{n_k} of the transform L). */
+enum {
+  HT_DCT2_ORTHO = 0,   /* orthonormal DCT-II, alpha = 1 */
+  HT_DFT_UNITARY = 1,  /* unitary DFT, alpha = 1 (complex slices; see below) */
+  HT_CUSTOM_REAL = 2   /* caller-supplied real U with U U^T = alpha I */
+};
+
+/* Arithmetic of the path. */
+enum {
+  HT_FP64 = 0,        /* tensors double; every step FP64 */
+  HT_FP32 = 1,        /* tensors float; sketches/transforms FP32, Gram/Cholesky/eigen FP64 */
+  HT_BF16_MIXED = 2   /* tensors float; transformed slices, Omega and Q in BF16 on MFMA
+                         with FP32 accumulation; Gram/Cholesky/eigen FP64 */
+};
+
+/* Penalty Phi of the low-rank term or psi of the sparse term.  Every penalty is
+ * normalized to slope 1 at 0 except LOG; parameters are absolute:
+ *   L1         phi(x) = x
+ *   MCP        phi(x) = x - x^2/(2 p0) (x <= p0), p0/2 beyond          (p0 = gamma > 0)
+ *   SCAD       phi(x) = x (x <= p1), (2 p0 p1 x - x^2 - p1^2)/(2 (p0-1) p1) (x <= p0 p1),
+ *              (p0+1) p1 / 2 beyond                                   (p0 = a > 2, p1 = b > 0)
+ *   LOG        phi(x) = log(1 + x / p0)                                (p0 = eps > 0)
+ *   CAPPED_L1  phi(x) = min(x, p0)                                     (p0 = theta > 0)
+ * Prox_{phi,mu}(v) = argmin_x mu*phi(x) + (x - v)^2/2 (the proximity operator of
+ * Sec. IV-B); ties between two global minimizers resolve to the smaller |x|. */
+enum { HT_PEN_L1 = 0, HT_PEN_MCP = 1, HT_PEN_SCAD = 2, HT_PEN_LOG = 3, HT_PEN_CAPPED_L1 = 4 };
+
+typedef struct {
+  int kind;
+  double p0, p1;
+} ht_penalty;
+
+/* Problem description for one tensor.
+ *  order       d, 2 <= d <= HT_MAX_ORDER (d = 2: one slice, no transform)
+ *  dims[k]     n_{k+1} >= 1
+ *  transform[k] for k = 2..d-1: transform kind of mode k+1
+ *  custom[k]   HOST pointer to the n x n row-major matrix U (CUSTOM_REAL only;
+ *              copied at plan creation)
+ *  r, p, q     target rank r >= 1, oversampling p >= 0, power steps q >= 0;
+ *              sketch width l = min(r + p, n1, n2) <= HT_MAX_WIDTH, kept k = min(r, l)
+ *  precision   HT_FP64 / HT_FP32 / HT_BF16_MIXED
+ *  seed, stream_id  key of the Gaussian sketch generator (Philox4x32-10,
+ *              counter (group, slice, call, stream_id), key = seed) */
+typedef struct {
+  int order;
+  int64_t dims[HT_MAX_ORDER];
+  int transform[HT_MAX_ORDER];
+  const double* custom[HT_MAX_ORDER];
+  int r, p, q;
+  int precision;
+  uint64_t seed;
+  uint32_t stream_id;
+} ht_plan_desc;
+
+typedef struct ht_plan ht_plan;
+
+/* Library version as 10000*major + 100*minor + patch. */
+int ht_version(void);
+
+/* Message describing the last failure on the calling thread ("" if none).
+ * The pointer stays valid until the next failing call on this thread. */
+const char* ht_last_error(void);
+
+/* Create a plan on the current HIP device.  Validates the description and
+ * uploads the transform tables.  Errors: INVALID_ARG (bad sizes/ranks/kinds),
+ * UNSUPPORTED (a valid request this build does not implement), HIP, ALLOC. */
+int ht_plan_create(const ht_plan_desc* desc, ht_plan** out);
+int ht_plan_destroy(ht_plan* plan);
+
+/* Bytes of device workspace needed by ht_gnhtsvt on this plan. */
+int ht_plan_workspace_size(const ht_plan* plan, size_t* bytes);
+
+/* Number of face slices P = n3*...*nd and the sketch width l of the plan. */
+int ht_plan_info(const ht_plan* plan, int64_t* n_slices, int* width, int* kept);
+
+/* Offset and size in bytes of a named region of the workspace, for
+ * inspecting intermediate results after a call: 0 transformed tensor A,
+ * 1 sketch matrices Omega, 2 orthonormal basis Q (n1 x l per slice),
+ * 3 B^T = A^T Q (n2 x l per slice), 4 shrink kernels K (l x l per slice),
+ * 5 Q K, 6 reconstructed transformed slices C, 7-9 solver buffers. */
+int ht_plan_workspace_region(const ht_plan* plan, int region, size_t* offset, size_t* bytes);
+
+/* Randomized GNHTSVT (Def. 4.3 computed slice-wise on sketches):
+ *   out = L^{-1}( slice-wise  Q_j U_k diag(Prox_{Phi,tau}(s_k)) V_k^T )
+ * where for each transformed slice A_j = L(X)^<j>:
+ *   Y = A_j Omega_j,  Q = orth(Y),  q times { Z = orth(A_j^T Q), Q = orth(A_j Z) },
+ *   B = Q^T A_j = U diag(s) V^T,  k = min(r, l).
+ * X, out: device tensors of the plan's storage type (double for FP64, float
+ * otherwise), N = n1*...*nd elements, may alias.  tau >= 0.  call_index keys the
+ * sketch draw (a solver passes its iteration number).  workspace: device buffer
+ * of >= ht_plan_workspace_size bytes, 256-byte aligned.
+ * stats (optional, device pointers, may be NULL):
+ *   sigma_out  P*l doubles, the l singular values of B_j (descending)
+ *   kept_out   P ints, how many shrunk values are nonzero
+ * Errors: INVALID_ARG (null pointers, tau < 0 or not finite, bad penalty
+ * parameters), WORKSPACE (too small or misaligned), HIP. */
+int ht_gnhtsvt(ht_plan* plan, const void* X, void* out, double tau, const ht_penalty* penalty,
+               uint32_t call_index, void* workspace, size_t workspace_bytes, void* stream,
+               double* sigma_out, int* kept_out);
+
+/* Write the FP64 sketch matrices of one call for every slice to dev_out
+ * (P * n2 * l doubles, slice-major, each column-major n2 x l), exactly as the
+ * t-SVT draws them before rounding to the storage type.  For checking the
+ * generator against an independent implementation. */
+int ht_omega_fp64(const ht_plan* plan, uint32_t call_index, double* dev_out, void* stream);
+
+/* Forward (inverse != 0: inverse) transform of a whole tensor, out-of-place
+ * or in place, in the plan's storage type. */
+int ht_transform(const ht_plan* plan, const void* X, void* out, int inverse, void* stream);
+
+/* Per-stage timing: when enabled, every kernel launch of the plan is bracketed
+ * by HIP events recorded on the launch stream.  ht_profile_read waits for the
+ * recorded events, returns the summed milliseconds and launch counts per stage
+ * (0 forward transform, 1 sketch generator, 2 Y = A W, 3 CholeskyQR,
+ * 4 Z = A^T Q, 5 small SVD + shrink, 6 Q K, 7 C = (Q K) B, 8 inverse transform,
+ * 9 ADMM update) for the first n_stages stages, and clears the records. */
+int ht_profile_enable(ht_plan* plan, int on);
+int ht_profile_read(ht_plan* plan, double* ms_total, int* count, int n_stages);
+
+/* ---------------------------------------------------------------------------
+ * Pure-L ADMM for completion (model = HT_COMPLETION) and robust completion
+ * (model = HT_RPCA), one iteration per call:
+ *   L   <- D_{Phi, 1/mu}(M - E + Y/mu)            (randomized t-SVT above)
+ *   H   <- M - L + Y/mu
+ *   E   <- mask ? (COMPLETION: 0 | RPCA: Prox_{psi, lambda/mu}(H)) : H
+ *   Y   <- Y + mu (M - L - E)
+ *   mu  <- min(mu_max, vartheta * mu)
+ * and the stopping terms max|dL|, max|dE|, max|M - L - E| of the iteration.
+ * --------------------------------------------------------------------------- */
+enum { HT_COMPLETION = 0, HT_RPCA = 1 };
+
+typedef struct {
+  int model;
+  ht_penalty phi;       /* low-rank penalty */
+  ht_penalty psi;       /* sparse penalty (RPCA only) */
+  double lambda;        /* weight of the sparse term (RPCA only) */
+  double mu0, vartheta, mu_max;
+} ht_admm_params;
+
+typedef struct {
+  int32_t iteration;    /* iterations completed */
+  double mu;            /* mu for the next iteration */
+  double dL, dE, resid; /* stopping terms of the last iteration (inf-norms) */
+} ht_admm_stats;
+
+/* Workspace for the ADMM calls (includes the t-SVT workspace). */
+int ht_admm_workspace_size(const ht_plan* plan, size_t* bytes);
+
+/* Zero L, E, Y and set mu = mu0, iteration = 0 (state kept in the workspace). */
+int ht_admm_init(ht_plan* plan, const ht_admm_params* prm, void* L, void* E, void* Y,
+                 void* workspace, size_t workspace_bytes, void* stream);
+
+/* Run n_iter iterations.  M: observed tensor (zero off the mask), mask: N
+ * bytes (nonzero = observed).  L, E, Y: solver state in the storage type.
+ * The sketch draw of iteration t uses call_index t. */
+int ht_admm_iterate(ht_plan* plan, const ht_admm_params* prm, const void* M, const uint8_t* mask,
+                    void* L, void* E, void* Y, int n_iter, void* workspace, size_t workspace_bytes,
+                    void* stream);
+
+/* Copy the solver scalars to the host (synchronizes the stream). */
+int ht_admm_get_stats(const ht_plan* plan, const void* workspace, void* stream, ht_admm_stats* out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HTSVT_H */

@@ -1,0 +1,147 @@
+// Element-wise recovery update of the pure-L ADMM (Sec. V updates of E, the
+// multiplier and mu), fused with the stopping-term reductions and with the
+// formation of the next iteration's t-SVT input M - E + Y/mu.
+#include "kernels.hpp"
+
+namespace ht {
+
+namespace {
+
+__device__ __forceinline__ unsigned long long dbits(double x) { return (unsigned long long)__double_as_longlong(x); }
+
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
+  return v;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_admm_input(const T* __restrict__ M, const T* __restrict__ E,
+                                                    const T* __restrict__ Y, const AdmmState* __restrict__ st,
+                                                    T* __restrict__ Xin, int64_t N) {
+  const double inv_mu = 1.0 / st->mu;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < N; i += (int64_t)gridDim.x * blockDim.x)
+    Xin[i] = (T)((double)M[i] - (double)E[i] + (double)Y[i] * inv_mu);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_admm_update(const T* __restrict__ M, const uint8_t* __restrict__ mask,
+                                                     const T* __restrict__ Lnew, T* __restrict__ L,
+                                                     T* __restrict__ E, T* __restrict__ Y, T* __restrict__ Xin,
+                                                     AdmmState* __restrict__ st, int64_t N, int model, Penalty psi,
+                                                     double lambda, double vartheta, double mu_max) {
+  const double mu = st->mu;
+  const double inv_mu = 1.0 / mu;
+  const double mu_next = fmin(mu_max, vartheta * mu);
+  const double inv_mu_next = 1.0 / mu_next;
+  const double thr = lambda * inv_mu;
+  double mdl = 0.0, mde = 0.0, mres = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < N; i += (int64_t)gridDim.x * blockDim.x) {
+    const double m = (double)M[i], ln = (double)Lnew[i], lo = (double)L[i];
+    const double e = (double)E[i], y = (double)Y[i];
+    const double h = m - ln + y * inv_mu;
+    double en;
+    if (mask[i])
+      en = (model == HT_RPCA) ? prox_signed(psi, h, thr) : 0.0;
+    else
+      en = h;
+    const double r = m - ln - en;
+    const double yn = y + mu * r;
+    mdl = fmax(mdl, fabs(ln - lo));
+    mde = fmax(mde, fabs(en - e));
+    mres = fmax(mres, fabs(r));
+    L[i] = (T)ln;
+    E[i] = (T)en;
+    Y[i] = (T)yn;
+    Xin[i] = (T)(m - en + yn * inv_mu_next);
+  }
+  __shared__ double red[3][4];
+  mdl = wave_max(mdl);
+  mde = wave_max(mde);
+  mres = wave_max(mres);
+  const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+  if (lane == 0) {
+    red[0][wave] = mdl;
+    red[1][wave] = mde;
+    red[2][wave] = mres;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double a = red[0][0], b = red[1][0], c = red[2][0];
+    for (int w = 1; w < (int)(blockDim.x / 64); ++w) {
+      a = fmax(a, red[0][w]);
+      b = fmax(b, red[1][w]);
+      c = fmax(c, red[2][w]);
+    }
+    atomicMax(&st->red_dL, dbits(a));
+    atomicMax(&st->red_dE, dbits(b));
+    atomicMax(&st->red_res, dbits(c));
+  }
+}
+
+__global__ void k_admm_finalize(AdmmState* st, double vartheta, double mu_max) {
+  st->dL = __longlong_as_double((long long)st->red_dL);
+  st->dE = __longlong_as_double((long long)st->red_dE);
+  st->resid = __longlong_as_double((long long)st->red_res);
+  st->red_dL = 0ull;
+  st->red_dE = 0ull;
+  st->red_res = 0ull;
+  st->mu = fmin(mu_max, vartheta * st->mu);
+  st->iteration += 1;
+}
+
+__global__ void k_admm_reset(AdmmState* st, double mu0) {
+  st->mu = mu0;
+  st->iteration = 0;
+  st->pad0 = 0;
+  st->dL = st->dE = st->resid = 0.0;
+  st->red_dL = st->red_dE = st->red_res = 0ull;
+}
+
+unsigned elementwise_blocks(int64_t N) {
+  int64_t b = ceil_div(N, 256);
+  return (unsigned)std::min<int64_t>(std::max<int64_t>(b, 1), 8192);
+}
+
+}  // namespace
+
+template <typename T>
+int launch_admm_input(const T* M, const T* E, const T* Y, const AdmmState* st, T* Xin, int64_t N, hipStream_t s) {
+  hipLaunchKernelGGL(k_admm_input<T>, dim3(elementwise_blocks(N)), dim3(256), 0, s, M, E, Y, st, Xin, N);
+  HT_CHECK_LAUNCH();
+  return HT_OK;
+}
+
+template <typename T>
+int launch_admm_update(const T* M, const uint8_t* mask, const T* Lnew, T* L, T* E, T* Y, T* Xin, AdmmState* st,
+                       int64_t N, int model, Penalty psi, double lambda, double vartheta, double mu_max,
+                       hipStream_t s) {
+  hipLaunchKernelGGL(k_admm_update<T>, dim3(elementwise_blocks(N)), dim3(256), 0, s, M, mask, Lnew, L, E, Y, Xin, st,
+                     N, model, psi, lambda, vartheta, mu_max);
+  HT_CHECK_LAUNCH();
+  return HT_OK;
+}
+
+int launch_admm_finalize(AdmmState* st, double vartheta, double mu_max, hipStream_t s) {
+  hipLaunchKernelGGL(k_admm_finalize, dim3(1), dim3(1), 0, s, st, vartheta, mu_max);
+  HT_CHECK_LAUNCH();
+  return HT_OK;
+}
+
+int launch_admm_reset(AdmmState* st, double mu0, hipStream_t s) {
+  hipLaunchKernelGGL(k_admm_reset, dim3(1), dim3(1), 0, s, st, mu0);
+  HT_CHECK_LAUNCH();
+  return HT_OK;
+}
+
+template int launch_admm_input<float>(const float*, const float*, const float*, const AdmmState*, float*, int64_t,
+                                      hipStream_t);
+template int launch_admm_input<double>(const double*, const double*, const double*, const AdmmState*, double*,
+                                       int64_t, hipStream_t);
+template int launch_admm_update<float>(const float*, const uint8_t*, const float*, float*, float*, float*, float*,
+                                       AdmmState*, int64_t, int, Penalty, double, double, double, hipStream_t);
+template int launch_admm_update<double>(const double*, const uint8_t*, const double*, double*, double*, double*,
+                                        double*, AdmmState*, int64_t, int, Penalty, double, double, double,
+                                        hipStream_t);
+
+}  // namespace ht

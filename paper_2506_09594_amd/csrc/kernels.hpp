@@ -1,0 +1,65 @@
+// Launch wrappers of the htsvt kernels (host side declarations).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdint>
+
+#include "common.hpp"
+#include "device.hpp"
+
+namespace ht {
+
+// Mode matrices of the transformed modes, as seen by the transform kernel.
+struct ModeTable {
+  int nmodes;
+  int n[HT_MAX_ORDER];
+  int stride[HT_MAX_ORDER];  // stride of mode m in the face-slice index
+  int off[HT_MAX_ORDER];     // offset of the n x n row-major matrix in the table
+};
+
+int transform_tile_width(int64_t P, size_t elem_bytes);
+
+template <typename T>
+int launch_transform(const T* in, T* out, int64_t NT, int P, const ModeTable& mt, const T* table, hipStream_t s);
+
+template <typename T>
+int launch_omega(T* om, double* om64, int P, int64_t per_slice, uint32_t call, const int32_t* call_dev,
+                 uint32_t stream_id, uint64_t seed, const int32_t* canon, hipStream_t s);
+
+// Batched thin products over P slices (slice strides in elements).
+//   nn:  Y_j (m x l)  = A_j (m x kd) W_j (kd x l)
+//   tn:  Z_j (n x l)  = A_j^T (n x m) Q_j (m x l)
+//   nt:  C_j (m x n)  = X_j (m x l) W_j^T (l x n)
+template <typename T>
+int launch_gemm_nn(const T* A, int64_t sA, int lda, const T* W, int64_t sW, int ldw, T* Y, int64_t sY, int ldy,
+                   int m, int kd, int l, int P, hipStream_t s);
+template <typename T>
+int launch_gemm_tn(const T* A, int64_t sA, int lda, const T* Q, int64_t sQ, int ldq, T* Z, int64_t sZ, int ldz,
+                   int m, int n, int l, int P, hipStream_t s);
+template <typename T>
+int launch_gemm_nt(const T* X, int64_t sX, int ldx, const T* W, int64_t sW, int ldw, T* C, int64_t sC, int ldc,
+                   int m, int n, int l, int P, hipStream_t s);
+
+// CholeskyQR with deflation, `passes` times, in place on Y_j (m x l).
+template <typename T>
+int launch_cholqr(T* Y, int64_t sY, int ldy, int m, int l, int P, int passes, hipStream_t s);
+
+// Small FP64 SVD of B_j = Bt_j^T via the Gram matrix, shrinkage of the top k
+// singular values, and K_j = U diag(prox(s)/s) U^T (l x l).
+template <typename T>
+int launch_smallsvd(const T* Bt, int64_t sB, int ldb, int n, int l, int k, int P, double tau, const double* mu_dev,
+                    Penalty pen, T* K, double* sigma_out, int* kept_out, hipStream_t s);
+
+// ADMM update (see htsvt.h) and the per-iteration scalar bookkeeping.
+template <typename T>
+int launch_admm_input(const T* M, const T* E, const T* Y, const AdmmState* st, T* Xin, int64_t N, hipStream_t s);
+template <typename T>
+int launch_admm_update(const T* M, const uint8_t* mask, const T* Lnew, T* L, T* E, T* Y, T* Xin,
+                       AdmmState* st, int64_t N, int model, Penalty psi, double lambda, double vartheta,
+                       double mu_max, hipStream_t s);
+int launch_admm_finalize(AdmmState* st, double vartheta, double mu_max, hipStream_t s);
+int launch_admm_reset(AdmmState* st, double mu0, hipStream_t s);
+
+}  // namespace ht

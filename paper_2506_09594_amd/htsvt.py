@@ -1,0 +1,287 @@
+"""Thin ctypes binding of the htsvt C-ABI library (argument marshalling only).
+
+Every step of the randomized t-SVT and of the ADMM update runs in the HIP
+kernels of libhtsvt.so; this module only converts arguments, allocates the
+caller-owned device buffers through PyTorch and passes raw pointers and the
+current HIP stream.  Tensors are passed as flat device tensors in Fortran order
+(i1 fastest), the library's storage layout; `to_device` / `from_device` convert
+from / to numpy arrays indexed (i1, ..., id).
+
+There is no fallback: if the library is missing, importing this module fails.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libhtsvt.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"libhtsvt.so not found at {LIB_PATH}; build it with paper_2506_09594_amd/build.py")
+
+_lib = ctypes.CDLL(LIB_PATH)
+
+MAX_ORDER = 8
+OK, ERR_INVALID_ARG, ERR_UNSUPPORTED, ERR_NONFINITE, ERR_WORKSPACE, ERR_HIP, ERR_ALLOC = 0, -1, -2, -3, -4, -5, -6
+TRANSFORMS = {"dct2": 0, "dft": 1, "custom": 2}
+PRECISIONS = {"fp64": 0, "fp32": 1, "bf16": 2}
+PENALTIES = {"l1": 0, "mcp": 1, "scad": 2, "log": 3, "capped_l1": 4}
+MODELS = {"completion": 0, "rpca": 1}
+REGIONS = {"A": 0, "omega": 1, "Q": 2, "Bt": 3, "K": 4, "QK": 5, "C": 6, "Lnew": 7, "Xin": 8, "state": 9}
+
+# Symbols the header declares (checked by the CPU test suite).
+EXPORTS = [
+    "ht_version", "ht_last_error", "ht_plan_create", "ht_plan_destroy", "ht_plan_workspace_size",
+    "ht_plan_info", "ht_plan_workspace_region", "ht_gnhtsvt", "ht_omega_fp64", "ht_transform",
+    "ht_admm_workspace_size", "ht_admm_init", "ht_admm_iterate", "ht_admm_get_stats",
+    "ht_profile_enable", "ht_profile_read",
+]
+STAGES = ["transform_fwd", "omega", "sketch_nn", "cholqr", "sketch_tn", "smallsvd", "recon_qk", "recon_nt",
+          "transform_inv", "admm_update"]
+
+
+class HtError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"htsvt error {code}: {msg}")
+        self.code = code
+
+
+class _Penalty(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int), ("p0", ctypes.c_double), ("p1", ctypes.c_double)]
+
+
+class _PlanDesc(ctypes.Structure):
+    _fields_ = [
+        ("order", ctypes.c_int),
+        ("dims", ctypes.c_int64 * MAX_ORDER),
+        ("transform", ctypes.c_int * MAX_ORDER),
+        ("custom", ctypes.POINTER(ctypes.c_double) * MAX_ORDER),
+        ("r", ctypes.c_int), ("p", ctypes.c_int), ("q", ctypes.c_int),
+        ("precision", ctypes.c_int),
+        ("seed", ctypes.c_uint64),
+        ("stream_id", ctypes.c_uint32),
+    ]
+
+
+class _AdmmParams(ctypes.Structure):
+    _fields_ = [
+        ("model", ctypes.c_int), ("phi", _Penalty), ("psi", _Penalty),
+        ("lam", ctypes.c_double), ("mu0", ctypes.c_double), ("vartheta", ctypes.c_double),
+        ("mu_max", ctypes.c_double),
+    ]
+
+
+class _AdmmStats(ctypes.Structure):
+    _fields_ = [("iteration", ctypes.c_int32), ("mu", ctypes.c_double), ("dL", ctypes.c_double),
+                ("dE", ctypes.c_double), ("resid", ctypes.c_double)]
+
+
+_vp = ctypes.c_void_p
+_sig = {
+    "ht_version": (ctypes.c_int, []),
+    "ht_last_error": (ctypes.c_char_p, []),
+    "ht_plan_create": (ctypes.c_int, [ctypes.POINTER(_PlanDesc), ctypes.POINTER(_vp)]),
+    "ht_plan_destroy": (ctypes.c_int, [_vp]),
+    "ht_plan_workspace_size": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_size_t)]),
+    "ht_plan_info": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int),
+                                    ctypes.POINTER(ctypes.c_int)]),
+    "ht_plan_workspace_region": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.POINTER(ctypes.c_size_t),
+                                                ctypes.POINTER(ctypes.c_size_t)]),
+    "ht_gnhtsvt": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_double, ctypes.POINTER(_Penalty), ctypes.c_uint32,
+                                  _vp, ctypes.c_size_t, _vp, _vp, _vp]),
+    "ht_omega_fp64": (ctypes.c_int, [_vp, ctypes.c_uint32, _vp, _vp]),
+    "ht_transform": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int, _vp]),
+    "ht_admm_workspace_size": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_size_t)]),
+    "ht_admm_init": (ctypes.c_int, [_vp, ctypes.POINTER(_AdmmParams), _vp, _vp, _vp, _vp, ctypes.c_size_t, _vp]),
+    "ht_admm_iterate": (ctypes.c_int, [_vp, ctypes.POINTER(_AdmmParams), _vp, _vp, _vp, _vp, _vp, ctypes.c_int,
+                                       _vp, ctypes.c_size_t, _vp]),
+    "ht_admm_get_stats": (ctypes.c_int, [_vp, _vp, _vp, ctypes.POINTER(_AdmmStats)]),
+    "ht_profile_enable": (ctypes.c_int, [_vp, ctypes.c_int]),
+    "ht_profile_read": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int),
+                                       ctypes.c_int]),
+}
+for _name, (_res, _args) in _sig.items():
+    _f = getattr(_lib, _name)
+    _f.restype = _res
+    _f.argtypes = _args
+
+
+def _check(rc):
+    if rc != OK:
+        raise HtError(rc, _lib.ht_last_error().decode(errors="replace"))
+
+
+def version():
+    return _lib.ht_version()
+
+
+def _penalty(pen):
+    kind, params = pen
+    params = tuple(params) + (0.0, 0.0)
+    return _Penalty(PENALTIES[kind], float(params[0]), float(params[1]))
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream():
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def to_device(X, dtype):
+    """numpy (n1, ..., nd) -> flat CUDA tensor in Fortran order."""
+    import torch
+    flat = np.ascontiguousarray(np.asarray(X).ravel(order="F"))
+    return torch.from_numpy(flat).to(device="cuda", dtype=dtype)
+
+
+def from_device(t, dims):
+    """flat CUDA tensor in Fortran order -> numpy (n1, ..., nd) float64."""
+    return t.detach().double().cpu().numpy().reshape(tuple(dims), order="F")
+
+
+class Plan:
+    """One tensor shape + transforms + sketch parameters on the current device."""
+
+    def __init__(self, dims, transforms=None, r=5, p=5, q=1, precision="fp32", seed=0, stream_id=0, custom=None):
+        dims = [int(d) for d in dims]
+        if not 2 <= len(dims) <= MAX_ORDER:
+            raise ValueError("order must be in [2, 8]")
+        transforms = transforms if transforms is not None else ["dct2"] * (len(dims) - 2)
+        d = _PlanDesc()
+        d.order = len(dims)
+        self._custom_keep = []
+        for i, n in enumerate(dims):
+            d.dims[i] = n
+        for k, kind in enumerate(transforms):
+            d.transform[k + 2] = TRANSFORMS[kind]
+            if kind == "custom":
+                U = np.ascontiguousarray(np.asarray(custom[k], dtype=np.float64))
+                self._custom_keep.append(U)
+                d.custom[k + 2] = U.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        d.r, d.p, d.q = int(r), int(p), int(q)
+        d.precision = PRECISIONS[precision]
+        d.seed = int(seed)
+        d.stream_id = int(stream_id)
+        h = _vp()
+        _check(_lib.ht_plan_create(ctypes.byref(d), ctypes.byref(h)))
+        self._h = h
+        self.dims = tuple(dims)
+        self.transforms = list(transforms)
+        self.precision = precision
+        self.r, self.p, self.q = int(r), int(p), int(q)
+        n_sl, w, k = ctypes.c_int64(), ctypes.c_int(), ctypes.c_int()
+        _check(_lib.ht_plan_info(h, ctypes.byref(n_sl), ctypes.byref(w), ctypes.byref(k)))
+        self.n_slices, self.width, self.kept = n_sl.value, w.value, k.value
+        self.N = int(np.prod(dims))
+        sz = ctypes.c_size_t()
+        _check(_lib.ht_plan_workspace_size(h, ctypes.byref(sz)))
+        self.workspace_bytes = sz.value
+        _check(_lib.ht_admm_workspace_size(h, ctypes.byref(sz)))
+        self.admm_workspace_bytes = sz.value
+
+    @property
+    def torch_dtype(self):
+        import torch
+        return torch.float64 if self.precision == "fp64" else torch.float32
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.ht_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def alloc_workspace(self, admm=False):
+        import torch
+        n = self.admm_workspace_bytes if admm else self.workspace_bytes
+        return torch.empty(n + 256, dtype=torch.uint8, device="cuda")
+
+    @staticmethod
+    def _aligned(ws):
+        off = (-ws.data_ptr()) % 256
+        return ctypes.c_void_p(ws.data_ptr() + off), ws.numel() - off
+
+    def region(self, ws, name, dtype=None):
+        """View of a named workspace region as a flat tensor."""
+        import torch
+        off, nb = ctypes.c_size_t(), ctypes.c_size_t()
+        _check(_lib.ht_plan_workspace_region(self._h, REGIONS[name], ctypes.byref(off), ctypes.byref(nb)))
+        base = (-ws.data_ptr()) % 256
+        dtype = dtype or self.torch_dtype
+        raw = ws[base + off.value: base + off.value + nb.value]
+        return raw.view(dtype)
+
+    def gnhtsvt(self, X, tau, penalty=("l1", ()), call_index=0, out=None, workspace=None, stats=False):
+        import torch
+        if out is None:
+            out = torch.empty_like(X)
+        if workspace is None:
+            workspace = self.alloc_workspace()
+        wp, wn = self._aligned(workspace)
+        sig = kept = None
+        if stats:
+            sig = torch.empty(self.n_slices * self.width, dtype=torch.float64, device=X.device)
+            kept = torch.empty(self.n_slices, dtype=torch.int32, device=X.device)
+        pen = _penalty(penalty)
+        _check(_lib.ht_gnhtsvt(self._h, _ptr(X), _ptr(out), float(tau), ctypes.byref(pen), int(call_index),
+                               wp, wn, _stream(), _ptr(sig), _ptr(kept)))
+        if stats:
+            return out, sig.view(self.n_slices, self.width), kept
+        return out
+
+    def omega_fp64(self, call_index=0):
+        import torch
+        o = torch.empty(self.n_slices * self.dims[1] * self.width, dtype=torch.float64, device="cuda")
+        _check(_lib.ht_omega_fp64(self._h, int(call_index), _ptr(o), _stream()))
+        return o
+
+    def profile(self, on=True):
+        _check(_lib.ht_profile_enable(self._h, 1 if on else 0))
+
+    def profile_read(self):
+        """{stage: (total_ms, launches)} for the launches recorded since the last read."""
+        n = len(STAGES)
+        ms = (ctypes.c_double * n)()
+        cnt = (ctypes.c_int * n)()
+        _check(_lib.ht_profile_read(self._h, ms, cnt, n))
+        return {STAGES[i]: (ms[i], cnt[i]) for i in range(n)}
+
+    def transform(self, X, inverse=False, out=None):
+        import torch
+        if out is None:
+            out = torch.empty_like(X)
+        _check(_lib.ht_transform(self._h, _ptr(X), _ptr(out), 1 if inverse else 0, _stream()))
+        return out
+
+
+class Admm:
+    """Pure-L ADMM (completion / robust completion) driven through the C-ABI."""
+
+    def __init__(self, plan, model="completion", phi=("l1", ()), psi=("l1", ()), lam=0.0, mu0=1e-3,
+                 vartheta=1.15, mu_max=1e10):
+        self.plan = plan
+        self.prm = _AdmmParams(MODELS[model], _penalty(phi), _penalty(psi), float(lam), float(mu0),
+                               float(vartheta), float(mu_max))
+
+    def init(self, L, E, Y, workspace):
+        wp, wn = Plan._aligned(workspace)
+        _check(_lib.ht_admm_init(self.plan._h, ctypes.byref(self.prm), _ptr(L), _ptr(E), _ptr(Y), wp, wn, _stream()))
+
+    def iterate(self, M, mask, L, E, Y, n_iter, workspace):
+        wp, wn = Plan._aligned(workspace)
+        _check(_lib.ht_admm_iterate(self.plan._h, ctypes.byref(self.prm), _ptr(M), _ptr(mask), _ptr(L), _ptr(E),
+                                    _ptr(Y), int(n_iter), wp, wn, _stream()))
+
+    def stats(self, workspace):
+        wp, _wn = Plan._aligned(workspace)
+        st = _AdmmStats()
+        _check(_lib.ht_admm_get_stats(self.plan._h, wp, _stream(), ctypes.byref(st)))
+        return {"iteration": st.iteration, "mu": st.mu, "dL": st.dL, "dE": st.dE, "resid": st.resid}
