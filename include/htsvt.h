@@ -40,7 +40,7 @@ extern "C" {
 #endif
 
 #define HT_MAX_ORDER 8
-#define HT_MAX_WIDTH 80    /* largest sketch width l = min(r + p, n1, n2) */
+#define HT_MAX_WIDTH 76    /* largest sketch width l = min(r + p, n1, n2) */
 #define HT_MAX_MODE 64     /* largest n_k of a transformed mode */
 
 enum {
@@ -130,9 +130,11 @@ int ht_plan_info(const ht_plan* plan, int64_t* n_slices, int* width, int* kept);
 
 /* Offset and size in bytes of a named region of the workspace, for
  * inspecting intermediate results after a call: 0 transformed tensor A,
- * 1 sketch matrices Omega, 2 orthonormal basis Q (n1 x l per slice),
- * 3 B^T = A^T Q (n2 x l per slice), 4 shrink kernels K (l x l per slice),
- * 5 Q K, 6 reconstructed transformed slices C, 7-9 solver buffers. */
+ * 1 sketch matrices Omega, 2 basis Q1 of the last CholeskyQR pass (n1 x l per
+ * slice; the final R2 correction is applied in the l x l space),
+ * 3 B^T = A^T Q1 (n2 x l per slice), 4 K' = R2^{-1} U diag(w) U^T R2^{-T}
+ * (l x l per slice), 5 Q1 K', 6 reconstructed transformed slices C,
+ * 7-9 solver buffers, 10-11 FP64 Gram partials. */
 int ht_plan_workspace_region(const ht_plan* plan, int region, size_t* offset, size_t* bytes);
 
 /* Randomized GNHTSVT (Def. 4.3 computed slice-wise on sketches):

@@ -2,7 +2,10 @@
 // of the randomized t-SVT and of the ADMM iteration.
 #include <cmath>
 #include <cstring>
+#include <mutex>
+#include <set>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "kernels.hpp"
@@ -13,12 +16,24 @@ static thread_local std::string g_last_error;
 
 void set_error(const std::string& msg) { g_last_error = msg; }
 
+int ensure_dynamic_lds(const void* kernel, size_t bytes) {
+  static std::mutex mu;
+  static std::set<std::pair<int, const void*>> done;
+  int dev = 0;
+  HT_CHECK_HIP(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lock(mu);
+  if (done.count({dev, kernel})) return HT_OK;
+  HT_CHECK_HIP(hipFuncSetAttribute(kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
+  done.insert({dev, kernel});
+  return HT_OK;
+}
+
 }  // namespace ht
 
 using namespace ht;
 
 // Named regions of the t-SVT workspace (for introspection by the tests).
-enum { WS_A = 0, WS_OMEGA, WS_Y, WS_Z, WS_K, WS_QK, WS_C, WS_LNEW, WS_XIN, WS_STATE, WS_COUNT };
+enum { WS_A = 0, WS_OMEGA, WS_Y, WS_Z, WS_K, WS_QK, WS_C, WS_LNEW, WS_XIN, WS_STATE, WS_GP1, WS_GP2, WS_COUNT };
 
 // Optional per-stage timing with HIP events recorded on the launch stream.
 enum { ST_TRANSFORM_FWD = 0, ST_OMEGA, ST_SKETCH_NN, ST_CHOLQR, ST_SKETCH_TN, ST_SMALLSVD, ST_RECON_QK, ST_RECON_NT,
@@ -105,11 +120,16 @@ void layout(ht_plan* pl) {
   pl->size[WS_LNEW] = (size_t)pl->N * es;
   pl->size[WS_XIN] = (size_t)pl->N * es;
   pl->size[WS_STATE] = sizeof(AdmmState);
+  const size_t t1 = (size_t)ceil_div(pl->n1, 64), t2 = (size_t)ceil_div(pl->n2, 64);
+  pl->size[WS_GP1] = P * std::max(t1, t2) * l * l * sizeof(double);
+  pl->size[WS_GP2] = P * t1 * l * l * sizeof(double);
+  // t-SVT regions first, then the solver-only regions
+  const int order_[] = {WS_A, WS_OMEGA, WS_Y, WS_Z, WS_K, WS_QK, WS_C, WS_GP1, WS_GP2, WS_LNEW, WS_XIN, WS_STATE};
   size_t o = 0;
-  for (int i = 0; i < WS_COUNT; ++i) {
-    pl->off[i] = o;
-    o += align256(pl->size[i]);
-    if (i == WS_C) pl->tsvt_bytes = o;
+  for (int r : order_) {
+    pl->off[r] = o;
+    o += align256(pl->size[r]);
+    if (r == WS_GP2) pl->tsvt_bytes = o;
   }
   pl->admm_bytes = o;
 }
@@ -176,38 +196,44 @@ int run_tsvt(const ht_plan* pl, const T* X, T* out, double tau, const double* mu
          return launch_omega<T>(Om, nullptr, (int)P, n2 * l, call, call_dev, pl->stream_id, pl->seed, nullptr, s);
        })))
     return rc;
+  double* gp1 = ws_ptr<double>(pl, ws, WS_GP1);
+  double* gp2 = ws_ptr<double>(pl, ws, WS_GP2);
+  const int t1 = (int)ceil_div(n1, 64), t2 = (int)ceil_div(n2, 64);
   auto sketch_nn = [&](const T* W) {
     return timed(pl, ST_SKETCH_NN, s, [&] {
-      return launch_gemm_nn<T>(A, sA, (int)n1, W, sZ, (int)n2, Y, sY, (int)n1, (int)n1, (int)n2, l, (int)P, s);
+      return launch_gemm_nn<T>(A, sA, (int)n1, W, sZ, (int)n2, Y, sY, (int)n1, (int)n1, (int)n2, l, (int)P, gp1, s);
     });
   };
   auto sketch_tn = [&]() {
     return timed(pl, ST_SKETCH_TN, s, [&] {
-      return launch_gemm_tn<T>(A, sA, (int)n1, Y, sY, (int)n1, Z, sZ, (int)n2, (int)n1, (int)n2, l, (int)P, s);
+      return launch_gemm_tn<T>(A, sA, (int)n1, Y, sY, (int)n1, Z, sZ, (int)n2, (int)n1, (int)n2, l, (int)P, gp1, s);
     });
   };
-  auto orth = [&](T* M, int64_t sM, int m) {
-    return timed(pl, ST_CHOLQR, s, [&] { return launch_cholqr<T>(M, sM, m, m, l, (int)P, 2, s); });
+  auto orth = [&](T* M, int64_t sM, int m, double* gout) {
+    return timed(pl, ST_CHOLQR, s, [&] { return launch_orth_apply<T>(M, sM, m, m, l, (int)P, gp1, gout, s); });
   };
-  // Y = A Omega, Q = orth(Y); q power steps; Bt = A^T Q
+  // Y = A Omega, Q1 = orth(Y); q power steps Z = orth(A^T Q1), Q1 = orth(A Z);
+  // the last orthonormalization also writes the Gram partials of Q1.
   if ((rc = sketch_nn(Om))) return rc;
-  if ((rc = orth(Y, sY, (int)n1))) return rc;
+  if ((rc = orth(Y, sY, (int)n1, pl->q == 0 ? gp2 : nullptr))) return rc;
   for (int it = 0; it < pl->q; ++it) {
     if ((rc = sketch_tn())) return rc;
-    if ((rc = orth(Z, sZ, (int)n2))) return rc;
+    if ((rc = orth(Z, sZ, (int)n2, nullptr))) return rc;
     if ((rc = sketch_nn(Z))) return rc;
-    if ((rc = orth(Y, sY, (int)n1))) return rc;
+    if ((rc = orth(Y, sY, (int)n1, it == pl->q - 1 ? gp2 : nullptr))) return rc;
   }
+  // Bt = A^T Q1 with the Gram partials of Bt
   if ((rc = sketch_tn())) return rc;
-  // small SVD of B = Bt^T and shrinkage -> K
+  // second CholeskyQR step in the small space, small SVD, shrink -> K'
   if ((rc = timed(pl, ST_SMALLSVD, s, [&] {
-         return launch_smallsvd<T>(Z, sZ, (int)n2, (int)n2, l, pl->k, (int)P, tau, mu_dev, pen, K, sigma_out,
+         return launch_smallsvd<T>(gp2, t1, (int)n1, gp1, t2, l, pl->k, (int)P, tau, mu_dev, pen, K, sigma_out,
                                    kept_out, s);
        })))
     return rc;
-  // C = (Q K) Bt^T, then the inverse transform
+  // C = (Q1 K') Bt^T, then the inverse transform
   if ((rc = timed(pl, ST_RECON_QK, s, [&] {
-         return launch_gemm_nn<T>(Y, sY, (int)n1, K, (int64_t)l * l, l, QK, sY, (int)n1, (int)n1, l, l, (int)P, s);
+         return launch_gemm_nn<T>(Y, sY, (int)n1, K, (int64_t)l * l, l, QK, sY, (int)n1, (int)n1, l, l, (int)P,
+                                  nullptr, s);
        })))
     return rc;
   if ((rc = timed(pl, ST_RECON_NT, s, [&] {
@@ -374,21 +400,21 @@ int ht_plan_create(const ht_plan_desc* d, ht_plan** out) {
     std::vector<float> tab32(tab.begin(), tab.end());
     if (hipMalloc(&pl->table64, tab.size() * sizeof(double)) != hipSuccess ||
         hipMalloc(&pl->table32, tab32.size() * sizeof(float)) != hipSuccess) {
-      hipFree(pl->table64);
+      (void)hipFree(pl->table64);
       delete pl;
       HT_FAIL(HT_ERR_ALLOC, "could not allocate transform tables");
     }
     if (hipMemcpy(pl->table64, tab.data(), tab.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(pl->table32, tab32.data(), tab32.size() * sizeof(float), hipMemcpyHostToDevice) != hipSuccess) {
-      hipFree(pl->table64);
-      hipFree(pl->table32);
+      (void)hipFree(pl->table64);
+      (void)hipFree(pl->table32);
       delete pl;
       HT_FAIL(HT_ERR_HIP, "could not upload transform tables");
     }
   }
   if (pl->mt_fwd.nmodes > 0 && transform_tile_width(P, elem_bytes(pl->precision)) == 0) {
-    hipFree(pl->table64);
-    hipFree(pl->table32);
+    (void)hipFree(pl->table64);
+    (void)hipFree(pl->table32);
     delete pl;
     HT_FAIL(HT_ERR_UNSUPPORTED, "too many face slices for the transform tile");
   }
@@ -401,13 +427,13 @@ int ht_plan_destroy(ht_plan* pl) {
   if (!pl) return HT_OK;
   if (pl->prof) {
     for (auto& r : pl->prof->recs) {
-      hipEventDestroy(r.a);
-      hipEventDestroy(r.b);
+      (void)hipEventDestroy(r.a);
+      (void)hipEventDestroy(r.b);
     }
     delete pl->prof;
   }
-  if (pl->table64) hipFree(pl->table64);
-  if (pl->table32) hipFree(pl->table32);
+  if (pl->table64) (void)hipFree(pl->table64);
+  if (pl->table32) (void)hipFree(pl->table32);
   delete pl;
   return HT_OK;
 }
@@ -438,8 +464,8 @@ int ht_profile_read(ht_plan* pl, double* ms_total, int* count, int n_stages) {
         count[r.stage] += 1;
       }
     }
-    hipEventDestroy(r.a);
-    hipEventDestroy(r.b);
+    (void)hipEventDestroy(r.a);
+    (void)hipEventDestroy(r.b);
   }
   pl->prof->recs.clear();
   return rc;

@@ -1,0 +1,205 @@
+// Block-level FP64 helpers shared by the orthonormalization and small-SVD
+// kernels: summation of per-tile Gram partials, Cholesky with deflation and
+// triangular solves.  All routines are called by every thread of the workgroup
+// (uniform control flow, __syncthreads inside).  They are latency-bound, so
+// every phase first issues all of a thread's independent loads and only then
+// computes and stores.
+#pragma once
+
+#include "kernels.hpp"
+
+namespace ht {
+
+// 1/x for x > 0 from the hardware estimate refined by two Newton steps
+// (relative error at the level of the FP64 rounding unit).
+__device__ __forceinline__ double fast_rcp(double x) {
+  double y = __builtin_amdgcn_rcp(x);
+  y = y * (2.0 - x * y);
+  y = y * (2.0 - x * y);
+  return y;
+}
+
+// 1/sqrt(x) for x > 0, estimate refined by two Newton steps.
+__device__ __forceinline__ double fast_rsqrt(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  y = y * (1.5 - 0.5 * x * y * y);
+  y = y * (1.5 - 0.5 * x * y * y);
+  return y;
+}
+
+// Broadcast lane `lane` (a compile-time or wave-uniform index) of a double.
+__device__ __forceinline__ double readlane_d(double v, int lane) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), lane);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// Cholesky with deflation held in registers of one wavefront: lane b owns
+// column b of G (g[a] = G[a][b], a < LB, LB <= 64).  On return g[a] holds
+// R[a][b] for a < b and g[b] = R[b][b] (0 for a skipped column); entries below
+// the diagonal are meaningless.  Rows of R are broadcast with readlane, so the
+// factorization needs no shared memory and no barriers.  delta: absolute pivot
+// threshold (uniform).
+template <int LB>
+__device__ __forceinline__ void chol_regs(double (&g)[LB], int l, double delta) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int j = 0; j < LB; ++j) {
+    if (j < l) {
+      const double d = readlane_d(g[j], j);
+      if (d > delta) {
+        const double inv_r = fast_rsqrt(d);
+        const double rjb = g[j] * inv_r;  // R[j][b] on lane b >= j (R[j][j] on lane j)
+        if (lane >= j) g[j] = rjb;
+#pragma unroll
+        for (int a = j + 1; a < LB; ++a) {
+          if (a < l) {
+            const double rja = readlane_d(rjb, a);
+            g[a] -= rja * rjb;
+          }
+        }
+      } else {
+        if (lane >= j) g[j] = 0.0;
+      }
+    }
+  }
+}
+
+// G (l x l, pitch gp) = sum over tiles t of part[t*l*l + a*l + b], in tile order.
+__device__ inline void sum_gram_partials(double* G, int gp, const double* __restrict__ part, int ntiles, int l) {
+  const int ll = l * l;
+  constexpr int E = 4;  // entries per batch
+  for (int e0 = threadIdx.x; e0 < ll; e0 += E * blockDim.x) {
+    double s[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) s[e] = 0.0;
+    for (int t0 = 0; t0 < ntiles; t0 += 4) {
+      double v[E][4];
+#pragma unroll
+      for (int e = 0; e < E; ++e)
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          const int idx = e0 + e * blockDim.x;
+          v[e][t] = (idx < ll && t0 + t < ntiles) ? part[(int64_t)(t0 + t) * ll + idx] : 0.0;
+        }
+#pragma unroll
+      for (int e = 0; e < E; ++e)
+#pragma unroll
+        for (int t = 0; t < 4; ++t) s[e] += v[e][t];
+    }
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const int idx = e0 + e * blockDim.x;
+      if (idx < ll) G[(idx / l) * gp + (idx % l)] = s[e];
+    }
+  }
+}
+
+// Right-looking Cholesky with deflation of the upper triangle of G (l x l,
+// pitch gp): on return the lower triangle holds R transposed,
+// G[b*gp + j] = R[j][b] for j < b, and dR[j] = R[j][j], with G = R^T R on the
+// kept columns.  A column whose Schur-complement pivot is <= delta_rel *
+// max_i G_ii is skipped (row of R = 0, dR = 0).  One barrier per column: the
+// trailing update reads the unscaled pivot row, which this column never
+// writes, and R goes to the (unused) lower triangle.  s_scratch: one shared
+// double.
+__device__ inline void chol_deflate(double* G, double* dR, int gp, int l, double delta_rel, double* s_scratch) {
+  const int tid = threadIdx.x, nt = blockDim.x;
+  if (tid == 0) {
+    double md = 0.0;
+    for (int a = 0; a < l; ++a) md = fmax(md, G[a * gp + a]);
+    *s_scratch = md;
+  }
+  __syncthreads();
+  const double maxdiag = *s_scratch;
+  const double delta = delta_rel * maxdiag;
+  constexpr int RB = 16;  // rows per batch of the trailing update
+  for (int j = 0; j < l; ++j) {
+    const double d = G[j * gp + j];
+    const bool keep = d > delta && maxdiag > 0.0;
+    const double inv_r = keep ? fast_rsqrt(d) : 0.0;  // 1 / R[j][j]
+    const double inv_d = inv_r * inv_r;
+    // branch-free: the loads below do not wait for the pivot arithmetic
+    for (int b = j + 1 + tid; b < l; b += nt) {
+      const double gjb = G[j * gp + b];
+      for (int a0 = j + 1; a0 <= b; a0 += RB) {
+        double gja[RB], gab[RB];
+#pragma unroll
+        for (int u = 0; u < RB; ++u) {
+          const int a = min(a0 + u, b);
+          gja[u] = G[j * gp + a];
+          gab[u] = G[a * gp + b];
+        }
+        const double f = gjb * inv_d;
+#pragma unroll
+        for (int u = 0; u < RB; ++u) {
+          const int a = a0 + u;
+          if (a <= b) G[a * gp + b] = gab[u] - gja[u] * f;
+        }
+      }
+      G[b * gp + j] = gjb * inv_r;
+    }
+    if (tid == 0) dR[j] = keep ? d * inv_r : 0.0;
+    __syncthreads();
+  }
+}
+
+// After chol_deflate: R^{-1} (zero rows and columns at skipped indices) into
+// Rinv (l x l, pitch gp, upper triangle; the strict lower triangle is zeroed).
+// Column c of R^{-1} by column-oriented back substitution in registers
+// (LB >= l): once x[b] is known it is removed from every pending row at once,
+// so the dependent chain is one multiply-add per row.
+template <int LB>
+__device__ inline void tri_inverse(const double* G, const double* dR, int gp, int l, double* Rinv) {
+  for (int c = threadIdx.x; c < l; c += blockDim.x) {
+    double s[LB];
+#pragma unroll
+    for (int a = 0; a < LB; ++a) s[a] = (a == c) ? 1.0 : 0.0;
+#pragma unroll
+    for (int b = LB - 1; b >= 0; --b) {
+      if (b <= c) {
+        const double d = dR[b];
+        const double xb = (d != 0.0) ? s[b] * fast_rcp(d) : 0.0;
+        s[b] = xb;
+#pragma unroll
+        for (int a = 0; a < b; ++a) s[a] -= G[b * gp + a] * xb;  // R[a][b]
+      }
+    }
+#pragma unroll
+    for (int a = 0; a < LB; ++a)
+      if (a < l) Rinv[a * gp + c] = (a <= c) ? s[a] : 0.0;
+  }
+  __syncthreads();
+}
+
+// Gram partial of an LDS tile S (rows x l, pitch gp, rows beyond the data zero):
+// out[a*l + b] = out[b*l + a] = sum_i S[i][a] S[i][b].
+__device__ inline void tile_gram_to_global(const double* S, int gp, int rows, int l, double* __restrict__ out) {
+  const int npairs = l * (l + 1) / 2;
+  for (int p0 = 0; p0 < npairs; p0 += blockDim.x) {
+    int p = p0 + threadIdx.x;
+    if (p >= npairs) break;
+    int a = 0, row_len = l;
+    while (p >= row_len) {
+      p -= row_len;
+      ++a;
+      --row_len;
+    }
+    const int b = a + p;
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    int i = 0;
+    for (; i + 4 <= rows; i += 4) {
+      s0 += S[i * gp + a] * S[i * gp + b];
+      s1 += S[(i + 1) * gp + a] * S[(i + 1) * gp + b];
+      s2 += S[(i + 2) * gp + a] * S[(i + 2) * gp + b];
+      s3 += S[(i + 3) * gp + a] * S[(i + 3) * gp + b];
+    }
+    for (; i < rows; ++i) s0 += S[i * gp + a] * S[i * gp + b];
+    const double s = (s0 + s1) + (s2 + s3);
+    out[a * l + b] = s;
+    out[b * l + a] = s;
+  }
+}
+
+}  // namespace ht

@@ -21,6 +21,9 @@ struct ModeTable {
 
 int transform_tile_width(int64_t P, size_t elem_bytes);
 
+// Raise a kernel's dynamic-LDS limit once per (device, kernel).
+int ensure_dynamic_lds(const void* kernel, size_t bytes);
+
 template <typename T>
 int launch_transform(const T* in, T* out, int64_t NT, int P, const ModeTable& mt, const T* table, hipStream_t s);
 
@@ -32,25 +35,34 @@ int launch_omega(T* om, double* om64, int P, int64_t per_slice, uint32_t call, c
 //   nn:  Y_j (m x l)  = A_j (m x kd) W_j (kd x l)
 //   tn:  Z_j (n x l)  = A_j^T (n x m) Q_j (m x l)
 //   nt:  C_j (m x n)  = X_j (m x l) W_j^T (l x n)
+//   gpart (optional): FP64 Gram partial of every 64-row output tile, laid out
+//   [slice][tile][l][l] with ceil(rows / 64) tiles per slice.
 template <typename T>
 int launch_gemm_nn(const T* A, int64_t sA, int lda, const T* W, int64_t sW, int ldw, T* Y, int64_t sY, int ldy,
-                   int m, int kd, int l, int P, hipStream_t s);
+                   int m, int kd, int l, int P, double* gpart, hipStream_t s);
 template <typename T>
 int launch_gemm_tn(const T* A, int64_t sA, int lda, const T* Q, int64_t sQ, int ldq, T* Z, int64_t sZ, int ldz,
-                   int m, int n, int l, int P, hipStream_t s);
+                   int m, int n, int l, int P, double* gpart, hipStream_t s);
 template <typename T>
 int launch_gemm_nt(const T* X, int64_t sX, int ldx, const T* W, int64_t sW, int ldw, T* C, int64_t sC, int ldc,
                    int m, int n, int l, int P, hipStream_t s);
 
-// CholeskyQR with deflation, `passes` times, in place on Y_j (m x l).
+// One CholeskyQR pass with deflation, in place on Y_j (m x l), from the Gram
+// partials written by the producing product (gin, ntiles = ceil(m/64) per
+// slice).  Optionally writes the Gram partials of the result (gout).
 template <typename T>
-int launch_cholqr(T* Y, int64_t sY, int ldy, int m, int l, int P, int passes, hipStream_t s);
+int launch_orth_apply(T* Y, int64_t sY, int ldy, int m, int l, int P, const double* gin, double* gout,
+                      hipStream_t s);
 
-// Small FP64 SVD of B_j = Bt_j^T via the Gram matrix, shrinkage of the top k
-// singular values, and K_j = U diag(prox(s)/s) U^T (l x l).
+// Small SVD and shrinkage in FP64.  Inputs: Gram partials of the basis Q1
+// (g2, ntiles_q per slice) and of Bt = A^T Q1 (gw, ntiles_b per slice).  With
+// R2 = chol(Q1^T Q1), B = R2^{-T} Bt^T, W = B B^T = U diag(s^2) U^T; writes
+// K' = R2^{-1} U diag(w) U^T R2^{-T} (l x l) with w_i = prox(s_i)/s_i, i < k.
+// The first l*l doubles of every slice's g2 partials are overwritten (scratch).
 template <typename T>
-int launch_smallsvd(const T* Bt, int64_t sB, int ldb, int n, int l, int k, int P, double tau, const double* mu_dev,
-                    Penalty pen, T* K, double* sigma_out, int* kept_out, hipStream_t s);
+int launch_smallsvd(double* g2, int ntiles_q, int m_q, const double* gw, int ntiles_b, int l, int k, int P,
+                    double tau, const double* mu_dev, Penalty pen, T* K, double* sigma_out, int* kept_out,
+                    hipStream_t s);
 
 // ADMM update (see htsvt.h) and the per-iteration scalar bookkeeping.
 template <typename T>

@@ -4,8 +4,11 @@
 // column-major with l <= 128 columns.  The kernels tile the long dimension in
 // 64-row (or 64-column) blocks per workgroup, stage a K-chunk of both operands
 // in LDS and accumulate in the storage precision (FP32 for float, FP64 for
-// double).  One pass reads every slice exactly once.
-#include "kernels.hpp"
+// double).  One pass reads every slice exactly once.  Optionally the epilogue
+// also writes, per output tile, the FP64 Gram matrix of the tile's rows as
+// stored (rounded to the storage type), so that the orthonormalization of the
+// thin result needs no extra pass over it.
+#include "chol.hpp"
 
 namespace ht {
 
@@ -15,12 +18,38 @@ constexpr int TM = 64;  // rows (or columns of A) per workgroup
 constexpr int KC = 32;  // K chunk staged in LDS
 
 template <typename T, int LB>
+constexpr size_t gemm_lds_bytes() {
+  constexpr size_t main = sizeof(T) * (KC * (TM + 1) + KC * LB);
+  constexpr size_t epi = sizeof(double) * TM * (LB + 1);
+  return main > epi ? main : epi;
+}
+
+// Epilogue: Gram partial of the 64 x l output tile held in registers acc[i] at
+// (row tr, column tc + 4 i).  Rows beyond the matrix contribute zero.
+template <typename T, int LB>
+__device__ inline void tile_gram_epilogue(unsigned char* smem, const T* acc, int tr, int tc, int rows, int l,
+                                          double* __restrict__ out) {
+  constexpr int CPT = LB / 4;
+  double* S = reinterpret_cast<double*>(smem);
+  const int gp = LB + 1;
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < CPT; ++i) {
+    const int c = tc + 4 * i;
+    if (c < l) S[tr * gp + c] = (tr < rows) ? (double)acc[i] : 0.0;
+  }
+  __syncthreads();
+  tile_gram_to_global(S, gp, TM, l, out);
+}
+
+template <typename T, int LB>
 __global__ __launch_bounds__(256) void k_gemm_nn(const T* __restrict__ A, int64_t sA, int lda,
                                                  const T* __restrict__ W, int64_t sW, int ldw, T* __restrict__ Y,
-                                                 int64_t sY, int ldy, int m, int kd, int l) {
+                                                 int64_t sY, int ldy, int m, int kd, int l, double* __restrict__ gpart) {
   constexpr int CPT = LB / 4;
-  __shared__ T As[KC][TM];
-  __shared__ T Ws[KC][LB];
+  __shared__ __align__(16) unsigned char smem[gemm_lds_bytes<T, LB>()];
+  T(*As)[TM + 1] = reinterpret_cast<T(*)[TM + 1]>(smem);
+  T(*Ws)[LB] = reinterpret_cast<T(*)[LB]>(smem + sizeof(T) * KC * (TM + 1));
   const int j = blockIdx.y;
   const int row0 = blockIdx.x * TM;
   const T* Aj = A + (int64_t)j * sA;
@@ -58,15 +87,19 @@ __global__ __launch_bounds__(256) void k_gemm_nn(const T* __restrict__ A, int64_
       if (c < l) Yj[gr + (int64_t)c * ldy] = acc[i];
     }
   }
+  if (gpart)
+    tile_gram_epilogue<T, LB>(smem, acc, tr, tc, m - row0, l,
+                              gpart + ((int64_t)j * gridDim.x + blockIdx.x) * (int64_t)l * l);
 }
 
 template <typename T, int LB>
 __global__ __launch_bounds__(256) void k_gemm_tn(const T* __restrict__ A, int64_t sA, int lda,
                                                  const T* __restrict__ Q, int64_t sQ, int ldq, T* __restrict__ Z,
-                                                 int64_t sZ, int ldz, int m, int n, int l) {
+                                                 int64_t sZ, int ldz, int m, int n, int l, double* __restrict__ gpart) {
   constexpr int CPT = LB / 4;
-  __shared__ T As[KC][TM + 1];
-  __shared__ T Qs[KC][LB];
+  __shared__ __align__(16) unsigned char smem[gemm_lds_bytes<T, LB>()];
+  T(*As)[TM + 1] = reinterpret_cast<T(*)[TM + 1]>(smem);
+  T(*Qs)[LB] = reinterpret_cast<T(*)[LB]>(smem + sizeof(T) * KC * (TM + 1));
   const int j = blockIdx.y;
   const int col0 = blockIdx.x * TM;
   const T* Aj = A + (int64_t)j * sA;
@@ -104,6 +137,9 @@ __global__ __launch_bounds__(256) void k_gemm_tn(const T* __restrict__ A, int64_
       if (c < l) Zj[gc + (int64_t)c * ldz] = acc[i];
     }
   }
+  if (gpart)
+    tile_gram_epilogue<T, LB>(smem, acc, tcol, tc, n - col0, l,
+                              gpart + ((int64_t)j * gridDim.x + blockIdx.x) * (int64_t)l * l);
 }
 
 // C_j (m x n) = X_j (m x l) W_j^T with W_j n x l: 64 x 64 output tile per
@@ -168,28 +204,30 @@ __global__ __launch_bounds__(256) void k_gemm_nt(const T* __restrict__ X, int64_
       hipLaunchKernelGGL((KERNEL<T, 16>), __VA_ARGS__);                        \
     else if ((l) <= 32)                                                        \
       hipLaunchKernelGGL((KERNEL<T, 32>), __VA_ARGS__);                        \
+    else if ((l) <= 48)                                                        \
+      hipLaunchKernelGGL((KERNEL<T, 48>), __VA_ARGS__);                        \
     else if ((l) <= 64)                                                        \
       hipLaunchKernelGGL((KERNEL<T, 64>), __VA_ARGS__);                        \
     else                                                                       \
-      hipLaunchKernelGGL((KERNEL<T, 128>), __VA_ARGS__);                       \
+      hipLaunchKernelGGL((KERNEL<T, 80>), __VA_ARGS__);                        \
   } while (0)
 
 template <typename T>
 int launch_gemm_nn(const T* A, int64_t sA, int lda, const T* W, int64_t sW, int ldw, T* Y, int64_t sY, int ldy,
-                   int m, int kd, int l, int P, hipStream_t s) {
-  if (l > HT_MAX_WIDTH) HT_FAIL(HT_ERR_UNSUPPORTED, "sketch width above 128");
+                   int m, int kd, int l, int P, double* gpart, hipStream_t s) {
+  if (l > HT_MAX_WIDTH) HT_FAIL(HT_ERR_UNSUPPORTED, "sketch width above HT_MAX_WIDTH");
   dim3 grid((unsigned)ceil_div(m, TM), (unsigned)P);
-  HT_WIDTH_DISPATCH(l, k_gemm_nn, grid, dim3(256), 0, s, A, sA, lda, W, sW, ldw, Y, sY, ldy, m, kd, l);
+  HT_WIDTH_DISPATCH(l, k_gemm_nn, grid, dim3(256), 0, s, A, sA, lda, W, sW, ldw, Y, sY, ldy, m, kd, l, gpart);
   HT_CHECK_LAUNCH();
   return HT_OK;
 }
 
 template <typename T>
 int launch_gemm_tn(const T* A, int64_t sA, int lda, const T* Q, int64_t sQ, int ldq, T* Z, int64_t sZ, int ldz,
-                   int m, int n, int l, int P, hipStream_t s) {
-  if (l > HT_MAX_WIDTH) HT_FAIL(HT_ERR_UNSUPPORTED, "sketch width above 128");
+                   int m, int n, int l, int P, double* gpart, hipStream_t s) {
+  if (l > HT_MAX_WIDTH) HT_FAIL(HT_ERR_UNSUPPORTED, "sketch width above HT_MAX_WIDTH");
   dim3 grid((unsigned)ceil_div(n, TM), (unsigned)P);
-  HT_WIDTH_DISPATCH(l, k_gemm_tn, grid, dim3(256), 0, s, A, sA, lda, Q, sQ, ldq, Z, sZ, ldz, m, n, l);
+  HT_WIDTH_DISPATCH(l, k_gemm_tn, grid, dim3(256), 0, s, A, sA, lda, Q, sQ, ldq, Z, sZ, ldz, m, n, l, gpart);
   HT_CHECK_LAUNCH();
   return HT_OK;
 }
@@ -205,9 +243,9 @@ int launch_gemm_nt(const T* X, int64_t sX, int ldx, const T* W, int64_t sW, int 
 
 #define HT_INST(T)                                                                                              \
   template int launch_gemm_nn<T>(const T*, int64_t, int, const T*, int64_t, int, T*, int64_t, int, int, int, int, \
-                                 int, hipStream_t);                                                             \
+                                 int, double*, hipStream_t);                                                    \
   template int launch_gemm_tn<T>(const T*, int64_t, int, const T*, int64_t, int, T*, int64_t, int, int, int, int, \
-                                 int, hipStream_t);                                                             \
+                                 int, double*, hipStream_t);                                                    \
   template int launch_gemm_nt<T>(const T*, int64_t, int, const T*, int64_t, int, T*, int64_t, int, int, int, int, \
                                  int, hipStream_t);
 HT_INST(float)

@@ -1,182 +1,208 @@
 // Small projected SVD and shrinkage, one workgroup per slice, FP64.
 //
-// With Bt = A_j^T Q (n x l), the projected matrix is B = Bt^T = U_B diag(s) V_B^T.
-// Its left singular pairs are the eigenpairs of W = B B^T = Bt^T Bt (l x l),
-// which is formed in FP64 and diagonalized by the parallel cyclic Jacobi
-// method (round-robin pair ordering, l/2 disjoint rotations per step).  With
-// s_i = sqrt(lambda_i) in descending order and k = min(r, l) kept values, the
-// shrunk reconstruction Q U_B[:, :k] diag(prox(s)) V_B[:, :k]^T equals
-//   Q K B   with  K = U_B diag(w) U_B^T,  w_i = prox(s_i)/s_i (i < k), 0 otherwise,
-// since V_B[:, i]^T = U_B[:, i]^T B / s_i.  The kernel writes K (l x l).
-#include "kernels.hpp"
+// Inputs are Gram partials written by earlier kernels: those of the basis Q1
+// (the last CholeskyQR pass of the sketch) and those of Bt = A_j^T Q1.  The
+// second CholeskyQR step is applied here in the l x l space: with
+// R2 = chol(Q1^T Q1) the orthonormal basis is Q = Q1 R2^{-1}, so
+//   B = Q^T A_j = R2^{-T} Bt^T,   W = B B^T = R2^{-T} (Bt^T Bt) R2^{-1}.
+// W = U diag(s^2) U^T is diagonalized by the parallel cyclic Jacobi method
+// (round-robin pair ordering, l/2 disjoint rotations per step).  With the k =
+// min(r, l) largest s shrunk by the proximity operator, the reconstruction
+// Q U[:, :k] diag(prox(s)) V_B[:, :k]^T equals Q1 K' Bt^T with
+//   K' = R2^{-1} U diag(w) U^T R2^{-T},  w_i = prox(s_i)/s_i (i < k), 0 otherwise,
+// because V_B[:, i]^T = U[:, i]^T B / s_i.  The kernel writes K' (l x l).
+//
+// One Jacobi step applies all l/2 disjoint rotations at once: one lane per pair
+// computes its rotation from the current matrix, then for pairs s and t the
+// 2 x 2 block of W on rows of s and columns of t becomes J_s^T W[s, t] J_t,
+// produced from old values only into a second buffer.  W is scaled to unit
+// maximum diagonal first, so the rotation formulas cannot overflow.
+#include "chol.hpp"
 
 namespace ht {
 
 namespace {
 
 constexpr int NT = 256;
+constexpr int LMAX = 80;
 
-struct SvdLds {
-  int pitch, CH;
-  size_t bytes;
-};
-
-__host__ __device__ inline SvdLds svd_lds(int l) {
-  SvdLds s;
-  s.pitch = l + 1;
-  const size_t mats = 2 * (size_t)l * s.pitch * 8;          // W, V
-  const size_t small = (size_t)(3 * 64 + 2 * 128) * 8;       // rotations, eigen bookkeeping
-  size_t avail = 150000 > mats + small ? 150000 - mats - small : 0;
-  int ch = (int)(avail / ((size_t)s.pitch * 8));
-  s.CH = ch > 64 ? 64 : ch;
-  s.bytes = mats + small + (size_t)s.CH * s.pitch * 8;
-  return s;
+size_t svd_lds_bytes(int l) {
+  const size_t gp = (size_t)l + 1;
+  return (3 * (size_t)l * gp + gp + 3 * LMAX + 2 * 64) * 8 + (LMAX + 2 * 64) * 4;
 }
 
-template <typename T>
-__global__ __launch_bounds__(NT) void k_smallsvd(const T* __restrict__ Btall, int64_t sB, int ldb, int n, int l,
-                                                 int kkeep, double tau_host, const double* __restrict__ mu_dev,
-                                                 Penalty pen, T* __restrict__ Kall, double* __restrict__ sigma_out,
-                                                 int* __restrict__ kept_out, int CH) {
+// Pair t of step `step` in the round-robin schedule on L2 (even) players;
+// q = -1 when the partner is the padding player (odd l).
+__device__ __forceinline__ void rr_pair(int step, int t, int L2, int l, int& p, int& q) {
+  int a, b;
+  if (t == 0) {
+    a = L2 - 1;
+    b = step;
+  } else {
+    a = (step + t) % (L2 - 1);
+    b = (step - t + (L2 - 1)) % (L2 - 1);
+  }
+  p = min(a, b);
+  q = max(a, b);
+  if (q >= l) q = -1;
+}
+
+// Symmetric Schur rotation (c, s) that annihilates W[p][q] (Golub-Van Loan,
+// written as t = 2 apq sgn(d) / (|d| + sqrt(d^2 + 4 apq^2)), d = aqq - app);
+// identity when the entry is below the rounding-level thresholds.  Entries are
+// at most 1 in magnitude (W is normalized), so nothing overflows.
+__device__ __forceinline__ void schur2(double app, double aqq, double apq, double abs_tol, double& c, double& s) {
+  c = 1.0;
+  s = 0.0;
+  if (fabs(apq) > abs_tol && fabs(apq) > 1e-15 * sqrt(fabs(app * aqq))) {
+    const double d = aqq - app;
+    const double h = sqrt(d * d + 4.0 * apq * apq);
+    const double t = 2.0 * apq * (d >= 0.0 ? 1.0 : -1.0) * fast_rcp(fabs(d) + h);
+    c = fast_rsqrt(1.0 + t * t);
+    s = t * c;
+  }
+}
+
+template <typename T, int LB>
+__global__ __launch_bounds__(NT) void k_smallsvd(double* __restrict__ g2, int nt_q, double delta_rel,
+                                                 const double* __restrict__ gw, int nt_b, int l, int kkeep,
+                                                 double tau_host, const double* __restrict__ mu_dev, Penalty pen,
+                                                 T* __restrict__ Kall, double* __restrict__ sigma_out,
+                                                 int* __restrict__ kept_out) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int gp = l + 1;
-  double* W = reinterpret_cast<double*>(smem_raw);
-  double* V = W + (size_t)l * gp;
-  double* rc = V + (size_t)l * gp;  // 64 cosines
-  double* rs = rc + 64;             // 64 sines
-  int* rp = reinterpret_cast<int*>(rs + 64);  // 64 p, 64 q
+  double* B0 = reinterpret_cast<double*>(smem_raw);  // G, then a Jacobi buffer
+  double* B1 = B0 + (size_t)l * gp;                  // W~, then W
+  double* V = B1 + (size_t)l * gp;                   // R2^{-1}, then eigenvectors
+  double* dR = V + (size_t)l * gp;
+  double* lam = dR + gp;
+  double* wv = lam + LMAX;
+  double* sig = wv + LMAX;
+  double* rc = sig + LMAX;
+  double* rs = rc + 64;
+  int* perm = reinterpret_cast<int*>(rs + 64);
+  int* rp = perm + LMAX;
   int* rq = rp + 64;
-  double* wv = rs + 128;                       // 128 shrink weights (after rp/rq: 64 doubles of room)
-  int* perm = reinterpret_cast<int*>(wv + 128);
-  double* S = reinterpret_cast<double*>(smem_raw) + 2 * (size_t)l * gp + 3 * 64 + 2 * 128;
-  __shared__ int s_rotated;
-  __shared__ int s_kept;
+  __shared__ double s_scr;
+  __shared__ int s_rot, s_kept;
 
   const int j = blockIdx.x;
-  const T* Bt = Btall + (int64_t)j * sB;
   const int tid = threadIdx.x;
   const double tau = mu_dev ? 1.0 / (*mu_dev) : tau_host;
+  const int ll = l * l;
+  double* gq = g2 + (int64_t)j * nt_q * ll;  // the slice's partials; reused to park R2^{-1}
 
-  // ---- W = Bt^T Bt (FP64), V = I ------------------------------------------
-  for (int idx = tid; idx < l * l; idx += NT) {
-    const int a = idx % l, b = idx / l;
-    V[a * gp + b] = (a == b) ? 1.0 : 0.0;
-  }
-  {
-    // each thread owns entries (a, b), a <= b, strided over the upper triangle
-    const int npairs = l * (l + 1) / 2;
-    for (int p0 = 0; p0 < npairs; p0 += NT) {
-      int p = p0 + tid;
-      int a = 0, b = -1;
-      if (p < npairs) {
-        int row_len = l;
-        while (p >= row_len) {
-          p -= row_len;
-          ++a;
-          --row_len;
-        }
-        b = a + p;
-      }
-      double acc = 0.0;
-      for (int r0 = 0; r0 < n; r0 += CH) {
-        const int ch = min(CH, n - r0);
-        __syncthreads();
-        for (int idx = tid; idx < ch * l; idx += NT) {
-          const int i = idx % ch, c = idx / ch;
-          S[i * gp + c] = (double)Bt[(r0 + i) + (int64_t)c * ldb];
-        }
-        __syncthreads();
-        if (b >= 0)
-          for (int i = 0; i < ch; ++i) acc += S[i * gp + a] * S[i * gp + b];
-      }
-      if (b >= 0) {
-        W[a * gp + b] = acc;
-        W[b * gp + a] = acc;
-      }
-    }
+  sum_gram_partials(B0, gp, gq, nt_q, l);
+  sum_gram_partials(B1, gp, gw + (int64_t)j * nt_b * ll, nt_b, l);
+  __syncthreads();
+  chol_deflate(B0, dR, gp, l, delta_rel, &s_scr);
+  tri_inverse<LB>(B0, dR, gp, l, V);  // V = R2^{-1} (upper)
+  for (int idx = tid; idx < ll; idx += NT) gq[idx] = V[(idx / l) * gp + (idx % l)];
+
+  // B0 = W~ R2^{-1};  B1 = R2^{-T} B0 (= W, then symmetrized);  V = I
+  for (int idx = tid; idx < ll; idx += NT) {
+    const int a = idx / l, b = idx % l;
+    double s = 0.0;
+    for (int c = 0; c <= b; ++c) s += B1[a * gp + c] * V[c * gp + b];
+    B0[a * gp + b] = s;
   }
   __syncthreads();
+  for (int idx = tid; idx < ll; idx += NT) {
+    const int a = idx / l, b = idx % l;
+    double s = 0.0;
+    for (int c = 0; c <= a; ++c) s += V[c * gp + a] * B0[c * gp + b];
+    B1[a * gp + b] = s;
+  }
+  __syncthreads();
+  for (int idx = tid; idx < ll; idx += NT) {
+    const int a = idx / l, b = idx % l;
+    if (a < b) {
+      const double m = 0.5 * (B1[a * gp + b] + B1[b * gp + a]);
+      B1[a * gp + b] = m;
+      B1[b * gp + a] = m;
+    }
+    V[a * gp + b] = (a == b) ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    double md = 0.0;
+    for (int a = 0; a < l; ++a) md = fmax(md, fabs(B1[a * gp + a]));
+    s_scr = md;
+  }
+  __syncthreads();
+  // A pair is rotated only when its off-diagonal entry is above both 1e-15
+  // relative to sqrt(|app aqq|) and 1e-15 * max diag: below that it is at the
+  // rounding level of W and rotating it would not change the result.
+  const double scale = s_scr > 0.0 ? s_scr : 1.0;  // W <- W / max diag
+  const double inv_scale = 1.0 / scale;
+  for (int idx = tid; idx < ll; idx += NT) B1[(idx / l) * gp + (idx % l)] *= inv_scale;
+  __syncthreads();
+  const double abs_tol = 1e-15;
 
-  // ---- parallel cyclic Jacobi ---------------------------------------------
+  // ---- parallel cyclic Jacobi, ping-pong between B1 and B0 -----------------
   const int L2 = l + (l & 1);
   const int half = L2 / 2;
-  for (int sweep = 0; sweep < 40; ++sweep) {
-    if (tid == 0) s_rotated = 0;
+  double* Wc = B1;
+  double* Wn = B0;
+  for (int sweep = 0; sweep < 30; ++sweep) {
+    if (tid == 0) s_rot = 0;
     __syncthreads();
     for (int step = 0; step < L2 - 1; ++step) {
       if (tid < half) {
         int p, q;
-        if (tid == 0) {
-          p = L2 - 1;
-          q = step;
-        } else {
-          p = (step + tid) % (L2 - 1);
-          q = (step - tid + (L2 - 1)) % (L2 - 1);
-        }
-        if (p > q) {
-          const int t = p;
-          p = q;
-          q = t;
-        }
-        double c = 1.0, s = 0.0;
-        if (q < l) {
-          const double app = W[p * gp + p], aqq = W[q * gp + q], apq = W[p * gp + q];
-          if (fabs(apq) > 1e-300 && fabs(apq) > 1e-17 * sqrt(fabs(app * aqq))) {
-            const double theta = (aqq - app) / (2.0 * apq);
-            double t;
-            if (fabs(theta) > 1e150)
-              t = 0.5 / theta;
-            else
-              t = (theta >= 0.0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(1.0 + theta * theta));
-            c = 1.0 / sqrt(1.0 + t * t);
-            s = t * c;
-            s_rotated = 1;
-          }
-        }
+        rr_pair(step, tid, L2, l, p, q);
+        double c = 1.0, sn = 0.0;
+        if (q >= 0) schur2(Wc[p * gp + p], Wc[q * gp + q], Wc[p * gp + q], abs_tol, c, sn);
         rc[tid] = c;
-        rs[tid] = s;
+        rs[tid] = sn;
         rp[tid] = p;
-        rq[tid] = (q < l) ? q : -1;
+        rq[tid] = q;
+        if (sn != 0.0) s_rot = 1;
       }
       __syncthreads();
-      // rows p, q of W
-      for (int idx = tid; idx < half * l; idx += NT) {
-        const int t = idx / l, x = idx % l;
-        const int q = rq[t];
-        if (q < 0 || rs[t] == 0.0) continue;
-        const int p = rp[t];
-        const double c = rc[t], s = rs[t];
-        const double wp = W[p * gp + x], wq = W[q * gp + x];
-        W[p * gp + x] = c * wp - s * wq;
-        W[q * gp + x] = s * wp + c * wq;
+      for (int item = tid; item < half * half; item += NT) {
+        const int st = item / half, tt = item - st * half;
+        const int ps = rp[st], qs = rq[st], pt = rp[tt], qt = rq[tt];
+        const double cs = rc[st], ss = rs[st], ct = rc[tt], sn = rs[tt];
+        const double w00 = Wc[ps * gp + pt];
+        const double w01 = qt >= 0 ? Wc[ps * gp + qt] : 0.0;
+        const double w10 = qs >= 0 ? Wc[qs * gp + pt] : 0.0;
+        const double w11 = (qs >= 0 && qt >= 0) ? Wc[qs * gp + qt] : 0.0;
+        const double r00 = cs * w00 - ss * w10, r01 = cs * w01 - ss * w11;
+        const double r10 = ss * w00 + cs * w10, r11 = ss * w01 + cs * w11;
+        Wn[ps * gp + pt] = ct * r00 - sn * r01;
+        if (qt >= 0) Wn[ps * gp + qt] = sn * r00 + ct * r01;
+        if (qs >= 0) Wn[qs * gp + pt] = ct * r10 - sn * r11;
+        if (qs >= 0 && qt >= 0) Wn[qs * gp + qt] = sn * r10 + ct * r11;
+      }
+      for (int item = tid; item < half * l; item += NT) {
+        const int tt = item / l, x = item - tt * l;
+        const double sn = rs[tt];
+        if (sn != 0.0) {
+          const int pt = rp[tt], qt = rq[tt];
+          const double ct = rc[tt];
+          const double vp = V[x * gp + pt], vq = V[x * gp + qt];
+          V[x * gp + pt] = ct * vp - sn * vq;
+          V[x * gp + qt] = sn * vp + ct * vq;
+        }
       }
       __syncthreads();
-      // columns p, q of W and V
-      for (int idx = tid; idx < half * l; idx += NT) {
-        const int t = idx / l, x = idx % l;
-        const int q = rq[t];
-        if (q < 0 || rs[t] == 0.0) continue;
-        const int p = rp[t];
-        const double c = rc[t], s = rs[t];
-        const double wp = W[x * gp + p], wq = W[x * gp + q];
-        W[x * gp + p] = c * wp - s * wq;
-        W[x * gp + q] = s * wp + c * wq;
-        const double vp = V[x * gp + p], vq = V[x * gp + q];
-        V[x * gp + p] = c * vp - s * vq;
-        V[x * gp + q] = s * vp + c * vq;
-      }
-      __syncthreads();
+      double* tmp = Wc;
+      Wc = Wn;
+      Wn = tmp;
     }
-    if (!s_rotated) break;
+    if (!s_rot) break;
     __syncthreads();
   }
 
-  // ---- order eigenvalues, shrink, K = U diag(w) U^T -------------------------
+  // ---- order, shrink, K = U diag(w) U^T, K' = R2^{-1} K R2^{-T} -------------
+  for (int a = tid; a < l; a += NT) lam[a] = Wc[a * gp + a] * scale;
+  __syncthreads();
   for (int a = tid; a < l; a += NT) {
-    const double la = W[a * gp + a];
+    const double la = lam[a];
     int rank = 0;
     for (int b = 0; b < l; ++b) {
-      const double lb = W[b * gp + b];
+      const double lb = lam[b];
       rank += (lb > la) || (lb == la && b < a);
     }
     perm[rank] = a;
@@ -184,26 +210,45 @@ __global__ __launch_bounds__(NT) void k_smallsvd(const T* __restrict__ Btall, in
   if (tid == 0) s_kept = 0;
   __syncthreads();
   for (int i = tid; i < l; i += NT) {
-    const double lam = W[perm[i] * gp + perm[i]];
-    const double sig = lam > 0.0 ? sqrt(lam) : 0.0;
+    const double lv = lam[perm[i]];
+    const double sv = lv > 0.0 ? sqrt(lv) : 0.0;
     double w = 0.0;
-    if (i < kkeep && sig > 0.0) {
-      const double sh = prox_pos(pen, sig, tau);
-      w = sh / sig;
+    if (i < kkeep && sv > 0.0) {
+      const double sh = prox_pos(pen, sv, tau);
+      w = sh / sv;
       if (sh > 0.0) atomicAdd(&s_kept, 1);
     }
     wv[i] = w;
-    if (sigma_out) sigma_out[(int64_t)j * l + i] = sig;
+    sig[i] = sv;
+    if (sigma_out) sigma_out[(int64_t)j * l + i] = sv;
   }
   __syncthreads();
-  T* K = Kall + (int64_t)j * l * l;
-  for (int idx = tid; idx < l * l; idx += NT) {
-    const int a = idx % l, b = idx / l;
+  double* Kb = Wn;  // free buffer
+  double* Ri = Wc;  // R2^{-1} reloaded from global
+  for (int idx = tid; idx < ll; idx += NT) {
+    const int a = idx / l, b = idx % l;
     double t = 0.0;
     for (int i = 0; i < kkeep; ++i) {
       const int e = perm[i];
       t += V[a * gp + e] * wv[i] * V[b * gp + e];
     }
+    Kb[a * gp + b] = t;
+  }
+  __syncthreads();
+  for (int idx = tid; idx < ll; idx += NT) Ri[(idx / l) * gp + (idx % l)] = gq[idx];
+  __syncthreads();
+  for (int idx = tid; idx < ll; idx += NT) {  // V = K R2^{-T}
+    const int a = idx / l, b = idx % l;
+    double t = 0.0;
+    for (int c = b; c < l; ++c) t += Kb[a * gp + c] * Ri[b * gp + c];
+    V[a * gp + b] = t;
+  }
+  __syncthreads();
+  T* K = Kall + (int64_t)j * ll;
+  for (int idx = tid; idx < ll; idx += NT) {  // K' = R2^{-1} V, column-major
+    const int a = idx % l, b = idx / l;
+    double t = 0.0;
+    for (int c = a; c < l; ++c) t += Ri[a * gp + c] * V[c * gp + b];
     K[a + (int64_t)b * l] = (T)t;
   }
   if (kept_out && tid == 0) kept_out[j] = s_kept;
@@ -212,21 +257,29 @@ __global__ __launch_bounds__(NT) void k_smallsvd(const T* __restrict__ Btall, in
 }  // namespace
 
 template <typename T>
-int launch_smallsvd(const T* Bt, int64_t sB, int ldb, int n, int l, int k, int P, double tau, const double* mu_dev,
-                    Penalty pen, T* K, double* sigma_out, int* kept_out, hipStream_t s) {
+int launch_smallsvd(double* g2, int ntiles_q, int m_q, const double* gw, int ntiles_b, int l, int k, int P,
+                    double tau, const double* mu_dev, Penalty pen, T* K, double* sigma_out, int* kept_out,
+                    hipStream_t s) {
   if (l > HT_MAX_WIDTH) HT_FAIL(HT_ERR_UNSUPPORTED, "sketch width above HT_MAX_WIDTH");
-  const SvdLds L = svd_lds(l);
-  HT_CHECK_HIP(hipFuncSetAttribute((const void*)k_smallsvd<T>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                   (int)L.bytes));
-  hipLaunchKernelGGL(k_smallsvd<T>, dim3((unsigned)P), dim3(NT), L.bytes, s, Bt, sB, ldb, n, l, k, tau, mu_dev, pen,
-                     K, sigma_out, kept_out, L.CH);
-  HT_CHECK_LAUNCH();
-  return HT_OK;
+  const double delta_rel = 8.0 * (double)m_q * 2.220446049250313e-16;
+  auto launch = [&](auto kern) -> int {
+    int rc = ensure_dynamic_lds((const void*)kern, svd_lds_bytes(HT_MAX_WIDTH));
+    if (rc) return rc;
+    hipLaunchKernelGGL(kern, dim3((unsigned)P), dim3(NT), svd_lds_bytes(l), s, g2, ntiles_q, delta_rel, gw,
+                       ntiles_b, l, k, tau, mu_dev, pen, K, sigma_out, kept_out);
+    HT_CHECK_LAUNCH();
+    return HT_OK;
+  };
+  if (l <= 16) return launch(k_smallsvd<T, 16>);
+  if (l <= 32) return launch(k_smallsvd<T, 32>);
+  if (l <= 48) return launch(k_smallsvd<T, 48>);
+  if (l <= 64) return launch(k_smallsvd<T, 64>);
+  return launch(k_smallsvd<T, 80>);
 }
 
-template int launch_smallsvd<float>(const float*, int64_t, int, int, int, int, int, double, const double*, Penalty,
-                                    float*, double*, int*, hipStream_t);
-template int launch_smallsvd<double>(const double*, int64_t, int, int, int, int, int, double, const double*, Penalty,
-                                     double*, double*, int*, hipStream_t);
+template int launch_smallsvd<float>(double*, int, int, const double*, int, int, int, int, double, const double*,
+                                    Penalty, float*, double*, int*, hipStream_t);
+template int launch_smallsvd<double>(double*, int, int, const double*, int, int, int, int, double, const double*,
+                                     Penalty, double*, double*, int*, hipStream_t);
 
 }  // namespace ht

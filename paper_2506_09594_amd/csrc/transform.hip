@@ -5,16 +5,46 @@
 // owns the n3*...*nd values X(t, j) = X[j*n1*n2 + t] across all face slices j,
 // and the transform acts on the slice index only.  One workgroup takes TP
 // consecutive tube positions for all P slices into LDS (TP*P values, loaded as
-// P coalesced runs of TP elements), applies every mode's n_k x n_k matrix to
-// the fibers of that mode with the fiber held in registers, and writes the tile
-// back.  HBM traffic is one read and one write of the tensor; the mode
-// matrices are broadcast from the scalar cache.
+// P coalesced runs of TP elements, 16-byte accesses batched in registers so
+// that many loads are in flight), applies every mode's n_k x n_k matrix to the
+// fibers of that mode with several fibers held in registers per thread, and
+// writes the tile back.  HBM traffic is one read and one write of the tensor;
+// the mode matrices are scalar operands.
 #include "kernels.hpp"
 
 namespace ht {
 
+// Apply U (n x n, row-major) to F fibers at once: fiber k of this thread starts
+// at tile[base[k]] with element stride `stride`.  N is the exact mode length
+// (compile-time) so U's entries are fixed scalar operands.
+template <typename T, int N, int F>
+__device__ __forceinline__ void apply_fibers_exact(T* tile, const int* base, int stride, int nvalid,
+                                                   const T* __restrict__ U) {
+  T v[F][N];
+#pragma unroll
+  for (int k = 0; k < F; ++k)
+#pragma unroll
+    for (int b = 0; b < N; ++b) v[k][b] = (k < nvalid) ? tile[base[k] + b * stride] : T(0);
+#pragma unroll
+  for (int a = 0; a < N; ++a) {
+    T acc[F];
+#pragma unroll
+    for (int k = 0; k < F; ++k) acc[k] = T(0);
+#pragma unroll
+    for (int b = 0; b < N; ++b) {
+      const T u = U[a * N + b];
+#pragma unroll
+      for (int k = 0; k < F; ++k) acc[k] += u * v[k][b];
+    }
+#pragma unroll
+    for (int k = 0; k < F; ++k)
+      if (k < nvalid) tile[base[k] + a * stride] = acc[k];
+  }
+}
+
+// Generic mode length n <= NMAX (predicated).
 template <typename T, int NMAX>
-__device__ __forceinline__ void apply_fiber(T* tile, int base, int stride, int n, const T* __restrict__ U) {
+__device__ __forceinline__ void apply_fiber_generic(T* tile, int base, int stride, int n, const T* __restrict__ U) {
   T v[NMAX];
 #pragma unroll
   for (int b = 0; b < NMAX; ++b) v[b] = (b < n) ? tile[base + b * stride] : T(0);
@@ -30,47 +60,133 @@ __device__ __forceinline__ void apply_fiber(T* tile, int base, int stride, int n
   }
 }
 
+// Fiber f of a mode with slice stride s and length n: tube position t = f % TP,
+// remaining multi-index rest = f / TP split around the mode.
+__device__ __forceinline__ int fiber_base(int f, int TP, int lgTP, int s, int n) {
+  const int t = f & (TP - 1);
+  const int rest = f >> lgTP;
+  const int lo = rest % s, hi = rest / s;
+  return (lo + hi * s * n) * TP + t;
+}
+
+template <typename T, int N>
+__device__ __forceinline__ void mode_exact(T* tile, int TP, int lgTP, int s, int nfib, const T* __restrict__ U) {
+  constexpr int F = (N <= 8) ? 4 : (N <= 16 ? 4 : 2);
+  for (int f0 = threadIdx.x; f0 < nfib; f0 += F * blockDim.x) {
+    int base[F];
+    int nvalid = 0;
+#pragma unroll
+    for (int k = 0; k < F; ++k) {
+      const int f = f0 + k * blockDim.x;
+      base[k] = (f < nfib) ? fiber_base(f, TP, lgTP, s, N) : 0;
+      nvalid += (f < nfib);
+    }
+    apply_fibers_exact<T, N, F>(tile, base, s * TP, nvalid, U);
+  }
+}
+
 template <typename T>
 __global__ __launch_bounds__(256) void k_transform(const T* __restrict__ in, T* __restrict__ out, int64_t NT,
-                                                   int P, int TP, ModeTable mt, const T* __restrict__ table) {
+                                                   int P, int TP, int lgTP, int vec, ModeTable mt,
+                                                   const T* __restrict__ table) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T* tile = reinterpret_cast<T*>(smem_raw);
+  constexpr int V = 16 / sizeof(T);  // elements per 16-byte access
+  constexpr int UNR = 8;
   const int64_t t0 = (int64_t)blockIdx.x * TP;
   const int64_t rem = NT - t0;
   const int tp = rem < TP ? (int)rem : TP;
   const int total = TP * P;
-  for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
-    const int j = idx / TP, t = idx - j * TP;
-    tile[idx] = (t < tp) ? in[(int64_t)j * NT + t0 + t] : T(0);
+  const int tid = threadIdx.x, nt = blockDim.x;
+
+  // ---- load the TP x P tile: P runs of TP contiguous elements --------------
+  if (vec) {
+    using VT = __attribute__((ext_vector_type(V))) T;
+    const int nv = total / V;
+    for (int v0 = tid; v0 < nv; v0 += UNR * nt) {
+      VT r[UNR];
+#pragma unroll
+      for (int u = 0; u < UNR; ++u) {
+        const int vi = v0 + u * nt;
+        const int idx = vi * V;
+        const int j = idx >> lgTP, t = idx & (TP - 1);
+        if (vi < nv && t < tp)
+          r[u] = *reinterpret_cast<const VT*>(in + (int64_t)j * NT + t0 + t);
+        else
+          r[u] = VT{};
+      }
+#pragma unroll
+      for (int u = 0; u < UNR; ++u) {
+        const int vi = v0 + u * nt;
+        if (vi < nv) *reinterpret_cast<VT*>(tile + vi * V) = r[u];
+      }
+    }
+  } else {
+    for (int i0 = tid; i0 < total; i0 += UNR * nt) {
+      T r[UNR];
+#pragma unroll
+      for (int u = 0; u < UNR; ++u) {
+        const int idx = i0 + u * nt;
+        const int j = idx >> lgTP, t = idx & (TP - 1);
+        r[u] = (idx < total && t < tp) ? in[(int64_t)j * NT + t0 + t] : T(0);
+      }
+#pragma unroll
+      for (int u = 0; u < UNR; ++u) {
+        const int idx = i0 + u * nt;
+        if (idx < total) tile[idx] = r[u];
+      }
+    }
   }
   __syncthreads();
+
+  // ---- modes ---------------------------------------------------------------
   for (int m = 0; m < mt.nmodes; ++m) {
     const int n = mt.n[m];
     const int s = mt.stride[m];
     const T* U = table + mt.off[m];
     const int nfib = total / n;
-    for (int f = threadIdx.x; f < nfib; f += blockDim.x) {
-      const int t = f % TP;
-      const int rest = f / TP;
-      const int lo = rest % s, hi = rest / s;
-      const int base = (lo + hi * s * n) * TP + t;
-      const int stride = s * TP;
-      if (n <= 4)
-        apply_fiber<T, 4>(tile, base, stride, n, U);
-      else if (n <= 8)
-        apply_fiber<T, 8>(tile, base, stride, n, U);
-      else if (n <= 16)
-        apply_fiber<T, 16>(tile, base, stride, n, U);
-      else if (n <= 32)
-        apply_fiber<T, 32>(tile, base, stride, n, U);
-      else
-        apply_fiber<T, 64>(tile, base, stride, n, U);
+    switch (n) {
+      case 2: mode_exact<T, 2>(tile, TP, lgTP, s, nfib, U); break;
+      case 3: mode_exact<T, 3>(tile, TP, lgTP, s, nfib, U); break;
+      case 4: mode_exact<T, 4>(tile, TP, lgTP, s, nfib, U); break;
+      case 8: mode_exact<T, 8>(tile, TP, lgTP, s, nfib, U); break;
+      case 16: mode_exact<T, 16>(tile, TP, lgTP, s, nfib, U); break;
+      case 32: mode_exact<T, 32>(tile, TP, lgTP, s, nfib, U); break;
+      default:
+        for (int f = tid; f < nfib; f += nt) {
+          const int base = fiber_base(f, TP, lgTP, s, n);
+          if (n <= 8)
+            apply_fiber_generic<T, 8>(tile, base, s * TP, n, U);
+          else if (n <= 16)
+            apply_fiber_generic<T, 16>(tile, base, s * TP, n, U);
+          else if (n <= 32)
+            apply_fiber_generic<T, 32>(tile, base, s * TP, n, U);
+          else
+            apply_fiber_generic<T, 64>(tile, base, s * TP, n, U);
+        }
     }
     __syncthreads();
   }
-  for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
-    const int j = idx / TP, t = idx - j * TP;
-    if (t < tp) out[(int64_t)j * NT + t0 + t] = tile[idx];
+
+  // ---- store ---------------------------------------------------------------
+  if (vec) {
+    using VT = __attribute__((ext_vector_type(V))) T;
+    const int nv = total / V;
+    for (int v0 = tid; v0 < nv; v0 += UNR * nt) {
+#pragma unroll
+      for (int u = 0; u < UNR; ++u) {
+        const int vi = v0 + u * nt;
+        const int idx = vi * V;
+        const int j = idx >> lgTP, t = idx & (TP - 1);
+        if (vi < nv && t < tp)
+          *reinterpret_cast<VT*>(out + (int64_t)j * NT + t0 + t) = *reinterpret_cast<const VT*>(tile + idx);
+      }
+    }
+  } else {
+    for (int idx = tid; idx < total; idx += nt) {
+      const int j = idx >> lgTP, t = idx & (TP - 1);
+      if (t < tp) out[(int64_t)j * NT + t0 + t] = tile[idx];
+    }
   }
 }
 
@@ -91,9 +207,15 @@ int launch_transform(const T* in, T* out, int64_t NT, int P, const ModeTable& mt
   }
   const int TP = transform_tile_width(P, sizeof(T));
   if (TP == 0) HT_FAIL(HT_ERR_UNSUPPORTED, "too many face slices for the LDS transform tile");
+  int lgTP = 0;
+  while ((1 << lgTP) < TP) ++lgTP;
+  constexpr int V = 16 / sizeof(T);
+  const int vec = (NT % V == 0) && (TP % V == 0) && (reinterpret_cast<uintptr_t>(in) % 16 == 0) &&
+                  (reinterpret_cast<uintptr_t>(out) % 16 == 0);
   const size_t lds = sizeof(T) * (size_t)TP * P;
   const int64_t blocks = ceil_div(NT, TP);
-  hipLaunchKernelGGL(k_transform<T>, dim3((unsigned)blocks), dim3(256), lds, stream, in, out, NT, P, TP, mt, table);
+  hipLaunchKernelGGL(k_transform<T>, dim3((unsigned)blocks), dim3(256), lds, stream, in, out, NT, P, TP, lgTP, vec,
+                     mt, table);
   HT_CHECK_LAUNCH();
   return HT_OK;
 }

@@ -28,7 +28,8 @@ TRANSFORMS = {"dct2": 0, "dft": 1, "custom": 2}
 PRECISIONS = {"fp64": 0, "fp32": 1, "bf16": 2}
 PENALTIES = {"l1": 0, "mcp": 1, "scad": 2, "log": 3, "capped_l1": 4}
 MODELS = {"completion": 0, "rpca": 1}
-REGIONS = {"A": 0, "omega": 1, "Q": 2, "Bt": 3, "K": 4, "QK": 5, "C": 6, "Lnew": 7, "Xin": 8, "state": 9}
+REGIONS = {"A": 0, "omega": 1, "Q": 2, "Bt": 3, "K": 4, "QK": 5, "C": 6, "Lnew": 7, "Xin": 8, "state": 9,
+           "gram": 10, "gram_q": 11}
 
 # Symbols the header declares (checked by the CPU test suite).
 EXPORTS = [
