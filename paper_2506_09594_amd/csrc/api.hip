@@ -65,6 +65,7 @@ struct ht_plan {
   size_t size[WS_COUNT];
   size_t tsvt_bytes, admm_bytes;
   Profiler* prof;
+  bool mfma;  // FP32 thin products on the matrix cores
 };
 
 namespace {
@@ -120,7 +121,7 @@ void layout(ht_plan* pl) {
   pl->size[WS_LNEW] = (size_t)pl->N * es;
   pl->size[WS_XIN] = (size_t)pl->N * es;
   pl->size[WS_STATE] = sizeof(AdmmState);
-  const size_t t1 = (size_t)ceil_div(pl->n1, 64), t2 = (size_t)ceil_div(pl->n2, 64);
+  const size_t t1 = (size_t)ceil_div(pl->n1, 64), t2 = (size_t)ceil_div(pl->n2, 64);  // >= 128-row counts
   pl->size[WS_GP1] = P * std::max(t1, t2) * l * l * sizeof(double);
   pl->size[WS_GP2] = P * t1 * l * l * sizeof(double);
   // t-SVT regions first, then the solver-only regions
@@ -198,35 +199,46 @@ int run_tsvt(const ht_plan* pl, const T* X, T* out, double tau, const double* mu
     return rc;
   double* gp1 = ws_ptr<double>(pl, ws, WS_GP1);
   double* gp2 = ws_ptr<double>(pl, ws, WS_GP2);
-  const int t1 = (int)ceil_div(n1, 64), t2 = (int)ceil_div(n2, 64);
+  const int t1 = (int)ceil_div(n1, 64);
+  // FP32 slices with 16-byte aligned columns run the products on the matrix cores
+  const bool mfma = pl->mfma;
+  const int rt = mfma ? mfma_tile_rows() : 64;
+  const int p1 = (int)ceil_div(n1, rt), p2 = (int)ceil_div(n2, rt);
   auto sketch_nn = [&](const T* W) {
     return timed(pl, ST_SKETCH_NN, s, [&] {
+      if (mfma)
+        return launch_mfma_nn((const float*)A, sA, (int)n1, (const float*)W, sZ, (int)n2, (float*)Y, sY, (int)n1,
+                              (int)n1, (int)n2, l, (int)P, gp1, s);
       return launch_gemm_nn<T>(A, sA, (int)n1, W, sZ, (int)n2, Y, sY, (int)n1, (int)n1, (int)n2, l, (int)P, gp1, s);
     });
   };
   auto sketch_tn = [&]() {
     return timed(pl, ST_SKETCH_TN, s, [&] {
+      if (mfma)
+        return launch_mfma_tn((const float*)A, sA, (int)n1, (const float*)Y, sY, (int)n1, (float*)Z, sZ, (int)n2,
+                              (int)n1, (int)n2, l, (int)P, gp1, s);
       return launch_gemm_tn<T>(A, sA, (int)n1, Y, sY, (int)n1, Z, sZ, (int)n2, (int)n1, (int)n2, l, (int)P, gp1, s);
     });
   };
-  auto orth = [&](T* M, int64_t sM, int m, double* gout) {
-    return timed(pl, ST_CHOLQR, s, [&] { return launch_orth_apply<T>(M, sM, m, m, l, (int)P, gp1, gout, s); });
+  auto orth = [&](T* M, int64_t sM, int m, int nparts, double* gout) {
+    return timed(pl, ST_CHOLQR, s,
+                 [&] { return launch_orth_apply<T>(M, sM, m, m, l, (int)P, gp1, nparts, gout, s); });
   };
   // Y = A Omega, Q1 = orth(Y); q power steps Z = orth(A^T Q1), Q1 = orth(A Z);
   // the last orthonormalization also writes the Gram partials of Q1.
   if ((rc = sketch_nn(Om))) return rc;
-  if ((rc = orth(Y, sY, (int)n1, pl->q == 0 ? gp2 : nullptr))) return rc;
+  if ((rc = orth(Y, sY, (int)n1, p1, pl->q == 0 ? gp2 : nullptr))) return rc;
   for (int it = 0; it < pl->q; ++it) {
     if ((rc = sketch_tn())) return rc;
-    if ((rc = orth(Z, sZ, (int)n2, nullptr))) return rc;
+    if ((rc = orth(Z, sZ, (int)n2, p2, nullptr))) return rc;
     if ((rc = sketch_nn(Z))) return rc;
-    if ((rc = orth(Y, sY, (int)n1, it == pl->q - 1 ? gp2 : nullptr))) return rc;
+    if ((rc = orth(Y, sY, (int)n1, p1, it == pl->q - 1 ? gp2 : nullptr))) return rc;
   }
   // Bt = A^T Q1 with the Gram partials of Bt
   if ((rc = sketch_tn())) return rc;
   // second CholeskyQR step in the small space, small SVD, shrink -> K'
   if ((rc = timed(pl, ST_SMALLSVD, s, [&] {
-         return launch_smallsvd<T>(gp2, t1, (int)n1, gp1, t2, l, pl->k, (int)P, tau, mu_dev, pen, K, sigma_out,
+         return launch_smallsvd<T>(gp2, t1, (int)n1, gp1, p2, l, pl->k, (int)P, tau, mu_dev, pen, K, sigma_out,
                                    kept_out, s);
        })))
     return rc;
@@ -418,6 +430,7 @@ int ht_plan_create(const ht_plan_desc* d, ht_plan** out) {
     delete pl;
     HT_FAIL(HT_ERR_UNSUPPORTED, "too many face slices for the transform tile");
   }
+  pl->mfma = pl->precision == HT_FP32 && pl->n1 % 4 == 0 && pl->n2 % 4 == 0;
   layout(pl);
   *out = pl;
   return HT_OK;

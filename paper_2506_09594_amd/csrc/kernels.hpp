@@ -47,11 +47,21 @@ template <typename T>
 int launch_gemm_nt(const T* X, int64_t sX, int ldx, const T* W, int64_t sW, int ldw, T* C, int64_t sC, int ldc,
                    int m, int n, int l, int P, hipStream_t s);
 
+// FP32 thin products on the matrix cores (128-row tiles; Gram partials per
+// 128-row tile).  Require 16-byte aligned columns (leading dimensions and
+// slice strides multiples of 4).
+int mfma_tile_rows();
+int launch_mfma_nn(const float* A, int64_t sA, int lda, const float* W, int64_t sW, int ldw, float* Y, int64_t sY,
+                   int ldy, int m, int kd, int l, int P, double* gpart, hipStream_t s);
+int launch_mfma_tn(const float* A, int64_t sA, int lda, const float* Q, int64_t sQ, int ldq, float* Z, int64_t sZ,
+                   int ldz, int m, int n, int l, int P, double* gpart, hipStream_t s);
+
 // One CholeskyQR pass with deflation, in place on Y_j (m x l), from the Gram
-// partials written by the producing product (gin, ntiles = ceil(m/64) per
-// slice).  Optionally writes the Gram partials of the result (gout).
+// partials written by the producing product (gin, nparts per slice).
+// Optionally writes the Gram partials of the result (gout, ceil(m/64) per
+// slice).
 template <typename T>
-int launch_orth_apply(T* Y, int64_t sY, int ldy, int m, int l, int P, const double* gin, double* gout,
+int launch_orth_apply(T* Y, int64_t sY, int ldy, int m, int l, int P, const double* gin, int nparts, double* gout,
                       hipStream_t s);
 
 // Small SVD and shrinkage in FP64.  Inputs: Gram partials of the basis Q1

@@ -31,7 +31,7 @@ constexpr int TR = 64;  // rows per workgroup (matches the producing products); 
 // solves q R = y with the rows of R broadcast by readlane.
 template <typename T, int LB>
 __global__ __launch_bounds__(TR) void k_orth_apply_regs(T* __restrict__ Yall, int64_t sY, int ldy, int m, int l,
-                                                        const double* __restrict__ gin, double* __restrict__ gout) {
+                                                        const double* __restrict__ gin, int nparts, double* __restrict__ gout) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int gp = l + 1;
   double* S = reinterpret_cast<double*>(smem_raw);  // TR x gp (Gram of the result)
@@ -44,12 +44,12 @@ __global__ __launch_bounds__(TR) void k_orth_apply_regs(T* __restrict__ Yall, in
   const int ll = l * l;
 
   // column `lane` of G = sum of the tile partials (fixed order)
-  const double* part = gin + (int64_t)j * ntiles * ll;
+  const double* part = gin + (int64_t)j * nparts * ll;
   double g[LB];
 #pragma unroll
   for (int a = 0; a < LB; ++a) g[a] = 0.0;
   const int bcol = lane < l ? lane : 0;
-  for (int t = 0; t < ntiles; ++t) {
+  for (int t = 0; t < nparts; ++t) {
     double v[LB];
 #pragma unroll
     for (int a = 0; a < LB; ++a) v[a] = (a < l) ? part[(int64_t)t * ll + a * l + bcol] : 0.0;
@@ -98,7 +98,7 @@ __global__ __launch_bounds__(TR) void k_orth_apply_regs(T* __restrict__ Yall, in
 
 template <typename T, int LB>
 __global__ __launch_bounds__(TR) void k_orth_apply(T* __restrict__ Yall, int64_t sY, int ldy, int m, int l,
-                                                   const double* __restrict__ gin, double* __restrict__ gout) {
+                                                   const double* __restrict__ gin, int nparts, double* __restrict__ gout) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int gp = l + 1;
   double* G = reinterpret_cast<double*>(smem_raw);  // l x gp
@@ -112,7 +112,7 @@ __global__ __launch_bounds__(TR) void k_orth_apply(T* __restrict__ Yall, int64_t
   const int i = threadIdx.x;
   const bool valid = i < rows;
 
-  sum_gram_partials(G, gp, gin + (int64_t)j * ntiles * l * l, ntiles, l);
+  sum_gram_partials(G, gp, gin + (int64_t)j * nparts * l * l, nparts, l);
   double y[LB];
 #pragma unroll
   for (int c = 0; c < LB; ++c) y[c] = (c < l && valid) ? (double)Y[i + (int64_t)c * ldy] : 0.0;
@@ -149,7 +149,7 @@ size_t orth_lds_bytes(int l) { return ((size_t)l * (l + 1) + (size_t)(l + 1) + (
 }  // namespace
 
 template <typename T>
-int launch_orth_apply(T* Y, int64_t sY, int ldy, int m, int l, int P, const double* gin, double* gout,
+int launch_orth_apply(T* Y, int64_t sY, int ldy, int m, int l, int P, const double* gin, int nparts, double* gout,
                       hipStream_t s) {
   if (l > HT_MAX_WIDTH) HT_FAIL(HT_ERR_UNSUPPORTED, "sketch width above HT_MAX_WIDTH");
   const size_t lds = orth_lds_bytes(l);
@@ -157,7 +157,7 @@ int launch_orth_apply(T* Y, int64_t sY, int ldy, int m, int l, int P, const doub
   auto launch = [&](auto kern) -> int {
     int rc = ensure_dynamic_lds((const void*)kern, orth_lds_bytes(HT_MAX_WIDTH));
     if (rc) return rc;
-    hipLaunchKernelGGL(kern, grid, dim3(TR), lds, s, Y, sY, ldy, m, l, gin, gout);
+    hipLaunchKernelGGL(kern, grid, dim3(TR), lds, s, Y, sY, ldy, m, l, gin, nparts, gout);
     HT_CHECK_LAUNCH();
     return HT_OK;
   };
@@ -168,7 +168,8 @@ int launch_orth_apply(T* Y, int64_t sY, int ldy, int m, int l, int P, const doub
   return launch(k_orth_apply<T, 80>);
 }
 
-template int launch_orth_apply<float>(float*, int64_t, int, int, int, int, const double*, double*, hipStream_t);
-template int launch_orth_apply<double>(double*, int64_t, int, int, int, int, const double*, double*, hipStream_t);
+template int launch_orth_apply<float>(float*, int64_t, int, int, int, int, const double*, int, double*, hipStream_t);
+template int launch_orth_apply<double>(double*, int64_t, int, int, int, int, const double*, int, double*,
+                                       hipStream_t);
 
 }  // namespace ht

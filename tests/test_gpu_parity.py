@@ -125,6 +125,17 @@ def test_tsvt_fp32(ht, pen, dims, kinds, rank, r, p, q):
     assert _rel(got, ref) < TOL["fp32"]
 
 
+@pytest.mark.parametrize("dims,kinds,rank,r,p,q", [
+    ((132, 100, 3, 2), ["dct2", "dct2"], 30, 30, 20, 1),   # l = 50: two 32-column blocks
+    ((200, 160, 2, 2), ["dct2", "dct2"], 50, 60, 10, 2),   # l = 70: three 32-column blocks
+    ((260, 36, 3), ["dct2"], 10, 10, 6, 2),                # tall, short rows of A^T
+    ((36, 300, 3), ["dct2"], 10, 12, 4, 1),                # wide
+])
+def test_tsvt_fp32_matrix_core_shapes(ht, dims, kinds, rank, r, p, q):
+    got, ref, _ = _run_case(ht, dims, kinds, rank, r, p, q, "fp32", tau=5.0, pen="mcp")
+    assert _rel(got, ref) < TOL["fp32"]
+
+
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 @pytest.mark.parametrize("dims,kinds,rank,r,p,q", [
     ((40, 30), [], 3, 3, 2, 1),              # order 2: one slice, no transform
