@@ -66,6 +66,46 @@ __device__ __forceinline__ void chol_regs(double (&g)[LB], int l, double delta) 
   }
 }
 
+// One wavefront: load column `lane` of the symmetric G (LDS, pitch gp), factor
+// G = R^T R with deflation in registers, and write R^{-1} (upper, strict lower
+// triangle zero) to Rinv (LDS, pitch gp).  Lane c forms column c of R^{-1} by
+// column-oriented back substitution with the entries R[a][b] broadcast from
+// lane b.  delta_rel: relative pivot threshold.
+template <int LB>
+__device__ inline void chol_inverse_regs(const double* G, int gp, int l, double delta_rel, double* Rinv) {
+  const int lane = threadIdx.x & 63;
+  const int col = lane < l ? lane : 0;
+  double g[LB];
+#pragma unroll
+  for (int a = 0; a < LB; ++a) g[a] = (a < l) ? G[a * gp + col] : 0.0;
+  double dmax = 0.0;
+#pragma unroll
+  for (int a = 0; a < LB; ++a)
+    if (a == lane && a < l) dmax = g[a];
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) dmax = fmax(dmax, __shfl_xor(dmax, off, 64));
+  chol_regs<LB>(g, l, dmax > 0.0 ? delta_rel * dmax : 1.0);
+  // back substitution: s[a] accumulates -sum_b R[a][b] x[b]
+  double s[LB];
+#pragma unroll
+  for (int a = 0; a < LB; ++a) s[a] = (a == lane) ? 1.0 : 0.0;
+#pragma unroll
+  for (int b = LB - 1; b >= 0; --b) {
+    if (b < l) {
+      const double rbb = readlane_d(g[b], b);
+      const double xb = (b <= lane && rbb != 0.0) ? s[b] * fast_rcp(rbb) : 0.0;
+      s[b] = xb;
+#pragma unroll
+      for (int a = 0; a < b; ++a) s[a] -= readlane_d(g[a], b) * xb;  // R[a][b]
+    }
+  }
+  if (lane < l) {
+#pragma unroll
+    for (int a = 0; a < LB; ++a)
+      if (a < l) Rinv[a * gp + lane] = (a <= lane) ? s[a] : 0.0;
+  }
+}
+
 // G (l x l, pitch gp) = sum over tiles t of part[t*l*l + a*l + b], in tile order.
 __device__ inline void sum_gram_partials(double* G, int gp, const double* __restrict__ part, int ntiles, int l) {
   const int ll = l * l;

@@ -28,19 +28,24 @@ constexpr int LMAX = 80;
 
 size_t svd_lds_bytes(int l) {
   const size_t gp = (size_t)l + 1;
+  const size_t L2 = (size_t)l + (l & 1);
+  (void)L2;
   return (3 * (size_t)l * gp + gp + 3 * LMAX + 2 * 64) * 8 + (LMAX + 2 * 64) * 4;
 }
 
 // Pair t of step `step` in the round-robin schedule on L2 (even) players;
 // q = -1 when the partner is the padding player (odd l).
 __device__ __forceinline__ void rr_pair(int step, int t, int L2, int l, int& p, int& q) {
+  const int m = L2 - 1;  // step, t < m, so each reduction is one conditional subtract
   int a, b;
   if (t == 0) {
-    a = L2 - 1;
+    a = m;
     b = step;
   } else {
-    a = (step + t) % (L2 - 1);
-    b = (step - t + (L2 - 1)) % (L2 - 1);
+    a = step + t;
+    a = a >= m ? a - m : a;
+    b = step - t + m;
+    b = b >= m ? b - m : b;
   }
   p = min(a, b);
   q = max(a, b);
@@ -54,7 +59,7 @@ __device__ __forceinline__ void rr_pair(int step, int t, int L2, int l, int& p, 
 __device__ __forceinline__ void schur2(double app, double aqq, double apq, double abs_tol, double& c, double& s) {
   c = 1.0;
   s = 0.0;
-  if (fabs(apq) > abs_tol && fabs(apq) > 1e-15 * sqrt(fabs(app * aqq))) {
+  if (fabs(apq) > abs_tol && apq * apq > 1e-30 * fabs(app * aqq)) {
     const double d = aqq - app;
     const double h = sqrt(d * d + 4.0 * apq * apq);
     const double t = 2.0 * apq * (d >= 0.0 ? 1.0 : -1.0) * fast_rcp(fabs(d) + h);
@@ -84,7 +89,7 @@ __global__ __launch_bounds__(NT) void k_smallsvd(double* __restrict__ g2, int nt
   int* rp = perm + LMAX;
   int* rq = rp + 64;
   __shared__ double s_scr;
-  __shared__ int s_rot, s_kept;
+  __shared__ int s_rot[2], s_kept, s_step[2];  // flags double-buffered by parity
 
   const int j = blockIdx.x;
   const int tid = threadIdx.x;
@@ -95,8 +100,14 @@ __global__ __launch_bounds__(NT) void k_smallsvd(double* __restrict__ g2, int nt
   sum_gram_partials(B0, gp, gq, nt_q, l);
   sum_gram_partials(B1, gp, gw + (int64_t)j * nt_b * ll, nt_b, l);
   __syncthreads();
-  chol_deflate(B0, dR, gp, l, delta_rel, &s_scr);
-  tri_inverse<LB>(B0, dR, gp, l, V);  // V = R2^{-1} (upper)
+  if constexpr (LB <= 64) {
+    // wave 0: R2 = chol(G2) and R2^{-1} in registers (lane b owns column b)
+    if (tid < 64) chol_inverse_regs<LB>(B0, gp, l, delta_rel, V);
+    __syncthreads();
+  } else {
+    chol_deflate(B0, dR, gp, l, delta_rel, &s_scr);
+    tri_inverse<LB>(B0, dR, gp, l, V);  // V = R2^{-1} (upper)
+  }
   for (int idx = tid; idx < ll; idx += NT) gq[idx] = V[(idx / l) * gp + (idx % l)];
 
   // B0 = W~ R2^{-1};  B1 = R2^{-T} B0 (= W, then symmetrized);  V = I
@@ -142,12 +153,42 @@ __global__ __launch_bounds__(NT) void k_smallsvd(double* __restrict__ g2, int nt
   // ---- parallel cyclic Jacobi, ping-pong between B1 and B0 -----------------
   const int L2 = l + (l & 1);
   const int half = L2 / 2;
+  // fixed work of this thread in every step: block items (s, t) and V items (t, x)
+  const int nblk = half * half, nvit = half * l;
+  constexpr int NBI = ((LB / 2) * (LB / 2) + NT - 1) / NT;  // block items per thread (LB >= l)
+  constexpr int NVI = ((LB / 2) * LB + NT - 1) / NT;        // V items per thread
+  int bs[NBI], bt[NBI], vt[NVI], vx[NVI];
+#pragma unroll
+  for (int u = 0; u < NBI; ++u) {
+    const int item = tid + u * NT;
+    bs[u] = item < nblk ? item / half : -1;
+    bt[u] = item < nblk ? item % half : 0;
+  }
+#pragma unroll
+  for (int u = 0; u < NVI; ++u) {
+    const int item = tid + u * NT;
+    vt[u] = item < nvit ? item / l : -1;
+    vx[u] = item < nvit ? item % l : 0;
+  }
+  if (tid == 0) {
+    s_step[0] = s_step[1] = 0;
+    s_rot[0] = s_rot[1] = 0;
+  }
+  __syncthreads();
   double* Wc = B1;
   double* Wn = B0;
+  // A flag of parity b is cleared only after every thread has passed the
+  // barriers that follow its last read, so no barrier is needed around it.
+  int gstep = 0;
   for (int sweep = 0; sweep < 30; ++sweep) {
-    if (tid == 0) s_rot = 0;
-    __syncthreads();
-    for (int step = 0; step < L2 - 1; ++step) {
+    const int sp = sweep & 1;
+    for (int step = 0; step < L2 - 1; ++step, ++gstep) {
+      const int fp = gstep & 1;
+      __syncthreads();  // previous step's update complete; previous flags read
+      if (tid == 0) {
+        s_step[fp ^ 1] = 0;
+        if (step == 0) s_rot[sp ^ 1] = 0;
+      }
       if (tid < half) {
         int p, q;
         rr_pair(step, tid, L2, l, p, q);
@@ -157,11 +198,17 @@ __global__ __launch_bounds__(NT) void k_smallsvd(double* __restrict__ g2, int nt
         rs[tid] = sn;
         rp[tid] = p;
         rq[tid] = q;
-        if (sn != 0.0) s_rot = 1;
+        if (sn != 0.0) {
+          s_step[fp] = 1;
+          s_rot[sp] = 1;
+        }
       }
       __syncthreads();
-      for (int item = tid; item < half * half; item += NT) {
-        const int st = item / half, tt = item - st * half;
+      if (!s_step[fp]) continue;  // nothing to rotate in this step: W and V unchanged
+#pragma unroll
+      for (int u = 0; u < NBI; ++u) {
+        if (bs[u] < 0) continue;
+        const int st = bs[u], tt = bt[u];
         const int ps = rp[st], qs = rq[st], pt = rp[tt], qt = rq[tt];
         const double cs = rc[st], ss = rs[st], ct = rc[tt], sn = rs[tt];
         const double w00 = Wc[ps * gp + pt];
@@ -175,8 +222,10 @@ __global__ __launch_bounds__(NT) void k_smallsvd(double* __restrict__ g2, int nt
         if (qs >= 0) Wn[qs * gp + pt] = ct * r10 - sn * r11;
         if (qs >= 0 && qt >= 0) Wn[qs * gp + qt] = sn * r10 + ct * r11;
       }
-      for (int item = tid; item < half * l; item += NT) {
-        const int tt = item / l, x = item - tt * l;
+#pragma unroll
+      for (int u = 0; u < NVI; ++u) {
+        if (vt[u] < 0) continue;
+        const int tt = vt[u], x = vx[u];
         const double sn = rs[tt];
         if (sn != 0.0) {
           const int pt = rp[tt], qt = rq[tt];
@@ -186,14 +235,14 @@ __global__ __launch_bounds__(NT) void k_smallsvd(double* __restrict__ g2, int nt
           V[x * gp + qt] = sn * vp + ct * vq;
         }
       }
-      __syncthreads();
       double* tmp = Wc;
       Wc = Wn;
       Wn = tmp;
     }
-    if (!s_rot) break;
     __syncthreads();
+    if (!s_rot[sp]) break;
   }
+  __syncthreads();
 
   // ---- order, shrink, K = U diag(w) U^T, K' = R2^{-1} K R2^{-T} -------------
   for (int a = tid; a < l; a += NT) lam[a] = Wc[a * gp + a] * scale;
