@@ -33,13 +33,17 @@ WORKLOAD = {
 
 
 def stage_bytes(stage, plan, es):
-    """Algorithmic HBM bytes of one launch of a stage (read once, write once)."""
+    """Algorithmic HBM bytes of one launch of a stage (read once, write once); the
+    transformed tensor is 2 bytes per entry in the BF16-mixed path."""
     n1, n2 = plan.dims[0], plan.dims[1]
     P, l, N = plan.n_slices, plan.width, plan.N
-    if stage in ("transform_fwd", "transform_inv"):
+    ea = 2 if plan.precision == "bf16" else es
+    if stage == "transform_fwd":
+        return N * (es + ea)
+    if stage == "transform_inv":
         return 2 * N * es
     if stage in ("sketch_nn", "sketch_tn"):
-        return P * (n1 * n2 + (n1 + n2) * l) * es
+        return P * (n1 * n2 * ea + (n1 + n2) * l * es)
     if stage == "recon_nt":
         return P * (n1 * n2 + (n1 + n2) * l) * es
     if stage == "recon_qk":
@@ -101,6 +105,8 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--precision", choices=["fp32", "bf16"], default="fp32",
+                    help="fp32 (default) or the BF16-mixed path (BF16 transformed slices and sketch products)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a plain 256 MiB device copy (known bytes) to calibrate HBM counters")
     args = ap.parse_args()
@@ -115,7 +121,10 @@ def main():
     from paper_2506_09594_amd import htsvt as ht
     from workloads import synth
 
-    wl = WORKLOAD
+    wl = dict(WORKLOAD)
+    if args.precision != wl["precision"]:
+        wl["precision"] = args.precision
+        wl["name"] = wl["name"].replace("_fp32_", "_" + args.precision + "_")
     torch.cuda.set_device(0)
     X = synth.lowrank_tensor(wl["dims"], wl["rank"], wl["kinds"], seed=wl["seed"]).astype(np.float32)
     plan = ht.Plan(wl["dims"], wl["kinds"], r=wl["r"], p=wl["p"], q=wl["q"], precision=wl["precision"],
@@ -148,7 +157,8 @@ def main():
     ms = stages[dom]["ms_per_launch"]
     achieved = stage_bytes(dom, plan, es) / (ms * 1e-3) / 1e9
     roof = {"kernel": dom, "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": counter_traffic(dom),
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": counter_traffic(dom) if wl["precision"] == "fp32" else None,
             "algorithmic_bytes_per_launch": stage_bytes(dom, plan, es), "ms_per_launch": round(ms, 5)}
     if args.calib_copy:
         src = torch.empty(64 * 1024 * 1024, dtype=torch.float32, device="cuda").fill_(1.0)
@@ -167,7 +177,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": "f32" if wl["precision"] == "fp32" else "bf16-f32acc",
         "data": "synthetic",
         "config": {"workload": wl["name"], "dims": list(wl["dims"]), "r": wl["r"], "p": wl["p"], "q": wl["q"],
                    "transform": "dct2 on modes 3,4", "penalty": "mcp", "slices_per_step": plan.n_slices},

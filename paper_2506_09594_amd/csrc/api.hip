@@ -111,7 +111,7 @@ void dct2_ortho(int n, std::vector<double>& U) {
 void layout(ht_plan* pl) {
   const size_t es = elem_bytes(pl->precision);
   const size_t P = (size_t)pl->P, n1 = (size_t)pl->n1, n2 = (size_t)pl->n2, l = (size_t)pl->l;
-  pl->size[WS_A] = (size_t)pl->N * es;
+  pl->size[WS_A] = (size_t)pl->N * (pl->precision == HT_BF16_MIXED ? 2 : es);
   pl->size[WS_OMEGA] = P * n2 * l * es;
   pl->size[WS_Y] = P * n1 * l * es;
   pl->size[WS_Z] = P * n2 * l * es;
@@ -190,8 +190,14 @@ int run_tsvt(const ht_plan* pl, const T* X, T* out, double tau, const double* mu
   T* QK = ws_ptr<T>(pl, ws, WS_QK);
   T* C = ws_ptr<T>(pl, ws, WS_C);
   const int64_t sA = NT, sY = n1 * l, sZ = n2 * l;
+  const bool bf16 = pl->precision == HT_BF16_MIXED;
+  const uint16_t* Ah = reinterpret_cast<const uint16_t*>(A);  // BF16 view of the transformed tensor
   int rc;
-  if ((rc = timed(pl, ST_TRANSFORM_FWD, s, [&] { return launch_transform<T>(X, A, NT, (int)P, pl->mt_fwd, table<T>(pl), s); })))
+  if ((rc = timed(pl, ST_TRANSFORM_FWD, s, [&] {
+         if (bf16)
+           return launch_transform_bf16((const float*)X, (uint16_t*)A, NT, (int)P, pl->mt_fwd, pl->table32, s);
+         return launch_transform<T>(X, A, NT, (int)P, pl->mt_fwd, table<T>(pl), s);
+       })))
     return rc;
   if ((rc = timed(pl, ST_OMEGA, s, [&] {
          return launch_omega<T>(Om, nullptr, (int)P, n2 * l, call, call_dev, pl->stream_id, pl->seed, nullptr, s);
@@ -202,10 +208,13 @@ int run_tsvt(const ht_plan* pl, const T* X, T* out, double tau, const double* mu
   const int t1 = (int)ceil_div(n1, 64);
   // FP32 slices with 16-byte aligned columns run the products on the matrix cores
   const bool mfma = pl->mfma;
-  const int rt = mfma ? mfma_tile_rows() : 64;
+  const int rt = (mfma || bf16) ? mfma_tile_rows() : 64;
   const int p1 = (int)ceil_div(n1, rt), p2 = (int)ceil_div(n2, rt);
   auto sketch_nn = [&](const T* W) {
     return timed(pl, ST_SKETCH_NN, s, [&] {
+      if (bf16)
+        return launch_bf16_nn(Ah, sA, (int)n1, (const float*)W, sZ, (int)n2, (float*)Y, sY, (int)n1, (int)n1,
+                              (int)n2, l, (int)P, gp1, s);
       if (mfma)
         return launch_mfma_nn((const float*)A, sA, (int)n1, (const float*)W, sZ, (int)n2, (float*)Y, sY, (int)n1,
                               (int)n1, (int)n2, l, (int)P, gp1, s);
@@ -214,6 +223,9 @@ int run_tsvt(const ht_plan* pl, const T* X, T* out, double tau, const double* mu
   };
   auto sketch_tn = [&]() {
     return timed(pl, ST_SKETCH_TN, s, [&] {
+      if (bf16)
+        return launch_bf16_tn(Ah, sA, (int)n1, (const float*)Y, sY, (int)n1, (float*)Z, sZ, (int)n2, (int)n1,
+                              (int)n2, l, (int)P, gp1, s);
       if (mfma)
         return launch_mfma_tn((const float*)A, sA, (int)n1, (const float*)Y, sY, (int)n1, (float*)Z, sZ, (int)n2,
                               (int)n1, (int)n2, l, (int)P, gp1, s);
@@ -308,7 +320,6 @@ int ht_plan_create(const ht_plan_desc* d, ht_plan** out) {
   if (d->order < 2 || d->order > HT_MAX_ORDER) HT_FAIL(HT_ERR_INVALID_ARG, "order must be in [2, 8]");
   if (d->precision != HT_FP64 && d->precision != HT_FP32 && d->precision != HT_BF16_MIXED)
     HT_FAIL(HT_ERR_INVALID_ARG, "unknown precision");
-  if (d->precision == HT_BF16_MIXED) HT_FAIL(HT_ERR_UNSUPPORTED, "BF16_MIXED is not implemented in this build");
   if (d->r < 1 || d->p < 0 || d->q < 0) HT_FAIL(HT_ERR_INVALID_ARG, "need r >= 1, p >= 0, q >= 0");
   ht_plan* pl = new ht_plan();
   std::memset(pl, 0, sizeof(ht_plan));

@@ -51,6 +51,14 @@ __device__ __forceinline__ void gaussian4(uint64_t g, uint32_t slice, uint32_t c
   z[3] = r23 * s3;
 }
 
+// FP32 -> BF16 bits, round to nearest even (NaN stays a quiet NaN).
+__device__ __forceinline__ uint16_t f32_to_bf16_rne(float f) {
+  uint32_t u = __float_as_uint(f);
+  if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40u);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+
 // ---------------------------------------------------------------------------
 // Penalties and their proximity operators, for v >= 0 (callers pass |v| and
 // restore the sign).  Prox_{phi,mu}(v) = argmin_x mu phi(x) + (x - v)^2 / 2.

@@ -27,6 +27,10 @@ int ensure_dynamic_lds(const void* kernel, size_t bytes);
 template <typename T>
 int launch_transform(const T* in, T* out, int64_t NT, int P, const ModeTable& mt, const T* table, hipStream_t s);
 
+// Forward transform of an FP32 tensor with the result rounded to BF16.
+int launch_transform_bf16(const float* in, uint16_t* out, int64_t NT, int P, const ModeTable& mt, const float* table,
+                          hipStream_t s);
+
 template <typename T>
 int launch_omega(T* om, double* om64, int P, int64_t per_slice, uint32_t call, const int32_t* call_dev,
                  uint32_t stream_id, uint64_t seed, const int32_t* canon, hipStream_t s);
@@ -55,6 +59,13 @@ int launch_mfma_nn(const float* A, int64_t sA, int lda, const float* W, int64_t 
                    int ldy, int m, int kd, int l, int P, double* gpart, hipStream_t s);
 int launch_mfma_tn(const float* A, int64_t sA, int lda, const float* Q, int64_t sQ, int ldq, float* Z, int64_t sZ,
                    int ldz, int m, int n, int l, int P, double* gpart, hipStream_t s);
+
+// BF16 thin products on the matrix cores (A in BF16, thin operands FP32 in
+// memory, rounded to BF16 when staged; FP32 results; 128-row tiles).
+int launch_bf16_nn(const uint16_t* A, int64_t sA, int lda, const float* W, int64_t sW, int ldw, float* Y,
+                   int64_t sY, int ldy, int m, int kd, int l, int P, double* gpart, hipStream_t s);
+int launch_bf16_tn(const uint16_t* A, int64_t sA, int lda, const float* Q, int64_t sQ, int ldq, float* Z,
+                   int64_t sZ, int ldz, int m, int n, int l, int P, double* gpart, hipStream_t s);
 
 // One CholeskyQR pass with deflation, in place on Y_j (m x l), from the Gram
 // partials written by the producing product (gin, nparts per slice).

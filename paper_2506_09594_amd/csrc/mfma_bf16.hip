@@ -1,0 +1,212 @@
+// BF16 sketch products on the matrix cores (v_mfma_f32_32x32x16_bf16), FP32
+// accumulation.  The transformed tensor A is stored in BF16; the thin operand
+// (sketch matrix or basis, FP32 in memory) is rounded to BF16 while it is
+// staged; the result and its FP64 Gram partials are written as in the FP32
+// kernel.
+//
+//   nn:  Y_j (m x l) = A_j (m x kd) W_j (kd x l)
+//   tn:  Z_j (n x l) = A_j^T (n x m) Q_j (m x l)
+//
+// Tiles: 128 output rows x l (<= 32 NB) per workgroup, wavefront w owns rows
+// 32w..32w+31.  K chunks of 32 are double-buffered in LDS, both operands stored
+// with k contiguous so that each lane fetches its 8 consecutive k values with
+// one 16-byte LDS read.  MFMA operand layout (32x32x16 bf16): lane t supplies
+// A[t % 32][8 (t / 32) .. 8 (t / 32) + 7] and B[8 (t / 32) ..][t % 32]; the
+// accumulator layout is that of the FP32 32x32 instruction.
+#include "chol.hpp"
+
+namespace ht {
+
+namespace {
+
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
+
+constexpr int MT = 128;
+constexpr int KC = 32;
+constexpr int NTH = 256;
+constexpr int KP = KC + 8;  // LDS pitch (bf16 elements) of a k-contiguous row: 80 bytes
+
+template <int NB>
+struct Bf16Lds {
+  static constexpr int A_ELEMS = MT * KP;
+  static constexpr int B_ELEMS = 32 * NB * KP;
+  static constexpr int MAIN_BYTES = 2 * (A_ELEMS + B_ELEMS) * 2;
+  static constexpr int EPI_BYTES = MT * (32 * NB + 1) * 8;
+  static constexpr int BYTES = MAIN_BYTES > EPI_BYTES ? MAIN_BYTES : EPI_BYTES;
+};
+
+template <int NB, bool TRANS>
+__global__ __launch_bounds__(NTH) void k_mfma_thin_bf16(const uint16_t* __restrict__ A, int64_t sA, int lda,
+                                                        const float* __restrict__ W, int64_t sW, int ldw,
+                                                        float* __restrict__ Y, int64_t sY, int ldy, int M_out,
+                                                        int K, int l, double* __restrict__ gpart, int vecA,
+                                                        int vecW) {
+  using L = Bf16Lds<NB>;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  uint16_t* const lds_h = reinterpret_cast<uint16_t*>(smem_raw);
+  const int j = blockIdx.y;
+  const int r0 = blockIdx.x * MT;
+  const uint16_t* Aj = A + (int64_t)j * sA;
+  const float* Wj = W + (int64_t)j * sW;
+  float* Yj = Y + (int64_t)j * sY;
+  const int tid = threadIdx.x;
+  const int wave = tid / 64, lane = tid % 64;
+  const int LW = 32 * NB;
+
+  // A chunk: 128 x 32 bf16 = 512 x 16-byte groups of 8, two per thread.
+  // nn: group = 8 consecutive rows of one column k;  tn: 8 consecutive k of one column.
+  u16x8 ra[2];
+  constexpr int NWB = (32 * NB * KC / 4 + NTH - 1) / NTH;  // float4 groups of the thin chunk per thread
+  f32x4 rw[NWB];
+  auto fetch = [&](int k0) {
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const int g = tid + u * NTH;
+      u16x8 v;
+      if (!TRANS) {
+        const int kk = g / (MT / 8), row = (g % (MT / 8)) * 8;
+        const int gr = r0 + row, gk = k0 + kk;
+        if (vecA && gk < K && gr + 7 < M_out) {
+          v = *reinterpret_cast<const u16x8*>(Aj + gr + (int64_t)gk * lda);
+        } else {
+#pragma unroll
+          for (int e = 0; e < 8; ++e) v[e] = (gk < K && gr + e < M_out) ? Aj[gr + e + (int64_t)gk * lda] : 0;
+        }
+      } else {
+        const int row = g / (KC / 8), kk = (g % (KC / 8)) * 8;
+        const int gc = r0 + row, gk = k0 + kk;
+        if (vecA && gc < M_out && gk + 7 < K) {
+          v = *reinterpret_cast<const u16x8*>(Aj + gk + (int64_t)gc * lda);
+        } else {
+#pragma unroll
+          for (int e = 0; e < 8; ++e) v[e] = (gc < M_out && gk + e < K) ? Aj[gk + e + (int64_t)gc * lda] : 0;
+        }
+      }
+      ra[u] = v;
+    }
+#pragma unroll
+    for (int u = 0; u < NWB; ++u) {
+      const int f = tid + u * NTH;
+      const int c = f / (KC / 4), k4 = (f % (KC / 4)) * 4;
+      const int gk = k0 + k4;
+      f32x4 v;
+      if (vecW && f < LW * KC / 4 && c < l && gk + 3 < K) {
+        v = *reinterpret_cast<const f32x4*>(Wj + gk + (int64_t)c * ldw);
+      } else {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) v[e] = (f < LW * KC / 4 && c < l && gk + e < K) ? Wj[gk + e + (int64_t)c * ldw] : 0.0f;
+      }
+      rw[u] = v;
+    }
+  };
+  auto stash = [&](int buf) {
+    uint16_t* As = lds_h + buf * L::A_ELEMS;
+    uint16_t* Ws = lds_h + 2 * L::A_ELEMS + buf * L::B_ELEMS;
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const int g = tid + u * NTH;
+      if (!TRANS) {
+        const int kk = g / (MT / 8), row = (g % (MT / 8)) * 8;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) As[(row + e) * KP + kk] = ra[u][e];
+      } else {
+        const int row = g / (KC / 8), kk = (g % (KC / 8)) * 8;
+        *reinterpret_cast<u16x8*>(As + row * KP + kk) = ra[u];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < NWB; ++u) {
+      const int f = tid + u * NTH;
+      if (f < LW * KC / 4) {
+        const int c = f / (KC / 4), k4 = (f % (KC / 4)) * 4;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) Ws[c * KP + k4 + e] = f32_to_bf16_rne(rw[u][e]);
+      }
+    }
+  };
+
+  f32x16 acc[NB];
+#pragma unroll
+  for (int b = 0; b < NB; ++b)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) acc[b][r] = 0.0f;
+
+  const int nchunks = (K + KC - 1) / KC;
+  fetch(0);
+  stash(0);
+  __syncthreads();
+  const int mrow = 32 * wave + (lane % 32);
+  const int koff = 8 * (lane / 32);
+  for (int ch = 0; ch < nchunks; ++ch) {
+    const int buf = ch & 1;
+    if (ch + 1 < nchunks) fetch((ch + 1) * KC);
+    const uint16_t* As = lds_h + buf * L::A_ELEMS;
+    const uint16_t* Ws = lds_h + 2 * L::A_ELEMS + buf * L::B_ELEMS;
+#pragma unroll
+    for (int kh = 0; kh < KC / 16; ++kh) {
+      const bf16x8 a = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u16x8*>(As + mrow * KP + 16 * kh + koff));
+#pragma unroll
+      for (int b = 0; b < NB; ++b) {
+        const bf16x8 bv = __builtin_bit_cast(
+            bf16x8, *reinterpret_cast<const u16x8*>(Ws + (32 * b + (lane % 32)) * KP + 16 * kh + koff));
+        acc[b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bv, acc[b], 0, 0, 0);
+      }
+    }
+    if (ch + 1 < nchunks) stash(buf ^ 1);
+    __syncthreads();
+  }
+
+  double* S = reinterpret_cast<double*>(smem_raw);
+  const int sp = LW + 1;
+  const int rows = min(MT, M_out - r0);
+#pragma unroll
+  for (int b = 0; b < NB; ++b)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int i = 32 * wave + 8 * (r / 4) + 4 * (lane / 32) + (r % 4);
+      const int c = 32 * b + (lane % 32);
+      S[i * sp + c] = (i < rows && c < l) ? (double)acc[b][r] : 0.0;
+    }
+  __syncthreads();
+  for (int idx = tid; idx < MT * l; idx += NTH) {
+    const int i = idx % MT, c = idx / MT;
+    if (i < rows) Yj[(r0 + i) + (int64_t)c * ldy] = (float)S[i * sp + c];
+  }
+  if (gpart) tile_gram_to_global(S, sp, MT, l, gpart + ((int64_t)j * gridDim.x + blockIdx.x) * (int64_t)l * l);
+}
+
+template <int NB, bool TRANS>
+int launch_thin_bf16(const uint16_t* A, int64_t sA, int lda, const float* W, int64_t sW, int ldw, float* Y,
+                     int64_t sY, int ldy, int M_out, int K, int l, int P, double* gpart, hipStream_t s) {
+  using L = Bf16Lds<NB>;
+  int rc = ensure_dynamic_lds((const void*)k_mfma_thin_bf16<NB, TRANS>, L::BYTES);
+  if (rc) return rc;
+  const int vecA = (lda % 8 == 0) && (sA % 8 == 0) && (reinterpret_cast<uintptr_t>(A) % 16 == 0);
+  const int vecW = (ldw % 4 == 0) && (sW % 4 == 0) && (reinterpret_cast<uintptr_t>(W) % 16 == 0);
+  dim3 grid((unsigned)ceil_div(M_out, MT), (unsigned)P);
+  hipLaunchKernelGGL((k_mfma_thin_bf16<NB, TRANS>), grid, dim3(NTH), L::BYTES, s, A, sA, lda, W, sW, ldw, Y, sY,
+                     ldy, M_out, K, l, gpart, vecA, vecW);
+  HT_CHECK_LAUNCH();
+  return HT_OK;
+}
+
+}  // namespace
+
+int launch_bf16_nn(const uint16_t* A, int64_t sA, int lda, const float* W, int64_t sW, int ldw, float* Y,
+                   int64_t sY, int ldy, int m, int kd, int l, int P, double* gpart, hipStream_t s) {
+  if (l <= 32) return launch_thin_bf16<1, false>(A, sA, lda, W, sW, ldw, Y, sY, ldy, m, kd, l, P, gpart, s);
+  if (l <= 64) return launch_thin_bf16<2, false>(A, sA, lda, W, sW, ldw, Y, sY, ldy, m, kd, l, P, gpart, s);
+  return launch_thin_bf16<3, false>(A, sA, lda, W, sW, ldw, Y, sY, ldy, m, kd, l, P, gpart, s);
+}
+
+int launch_bf16_tn(const uint16_t* A, int64_t sA, int lda, const float* Q, int64_t sQ, int ldq, float* Z,
+                   int64_t sZ, int ldz, int m, int n, int l, int P, double* gpart, hipStream_t s) {
+  if (l <= 32) return launch_thin_bf16<1, true>(A, sA, lda, Q, sQ, ldq, Z, sZ, ldz, n, m, l, P, gpart, s);
+  if (l <= 64) return launch_thin_bf16<2, true>(A, sA, lda, Q, sQ, ldq, Z, sZ, ldz, n, m, l, P, gpart, s);
+  return launch_thin_bf16<3, true>(A, sA, lda, Q, sQ, ldq, Z, sZ, ldz, n, m, l, P, gpart, s);
+}
+
+}  // namespace ht

@@ -10,6 +10,8 @@
 // fibers of that mode with several fibers held in registers per thread, and
 // writes the tile back.  HBM traffic is one read and one write of the tensor;
 // the mode matrices are scalar operands.
+#include <type_traits>
+
 #include "kernels.hpp"
 
 namespace ht {
@@ -85,8 +87,9 @@ __device__ __forceinline__ void mode_exact(T* tile, int TP, int lgTP, int s, int
   }
 }
 
-template <typename T>
-__global__ __launch_bounds__(256) void k_transform(const T* __restrict__ in, T* __restrict__ out, int64_t NT,
+// TO = T, or uint16_t for BF16 output (rounded to nearest even).
+template <typename T, typename TO>
+__global__ __launch_bounds__(256) void k_transform(const T* __restrict__ in, TO* __restrict__ out, int64_t NT,
                                                    int P, int TP, int lgTP, int vec, ModeTable mt,
                                                    const T* __restrict__ table) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -169,7 +172,12 @@ __global__ __launch_bounds__(256) void k_transform(const T* __restrict__ in, T* 
   }
 
   // ---- store ---------------------------------------------------------------
-  if (vec) {
+  if constexpr (!std::is_same<TO, T>::value) {
+    for (int idx = tid; idx < total; idx += nt) {
+      const int j = idx >> lgTP, t = idx & (TP - 1);
+      if (t < tp) out[(int64_t)j * NT + t0 + t] = f32_to_bf16_rne((float)tile[idx]);
+    }
+  } else if (vec) {
     using VT = __attribute__((ext_vector_type(V))) T;
     const int nv = total / V;
     for (int v0 = tid; v0 < nv; v0 += UNR * nt) {
@@ -198,11 +206,12 @@ int transform_tile_width(int64_t P, size_t elem_bytes) {
   return (int)tp;
 }
 
-template <typename T>
-int launch_transform(const T* in, T* out, int64_t NT, int P, const ModeTable& mt, const T* table,
-                     hipStream_t stream) {
-  if (mt.nmodes == 0) {
-    if (in != out) HT_CHECK_HIP(hipMemcpyAsync(out, in, sizeof(T) * NT * P, hipMemcpyDeviceToDevice, stream));
+template <typename T, typename TO>
+int launch_transform_impl(const T* in, TO* out, int64_t NT, int P, const ModeTable& mt, const T* table,
+                          hipStream_t stream) {
+  if (mt.nmodes == 0 && std::is_same<TO, T>::value) {
+    if ((const void*)in != (const void*)out)
+      HT_CHECK_HIP(hipMemcpyAsync(out, in, sizeof(T) * NT * P, hipMemcpyDeviceToDevice, stream));
     return HT_OK;
   }
   const int TP = transform_tile_width(P, sizeof(T));
@@ -214,10 +223,21 @@ int launch_transform(const T* in, T* out, int64_t NT, int P, const ModeTable& mt
                   (reinterpret_cast<uintptr_t>(out) % 16 == 0);
   const size_t lds = sizeof(T) * (size_t)TP * P;
   const int64_t blocks = ceil_div(NT, TP);
-  hipLaunchKernelGGL(k_transform<T>, dim3((unsigned)blocks), dim3(256), lds, stream, in, out, NT, P, TP, lgTP, vec,
-                     mt, table);
+  hipLaunchKernelGGL((k_transform<T, TO>), dim3((unsigned)blocks), dim3(256), lds, stream, in, out, NT, P, TP, lgTP,
+                     vec, mt, table);
   HT_CHECK_LAUNCH();
   return HT_OK;
+}
+
+template <typename T>
+int launch_transform(const T* in, T* out, int64_t NT, int P, const ModeTable& mt, const T* table,
+                     hipStream_t stream) {
+  return launch_transform_impl<T, T>(in, out, NT, P, mt, table, stream);
+}
+
+int launch_transform_bf16(const float* in, uint16_t* out, int64_t NT, int P, const ModeTable& mt,
+                          const float* table, hipStream_t stream) {
+  return launch_transform_impl<float, uint16_t>(in, out, NT, P, mt, table, stream);
 }
 
 template int launch_transform<float>(const float*, float*, int64_t, int, const ModeTable&, const float*, hipStream_t);
