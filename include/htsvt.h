@@ -134,7 +134,9 @@ int ht_plan_info(const ht_plan* plan, int64_t* n_slices, int* width, int* kept);
  * slice; the final R2 correction is applied in the l x l space),
  * 3 B^T = A^T Q1 (n2 x l per slice), 4 K' = R2^{-1} U diag(w) U^T R2^{-T}
  * (l x l per slice), 5 Q1 K', 6 reconstructed transformed slices C,
- * 7-9 solver buffers, 10-11 FP64 Gram partials. */
+ * 7-9 solver buffers, 10-11 FP64 Gram partials, 12 per-slice widths,
+ * 13 the call index of a replayed graph.  Thin blocks of slice j start at
+ * j * align4(rows * l) elements (align4 rounds up to a multiple of 4). */
 int ht_plan_workspace_region(const ht_plan* plan, int region, size_t* offset, size_t* bytes);
 
 /* Randomized GNHTSVT (Def. 4.3 computed slice-wise on sketches):
@@ -164,6 +166,63 @@ int ht_omega_fp64(const ht_plan* plan, uint32_t call_index, double* dev_out, voi
 /* Forward (inverse != 0: inverse) transform of a whole tensor, out-of-place
  * or in place, in the plan's storage type. */
 int ht_transform(const ht_plan* plan, const void* X, void* out, int inverse, void* stream);
+
+/* ---------------------------------------------------------------------------
+ * Batches of tensors of different shapes.  Every tensor of a batch is a
+ * separate problem (its own transforms, r and p, threshold tau_t); they share
+ * q, the precision and the sketch key (seed; the Philox stream word of tensor
+ * t is stream_id + t, its slice words are its own slice indices).  Each stage
+ * of the method is one launch over every slice of every tensor.
+ * The tensors live in one packed device buffer of packed_numel elements:
+ * tensor t at element offset offset_t (a multiple of 64), in Fortran order;
+ * gaps between tensors are ignored on input and left untouched on output.
+ * --------------------------------------------------------------------------- */
+
+/* Create a plan over n_tensors descriptions (q, precision, seed and stream_id
+ * must agree).  Errors as ht_plan_create. */
+int ht_batch_plan_create(int n_tensors, const ht_plan_desc* descs, ht_plan** out);
+
+/* Packed buffer size (elements) and tensor count of any plan (a single-tensor
+ * plan is a batch of one at offset 0). */
+int ht_batch_info(const ht_plan* plan, int64_t* packed_numel, int* n_tensors);
+
+/* Offset and size (elements) of tensor t in the packed buffer, its first
+ * slice in the plan's slice order, its sketch width l and kept count k. */
+int ht_batch_tensor_info(const ht_plan* plan, int t, int64_t* offset, int64_t* numel, int64_t* first_slice,
+                         int* width, int* kept);
+
+/* Randomized GNHTSVT of every tensor of a batch plan with threshold
+ * tau_dev[t] (DEVICE array of n_tensors doubles, read when the call runs).
+ * X, out: packed device buffers; sigma_out (P_total * l_max doubles, rows of
+ * l_max with zeros past a slice's own width) and kept_out (P_total ints) are
+ * optional, slice order as ht_batch_tensor_info.  Errors as ht_gnhtsvt. */
+int ht_batch_gnhtsvt(ht_plan* plan, const void* X, void* out, const double* tau_dev, const ht_penalty* penalty,
+                     uint32_t call_index, void* workspace, size_t workspace_bytes, void* stream,
+                     double* sigma_out, int* kept_out);
+
+/* Tile choices of a plan: output rows per workgroup of the sketch products
+ * (64 or 128; FP64 always 64) and the LDS budget of one transform tile (32, 64
+ * or 128 KiB; a budget that does not hold the tensor's face slices fails with
+ * UNSUPPORTED).  0 keeps the current value.  Results do not depend on the
+ * choice beyond rounding order. */
+int ht_plan_set_tuning(ht_plan* plan, int prod_rows, int transform_lds_kib);
+int ht_plan_get_tuning(const ht_plan* plan, int* prod_rows, int* transform_lds_kib);
+
+/* Autotuner: times whole t-SVT calls on X (L1, tau = 0; out is overwritten)
+ * for every tile choice, one knob at a time (product rows, then transform
+ * budget), `repeats` timed calls each after one warm-up, keeps the fastest and
+ * reports its milliseconds per call.  Synchronizes the stream. */
+int ht_plan_autotune(ht_plan* plan, const void* X, void* out, void* workspace, size_t workspace_bytes,
+                     void* stream, int repeats, double* best_ms);
+
+/* Graph replay (on != 0): the next t-SVT call on the plan records its launch
+ * sequence as a HIP graph (stream capture); later calls with the same X, out,
+ * workspace, stream, tau (or tau_dev), penalty and stats pointers launch the
+ * recorded graph, whose first node writes the call index into the workspace.
+ * Any other argument set records a new graph.  Per-stage profiling bypasses
+ * the graph.  The stream must be a created stream (INVALID_ARG for the null
+ * stream, which cannot be captured).  on = 0 drops the graph. */
+int ht_plan_graph_enable(ht_plan* plan, int on);
 
 /* Per-stage timing: when enabled, every kernel launch of the plan is bracketed
  * by HIP events recorded on the launch stream.  ht_profile_read waits for the

@@ -1,8 +1,18 @@
-// C-ABI entry points: plans, workspace layout and the per-call orchestration
-// of the randomized t-SVT and of the ADMM iteration.
+// C-ABI entry points: plans (one tensor or a batch of tensors of different
+// shapes), their device tables, work-item lists and workspace layout, and the
+// per-call orchestration of the randomized t-SVT and of the ADMM iteration.
+//
+// A plan is a list of tensors cut into transformed face slices.  Every stage of
+// the t-SVT is one launch over all slices of all tensors: the kernels find a
+// slice's operands through the device slice table and take their work from an
+// item list built here, so a batch of uneven tensors costs the same number of
+// launches as one tensor.  The whole launch sequence can be replayed as one
+// HIP graph.
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <mutex>
+#include <numeric>
 #include <set>
 #include <string>
 #include <utility>
@@ -28,12 +38,18 @@ int ensure_dynamic_lds(const void* kernel, size_t bytes) {
   return HT_OK;
 }
 
+// Writes the sketch call index into the workspace (first node of a replayed graph).
+__global__ void k_set_call(int32_t* slot, int32_t v) {
+  if (threadIdx.x == 0) *slot = v;
+}
+
 }  // namespace ht
 
 using namespace ht;
 
-// Named regions of the t-SVT workspace (for introspection by the tests).
-enum { WS_A = 0, WS_OMEGA, WS_Y, WS_Z, WS_K, WS_QK, WS_C, WS_LNEW, WS_XIN, WS_STATE, WS_GP1, WS_GP2, WS_COUNT };
+// Named regions of the workspace (for introspection by the tests).
+enum { WS_A = 0, WS_OMEGA, WS_Y, WS_Z, WS_K, WS_QK, WS_C, WS_LNEW, WS_XIN, WS_STATE, WS_GP1, WS_GP2, WS_WK, WS_CALL,
+       WS_COUNT };
 
 // Optional per-stage timing with HIP events recorded on the launch stream.
 enum { ST_TRANSFORM_FWD = 0, ST_OMEGA, ST_SKETCH_NN, ST_CHOLQR, ST_SKETCH_TN, ST_SMALLSVD, ST_RECON_QK, ST_RECON_NT,
@@ -48,29 +64,88 @@ struct Profiler {
   std::vector<Rec> recs;
 };
 
-struct ht_plan {
+struct TensorHost {
   int order;
   int64_t dims[HT_MAX_ORDER];
-  int kinds[HT_MAX_ORDER];
   int64_t n1, n2, P, N;
-  int r, p, q, l, k;
-  int precision;
+  int r, p, l, k;
+  int64_t x;       // offset in the packed buffers
+  int64_t slice0;  // first slice in the slice table
+  ModeTable fwd, inv;
+};
+
+struct ItemList {
+  int64_t off;  // into the device item array
+  int n;
+};
+
+// Key of a recorded graph: everything the launch sequence captures by value.
+struct GraphKey {
+  const void* X;
+  void* out;
+  void* ws;
+  const double* tau_dev;
+  double tau;
+  int kind;
+  double p0, p1;
+  double* sigma;
+  int* kept;
+  hipStream_t stream;
+  bool operator==(const GraphKey& o) const {
+    return X == o.X && out == o.out && ws == o.ws && tau_dev == o.tau_dev && tau == o.tau && kind == o.kind &&
+           p0 == o.p0 && p1 == o.p1 && sigma == o.sigma && kept == o.kept && stream == o.stream;
+  }
+};
+
+struct GraphCache {
+  bool valid = false;
+  GraphKey key{};
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  hipGraphNode_t call_node = nullptr;
+  void reset() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    exec = nullptr;
+    graph = nullptr;
+    call_node = nullptr;
+    valid = false;
+  }
+};
+
+struct ht_plan {
+  bool batch;
+  int precision, q;
   uint64_t seed;
   uint32_t stream_id;
   int device;
-  ModeTable mt_fwd, mt_inv;
-  double* table64;  // device: forward then inverse matrices
+  std::vector<TensorHost> tens;
+  int64_t Ntot, Ptot;
+  int lmax, kmax;
+  int64_t max_n2l;
+  int prod_rows;     // output rows per product workgroup (64 or 128)
+  size_t tf_budget;  // LDS bytes of one transform tile
+  size_t tf_lds;
+  std::vector<SliceDesc> h_slices;
+  TensorDesc* d_tens;
+  SliceDesc* d_slices;
+  int2* d_items;
+  double* table64;
   float* table32;
+  ItemList it_nn[2], it_tn[2], it_oy, it_oz, it_qk, it_nt, it_tf;  // [0]: 64-row tiles, [1]: 128-row tiles
+  int tf_capacity;
   size_t off[WS_COUNT];
   size_t size[WS_COUNT];
   size_t tsvt_bytes, admm_bytes;
   Profiler* prof;
-  bool mfma;  // FP32 thin products on the matrix cores
+  bool graph_on;
+  GraphCache* graph;
 };
 
 namespace {
 
 size_t elem_bytes(int precision) { return precision == HT_FP64 ? 8 : 4; }
+int64_t align4(int64_t x) { return (x + 3) & ~int64_t(3); }
 
 int check_penalty(const ht_penalty* pen) {
   if (!pen) HT_FAIL(HT_ERR_INVALID_ARG, "penalty is NULL");
@@ -108,31 +183,381 @@ void dct2_ortho(int n, std::vector<double>& U) {
     }
 }
 
-void layout(ht_plan* pl) {
+void free_plan(ht_plan* pl) {
+  if (!pl) return;
+  if (pl->graph) {
+    pl->graph->reset();
+    delete pl->graph;
+  }
+  if (pl->prof) {
+    for (auto& r : pl->prof->recs) {
+      (void)hipEventDestroy(r.a);
+      (void)hipEventDestroy(r.b);
+    }
+    delete pl->prof;
+  }
+  if (pl->table64) (void)hipFree(pl->table64);
+  if (pl->table32) (void)hipFree(pl->table32);
+  if (pl->d_tens) (void)hipFree(pl->d_tens);
+  if (pl->d_slices) (void)hipFree(pl->d_slices);
+  if (pl->d_items) (void)hipFree(pl->d_items);
+  delete pl;
+}
+
+// Validate one tensor description and append its transform matrices (forward
+// U_k, then inverse U_k^T / alpha_k, row-major) to tab.
+int add_tensor(const ht_plan_desc* d, std::vector<double>& tab, TensorHost& t) {
+  if (d->order < 2 || d->order > HT_MAX_ORDER) HT_FAIL(HT_ERR_INVALID_ARG, "order must be in [2, 8]");
+  if (d->r < 1 || d->p < 0 || d->q < 0) HT_FAIL(HT_ERR_INVALID_ARG, "need r >= 1, p >= 0, q >= 0");
+  t.order = d->order;
+  int64_t P = 1;
+  for (int i = 0; i < d->order; ++i) {
+    if (d->dims[i] < 1) HT_FAIL(HT_ERR_INVALID_ARG, "dims must be >= 1");
+    t.dims[i] = d->dims[i];
+    if (i >= 2) P *= d->dims[i];
+  }
+  t.n1 = d->dims[0];
+  t.n2 = d->dims[1];
+  t.P = P;
+  if (t.n1 * t.n2 > (int64_t)INT32_MAX || P > (int64_t)INT32_MAX / 4)
+    HT_FAIL(HT_ERR_UNSUPPORTED, "face slice above 2^31 elements or too many slices");
+  t.N = t.n1 * t.n2 * P;
+  t.r = d->r;
+  t.p = d->p;
+  t.l = (int)std::min<int64_t>(std::min<int64_t>((int64_t)d->r + d->p, t.n1), t.n2);
+  t.k = std::min(d->r, t.l);
+  if (t.l > HT_MAX_WIDTH) HT_FAIL(HT_ERR_UNSUPPORTED, "sketch width min(r+p, n1, n2) above HT_MAX_WIDTH");
+  t.fwd.nmodes = t.inv.nmodes = d->order - 2;
+  int stride = 1;
+  for (int m = 0; m < d->order - 2; ++m) {
+    const int n = (int)d->dims[m + 2];
+    const int kind = d->transform[m + 2];
+    if (n > HT_MAX_MODE) HT_FAIL(HT_ERR_UNSUPPORTED, "transformed mode longer than HT_MAX_MODE");
+    std::vector<double> U;
+    double alpha = 1.0;
+    if (kind == HT_DCT2_ORTHO) {
+      dct2_ortho(n, U);
+    } else if (kind == HT_CUSTOM_REAL) {
+      if (!d->custom[m + 2]) HT_FAIL(HT_ERR_INVALID_ARG, "CUSTOM_REAL transform needs a matrix");
+      U.assign(d->custom[m + 2], d->custom[m + 2] + (size_t)n * n);
+      double tr = 0.0;
+      for (size_t i = 0; i < U.size(); ++i) tr += U[i] * U[i];
+      alpha = tr / n;
+      double err = 0.0;
+      for (int a = 0; a < n; ++a)
+        for (int b = 0; b < n; ++b) {
+          double sdot = 0.0;
+          for (int c = 0; c < n; ++c) sdot += U[(size_t)a * n + c] * U[(size_t)b * n + c];
+          err = std::max(err, std::fabs(sdot - (a == b ? alpha : 0.0)));
+        }
+      if (!(alpha > 0.0) || err > 1e-10 * alpha)
+        HT_FAIL(HT_ERR_INVALID_ARG, "CUSTOM_REAL matrix must satisfy U U^T = alpha I");
+    } else if (kind == HT_DFT_UNITARY) {
+      HT_FAIL(HT_ERR_UNSUPPORTED, "DFT_UNITARY transforms are not implemented in this build");
+    } else {
+      HT_FAIL(HT_ERR_INVALID_ARG, "unknown transform kind");
+    }
+    t.fwd.n[m] = t.inv.n[m] = n;
+    t.fwd.stride[m] = t.inv.stride[m] = stride;
+    stride *= n;
+    t.fwd.off[m] = (int)tab.size();
+    tab.insert(tab.end(), U.begin(), U.end());
+    t.inv.off[m] = (int)tab.size();
+    for (int a = 0; a < n; ++a)
+      for (int b = 0; b < n; ++b) tab.push_back(U[(size_t)b * n + a] / alpha);
+  }
+  // the inverse applies mode d first, then d-1, ..., 3 (the mode products
+  // commute, so the order does not change the result)
+  ModeTable rev = t.inv;
+  const int nm = t.inv.nmodes;
+  for (int m = 0; m < nm; ++m) {
+    rev.n[m] = t.inv.n[nm - 1 - m];
+    rev.stride[m] = t.inv.stride[nm - 1 - m];
+    rev.off[m] = t.inv.off[nm - 1 - m];
+  }
+  t.inv = rev;
+  return HT_OK;
+}
+
+// Order per-slice item groups so that all items of a group run on one XCD.
+// The dispatcher hands workgroups to the 8 XCDs round-robin in launch order,
+// so the items of XCD x go to positions x, x + 8, x + 16, ...; groups are
+// assigned largest first to the least-loaded XCD.  Tiles of one slice share
+// its thin operands, which then stay in that XCD's L2.
+std::vector<int2> xcd_grouped(const std::vector<std::vector<int2>>& groups, const std::vector<double>& cost) {
+  constexpr int NX = 8;
+  std::vector<int> order(groups.size());
+  std::iota(order.begin(), order.end(), 0);
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+    return cost[a] * groups[a].size() > cost[b] * groups[b].size();
+  });
+  std::vector<std::vector<int2>> q(NX);
+  std::vector<double> load(NX, 0.0);
+  for (int g : order) {
+    const int x = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+    q[x].insert(q[x].end(), groups[g].begin(), groups[g].end());
+    load[x] += cost[g] * groups[g].size();
+  }
+  std::vector<int2> out;
+  size_t longest = 0;
+  for (auto& v : q) longest = std::max(longest, v.size());
+  for (size_t i = 0; i < longest; ++i)
+    for (int x = 0; x < NX; ++x)
+      if (i < q[x].size()) out.push_back(q[x][i]);
+  return out;
+}
+
+// Tiles of `rows` rows over dimension n of every slice (n = n1 or n2).
+std::vector<int2> row_items(const ht_plan* pl, bool over_n2, int rows, bool cost_is_other_dim) {
+  std::vector<std::vector<int2>> groups(pl->Ptot);
+  std::vector<double> cost(pl->Ptot);
+  for (int64_t s = 0; s < pl->Ptot; ++s) {
+    const SliceDesc& d = pl->h_slices[s];
+    const int n = over_n2 ? d.n2 : d.n1;
+    for (int r0 = 0; r0 < n; r0 += rows) groups[s].push_back(make_int2((int)s, r0));
+    cost[s] = cost_is_other_dim ? (double)(over_n2 ? d.n1 : d.n2) : 1.0;
+  }
+  return xcd_grouped(groups, cost);
+}
+
+std::vector<int2> nt_items(const ht_plan* pl) {
+  std::vector<std::vector<int2>> groups(pl->Ptot);
+  std::vector<double> cost(pl->Ptot, 1.0);
+  for (int64_t s = 0; s < pl->Ptot; ++s) {
+    const SliceDesc& d = pl->h_slices[s];
+    const int nt = (int)(ceil_div(d.n1, 64) * ceil_div(d.n2, 64));
+    for (int t = 0; t < nt; ++t) groups[s].push_back(make_int2((int)s, t));
+  }
+  return xcd_grouped(groups, cost);
+}
+
+// Transform tiles of every tensor for an LDS budget; fills TP and the LDS size.
+int tf_items(ht_plan* pl, size_t budget, std::vector<int2>& items, std::vector<int>& tps, size_t& lds) {
   const size_t es = elem_bytes(pl->precision);
-  const size_t P = (size_t)pl->P, n1 = (size_t)pl->n1, n2 = (size_t)pl->n2, l = (size_t)pl->l;
-  pl->size[WS_A] = (size_t)pl->N * (pl->precision == HT_BF16_MIXED ? 2 : es);
-  pl->size[WS_OMEGA] = P * n2 * l * es;
-  pl->size[WS_Y] = P * n1 * l * es;
-  pl->size[WS_Z] = P * n2 * l * es;
-  pl->size[WS_K] = P * l * l * es;
-  pl->size[WS_QK] = P * n1 * l * es;
-  pl->size[WS_C] = (size_t)pl->N * es;
-  pl->size[WS_LNEW] = (size_t)pl->N * es;
-  pl->size[WS_XIN] = (size_t)pl->N * es;
+  items.clear();
+  tps.clear();
+  lds = 0;
+  for (size_t t = 0; t < pl->tens.size(); ++t) {
+    const TensorHost& th = pl->tens[t];
+    const int TP = transform_tile_width(th.P, es, budget);
+    if (TP == 0) HT_FAIL(HT_ERR_UNSUPPORTED, "too many face slices for the transform tile");
+    tps.push_back(TP);
+    lds = std::max(lds, (size_t)TP * th.P * es);
+    const int64_t NT = th.n1 * th.n2;
+    for (int64_t t0 = 0; t0 < NT; t0 += TP) items.push_back(make_int2((int)t, (int)t0));
+  }
+  return HT_OK;
+}
+
+int upload_tensors(ht_plan* pl, const std::vector<int>& tps) {
+  std::vector<TensorDesc> td(pl->tens.size());
+  for (size_t t = 0; t < pl->tens.size(); ++t) {
+    const TensorHost& th = pl->tens[t];
+    TensorDesc& d = td[t];
+    std::memset(&d, 0, sizeof(d));
+    d.x = th.x;
+    d.NT = th.n1 * th.n2;
+    d.P = (int32_t)th.P;
+    d.TP = tps[t];
+    int lg = 0;
+    while ((1 << lg) < d.TP) ++lg;
+    d.lgTP = lg;
+    d.slice0 = (int32_t)th.slice0;
+    d.fwd = th.fwd;
+    d.inv = th.inv;
+  }
+  HT_CHECK_HIP(hipMemcpy(pl->d_tens, td.data(), td.size() * sizeof(TensorDesc), hipMemcpyHostToDevice));
+  return HT_OK;
+}
+
+// (Re)build the transform tiling for an LDS budget and upload it.
+int set_transform_budget(ht_plan* pl, size_t budget) {
+  std::vector<int2> items;
+  std::vector<int> tps;
+  size_t lds = 0;
+  int rc = tf_items(pl, budget, items, tps, lds);
+  if (rc) return rc;
+  if ((int)items.size() > pl->tf_capacity) HT_FAIL(HT_ERR_UNSUPPORTED, "transform budget below the planned minimum");
+  if ((rc = upload_tensors(pl, tps))) return rc;
+  HT_CHECK_HIP(hipMemcpy(pl->d_items + pl->it_tf.off, items.data(), items.size() * sizeof(int2),
+                         hipMemcpyHostToDevice));
+  pl->it_tf.n = (int)items.size();
+  pl->tf_budget = budget;
+  pl->tf_lds = lds;
+  if (pl->graph) pl->graph->reset();
+  return HT_OK;
+}
+
+constexpr size_t kTfBudgets[] = {32 * 1024, 64 * 1024, 128 * 1024};
+
+void layout(ht_plan* pl, int64_t nY, int64_t nZ, int64_t nK, int64_t nG1, int64_t nG2) {
+  const size_t es = elem_bytes(pl->precision);
+  pl->size[WS_A] = (size_t)pl->Ntot * (pl->precision == HT_BF16_MIXED ? 2 : es);
+  pl->size[WS_OMEGA] = (size_t)nZ * es;
+  pl->size[WS_Y] = (size_t)nY * es;
+  pl->size[WS_Z] = (size_t)nZ * es;
+  pl->size[WS_K] = (size_t)nK * es;
+  pl->size[WS_QK] = (size_t)nY * es;
+  pl->size[WS_C] = (size_t)pl->Ntot * es;
+  pl->size[WS_GP1] = (size_t)nG1 * sizeof(double);
+  pl->size[WS_GP2] = (size_t)nG2 * sizeof(double);
+  pl->size[WS_WK] = (size_t)pl->Ptot * sizeof(int2);
+  pl->size[WS_CALL] = 256;
+  pl->size[WS_LNEW] = (size_t)pl->Ntot * es;
+  pl->size[WS_XIN] = (size_t)pl->Ntot * es;
   pl->size[WS_STATE] = sizeof(AdmmState);
-  const size_t t1 = (size_t)ceil_div(pl->n1, 64), t2 = (size_t)ceil_div(pl->n2, 64);  // >= 128-row counts
-  pl->size[WS_GP1] = P * std::max(t1, t2) * l * l * sizeof(double);
-  pl->size[WS_GP2] = P * t1 * l * l * sizeof(double);
   // t-SVT regions first, then the solver-only regions
-  const int order_[] = {WS_A, WS_OMEGA, WS_Y, WS_Z, WS_K, WS_QK, WS_C, WS_GP1, WS_GP2, WS_LNEW, WS_XIN, WS_STATE};
+  const int order_[] = {WS_A,   WS_OMEGA, WS_Y,   WS_Z,    WS_K,    WS_QK,   WS_C,
+                        WS_GP1, WS_GP2,   WS_WK,  WS_CALL, WS_LNEW, WS_XIN,  WS_STATE};
   size_t o = 0;
   for (int r : order_) {
     pl->off[r] = o;
     o += align256(pl->size[r]);
-    if (r == WS_GP2) pl->tsvt_bytes = o;
+    if (r == WS_CALL) pl->tsvt_bytes = o;
   }
   pl->admm_bytes = o;
+}
+
+// Build a plan from tensor descriptions (one for ht_plan_create).
+int build_plan(const ht_plan_desc* descs, int n, bool batch, ht_plan** out) {
+  *out = nullptr;
+  if (n < 1) HT_FAIL(HT_ERR_INVALID_ARG, "need at least one tensor");
+  const ht_plan_desc& d0 = descs[0];
+  if (d0.precision != HT_FP64 && d0.precision != HT_FP32 && d0.precision != HT_BF16_MIXED)
+    HT_FAIL(HT_ERR_INVALID_ARG, "unknown precision");
+  for (int t = 1; t < n; ++t)
+    if (descs[t].precision != d0.precision || descs[t].q != d0.q || descs[t].seed != d0.seed ||
+        descs[t].stream_id != d0.stream_id)
+      HT_FAIL(HT_ERR_INVALID_ARG, "precision, q, seed and stream_id must agree across a batch");
+  ht_plan* pl = new ht_plan();
+  pl->batch = batch;
+  pl->precision = d0.precision;
+  pl->q = d0.q;
+  pl->seed = d0.seed;
+  pl->stream_id = d0.stream_id;
+  if (hipGetDevice(&pl->device) != hipSuccess) pl->device = 0;
+  std::vector<double> tab;
+  pl->tens.resize(n);
+  int64_t x = 0, P = 0;
+  pl->lmax = 0;
+  pl->kmax = 0;
+  pl->max_n2l = 0;
+  for (int t = 0; t < n; ++t) {
+    int rc = add_tensor(&descs[t], tab, pl->tens[t]);
+    if (rc) {
+      free_plan(pl);
+      return rc;
+    }
+    TensorHost& th = pl->tens[t];
+    th.x = x;
+    th.slice0 = P;
+    x += batch ? (th.N + 63) / 64 * 64 : th.N;  // 256-byte aligned tensors in a packed batch
+    P += th.P;
+    pl->lmax = std::max(pl->lmax, th.l);
+    pl->kmax = std::max(pl->kmax, th.k);
+    pl->max_n2l = std::max<int64_t>(pl->max_n2l, th.n2 * th.l);
+  }
+  if (P > (int64_t)INT32_MAX / 64) {
+    free_plan(pl);
+    HT_FAIL(HT_ERR_UNSUPPORTED, "too many face slices in one plan");
+  }
+  pl->Ntot = x;
+  pl->Ptot = P;
+
+  // slice table
+  pl->h_slices.resize(P);
+  int64_t oY = 0, oZ = 0, oK = 0, oG1 = 0, oG2 = 0;
+  for (int t = 0; t < n; ++t) {
+    const TensorHost& th = pl->tens[t];
+    const int64_t NT = th.n1 * th.n2, l = th.l;
+    for (int64_t j = 0; j < th.P; ++j) {
+      SliceDesc& d = pl->h_slices[th.slice0 + j];
+      d.a = th.x + j * NT;
+      d.y = oY;
+      d.z = oZ;
+      d.kq = oK;
+      d.g1 = oG1;
+      d.g2 = oG2;
+      d.n1 = (int32_t)th.n1;
+      d.n2 = (int32_t)th.n2;
+      d.l = th.l;
+      d.k = th.k;
+      d.tensor = t;
+      d.local = (int32_t)j;
+      oY += align4(th.n1 * l);
+      oZ += align4(th.n2 * l);
+      oK += align4(l * l);
+      oG1 += ceil_div(std::max(th.n1, th.n2), 64) * l * l;
+      oG2 += ceil_div(th.n1, 64) * l * l;
+    }
+  }
+  layout(pl, oY, oZ, oK, oG1, oG2);
+
+  // item lists (the transform list is sized for the smallest LDS budget)
+  std::vector<std::vector<int2>> lists;
+  lists.push_back(row_items(pl, false, 64, true));   // nn, 64 rows
+  lists.push_back(row_items(pl, true, 64, true));    // tn, 64 rows
+  lists.push_back(row_items(pl, false, 128, true));  // nn, 128 rows
+  lists.push_back(row_items(pl, true, 128, true));   // tn, 128 rows
+  lists.push_back(row_items(pl, false, 64, false));  // orth Y
+  lists.push_back(row_items(pl, true, 64, false));   // orth Z
+  lists.push_back(row_items(pl, false, 64, false));  // recon QK
+  lists.push_back(nt_items(pl));                     // recon C
+  // the smallest LDS budget that fits every tensor sets the item capacity
+  std::vector<int2> tfi;
+  std::vector<int> tps;
+  size_t lds = 0, bmin = 0;
+  int rc = HT_ERR_UNSUPPORTED;
+  for (size_t b : kTfBudgets) {
+    if ((rc = tf_items(pl, b, tfi, tps, lds)) == HT_OK) {
+      bmin = b;
+      break;
+    }
+  }
+  if (rc) {
+    free_plan(pl);
+    return rc;
+  }
+  pl->tf_capacity = (int)tfi.size();
+  ItemList* dst[] = {&pl->it_nn[0], &pl->it_tn[0], &pl->it_nn[1], &pl->it_tn[1], &pl->it_oy, &pl->it_oz,
+                     &pl->it_qk, &pl->it_nt};
+  std::vector<int2> all;
+  for (size_t i = 0; i < lists.size(); ++i) {
+    dst[i]->off = (int64_t)all.size();
+    dst[i]->n = (int)lists[i].size();
+    all.insert(all.end(), lists[i].begin(), lists[i].end());
+  }
+  pl->it_tf.off = (int64_t)all.size();
+  pl->it_tf.n = 0;
+  all.resize(all.size() + pl->tf_capacity);
+
+  // device tables
+  bool ok = hipMalloc(&pl->d_tens, n * sizeof(TensorDesc)) == hipSuccess &&
+            hipMalloc(&pl->d_slices, P * sizeof(SliceDesc)) == hipSuccess &&
+            hipMalloc(&pl->d_items, all.size() * sizeof(int2)) == hipSuccess;
+  if (ok && !tab.empty()) {
+    std::vector<float> tab32(tab.begin(), tab.end());
+    ok = hipMalloc(&pl->table64, tab.size() * sizeof(double)) == hipSuccess &&
+         hipMalloc(&pl->table32, tab32.size() * sizeof(float)) == hipSuccess &&
+         hipMemcpy(pl->table64, tab.data(), tab.size() * sizeof(double), hipMemcpyHostToDevice) == hipSuccess &&
+         hipMemcpy(pl->table32, tab32.data(), tab32.size() * sizeof(float), hipMemcpyHostToDevice) == hipSuccess;
+  }
+  if (!ok) {
+    free_plan(pl);
+    HT_FAIL(HT_ERR_ALLOC, "could not allocate or upload the plan tables");
+  }
+  if (hipMemcpy(pl->d_slices, pl->h_slices.data(), P * sizeof(SliceDesc), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(pl->d_items, all.data(), all.size() * sizeof(int2), hipMemcpyHostToDevice) != hipSuccess) {
+    free_plan(pl);
+    HT_FAIL(HT_ERR_HIP, "could not upload the plan tables");
+  }
+  pl->prod_rows = pl->precision == HT_FP64 ? 64 : 128;
+  if ((rc = set_transform_budget(pl, std::max<size_t>(bmin, 64 * 1024)))) {
+    free_plan(pl);
+    return rc;
+  }
+  *out = pl;
+  return HT_OK;
 }
 
 template <typename T>
@@ -151,12 +576,11 @@ const float* table<float>(const ht_plan* pl) {
   return pl->table32;
 }
 
-int check_ws(const ht_plan* pl, const void* ws, size_t bytes, size_t need) {
+int check_ws(const void* ws, size_t bytes, size_t need) {
   if (!ws) HT_FAIL(HT_ERR_INVALID_ARG, "workspace is NULL");
   if (reinterpret_cast<uintptr_t>(ws) % 256 != 0) HT_FAIL(HT_ERR_WORKSPACE, "workspace must be 256-byte aligned");
   if (bytes < need)
     HT_FAIL(HT_ERR_WORKSPACE, "workspace too small: " + std::to_string(bytes) + " < " + std::to_string(need));
-  (void)pl;
   return HT_OK;
 }
 
@@ -175,13 +599,19 @@ int timed(const ht_plan* pl, int stage, hipStream_t s, F&& launch) {
   return rc;
 }
 
-// The randomized t-SVT on one plan; tau from the host, or 1/(*mu_dev) when
-// mu_dev is given; sketch key from call or *call_dev.
+const int2* items(const ht_plan* pl, const ItemList& L) { return pl->d_items + L.off; }
+
+// The randomized t-SVT over every slice of the plan.  tau: 1/(*mu_dev) when
+// mu_dev is set (solver), else tau_dev[tensor] when tau_dev is set (batch),
+// else the scalar.  The sketch call index is *call_dev when set, else call.
 template <typename T>
-int run_tsvt(const ht_plan* pl, const T* X, T* out, double tau, const double* mu_dev, const Penalty& pen,
-             uint32_t call, const int32_t* call_dev, void* ws, hipStream_t s, double* sigma_out, int* kept_out) {
-  const int64_t n1 = pl->n1, n2 = pl->n2, P = pl->P, NT = n1 * n2;
-  const int l = pl->l;
+int run_tsvt(const ht_plan* pl, const T* X, T* out, double tau, const double* tau_dev, const double* mu_dev,
+             const Penalty& pen, uint32_t call, const int32_t* call_dev, void* ws, hipStream_t s, double* sigma_out,
+             int* kept_out) {
+  const int lmax = pl->lmax;
+  const int P = (int)pl->Ptot;
+  const SliceDesc* sd = pl->d_slices;
+  const int2* wk = nullptr;
   T* A = ws_ptr<T>(pl, ws, WS_A);
   T* Om = ws_ptr<T>(pl, ws, WS_OMEGA);
   T* Y = ws_ptr<T>(pl, ws, WS_Y);
@@ -189,83 +619,138 @@ int run_tsvt(const ht_plan* pl, const T* X, T* out, double tau, const double* mu
   T* K = ws_ptr<T>(pl, ws, WS_K);
   T* QK = ws_ptr<T>(pl, ws, WS_QK);
   T* C = ws_ptr<T>(pl, ws, WS_C);
-  const int64_t sA = NT, sY = n1 * l, sZ = n2 * l;
+  double* gp1 = ws_ptr<double>(pl, ws, WS_GP1);
+  double* gp2 = ws_ptr<double>(pl, ws, WS_GP2);
   const bool bf16 = pl->precision == HT_BF16_MIXED;
+  const bool fp64 = pl->precision == HT_FP64;
   const uint16_t* Ah = reinterpret_cast<const uint16_t*>(A);  // BF16 view of the transformed tensor
+  const int rows = fp64 ? 64 : pl->prod_rows;
+  const int ri = rows == 128 ? 1 : 0;
   int rc;
   if ((rc = timed(pl, ST_TRANSFORM_FWD, s, [&] {
          if (bf16)
-           return launch_transform_bf16((const float*)X, (uint16_t*)A, NT, (int)P, pl->mt_fwd, pl->table32, s);
-         return launch_transform<T>(X, A, NT, (int)P, pl->mt_fwd, table<T>(pl), s);
+           return launch_transform<float, uint16_t>((const float*)X, (uint16_t*)A, pl->d_tens, items(pl, pl->it_tf),
+                                                    pl->it_tf.n, pl->tf_lds, pl->table32, 0, s);
+         return launch_transform<T, T>(X, A, pl->d_tens, items(pl, pl->it_tf), pl->it_tf.n, pl->tf_lds, table<T>(pl),
+                                       0, s);
        })))
     return rc;
   if ((rc = timed(pl, ST_OMEGA, s, [&] {
-         return launch_omega<T>(Om, nullptr, (int)P, n2 * l, call, call_dev, pl->stream_id, pl->seed, nullptr, s);
+         return launch_omega<T>(Om, nullptr, sd, wk, P, pl->max_n2l, call, call_dev, pl->stream_id, pl->seed, 0, s);
        })))
     return rc;
-  double* gp1 = ws_ptr<double>(pl, ws, WS_GP1);
-  double* gp2 = ws_ptr<double>(pl, ws, WS_GP2);
-  const int t1 = (int)ceil_div(n1, 64);
-  // FP32 slices with 16-byte aligned columns run the products on the matrix cores
-  const bool mfma = pl->mfma;
-  const int rt = (mfma || bf16) ? mfma_tile_rows() : 64;
-  const int p1 = (int)ceil_div(n1, rt), p2 = (int)ceil_div(n2, rt);
   auto sketch_nn = [&](const T* W) {
     return timed(pl, ST_SKETCH_NN, s, [&] {
+      const ItemList& L = pl->it_nn[ri];
       if (bf16)
-        return launch_bf16_nn(Ah, sA, (int)n1, (const float*)W, sZ, (int)n2, (float*)Y, sY, (int)n1, (int)n1,
-                              (int)n2, l, (int)P, gp1, s);
-      if (mfma)
-        return launch_mfma_nn((const float*)A, sA, (int)n1, (const float*)W, sZ, (int)n2, (float*)Y, sY, (int)n1,
-                              (int)n1, (int)n2, l, (int)P, gp1, s);
-      return launch_gemm_nn<T>(A, sA, (int)n1, W, sZ, (int)n2, Y, sY, (int)n1, (int)n1, (int)n2, l, (int)P, gp1, s);
+        return launch_bf16_nn(Ah, (const float*)W, (float*)Y, sd, wk, items(pl, L), L.n, lmax, rows, gp1, s);
+      if (!fp64)
+        return launch_mfma_nn((const float*)A, (const float*)W, (float*)Y, sd, wk, items(pl, L), L.n, lmax, rows, gp1,
+                              s);
+      return launch_gemm_nn<T>(A, W, Y, sd, wk, items(pl, L), L.n, lmax, gp1, s);
     });
   };
   auto sketch_tn = [&]() {
     return timed(pl, ST_SKETCH_TN, s, [&] {
-      if (bf16)
-        return launch_bf16_tn(Ah, sA, (int)n1, (const float*)Y, sY, (int)n1, (float*)Z, sZ, (int)n2, (int)n1,
-                              (int)n2, l, (int)P, gp1, s);
-      if (mfma)
-        return launch_mfma_tn((const float*)A, sA, (int)n1, (const float*)Y, sY, (int)n1, (float*)Z, sZ, (int)n2,
-                              (int)n1, (int)n2, l, (int)P, gp1, s);
-      return launch_gemm_tn<T>(A, sA, (int)n1, Y, sY, (int)n1, Z, sZ, (int)n2, (int)n1, (int)n2, l, (int)P, gp1, s);
+      const ItemList& L = pl->it_tn[ri];
+      if (bf16) return launch_bf16_tn(Ah, (const float*)Y, (float*)Z, sd, wk, items(pl, L), L.n, lmax, rows, gp1, s);
+      if (!fp64)
+        return launch_mfma_tn((const float*)A, (const float*)Y, (float*)Z, sd, wk, items(pl, L), L.n, lmax, rows, gp1,
+                              s);
+      return launch_gemm_tn<T>(A, Y, Z, sd, wk, items(pl, L), L.n, lmax, gp1, s);
     });
   };
-  auto orth = [&](T* M, int64_t sM, int m, int nparts, double* gout) {
-    return timed(pl, ST_CHOLQR, s,
-                 [&] { return launch_orth_apply<T>(M, sM, m, m, l, (int)P, gp1, nparts, gout, s); });
+  auto orth = [&](int which, double* gout) {
+    return timed(pl, ST_CHOLQR, s, [&] {
+      const ItemList& L = which ? pl->it_oz : pl->it_oy;
+      return launch_orth_apply<T>(which ? Z : Y, which, sd, wk, items(pl, L), L.n, lmax, gp1, rows, gout, s);
+    });
   };
   // Y = A Omega, Q1 = orth(Y); q power steps Z = orth(A^T Q1), Q1 = orth(A Z);
   // the last orthonormalization also writes the Gram partials of Q1.
   if ((rc = sketch_nn(Om))) return rc;
-  if ((rc = orth(Y, sY, (int)n1, p1, pl->q == 0 ? gp2 : nullptr))) return rc;
+  if ((rc = orth(0, pl->q == 0 ? gp2 : nullptr))) return rc;
   for (int it = 0; it < pl->q; ++it) {
     if ((rc = sketch_tn())) return rc;
-    if ((rc = orth(Z, sZ, (int)n2, p2, nullptr))) return rc;
+    if ((rc = orth(1, nullptr))) return rc;
     if ((rc = sketch_nn(Z))) return rc;
-    if ((rc = orth(Y, sY, (int)n1, p1, it == pl->q - 1 ? gp2 : nullptr))) return rc;
+    if ((rc = orth(0, it == pl->q - 1 ? gp2 : nullptr))) return rc;
   }
   // Bt = A^T Q1 with the Gram partials of Bt
   if ((rc = sketch_tn())) return rc;
   // second CholeskyQR step in the small space, small SVD, shrink -> K'
   if ((rc = timed(pl, ST_SMALLSVD, s, [&] {
-         return launch_smallsvd<T>(gp2, t1, (int)n1, gp1, p2, l, pl->k, (int)P, tau, mu_dev, pen, K, sigma_out,
-                                   kept_out, s);
+         return launch_smallsvd<T>(gp2, gp1, sd, wk, P, lmax, rows, tau, tau_dev, mu_dev, pen, K, sigma_out, kept_out,
+                                   s);
        })))
     return rc;
   // C = (Q1 K') Bt^T, then the inverse transform
   if ((rc = timed(pl, ST_RECON_QK, s, [&] {
-         return launch_gemm_nn<T>(Y, sY, (int)n1, K, (int64_t)l * l, l, QK, sY, (int)n1, (int)n1, l, l, (int)P,
-                                  nullptr, s);
+         return launch_recon_qk<T>(Y, K, QK, sd, wk, items(pl, pl->it_qk), pl->it_qk.n, lmax, s);
        })))
     return rc;
   if ((rc = timed(pl, ST_RECON_NT, s, [&] {
-         return launch_gemm_nt<T>(QK, sY, (int)n1, Z, sZ, (int)n2, C, sA, (int)n1, (int)n1, (int)n2, l, (int)P, s);
+         return launch_gemm_nt<T>(QK, Z, C, sd, wk, items(pl, pl->it_nt), pl->it_nt.n, s);
        })))
     return rc;
-  return timed(pl, ST_TRANSFORM_INV, s,
-               [&] { return launch_transform<T>(C, out, NT, (int)P, pl->mt_inv, table<T>(pl), s); });
+  return timed(pl, ST_TRANSFORM_INV, s, [&] {
+    return launch_transform<T, T>(C, out, pl->d_tens, items(pl, pl->it_tf), pl->it_tf.n, pl->tf_lds, table<T>(pl), 1,
+                                  s);
+  });
+}
+
+// Eager launch, or (graph mode) replay of a recorded graph of the same
+// launches whose first node writes the call index into the workspace.
+int run_tsvt_any(ht_plan* pl, const void* X, void* out, double tau, const double* tau_dev, const ht_penalty* penalty,
+                 uint32_t call, void* ws, hipStream_t s, double* sigma_out, int* kept_out) {
+  const Penalty pen = to_dev(penalty);
+  auto enqueue = [&](const int32_t* call_dev) -> int {
+    if (pl->precision == HT_FP64)
+      return run_tsvt<double>(pl, static_cast<const double*>(X), static_cast<double*>(out), tau, tau_dev, nullptr,
+                              pen, call, call_dev, ws, s, sigma_out, kept_out);
+    return run_tsvt<float>(pl, static_cast<const float*>(X), static_cast<float*>(out), tau, tau_dev, nullptr, pen,
+                           call, call_dev, ws, s, sigma_out, kept_out);
+  };
+  if (!pl->graph_on || (pl->prof && pl->prof->on)) return enqueue(nullptr);
+  if (s == nullptr) HT_FAIL(HT_ERR_INVALID_ARG, "graph replay needs a created stream (the null stream cannot be captured)");
+  int32_t* slot = ws_ptr<int32_t>(pl, ws, WS_CALL);
+  GraphCache& g = *pl->graph;
+  const GraphKey key{X, out, ws, tau_dev, tau, penalty->kind, penalty->p0, penalty->p1, sigma_out, kept_out, s};
+  int32_t callv = (int32_t)call;
+  void* args[] = {&slot, &callv};
+  hipKernelNodeParams np{};
+  np.func = reinterpret_cast<void*>(k_set_call);
+  np.gridDim = dim3(1);
+  np.blockDim = dim3(64);
+  np.sharedMemBytes = 0;
+  np.kernelParams = args;
+  np.extra = nullptr;
+  if (!g.valid || !(g.key == key)) {
+    g.reset();
+    HT_CHECK_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed));
+    const int rc = enqueue(slot);
+    hipGraph_t graph = nullptr;
+    const hipError_t e = hipStreamEndCapture(s, &graph);
+    if (rc || e != hipSuccess) {
+      if (graph) (void)hipGraphDestroy(graph);
+      if (rc) return rc;
+      HT_CHECK_HIP(e);
+    }
+    g.graph = graph;
+    size_t nroots = 0;
+    HT_CHECK_HIP(hipGraphGetRootNodes(graph, nullptr, &nroots));
+    std::vector<hipGraphNode_t> roots(nroots);
+    if (nroots) HT_CHECK_HIP(hipGraphGetRootNodes(graph, roots.data(), &nroots));
+    HT_CHECK_HIP(hipGraphAddKernelNode(&g.call_node, graph, nullptr, 0, &np));
+    for (auto& r : roots) HT_CHECK_HIP(hipGraphAddDependencies(graph, &g.call_node, &r, 1));
+    HT_CHECK_HIP(hipGraphInstantiate(&g.exec, graph, nullptr, nullptr, 0));
+    g.key = key;
+    g.valid = true;
+  } else {
+    HT_CHECK_HIP(hipGraphExecKernelNodeSetParams(g.exec, g.call_node, &np));
+  }
+  HT_CHECK_HIP(hipGraphLaunch(g.exec, s));
+  return HT_OK;
 }
 
 template <typename T>
@@ -278,11 +763,12 @@ int run_admm(const ht_plan* pl, const ht_admm_params* prm, const T* M, const uin
   const Penalty psi = to_dev(&prm->psi);
   int rc;
   if (n_iter <= 0) return HT_OK;
-  if ((rc = launch_admm_input<T>(M, E, Yv, st, Xin, pl->N, s))) return rc;
+  if ((rc = launch_admm_input<T>(M, E, Yv, st, Xin, pl->Ntot, s))) return rc;
   for (int it = 0; it < n_iter; ++it) {
-    if ((rc = run_tsvt<T>(pl, Xin, Lnew, 0.0, &st->mu, phi, 0, &st->iteration, ws, s, nullptr, nullptr))) return rc;
+    if ((rc = run_tsvt<T>(pl, Xin, Lnew, 0.0, nullptr, &st->mu, phi, 0, &st->iteration, ws, s, nullptr, nullptr)))
+      return rc;
     if ((rc = timed(pl, ST_ADMM_UPDATE, s, [&] {
-           return launch_admm_update<T>(M, mask, Lnew, L, E, Yv, Xin, st, pl->N, prm->model, psi, prm->lambda,
+           return launch_admm_update<T>(M, mask, Lnew, L, E, Yv, Xin, st, pl->Ntot, prm->model, psi, prm->lambda,
                                         prm->vartheta, prm->mu_max, s);
          })))
       return rc;
@@ -310,155 +796,42 @@ int check_admm_params(const ht_admm_params* prm) {
 
 extern "C" {
 
-int ht_version(void) { return 100; }
+int ht_version(void) { return 200; }
 
 const char* ht_last_error(void) { return g_last_error.c_str(); }
 
 int ht_plan_create(const ht_plan_desc* d, ht_plan** out) {
   if (!d || !out) HT_FAIL(HT_ERR_INVALID_ARG, "desc/out is NULL");
-  *out = nullptr;
-  if (d->order < 2 || d->order > HT_MAX_ORDER) HT_FAIL(HT_ERR_INVALID_ARG, "order must be in [2, 8]");
-  if (d->precision != HT_FP64 && d->precision != HT_FP32 && d->precision != HT_BF16_MIXED)
-    HT_FAIL(HT_ERR_INVALID_ARG, "unknown precision");
-  if (d->r < 1 || d->p < 0 || d->q < 0) HT_FAIL(HT_ERR_INVALID_ARG, "need r >= 1, p >= 0, q >= 0");
-  ht_plan* pl = new ht_plan();
-  std::memset(pl, 0, sizeof(ht_plan));
-  pl->order = d->order;
-  int64_t P = 1;
-  for (int i = 0; i < d->order; ++i) {
-    if (d->dims[i] < 1) {
-      delete pl;
-      HT_FAIL(HT_ERR_INVALID_ARG, "dims must be >= 1");
-    }
-    pl->dims[i] = d->dims[i];
-    if (i >= 2) P *= d->dims[i];
-  }
-  pl->n1 = d->dims[0];
-  pl->n2 = d->dims[1];
-  pl->P = P;
-  pl->N = pl->n1 * pl->n2 * P;
-  if (pl->n1 > (1 << 30) || pl->n2 > (1 << 30) || P > 65535) {
-    delete pl;
-    HT_FAIL(HT_ERR_UNSUPPORTED, "slice count above 65535 or a spatial mode above 2^30");
-  }
-  pl->r = d->r;
-  pl->p = d->p;
-  pl->q = d->q;
-  pl->l = (int)std::min<int64_t>(std::min<int64_t>(d->r + d->p, pl->n1), pl->n2);
-  pl->k = std::min(d->r, pl->l);
-  if (pl->l > HT_MAX_WIDTH) {
-    delete pl;
-    HT_FAIL(HT_ERR_UNSUPPORTED, "sketch width min(r+p, n1, n2) above HT_MAX_WIDTH");
-  }
-  pl->precision = d->precision;
-  pl->seed = d->seed;
-  pl->stream_id = d->stream_id;
-  if (hipGetDevice(&pl->device) != hipSuccess) pl->device = 0;
+  return build_plan(d, 1, false, out);
+}
 
-  // transform tables: forward U_k and inverse U_k^T / alpha_k, row-major
-  std::vector<double> tab;
-  pl->mt_fwd.nmodes = pl->mt_inv.nmodes = d->order - 2;
-  int stride = 1;
-  for (int m = 0; m < d->order - 2; ++m) {
-    const int n = (int)d->dims[m + 2];
-    const int kind = d->transform[m + 2];
-    pl->kinds[m + 2] = kind;
-    if (n > HT_MAX_MODE) {
-      delete pl;
-      HT_FAIL(HT_ERR_UNSUPPORTED, "transformed mode longer than HT_MAX_MODE");
-    }
-    std::vector<double> U;
-    double alpha = 1.0;
-    if (kind == HT_DCT2_ORTHO) {
-      dct2_ortho(n, U);
-    } else if (kind == HT_CUSTOM_REAL) {
-      if (!d->custom[m + 2]) {
-        delete pl;
-        HT_FAIL(HT_ERR_INVALID_ARG, "CUSTOM_REAL transform needs a matrix");
-      }
-      U.assign(d->custom[m + 2], d->custom[m + 2] + (size_t)n * n);
-      double tr = 0.0;
-      for (size_t i = 0; i < U.size(); ++i) tr += U[i] * U[i];
-      alpha = tr / n;
-      double err = 0.0;
-      for (int a = 0; a < n; ++a)
-        for (int b = 0; b < n; ++b) {
-          double sdot = 0.0;
-          for (int c = 0; c < n; ++c) sdot += U[(size_t)a * n + c] * U[(size_t)b * n + c];
-          err = std::max(err, std::fabs(sdot - (a == b ? alpha : 0.0)));
-        }
-      if (!(alpha > 0.0) || err > 1e-10 * alpha) {
-        delete pl;
-        HT_FAIL(HT_ERR_INVALID_ARG, "CUSTOM_REAL matrix must satisfy U U^T = alpha I");
-      }
-    } else if (kind == HT_DFT_UNITARY) {
-      delete pl;
-      HT_FAIL(HT_ERR_UNSUPPORTED, "DFT_UNITARY transforms are not implemented in this build");
-    } else {
-      delete pl;
-      HT_FAIL(HT_ERR_INVALID_ARG, "unknown transform kind");
-    }
-    pl->mt_fwd.n[m] = pl->mt_inv.n[m] = n;
-    pl->mt_fwd.stride[m] = pl->mt_inv.stride[m] = stride;
-    stride *= n;
-    pl->mt_fwd.off[m] = (int)tab.size();
-    tab.insert(tab.end(), U.begin(), U.end());
-    pl->mt_inv.off[m] = (int)tab.size();
-    for (int a = 0; a < n; ++a)
-      for (int b = 0; b < n; ++b) tab.push_back(U[(size_t)b * n + a] / alpha);
-  }
-  // the inverse applies mode d first, then d-1, ..., 3 (order does not change
-  // the result since the mode products commute; kept as in the definition)
-  {
-    ModeTable rev = pl->mt_inv;
-    const int nm = pl->mt_inv.nmodes;
-    for (int m = 0; m < nm; ++m) {
-      rev.n[m] = pl->mt_inv.n[nm - 1 - m];
-      rev.stride[m] = pl->mt_inv.stride[nm - 1 - m];
-      rev.off[m] = pl->mt_inv.off[nm - 1 - m];
-    }
-    pl->mt_inv = rev;
-  }
-  if (!tab.empty()) {
-    std::vector<float> tab32(tab.begin(), tab.end());
-    if (hipMalloc(&pl->table64, tab.size() * sizeof(double)) != hipSuccess ||
-        hipMalloc(&pl->table32, tab32.size() * sizeof(float)) != hipSuccess) {
-      (void)hipFree(pl->table64);
-      delete pl;
-      HT_FAIL(HT_ERR_ALLOC, "could not allocate transform tables");
-    }
-    if (hipMemcpy(pl->table64, tab.data(), tab.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess ||
-        hipMemcpy(pl->table32, tab32.data(), tab32.size() * sizeof(float), hipMemcpyHostToDevice) != hipSuccess) {
-      (void)hipFree(pl->table64);
-      (void)hipFree(pl->table32);
-      delete pl;
-      HT_FAIL(HT_ERR_HIP, "could not upload transform tables");
-    }
-  }
-  if (pl->mt_fwd.nmodes > 0 && transform_tile_width(P, elem_bytes(pl->precision)) == 0) {
-    (void)hipFree(pl->table64);
-    (void)hipFree(pl->table32);
-    delete pl;
-    HT_FAIL(HT_ERR_UNSUPPORTED, "too many face slices for the transform tile");
-  }
-  pl->mfma = pl->precision == HT_FP32 && pl->n1 % 4 == 0 && pl->n2 % 4 == 0;
-  layout(pl);
-  *out = pl;
-  return HT_OK;
+int ht_batch_plan_create(int n_tensors, const ht_plan_desc* descs, ht_plan** out) {
+  if (!descs || !out) HT_FAIL(HT_ERR_INVALID_ARG, "descs/out is NULL");
+  if (n_tensors < 1) HT_FAIL(HT_ERR_INVALID_ARG, "n_tensors must be >= 1");
+  return build_plan(descs, n_tensors, true, out);
 }
 
 int ht_plan_destroy(ht_plan* pl) {
-  if (!pl) return HT_OK;
-  if (pl->prof) {
-    for (auto& r : pl->prof->recs) {
-      (void)hipEventDestroy(r.a);
-      (void)hipEventDestroy(r.b);
-    }
-    delete pl->prof;
-  }
-  if (pl->table64) (void)hipFree(pl->table64);
-  if (pl->table32) (void)hipFree(pl->table32);
-  delete pl;
+  free_plan(pl);
+  return HT_OK;
+}
+
+int ht_batch_info(const ht_plan* pl, int64_t* packed_numel, int* n_tensors) {
+  if (!pl) HT_FAIL(HT_ERR_INVALID_ARG, "plan is NULL");
+  if (packed_numel) *packed_numel = pl->Ntot;
+  if (n_tensors) *n_tensors = (int)pl->tens.size();
+  return HT_OK;
+}
+
+int ht_batch_tensor_info(const ht_plan* pl, int t, int64_t* offset, int64_t* numel, int64_t* first_slice, int* width,
+                         int* kept) {
+  if (!pl || t < 0 || t >= (int)pl->tens.size()) HT_FAIL(HT_ERR_INVALID_ARG, "bad plan or tensor index");
+  const TensorHost& th = pl->tens[t];
+  if (offset) *offset = th.x;
+  if (numel) *numel = th.N;
+  if (first_slice) *first_slice = th.slice0;
+  if (width) *width = th.l;
+  if (kept) *kept = th.k;
   return HT_OK;
 }
 
@@ -503,9 +876,9 @@ int ht_plan_workspace_size(const ht_plan* pl, size_t* bytes) {
 
 int ht_plan_info(const ht_plan* pl, int64_t* n_slices, int* width, int* kept) {
   if (!pl) HT_FAIL(HT_ERR_INVALID_ARG, "plan is NULL");
-  if (n_slices) *n_slices = pl->P;
-  if (width) *width = pl->l;
-  if (kept) *kept = pl->k;
+  if (n_slices) *n_slices = pl->Ptot;
+  if (width) *width = pl->lmax;
+  if (kept) *kept = pl->kmax;
   return HT_OK;
 }
 
@@ -516,38 +889,146 @@ int ht_plan_workspace_region(const ht_plan* pl, int region, size_t* offset, size
   return HT_OK;
 }
 
+int ht_plan_set_tuning(ht_plan* pl, int prod_rows, int transform_lds_kib) {
+  if (!pl) HT_FAIL(HT_ERR_INVALID_ARG, "plan is NULL");
+  if (prod_rows != 0) {
+    if (prod_rows != 64 && prod_rows != 128) HT_FAIL(HT_ERR_INVALID_ARG, "prod_rows must be 64 or 128");
+    if (pl->precision == HT_FP64 && prod_rows != 64) HT_FAIL(HT_ERR_UNSUPPORTED, "FP64 products use 64-row tiles");
+    pl->prod_rows = prod_rows;
+    if (pl->graph) pl->graph->reset();
+  }
+  if (transform_lds_kib != 0) {
+    const size_t b = (size_t)transform_lds_kib * 1024;
+    bool known = false;
+    for (size_t kb : kTfBudgets) known |= kb == b;
+    if (!known) HT_FAIL(HT_ERR_INVALID_ARG, "transform LDS budget must be 32, 64 or 128 KiB");
+    return set_transform_budget(pl, b);
+  }
+  return HT_OK;
+}
+
+int ht_plan_get_tuning(const ht_plan* pl, int* prod_rows, int* transform_lds_kib) {
+  if (!pl) HT_FAIL(HT_ERR_INVALID_ARG, "plan is NULL");
+  if (prod_rows) *prod_rows = pl->precision == HT_FP64 ? 64 : pl->prod_rows;
+  if (transform_lds_kib) *transform_lds_kib = (int)(pl->tf_budget / 1024);
+  return HT_OK;
+}
+
+int ht_plan_autotune(ht_plan* pl, const void* X, void* out, void* ws, size_t ws_bytes, void* stream, int repeats,
+                     double* best_ms) {
+  if (!pl || !X || !out) HT_FAIL(HT_ERR_INVALID_ARG, "plan/X/out is NULL");
+  int rc;
+  if ((rc = check_ws(ws, ws_bytes, pl->tsvt_bytes))) return rc;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  repeats = std::max(1, repeats);
+  const ht_penalty pen{HT_PEN_L1, 0.0, 0.0};
+  std::vector<double> taus(pl->tens.size(), 0.0);
+  const bool prof_on = pl->prof && pl->prof->on;
+  if (pl->prof) pl->prof->on = false;
+  const bool graph_on = pl->graph_on;
+  pl->graph_on = false;
+  hipEvent_t e0, e1;
+  HT_CHECK_HIP(hipEventCreate(&e0));
+  HT_CHECK_HIP(hipEventCreate(&e1));
+  // time one configuration: a warm-up call, then `repeats` calls
+  auto measure = [&](double& ms) -> int {
+    int r = run_tsvt_any(pl, X, out, 0.0, nullptr, &pen, 0, ws, s, nullptr, nullptr);
+    if (r) return r;
+    HT_CHECK_HIP(hipEventRecord(e0, s));
+    for (int i = 0; i < repeats; ++i)
+      if ((r = run_tsvt_any(pl, X, out, 0.0, nullptr, &pen, (uint32_t)i, ws, s, nullptr, nullptr))) return r;
+    HT_CHECK_HIP(hipEventRecord(e1, s));
+    HT_CHECK_HIP(hipEventSynchronize(e1));
+    float f = 0.0f;
+    HT_CHECK_HIP(hipEventElapsedTime(&f, e0, e1));
+    ms = f / repeats;
+    return HT_OK;
+  };
+  double best = 1e300;
+  int best_rows = pl->prod_rows;
+  size_t best_budget = pl->tf_budget;
+  rc = HT_OK;
+  const int rows_c[] = {128, 64};
+  for (int rows : rows_c) {
+    if (pl->precision == HT_FP64 && rows != 64) continue;
+    pl->prod_rows = rows;
+    double ms = 0.0;
+    if ((rc = measure(ms))) break;
+    if (ms < best) {
+      best = ms;
+      best_rows = rows;
+    }
+  }
+  pl->prod_rows = best_rows;
+  if (rc == HT_OK) {
+    for (size_t b : kTfBudgets) {
+      if (set_transform_budget(pl, b) != HT_OK) continue;  // a budget too small for this plan
+      double ms = 0.0;
+      if ((rc = measure(ms))) break;
+      if (ms < best) {
+        best = ms;
+        best_budget = b;
+      }
+    }
+    const int rc2 = set_transform_budget(pl, best_budget);
+    if (rc == HT_OK) rc = rc2;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (pl->prof) pl->prof->on = prof_on;
+  pl->graph_on = graph_on;
+  if (pl->graph) pl->graph->reset();
+  if (best_ms) *best_ms = best;
+  return rc;
+}
+
+int ht_plan_graph_enable(ht_plan* pl, int on) {
+  if (!pl) HT_FAIL(HT_ERR_INVALID_ARG, "plan is NULL");
+  if (!pl->graph) pl->graph = new GraphCache();
+  pl->graph->reset();
+  pl->graph_on = on != 0;
+  return HT_OK;
+}
+
 int ht_gnhtsvt(ht_plan* pl, const void* X, void* out, double tau, const ht_penalty* penalty, uint32_t call_index,
                void* ws, size_t ws_bytes, void* stream, double* sigma_out, int* kept_out) {
   if (!pl || !X || !out) HT_FAIL(HT_ERR_INVALID_ARG, "plan/X/out is NULL");
+  if (pl->batch) HT_FAIL(HT_ERR_INVALID_ARG, "batch plans take ht_batch_gnhtsvt");
   if (!(tau >= 0.0) || !std::isfinite(tau)) HT_FAIL(HT_ERR_INVALID_ARG, "tau must be finite and >= 0");
   int rc;
   if ((rc = check_penalty(penalty))) return rc;
-  if ((rc = check_ws(pl, ws, ws_bytes, pl->tsvt_bytes))) return rc;
-  hipStream_t s = static_cast<hipStream_t>(stream);
-  const Penalty pen = to_dev(penalty);
-  if (pl->precision == HT_FP64)
-    return run_tsvt<double>(pl, static_cast<const double*>(X), static_cast<double*>(out), tau, nullptr, pen,
-                            call_index, nullptr, ws, s, sigma_out, kept_out);
-  return run_tsvt<float>(pl, static_cast<const float*>(X), static_cast<float*>(out), tau, nullptr, pen, call_index,
-                         nullptr, ws, s, sigma_out, kept_out);
+  if ((rc = check_ws(ws, ws_bytes, pl->tsvt_bytes))) return rc;
+  return run_tsvt_any(pl, X, out, tau, nullptr, penalty, call_index, ws, static_cast<hipStream_t>(stream), sigma_out,
+                      kept_out);
+}
+
+int ht_batch_gnhtsvt(ht_plan* pl, const void* X, void* out, const double* tau_dev, const ht_penalty* penalty,
+                     uint32_t call_index, void* ws, size_t ws_bytes, void* stream, double* sigma_out, int* kept_out) {
+  if (!pl || !X || !out || !tau_dev) HT_FAIL(HT_ERR_INVALID_ARG, "plan/X/out/tau is NULL");
+  int rc;
+  if ((rc = check_penalty(penalty))) return rc;
+  if ((rc = check_ws(ws, ws_bytes, pl->tsvt_bytes))) return rc;
+  return run_tsvt_any(pl, X, out, 0.0, tau_dev, penalty, call_index, ws, static_cast<hipStream_t>(stream), sigma_out,
+                      kept_out);
 }
 
 int ht_omega_fp64(const ht_plan* pl, uint32_t call_index, double* dev_out, void* stream) {
   if (!pl || !dev_out) HT_FAIL(HT_ERR_INVALID_ARG, "plan/out is NULL");
-  return launch_omega<double>(nullptr, dev_out, (int)pl->P, pl->n2 * pl->l, call_index, nullptr, pl->stream_id,
-                              pl->seed, nullptr, static_cast<hipStream_t>(stream));
+  if (pl->batch) HT_FAIL(HT_ERR_UNSUPPORTED, "ht_omega_fp64 takes a single-tensor plan");
+  const TensorHost& th = pl->tens[0];
+  return launch_omega<double>(nullptr, dev_out, pl->d_slices, nullptr, (int)pl->Ptot, pl->max_n2l, call_index, nullptr,
+                              pl->stream_id, pl->seed, th.n2 * th.l, static_cast<hipStream_t>(stream));
 }
 
 int ht_transform(const ht_plan* pl, const void* X, void* out, int inverse, void* stream) {
   if (!pl || !X || !out) HT_FAIL(HT_ERR_INVALID_ARG, "plan/X/out is NULL");
   hipStream_t s = static_cast<hipStream_t>(stream);
-  const ModeTable& mt = inverse ? pl->mt_inv : pl->mt_fwd;
-  const int64_t NT = pl->n1 * pl->n2;
+  const int inv = inverse ? 1 : 0;
   if (pl->precision == HT_FP64)
-    return launch_transform<double>(static_cast<const double*>(X), static_cast<double*>(out), NT, (int)pl->P, mt,
-                                    pl->table64, s);
-  return launch_transform<float>(static_cast<const float*>(X), static_cast<float*>(out), NT, (int)pl->P, mt,
-                                 pl->table32, s);
+    return launch_transform<double, double>(static_cast<const double*>(X), static_cast<double*>(out), pl->d_tens,
+                                            items(pl, pl->it_tf), pl->it_tf.n, pl->tf_lds, pl->table64, inv, s);
+  return launch_transform<float, float>(static_cast<const float*>(X), static_cast<float*>(out), pl->d_tens,
+                                        items(pl, pl->it_tf), pl->it_tf.n, pl->tf_lds, pl->table32, inv, s);
 }
 
 int ht_admm_workspace_size(const ht_plan* pl, size_t* bytes) {
@@ -559,11 +1040,12 @@ int ht_admm_workspace_size(const ht_plan* pl, size_t* bytes) {
 int ht_admm_init(ht_plan* pl, const ht_admm_params* prm, void* L, void* E, void* Y, void* ws, size_t ws_bytes,
                  void* stream) {
   if (!pl || !L || !E || !Y) HT_FAIL(HT_ERR_INVALID_ARG, "plan/L/E/Y is NULL");
+  if (pl->batch) HT_FAIL(HT_ERR_UNSUPPORTED, "the solver takes a single-tensor plan");
   int rc;
   if ((rc = check_admm_params(prm))) return rc;
-  if ((rc = check_ws(pl, ws, ws_bytes, pl->admm_bytes))) return rc;
+  if ((rc = check_ws(ws, ws_bytes, pl->admm_bytes))) return rc;
   hipStream_t s = static_cast<hipStream_t>(stream);
-  const size_t bytes = (size_t)pl->N * elem_bytes(pl->precision);
+  const size_t bytes = (size_t)pl->Ntot * elem_bytes(pl->precision);
   HT_CHECK_HIP(hipMemsetAsync(L, 0, bytes, s));
   HT_CHECK_HIP(hipMemsetAsync(E, 0, bytes, s));
   HT_CHECK_HIP(hipMemsetAsync(Y, 0, bytes, s));
@@ -573,10 +1055,11 @@ int ht_admm_init(ht_plan* pl, const ht_admm_params* prm, void* L, void* E, void*
 int ht_admm_iterate(ht_plan* pl, const ht_admm_params* prm, const void* M, const uint8_t* mask, void* L, void* E,
                     void* Y, int n_iter, void* ws, size_t ws_bytes, void* stream) {
   if (!pl || !M || !mask || !L || !E || !Y) HT_FAIL(HT_ERR_INVALID_ARG, "plan/M/mask/L/E/Y is NULL");
+  if (pl->batch) HT_FAIL(HT_ERR_UNSUPPORTED, "the solver takes a single-tensor plan");
   if (n_iter < 0) HT_FAIL(HT_ERR_INVALID_ARG, "n_iter must be >= 0");
   int rc;
   if ((rc = check_admm_params(prm))) return rc;
-  if ((rc = check_ws(pl, ws, ws_bytes, pl->admm_bytes))) return rc;
+  if ((rc = check_ws(ws, ws_bytes, pl->admm_bytes))) return rc;
   hipStream_t s = static_cast<hipStream_t>(stream);
   if (pl->precision == HT_FP64)
     return run_admm<double>(pl, prm, static_cast<const double*>(M), mask, static_cast<double*>(L),

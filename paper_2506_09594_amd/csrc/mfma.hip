@@ -1,15 +1,16 @@
 // FP32 sketch products on the matrix cores (v_mfma_f32_32x32x2_f32).
 //
-//   nn:  Y_j (m x l) = A_j (m x kd) W_j (kd x l)      (range sketch, power step)
-//   tn:  Z_j (n x l) = A_j^T (n x m) Q_j (m x l)      (adjoint step, projection)
+//   nn:  Y_s (n1 x l) = A_s (n1 x n2) W_s (n2 x l)    (range sketch, power step)
+//   tn:  Z_s (n2 x l) = A_s^T (n2 x n1) Q_s (n1 x l)  (adjoint step, projection)
 //
-// A workgroup of four wavefronts owns a 128-row output tile of one slice and
-// all l (<= 32 * NB) columns; wavefront w computes rows 32w..32w+31 as NB
-// 32 x 32 MFMA blocks.  K is walked in chunks of 32: the A chunk (128 x 32) and
-// the thin-operand chunk (32 x l) are fetched with 16-byte coalesced loads
-// into registers while the matrix cores work on the previous chunk in LDS
-// (double buffering).  MFMA operand layout (32x32x2, one block): lane t
-// supplies A[t % 32][t / 32] and B[t / 32][t % 32]; accumulator r of lane t is
+// One workgroup per work item (slice s, first output row): NW wavefronts own
+// MT = 32 NW output rows and all l (<= 32 NB) columns, wavefront w computing
+// rows 32w..32w+31 as NB 32 x 32 MFMA blocks.  The reduction dimension is
+// walked in chunks of 32: the A chunk (MT x 32) and the thin-operand chunk
+// (32 x l) are fetched into registers (16-byte loads where the slice's columns
+// allow it) while the matrix cores work on the previous chunk in LDS (double
+// buffering).  MFMA operand layout (32x32x2, one block): lane t supplies
+// A[t % 32][t / 32] and B[t / 32][t % 32]; accumulator r of lane t is
 // D[8 (r / 4) + 4 (t / 32) + r % 4][t % 32].
 //
 // Epilogue: the tile goes through LDS so that the column-major store is
@@ -24,16 +25,15 @@ namespace {
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
-constexpr int MT = 128;  // output rows per workgroup
-constexpr int KC = 32;   // K chunk
-constexpr int NTH = 256;
+constexpr int KC = 32;  // K chunk
 
-template <int NB>
+template <int NB, int NW>
 struct MfmaLds {
+  static constexpr int MT = 32 * NW;
   // A chunk stored as [k][row] (nn) or [row][k] (tn); thin chunk as [k][col]
-  static constexpr int AP_NN = MT + 4;   // pitch of [k][row]
-  static constexpr int AP_TN = KC + 1;   // pitch of [row][k]
-  static constexpr int BP = 32 * NB + 1; // pitch of [k][col]
+  static constexpr int AP_NN = MT + 4;    // pitch of [k][row]
+  static constexpr int AP_TN = KC + 1;    // pitch of [row][k]
+  static constexpr int BP = 32 * NB + 1;  // pitch of [k][col]
   static constexpr int A_WORDS = (KC * AP_NN > MT * AP_TN) ? KC * AP_NN : MT * AP_TN;
   static constexpr int B_WORDS = KC * BP;
   static constexpr int MAIN_BYTES = 2 * (A_WORDS + B_WORDS) * 4;
@@ -42,42 +42,52 @@ struct MfmaLds {
 };
 
 // TRANS = false: nn (A rows are output rows); TRANS = true: tn (A columns are
-// output rows).  M_out: output rows, K: reduction length, lda: column stride of A.
-template <int NB, bool TRANS>
-__global__ __launch_bounds__(NTH) void k_mfma_thin(const float* __restrict__ A, int64_t sA, int lda,
-                                                   const float* __restrict__ W, int64_t sW, int ldw,
-                                                   float* __restrict__ Y, int64_t sY, int ldy, int M_out, int K,
-                                                   int l, double* __restrict__ gpart) {
-  using L = MfmaLds<NB>;
+// output rows).
+template <int NB, int NW, bool TRANS>
+__global__ __launch_bounds__(64 * NW) void k_mfma_thin(const float* __restrict__ Aall, const float* __restrict__ Wall,
+                                                       float* __restrict__ Yall, const SliceDesc* __restrict__ sd,
+                                                       const int2* __restrict__ wk, const int2* __restrict__ items,
+                                                       double* __restrict__ gpart, int aligned) {
+  using L = MfmaLds<NB, NW>;
+  constexpr int MT = L::MT;
+  constexpr int NTH = 64 * NW;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   float* const lds_f = reinterpret_cast<float*>(smem_raw);
   // buffer b: A chunk at lds_f + b * A_WORDS, thin chunk at lds_f + 2 * A_WORDS + b * B_WORDS
-  const int j = blockIdx.y;
-  const int r0 = blockIdx.x * MT;
-  const float* Aj = A + (int64_t)j * sA;
-  const float* Wj = W + (int64_t)j * sW;
-  float* Yj = Y + (int64_t)j * sY;
+  const int2 item = items[blockIdx.x];
+  const int s = item.x, r0 = item.y;
+  const SliceDesc d = sd[s];
+  const int l = slice_width(d, wk, s);
+  const int lda = d.n1;
+  const int M_out = TRANS ? d.n2 : d.n1;
+  const int K = TRANS ? d.n1 : d.n2;
+  const int ldw = K, ldy = M_out;
+  const int64_t woff = TRANS ? d.y : d.z, yoff = TRANS ? d.z : d.y;
+  const float* Aj = Aall + d.a;
+  const float* Wj = Wall + woff;
+  float* Yj = Yall + yoff;
+  const bool vecA = aligned && (lda % 4 == 0) && (d.a % 4 == 0);
+  const bool vecW = aligned && (ldw % 4 == 0) && (woff % 4 == 0);
   const int tid = threadIdx.x;
   const int wave = tid / 64, lane = tid % 64;
   const int LW = 32 * NB;
 
   // ---- global -> register staging of one K chunk --------------------------
-  // A chunk: MT x KC values = 1024 float4; 4 per thread.
+  // A chunk: MT x KC values = 8 MT float4 groups; 4 per thread.
   // nn: column-major A, rows r0.. (contiguous) for columns k0..k0+31
-  // tn: column-major A, rows k0..k0+31 (contiguous) for columns r0..r0+127
-  f32x4 ra[4];
-  f32x4 rb[(KC * 32 * NB / 4 + NTH - 1) / NTH];
+  // tn: column-major A, rows k0..k0+31 (contiguous) for columns r0..r0+MT-1
+  constexpr int NRA = MT * KC / 4 / NTH;
   constexpr int NRB = (KC * 32 * NB / 4 + NTH - 1) / NTH;
+  f32x4 ra[NRA];
+  f32x4 rb[NRB];
   auto fetch = [&](int k0) {
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
+    for (int u = 0; u < NRA; ++u) {
       const int f = tid + u * NTH;
-      int row, kk;
       if (!TRANS) {
-        kk = f / (MT / 4);
-        row = (f % (MT / 4)) * 4;
+        const int kk = f / (MT / 4), row = (f % (MT / 4)) * 4;
         const int gr = r0 + row, gk = k0 + kk;
-        if (gk < K && gr + 3 < M_out) {
+        if (vecA && gk < K && gr + 3 < M_out) {
           ra[u] = *reinterpret_cast<const f32x4*>(Aj + gr + (int64_t)gk * lda);
         } else {
           f32x4 v;
@@ -86,10 +96,9 @@ __global__ __launch_bounds__(NTH) void k_mfma_thin(const float* __restrict__ A, 
           ra[u] = v;
         }
       } else {
-        row = f / (KC / 4);
-        kk = (f % (KC / 4)) * 4;
+        const int row = f / (KC / 4), kk = (f % (KC / 4)) * 4;
         const int gc = r0 + row, gk = k0 + kk;
-        if (gc < M_out && gk + 3 < K) {
+        if (vecA && gc < M_out && gk + 3 < K) {
           ra[u] = *reinterpret_cast<const f32x4*>(Aj + gk + (int64_t)gc * lda);
         } else {
           f32x4 v;
@@ -106,7 +115,7 @@ __global__ __launch_bounds__(NTH) void k_mfma_thin(const float* __restrict__ A, 
       const int c = f / (KC / 4), k4 = (f % (KC / 4)) * 4;
       f32x4 v;
       const int gk = k0 + k4;
-      if (f < KC * LW / 4 && c < l && gk + 3 < K) {
+      if (vecW && f < KC * LW / 4 && c < l && gk + 3 < K) {
         v = *reinterpret_cast<const f32x4*>(Wj + gk + (int64_t)c * ldw);
       } else {
 #pragma unroll
@@ -120,7 +129,7 @@ __global__ __launch_bounds__(NTH) void k_mfma_thin(const float* __restrict__ A, 
     float* As = lds_f + buf * L::A_WORDS;
     float* Bs = lds_f + 2 * L::A_WORDS + buf * L::B_WORDS;
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
+    for (int u = 0; u < NRA; ++u) {
       const int f = tid + u * NTH;
       if (!TRANS) {
         const int kk = f / (MT / 4), row = (f % (MT / 4)) * 4;
@@ -149,6 +158,7 @@ __global__ __launch_bounds__(NTH) void k_mfma_thin(const float* __restrict__ A, 
     for (int r = 0; r < 16; ++r) acc[b][r] = 0.0f;
 
   const int nchunks = (K + KC - 1) / KC;
+  const int nbl = (l + 31) / 32;  // column blocks in use (uniform)
   fetch(0);
   stash(0);
   __syncthreads();
@@ -165,8 +175,10 @@ __global__ __launch_bounds__(NTH) void k_mfma_thin(const float* __restrict__ A, 
       const float a = TRANS ? As[mrow * L::AP_TN + k] : As[k * L::AP_NN + mrow];
 #pragma unroll
       for (int b = 0; b < NB; ++b) {
-        const float bv = Bs[k * L::BP + 32 * b + (lane % 32)];
-        acc[b] = __builtin_amdgcn_mfma_f32_32x32x2f32(a, bv, acc[b], 0, 0, 0);
+        if (b < nbl) {
+          const float bv = Bs[k * L::BP + 32 * b + (lane % 32)];
+          acc[b] = __builtin_amdgcn_mfma_f32_32x32x2f32(a, bv, acc[b], 0, 0, 0);
+        }
       }
     }
     if (ch + 1 < nchunks) stash(buf ^ 1);
@@ -190,38 +202,48 @@ __global__ __launch_bounds__(NTH) void k_mfma_thin(const float* __restrict__ A, 
     const int i = idx % MT, c = idx / MT;
     if (i < rows) Yj[(r0 + i) + (int64_t)c * ldy] = (float)S[i * sp + c];
   }
-  if (gpart) tile_gram_to_global(S, sp, MT, l, gpart + ((int64_t)j * gridDim.x + blockIdx.x) * (int64_t)l * l);
+  if (gpart) tile_gram_to_global(S, sp, MT, l, gpart + d.g1 + (int64_t)(r0 / MT) * l * l);
 }
 
-template <int NB, bool TRANS>
-int launch_thin(const float* A, int64_t sA, int lda, const float* W, int64_t sW, int ldw, float* Y, int64_t sY,
-                int ldy, int M_out, int K, int l, int P, double* gpart, hipStream_t s) {
-  using L = MfmaLds<NB>;
-  int rc = ensure_dynamic_lds((const void*)k_mfma_thin<NB, TRANS>, L::BYTES);
+template <int NB, int NW, bool TRANS>
+int launch_thin(const float* A, const float* W, float* Y, const SliceDesc* sd, const int2* wk, const int2* items,
+                int nitems, double* gpart, hipStream_t s) {
+  using L = MfmaLds<NB, NW>;
+  if (nitems == 0) return HT_OK;
+  int rc = ensure_dynamic_lds((const void*)k_mfma_thin<NB, NW, TRANS>, L::BYTES);
   if (rc) return rc;
-  dim3 grid((unsigned)ceil_div(M_out, MT), (unsigned)P);
-  hipLaunchKernelGGL((k_mfma_thin<NB, TRANS>), grid, dim3(NTH), L::BYTES, s, A, sA, lda, W, sW, ldw, Y, sY, ldy,
-                     M_out, K, l, gpart);
+  const int aligned = (reinterpret_cast<uintptr_t>(A) % 16 == 0) && (reinterpret_cast<uintptr_t>(W) % 16 == 0);
+  hipLaunchKernelGGL((k_mfma_thin<NB, NW, TRANS>), dim3((unsigned)nitems), dim3(64 * NW), L::BYTES, s, A, W, Y, sd,
+                     wk, items, gpart, aligned);
   HT_CHECK_LAUNCH();
   return HT_OK;
 }
 
-}  // namespace
-
-int mfma_tile_rows() { return MT; }
-
-int launch_mfma_nn(const float* A, int64_t sA, int lda, const float* W, int64_t sW, int ldw, float* Y, int64_t sY,
-                   int ldy, int m, int kd, int l, int P, double* gpart, hipStream_t s) {
-  if (l <= 32) return launch_thin<1, false>(A, sA, lda, W, sW, ldw, Y, sY, ldy, m, kd, l, P, gpart, s);
-  if (l <= 64) return launch_thin<2, false>(A, sA, lda, W, sW, ldw, Y, sY, ldy, m, kd, l, P, gpart, s);
-  return launch_thin<3, false>(A, sA, lda, W, sW, ldw, Y, sY, ldy, m, kd, l, P, gpart, s);
+template <bool TRANS>
+int dispatch(const float* A, const float* W, float* Y, const SliceDesc* sd, const int2* wk, const int2* items,
+             int nitems, int lmax, int rows, double* gpart, hipStream_t s) {
+  if (rows == 64) {
+    if (lmax <= 32) return launch_thin<1, 2, TRANS>(A, W, Y, sd, wk, items, nitems, gpart, s);
+    if (lmax <= 64) return launch_thin<2, 2, TRANS>(A, W, Y, sd, wk, items, nitems, gpart, s);
+    return launch_thin<3, 2, TRANS>(A, W, Y, sd, wk, items, nitems, gpart, s);
+  }
+  if (lmax <= 32) return launch_thin<1, 4, TRANS>(A, W, Y, sd, wk, items, nitems, gpart, s);
+  if (lmax <= 64) return launch_thin<2, 4, TRANS>(A, W, Y, sd, wk, items, nitems, gpart, s);
+  return launch_thin<3, 4, TRANS>(A, W, Y, sd, wk, items, nitems, gpart, s);
 }
 
-int launch_mfma_tn(const float* A, int64_t sA, int lda, const float* Q, int64_t sQ, int ldq, float* Z, int64_t sZ,
-                   int ldz, int m, int n, int l, int P, double* gpart, hipStream_t s) {
-  if (l <= 32) return launch_thin<1, true>(A, sA, lda, Q, sQ, ldq, Z, sZ, ldz, n, m, l, P, gpart, s);
-  if (l <= 64) return launch_thin<2, true>(A, sA, lda, Q, sQ, ldq, Z, sZ, ldz, n, m, l, P, gpart, s);
-  return launch_thin<3, true>(A, sA, lda, Q, sQ, ldq, Z, sZ, ldz, n, m, l, P, gpart, s);
+}  // namespace
+
+int launch_mfma_nn(const float* A, const float* W, float* Y, const SliceDesc* sd, const int2* wk, const int2* items,
+                   int nitems, int lmax, int rows, double* gpart, hipStream_t s) {
+  if (lmax > 96 || (rows != 64 && rows != 128)) HT_FAIL(HT_ERR_UNSUPPORTED, "matrix-core product: bad width or tile");
+  return dispatch<false>(A, W, Y, sd, wk, items, nitems, lmax, rows, gpart, s);
+}
+
+int launch_mfma_tn(const float* A, const float* Q, float* Z, const SliceDesc* sd, const int2* wk, const int2* items,
+                   int nitems, int lmax, int rows, double* gpart, hipStream_t s) {
+  if (lmax > 96 || (rows != 64 && rows != 128)) HT_FAIL(HT_ERR_UNSUPPORTED, "matrix-core product: bad width or tile");
+  return dispatch<true>(A, Q, Z, sd, wk, items, nitems, lmax, rows, gpart, s);
 }
 
 }  // namespace ht

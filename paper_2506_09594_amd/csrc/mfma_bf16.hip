@@ -4,12 +4,12 @@
 // staged; the result and its FP64 Gram partials are written as in the FP32
 // kernel.
 //
-//   nn:  Y_j (m x l) = A_j (m x kd) W_j (kd x l)
-//   tn:  Z_j (n x l) = A_j^T (n x m) Q_j (m x l)
+//   nn:  Y_s (n1 x l) = A_s (n1 x n2) W_s (n2 x l)
+//   tn:  Z_s (n2 x l) = A_s^T (n2 x n1) Q_s (n1 x l)
 //
-// Tiles: 128 output rows x l (<= 32 NB) per workgroup, wavefront w owns rows
-// 32w..32w+31.  K chunks of 32 are double-buffered in LDS, both operands stored
-// with k contiguous so that each lane fetches its 8 consecutive k values with
+// One workgroup per work item (slice, first output row): MT = 32 NW output
+// rows x l (<= 32 NB) columns, wavefront w owns rows 32w..32w+31.  K chunks of
+// 32 are double-buffered in LDS, both operands stored with k contiguous so that each lane fetches its 8 consecutive k values with
 // one 16-byte LDS read.  MFMA operand layout (32x32x16 bf16): lane t supplies
 // A[t % 32][8 (t / 32) .. 8 (t / 32) + 7] and B[8 (t / 32) ..][t % 32]; the
 // accumulator layout is that of the FP32 32x32 instruction.
@@ -24,13 +24,12 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
 
-constexpr int MT = 128;
 constexpr int KC = 32;
-constexpr int NTH = 256;
 constexpr int KP = KC + 8;  // LDS pitch (bf16 elements) of a k-contiguous row: 80 bytes
 
-template <int NB>
+template <int NB, int NW>
 struct Bf16Lds {
+  static constexpr int MT = 32 * NW;
   static constexpr int A_ELEMS = MT * KP;
   static constexpr int B_ELEMS = 32 * NB * KP;
   static constexpr int MAIN_BYTES = 2 * (A_ELEMS + B_ELEMS) * 2;
@@ -38,32 +37,44 @@ struct Bf16Lds {
   static constexpr int BYTES = MAIN_BYTES > EPI_BYTES ? MAIN_BYTES : EPI_BYTES;
 };
 
-template <int NB, bool TRANS>
-__global__ __launch_bounds__(NTH) void k_mfma_thin_bf16(const uint16_t* __restrict__ A, int64_t sA, int lda,
-                                                        const float* __restrict__ W, int64_t sW, int ldw,
-                                                        float* __restrict__ Y, int64_t sY, int ldy, int M_out,
-                                                        int K, int l, double* __restrict__ gpart, int vecA,
-                                                        int vecW) {
-  using L = Bf16Lds<NB>;
+template <int NB, int NW, bool TRANS>
+__global__ __launch_bounds__(64 * NW) void k_mfma_thin_bf16(const uint16_t* __restrict__ Aall,
+                                                            const float* __restrict__ Wall, float* __restrict__ Yall,
+                                                            const SliceDesc* __restrict__ sd,
+                                                            const int2* __restrict__ wk, const int2* __restrict__ items,
+                                                            double* __restrict__ gpart, int aligned) {
+  using L = Bf16Lds<NB, NW>;
+  constexpr int MT = L::MT;
+  constexpr int NTH = 64 * NW;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   uint16_t* const lds_h = reinterpret_cast<uint16_t*>(smem_raw);
-  const int j = blockIdx.y;
-  const int r0 = blockIdx.x * MT;
-  const uint16_t* Aj = A + (int64_t)j * sA;
-  const float* Wj = W + (int64_t)j * sW;
-  float* Yj = Y + (int64_t)j * sY;
+  const int2 item = items[blockIdx.x];
+  const int s = item.x, r0 = item.y;
+  const SliceDesc d = sd[s];
+  const int l = slice_width(d, wk, s);
+  const int lda = d.n1;
+  const int M_out = TRANS ? d.n2 : d.n1;
+  const int K = TRANS ? d.n1 : d.n2;
+  const int ldw = K, ldy = M_out;
+  const int64_t woff = TRANS ? d.y : d.z, yoff = TRANS ? d.z : d.y;
+  const uint16_t* Aj = Aall + d.a;
+  const float* Wj = Wall + woff;
+  float* Yj = Yall + yoff;
+  const bool vecA = aligned && (lda % 8 == 0) && (d.a % 8 == 0);
+  const bool vecW = aligned && (ldw % 4 == 0) && (woff % 4 == 0);
   const int tid = threadIdx.x;
   const int wave = tid / 64, lane = tid % 64;
   const int LW = 32 * NB;
 
-  // A chunk: 128 x 32 bf16 = 512 x 16-byte groups of 8, two per thread.
+  // A chunk: MT x 32 bf16 = 4 MT 16-byte groups of 8, two per thread.
   // nn: group = 8 consecutive rows of one column k;  tn: 8 consecutive k of one column.
-  u16x8 ra[2];
+  constexpr int NRA = MT * KC / 8 / NTH;
+  u16x8 ra[NRA];
   constexpr int NWB = (32 * NB * KC / 4 + NTH - 1) / NTH;  // float4 groups of the thin chunk per thread
   f32x4 rw[NWB];
   auto fetch = [&](int k0) {
 #pragma unroll
-    for (int u = 0; u < 2; ++u) {
+    for (int u = 0; u < NRA; ++u) {
       const int g = tid + u * NTH;
       u16x8 v;
       if (!TRANS) {
@@ -106,7 +117,7 @@ __global__ __launch_bounds__(NTH) void k_mfma_thin_bf16(const uint16_t* __restri
     uint16_t* As = lds_h + buf * L::A_ELEMS;
     uint16_t* Ws = lds_h + 2 * L::A_ELEMS + buf * L::B_ELEMS;
 #pragma unroll
-    for (int u = 0; u < 2; ++u) {
+    for (int u = 0; u < NRA; ++u) {
       const int g = tid + u * NTH;
       if (!TRANS) {
         const int kk = g / (MT / 8), row = (g % (MT / 8)) * 8;
@@ -135,6 +146,7 @@ __global__ __launch_bounds__(NTH) void k_mfma_thin_bf16(const uint16_t* __restri
     for (int r = 0; r < 16; ++r) acc[b][r] = 0.0f;
 
   const int nchunks = (K + KC - 1) / KC;
+  const int nbl = (l + 31) / 32;
   fetch(0);
   stash(0);
   __syncthreads();
@@ -150,9 +162,11 @@ __global__ __launch_bounds__(NTH) void k_mfma_thin_bf16(const uint16_t* __restri
       const bf16x8 a = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u16x8*>(As + mrow * KP + 16 * kh + koff));
 #pragma unroll
       for (int b = 0; b < NB; ++b) {
-        const bf16x8 bv = __builtin_bit_cast(
-            bf16x8, *reinterpret_cast<const u16x8*>(Ws + (32 * b + (lane % 32)) * KP + 16 * kh + koff));
-        acc[b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bv, acc[b], 0, 0, 0);
+        if (b < nbl) {
+          const bf16x8 bv = __builtin_bit_cast(
+              bf16x8, *reinterpret_cast<const u16x8*>(Ws + (32 * b + (lane % 32)) * KP + 16 * kh + koff));
+          acc[b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bv, acc[b], 0, 0, 0);
+        }
       }
     }
     if (ch + 1 < nchunks) stash(buf ^ 1);
@@ -175,38 +189,47 @@ __global__ __launch_bounds__(NTH) void k_mfma_thin_bf16(const uint16_t* __restri
     const int i = idx % MT, c = idx / MT;
     if (i < rows) Yj[(r0 + i) + (int64_t)c * ldy] = (float)S[i * sp + c];
   }
-  if (gpart) tile_gram_to_global(S, sp, MT, l, gpart + ((int64_t)j * gridDim.x + blockIdx.x) * (int64_t)l * l);
+  if (gpart) tile_gram_to_global(S, sp, MT, l, gpart + d.g1 + (int64_t)(r0 / MT) * l * l);
 }
 
-template <int NB, bool TRANS>
-int launch_thin_bf16(const uint16_t* A, int64_t sA, int lda, const float* W, int64_t sW, int ldw, float* Y,
-                     int64_t sY, int ldy, int M_out, int K, int l, int P, double* gpart, hipStream_t s) {
-  using L = Bf16Lds<NB>;
-  int rc = ensure_dynamic_lds((const void*)k_mfma_thin_bf16<NB, TRANS>, L::BYTES);
+template <int NB, int NW, bool TRANS>
+int launch_thin_bf16(const uint16_t* A, const float* W, float* Y, const SliceDesc* sd, const int2* wk,
+                     const int2* items, int nitems, double* gpart, hipStream_t s) {
+  using L = Bf16Lds<NB, NW>;
+  if (nitems == 0) return HT_OK;
+  int rc = ensure_dynamic_lds((const void*)k_mfma_thin_bf16<NB, NW, TRANS>, L::BYTES);
   if (rc) return rc;
-  const int vecA = (lda % 8 == 0) && (sA % 8 == 0) && (reinterpret_cast<uintptr_t>(A) % 16 == 0);
-  const int vecW = (ldw % 4 == 0) && (sW % 4 == 0) && (reinterpret_cast<uintptr_t>(W) % 16 == 0);
-  dim3 grid((unsigned)ceil_div(M_out, MT), (unsigned)P);
-  hipLaunchKernelGGL((k_mfma_thin_bf16<NB, TRANS>), grid, dim3(NTH), L::BYTES, s, A, sA, lda, W, sW, ldw, Y, sY,
-                     ldy, M_out, K, l, gpart, vecA, vecW);
+  const int aligned = (reinterpret_cast<uintptr_t>(A) % 16 == 0) && (reinterpret_cast<uintptr_t>(W) % 16 == 0);
+  hipLaunchKernelGGL((k_mfma_thin_bf16<NB, NW, TRANS>), dim3((unsigned)nitems), dim3(64 * NW), L::BYTES, s, A, W, Y,
+                     sd, wk, items, gpart, aligned);
   HT_CHECK_LAUNCH();
   return HT_OK;
 }
 
-}  // namespace
-
-int launch_bf16_nn(const uint16_t* A, int64_t sA, int lda, const float* W, int64_t sW, int ldw, float* Y,
-                   int64_t sY, int ldy, int m, int kd, int l, int P, double* gpart, hipStream_t s) {
-  if (l <= 32) return launch_thin_bf16<1, false>(A, sA, lda, W, sW, ldw, Y, sY, ldy, m, kd, l, P, gpart, s);
-  if (l <= 64) return launch_thin_bf16<2, false>(A, sA, lda, W, sW, ldw, Y, sY, ldy, m, kd, l, P, gpart, s);
-  return launch_thin_bf16<3, false>(A, sA, lda, W, sW, ldw, Y, sY, ldy, m, kd, l, P, gpart, s);
+template <bool TRANS>
+int dispatch_bf16(const uint16_t* A, const float* W, float* Y, const SliceDesc* sd, const int2* wk,
+                  const int2* items, int nitems, int lmax, int rows, double* gpart, hipStream_t s) {
+  if (lmax > 96 || (rows != 64 && rows != 128)) HT_FAIL(HT_ERR_UNSUPPORTED, "matrix-core product: bad width or tile");
+  if (rows == 64) {
+    if (lmax <= 32) return launch_thin_bf16<1, 2, TRANS>(A, W, Y, sd, wk, items, nitems, gpart, s);
+    if (lmax <= 64) return launch_thin_bf16<2, 2, TRANS>(A, W, Y, sd, wk, items, nitems, gpart, s);
+    return launch_thin_bf16<3, 2, TRANS>(A, W, Y, sd, wk, items, nitems, gpart, s);
+  }
+  if (lmax <= 32) return launch_thin_bf16<1, 4, TRANS>(A, W, Y, sd, wk, items, nitems, gpart, s);
+  if (lmax <= 64) return launch_thin_bf16<2, 4, TRANS>(A, W, Y, sd, wk, items, nitems, gpart, s);
+  return launch_thin_bf16<3, 4, TRANS>(A, W, Y, sd, wk, items, nitems, gpart, s);
 }
 
-int launch_bf16_tn(const uint16_t* A, int64_t sA, int lda, const float* Q, int64_t sQ, int ldq, float* Z,
-                   int64_t sZ, int ldz, int m, int n, int l, int P, double* gpart, hipStream_t s) {
-  if (l <= 32) return launch_thin_bf16<1, true>(A, sA, lda, Q, sQ, ldq, Z, sZ, ldz, n, m, l, P, gpart, s);
-  if (l <= 64) return launch_thin_bf16<2, true>(A, sA, lda, Q, sQ, ldq, Z, sZ, ldz, n, m, l, P, gpart, s);
-  return launch_thin_bf16<3, true>(A, sA, lda, Q, sQ, ldq, Z, sZ, ldz, n, m, l, P, gpart, s);
+}  // namespace
+
+int launch_bf16_nn(const uint16_t* A, const float* W, float* Y, const SliceDesc* sd, const int2* wk,
+                   const int2* items, int nitems, int lmax, int rows, double* gpart, hipStream_t s) {
+  return dispatch_bf16<false>(A, W, Y, sd, wk, items, nitems, lmax, rows, gpart, s);
+}
+
+int launch_bf16_tn(const uint16_t* A, const float* Q, float* Z, const SliceDesc* sd, const int2* wk,
+                   const int2* items, int nitems, int lmax, int rows, double* gpart, hipStream_t s) {
+  return dispatch_bf16<true>(A, Q, Z, sd, wk, items, nitems, lmax, rows, gpart, s);
 }
 
 }  // namespace ht

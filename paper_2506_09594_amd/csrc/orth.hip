@@ -26,25 +26,52 @@ namespace {
 
 constexpr int TR = 64;  // rows per workgroup (matches the producing products); one lane per row
 
+// Work item (slice, first row) of the basis `which` (0: Y, n1 rows; 1: Z, n2
+// rows): its operand, row count and the number of Gram partials of the
+// producing product (prod_rows rows each).
+struct OrthItem {
+  int64_t off, g1, g2;
+  int m, l, row0, nparts;
+};
+
+__device__ __forceinline__ OrthItem orth_item(const SliceDesc* sd, const int2* wk, const int2* items, int which,
+                                              int prod_rows) {
+  const int2 it = items[blockIdx.x];
+  const SliceDesc d = sd[it.x];
+  OrthItem o;
+  o.m = which ? d.n2 : d.n1;
+  o.off = which ? d.z : d.y;
+  o.l = slice_width(d, wk, it.x);
+  o.row0 = it.y;
+  o.nparts = (o.m + prod_rows - 1) / prod_rows;
+  o.g1 = d.g1;
+  o.g2 = d.g2;
+  return o;
+}
+
 // Register path (l <= 64): lane b sums column b of G from the partials and
 // the factorization runs in registers; lane i then owns row i of the tile and
 // solves q R = y with the rows of R broadcast by readlane.
 template <typename T, int LB>
-__global__ __launch_bounds__(TR) void k_orth_apply_regs(T* __restrict__ Yall, int64_t sY, int ldy, int m, int l,
-                                                        const double* __restrict__ gin, int nparts, double* __restrict__ gout) {
+__global__ __launch_bounds__(TR) void k_orth_apply_regs(T* __restrict__ Yall, int which, const SliceDesc* __restrict__ sd,
+                                                        const int2* __restrict__ wk, const int2* __restrict__ items,
+                                                        const double* __restrict__ gin_all, int prod_rows,
+                                                        double* __restrict__ gout_all) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
+  const OrthItem o = orth_item(sd, wk, items, which, prod_rows);
+  const int l = o.l, m = o.m, ldy = m, nparts = o.nparts;
   const int gp = l + 1;
   double* S = reinterpret_cast<double*>(smem_raw);  // TR x gp (Gram of the result)
-  const int j = blockIdx.y, tile = blockIdx.x, ntiles = gridDim.x;
-  const int row0 = tile * TR;
+  const int row0 = o.row0;
   const int rows = min(TR, m - row0);
-  T* Y = Yall + (int64_t)j * sY + row0;
+  T* Y = Yall + o.off + row0;
+  double* gout = gout_all ? gout_all + o.g2 + (int64_t)(row0 / TR) * l * l : nullptr;
   const int lane = threadIdx.x;
   const bool valid = lane < rows;
   const int ll = l * l;
 
   // column `lane` of G = sum of the tile partials (fixed order)
-  const double* part = gin + (int64_t)j * nparts * ll;
+  const double* part = gin_all + o.g1;
   double g[LB];
 #pragma unroll
   for (int a = 0; a < LB; ++a) g[a] = 0.0;
@@ -92,27 +119,31 @@ __global__ __launch_bounds__(TR) void k_orth_apply_regs(T* __restrict__ Yall, in
   }
   if (gout) {
     __syncthreads();
-    tile_gram_to_global(S, gp, TR, l, gout + ((int64_t)j * ntiles + tile) * (int64_t)ll);
+    tile_gram_to_global(S, gp, TR, l, gout);
   }
 }
 
 template <typename T, int LB>
-__global__ __launch_bounds__(TR) void k_orth_apply(T* __restrict__ Yall, int64_t sY, int ldy, int m, int l,
-                                                   const double* __restrict__ gin, int nparts, double* __restrict__ gout) {
+__global__ __launch_bounds__(TR) void k_orth_apply(T* __restrict__ Yall, int which, const SliceDesc* __restrict__ sd,
+                                                   const int2* __restrict__ wk, const int2* __restrict__ items,
+                                                   const double* __restrict__ gin_all, int prod_rows,
+                                                   double* __restrict__ gout_all) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
+  const OrthItem o = orth_item(sd, wk, items, which, prod_rows);
+  const int l = o.l, m = o.m, ldy = m, nparts = o.nparts;
   const int gp = l + 1;
   double* G = reinterpret_cast<double*>(smem_raw);  // l x gp
   double* dR = G + (size_t)l * gp;                  // gp
   double* S = dR + gp;                               // TR x gp (Gram of the result)
   __shared__ double s_scratch;
-  const int j = blockIdx.y, tile = blockIdx.x, ntiles = gridDim.x;
-  const int row0 = tile * TR;
+  const int row0 = o.row0;
   const int rows = min(TR, m - row0);
-  T* Y = Yall + (int64_t)j * sY + row0;
+  T* Y = Yall + o.off + row0;
+  double* gout = gout_all ? gout_all + o.g2 + (int64_t)(row0 / TR) * l * l : nullptr;
   const int i = threadIdx.x;
   const bool valid = i < rows;
 
-  sum_gram_partials(G, gp, gin + (int64_t)j * nparts * l * l, nparts, l);
+  sum_gram_partials(G, gp, gin_all + o.g1, nparts, l);
   double y[LB];
 #pragma unroll
   for (int c = 0; c < LB; ++c) y[c] = (c < l && valid) ? (double)Y[i + (int64_t)c * ldy] : 0.0;
@@ -140,7 +171,7 @@ __global__ __launch_bounds__(TR) void k_orth_apply(T* __restrict__ Yall, int64_t
   }
   if (gout) {
     __syncthreads();
-    tile_gram_to_global(S, gp, TR, l, gout + ((int64_t)j * ntiles + tile) * (int64_t)l * l);
+    tile_gram_to_global(S, gp, TR, l, gout);
   }
 }
 
@@ -149,27 +180,28 @@ size_t orth_lds_bytes(int l) { return ((size_t)l * (l + 1) + (size_t)(l + 1) + (
 }  // namespace
 
 template <typename T>
-int launch_orth_apply(T* Y, int64_t sY, int ldy, int m, int l, int P, const double* gin, int nparts, double* gout,
-                      hipStream_t s) {
-  if (l > HT_MAX_WIDTH) HT_FAIL(HT_ERR_UNSUPPORTED, "sketch width above HT_MAX_WIDTH");
-  const size_t lds = orth_lds_bytes(l);
-  const dim3 grid((unsigned)ceil_div(m, TR), (unsigned)P);
+int launch_orth_apply(T* Y, int which, const SliceDesc* sd, const int2* wk, const int2* items, int nitems, int lmax,
+                      const double* gin, int prod_rows, double* gout, hipStream_t s) {
+  if (lmax > HT_MAX_WIDTH) HT_FAIL(HT_ERR_UNSUPPORTED, "sketch width above HT_MAX_WIDTH");
+  if (nitems == 0) return HT_OK;
+  const size_t lds = orth_lds_bytes(lmax);
   auto launch = [&](auto kern) -> int {
     int rc = ensure_dynamic_lds((const void*)kern, orth_lds_bytes(HT_MAX_WIDTH));
     if (rc) return rc;
-    hipLaunchKernelGGL(kern, grid, dim3(TR), lds, s, Y, sY, ldy, m, l, gin, nparts, gout);
+    hipLaunchKernelGGL(kern, dim3((unsigned)nitems), dim3(TR), lds, s, Y, which, sd, wk, items, gin, prod_rows, gout);
     HT_CHECK_LAUNCH();
     return HT_OK;
   };
-  if (l <= 16) return launch(k_orth_apply_regs<T, 16>);
-  if (l <= 32) return launch(k_orth_apply_regs<T, 32>);
-  if (l <= 48) return launch(k_orth_apply_regs<T, 48>);
-  if (l <= 64) return launch(k_orth_apply_regs<T, 64>);
+  if (lmax <= 16) return launch(k_orth_apply_regs<T, 16>);
+  if (lmax <= 32) return launch(k_orth_apply_regs<T, 32>);
+  if (lmax <= 48) return launch(k_orth_apply_regs<T, 48>);
+  if (lmax <= 64) return launch(k_orth_apply_regs<T, 64>);
   return launch(k_orth_apply<T, 80>);
 }
 
-template int launch_orth_apply<float>(float*, int64_t, int, int, int, int, const double*, int, double*, hipStream_t);
-template int launch_orth_apply<double>(double*, int64_t, int, int, int, int, const double*, int, double*,
-                                       hipStream_t);
+template int launch_orth_apply<float>(float*, int, const SliceDesc*, const int2*, const int2*, int, int, const double*,
+                                      int, double*, hipStream_t);
+template int launch_orth_apply<double>(double*, int, const SliceDesc*, const int2*, const int2*, int, int,
+                                       const double*, int, double*, hipStream_t);
 
 }  // namespace ht

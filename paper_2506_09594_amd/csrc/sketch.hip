@@ -1,13 +1,17 @@
-// Thin batched products of the sketch: Y = A W, Z = A^T Q, C = X W^T.
+// Thin products on the vector ALUs: the FP64 sketch products and the
+// reconstruction products of every precision.
 //
-// Each face slice A_j is a column-major n1 x n2 block; the thin factors are
-// column-major with l <= 128 columns.  The kernels tile the long dimension in
-// 64-row (or 64-column) blocks per workgroup, stage a K-chunk of both operands
-// in LDS and accumulate in the storage precision (FP32 for float, FP64 for
-// double).  One pass reads every slice exactly once.  Optionally the epilogue
-// also writes, per output tile, the FP64 Gram matrix of the tile's rows as
-// stored (rounded to the storage type), so that the orthonormalization of the
-// thin result needs no extra pass over it.
+//   sketch nn:  Y_s (n1 x l) = A_s (n1 x n2) W_s (n2 x l)
+//   sketch tn:  Z_s (n2 x l) = A_s^T Q_s
+//   recon nn:   (Q1 K')_s (n1 x l) = Q1_s (n1 x l) K'_s (l x l)
+//   recon nt:   C_s (n1 x n2) = (Q1 K')_s Bt_s^T
+//
+// Every slice is a column-major block found through the slice table; one
+// workgroup per work item (slice, 64-row tile) stages a K-chunk of both
+// operands in LDS and accumulates in the storage precision.  One pass reads
+// every slice once.  Optionally the epilogue also writes, per output tile, the
+// FP64 Gram matrix of the tile's rows as stored, so that the orthonormalization
+// of the thin result needs no extra pass over it.
 #include "chol.hpp"
 
 namespace ht {
@@ -42,19 +46,25 @@ __device__ inline void tile_gram_epilogue(unsigned char* smem, const T* acc, int
   tile_gram_to_global(S, gp, TM, l, out);
 }
 
-template <typename T, int LB>
-__global__ __launch_bounds__(256) void k_gemm_nn(const T* __restrict__ A, int64_t sA, int lda,
-                                                 const T* __restrict__ W, int64_t sW, int ldw, T* __restrict__ Y,
-                                                 int64_t sY, int ldy, int m, int kd, int l, double* __restrict__ gpart) {
+// RECON = false: Y = A W (sketch); RECON = true: QK = Q1 K'.
+template <typename T, int LB, bool RECON>
+__global__ __launch_bounds__(256) void k_gemm_nn(const T* __restrict__ Aall, const T* __restrict__ Wall,
+                                                 T* __restrict__ Yall, const SliceDesc* __restrict__ sd,
+                                                 const int2* __restrict__ wk, const int2* __restrict__ items,
+                                                 double* __restrict__ gpart) {
   constexpr int CPT = LB / 4;
   __shared__ __align__(16) unsigned char smem[gemm_lds_bytes<T, LB>()];
   T(*As)[TM + 1] = reinterpret_cast<T(*)[TM + 1]>(smem);
   T(*Ws)[LB] = reinterpret_cast<T(*)[LB]>(smem + sizeof(T) * KC * (TM + 1));
-  const int j = blockIdx.y;
-  const int row0 = blockIdx.x * TM;
-  const T* Aj = A + (int64_t)j * sA;
-  const T* Wj = W + (int64_t)j * sW;
-  T* Yj = Y + (int64_t)j * sY;
+  const int2 item = items[blockIdx.x];
+  const int s = item.x, row0 = item.y;
+  const SliceDesc d = sd[s];
+  const int l = slice_width(d, wk, s);
+  const int m = d.n1, kd = RECON ? l : d.n2;
+  const int lda = d.n1, ldw = RECON ? l : d.n2, ldy = d.n1;
+  const T* Aj = Aall + (RECON ? d.y : d.a);
+  const T* Wj = Wall + (RECON ? d.kq : d.z);
+  T* Yj = Yall + d.y;
   const int tr = threadIdx.x % TM, tc = threadIdx.x / TM;
   T acc[CPT];
 #pragma unroll
@@ -88,23 +98,27 @@ __global__ __launch_bounds__(256) void k_gemm_nn(const T* __restrict__ A, int64_
     }
   }
   if (gpart)
-    tile_gram_epilogue<T, LB>(smem, acc, tr, tc, m - row0, l,
-                              gpart + ((int64_t)j * gridDim.x + blockIdx.x) * (int64_t)l * l);
+    tile_gram_epilogue<T, LB>(smem, acc, tr, tc, m - row0, l, gpart + d.g1 + (int64_t)(row0 / TM) * l * l);
 }
 
 template <typename T, int LB>
-__global__ __launch_bounds__(256) void k_gemm_tn(const T* __restrict__ A, int64_t sA, int lda,
-                                                 const T* __restrict__ Q, int64_t sQ, int ldq, T* __restrict__ Z,
-                                                 int64_t sZ, int ldz, int m, int n, int l, double* __restrict__ gpart) {
+__global__ __launch_bounds__(256) void k_gemm_tn(const T* __restrict__ Aall, const T* __restrict__ Qall,
+                                                 T* __restrict__ Zall, const SliceDesc* __restrict__ sd,
+                                                 const int2* __restrict__ wk, const int2* __restrict__ items,
+                                                 double* __restrict__ gpart) {
   constexpr int CPT = LB / 4;
   __shared__ __align__(16) unsigned char smem[gemm_lds_bytes<T, LB>()];
   T(*As)[TM + 1] = reinterpret_cast<T(*)[TM + 1]>(smem);
   T(*Qs)[LB] = reinterpret_cast<T(*)[LB]>(smem + sizeof(T) * KC * (TM + 1));
-  const int j = blockIdx.y;
-  const int col0 = blockIdx.x * TM;
-  const T* Aj = A + (int64_t)j * sA;
-  const T* Qj = Q + (int64_t)j * sQ;
-  T* Zj = Z + (int64_t)j * sZ;
+  const int2 item = items[blockIdx.x];
+  const int s = item.x, col0 = item.y;
+  const SliceDesc d = sd[s];
+  const int l = slice_width(d, wk, s);
+  const int m = d.n1, n = d.n2;
+  const int lda = m, ldq = m, ldz = n;
+  const T* Aj = Aall + d.a;
+  const T* Qj = Qall + d.y;
+  T* Zj = Zall + d.z;
   const int tcol = threadIdx.x % TM, tc = threadIdx.x / TM;
   T acc[CPT];
 #pragma unroll
@@ -138,24 +152,30 @@ __global__ __launch_bounds__(256) void k_gemm_tn(const T* __restrict__ A, int64_
     }
   }
   if (gpart)
-    tile_gram_epilogue<T, LB>(smem, acc, tcol, tc, n - col0, l,
-                              gpart + ((int64_t)j * gridDim.x + blockIdx.x) * (int64_t)l * l);
+    tile_gram_epilogue<T, LB>(smem, acc, tcol, tc, n - col0, l, gpart + d.g1 + (int64_t)(col0 / TM) * l * l);
 }
 
-// C_j (m x n) = X_j (m x l) W_j^T with W_j n x l: 64 x 64 output tile per
-// workgroup, 4 x 4 outputs per thread, K = l in chunks of 16.
+// C_s (n1 x n2) = X_s (n1 x l) W_s^T with W_s n2 x l: 64 x 64 output tile per
+// work item (slice, tile index; row tiles fastest), 4 x 4 outputs per thread,
+// K = l in chunks of 16.
 template <typename T>
-__global__ __launch_bounds__(256) void k_gemm_nt(const T* __restrict__ X, int64_t sX, int ldx,
-                                                 const T* __restrict__ W, int64_t sW, int ldw, T* __restrict__ C,
-                                                 int64_t sC, int ldc, int m, int n, int l) {
+__global__ __launch_bounds__(256) void k_gemm_nt(const T* __restrict__ Xall, const T* __restrict__ Wall,
+                                                 T* __restrict__ Call, const SliceDesc* __restrict__ sd,
+                                                 const int2* __restrict__ wk, const int2* __restrict__ items) {
   constexpr int KN = 16;
   __shared__ T Xs[KN][64];
   __shared__ T Ws[KN][64];
-  const int j = blockIdx.z;
-  const int row0 = blockIdx.x * 64, col0 = blockIdx.y * 64;
-  const T* Xj = X + (int64_t)j * sX;
-  const T* Wj = W + (int64_t)j * sW;
-  T* Cj = C + (int64_t)j * sC;
+  const int2 item = items[blockIdx.x];
+  const int s = item.x;
+  const SliceDesc d = sd[s];
+  const int l = slice_width(d, wk, s);
+  const int m = d.n1, n = d.n2;
+  const int nrt = (m + 63) / 64;
+  const int row0 = (item.y % nrt) * 64, col0 = (item.y / nrt) * 64;
+  const T* Xj = Xall + d.y;
+  const T* Wj = Wall + d.z;
+  T* Cj = Call + d.a;
+  const int ldx = m, ldw = n, ldc = m;
   const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
   T acc[4][4];
 #pragma unroll
@@ -198,56 +218,85 @@ __global__ __launch_bounds__(256) void k_gemm_nt(const T* __restrict__ X, int64_
 
 }  // namespace
 
-#define HT_WIDTH_DISPATCH(l, KERNEL, ...)                                      \
-  do {                                                                         \
-    if ((l) <= 16)                                                             \
-      hipLaunchKernelGGL((KERNEL<T, 16>), __VA_ARGS__);                        \
-    else if ((l) <= 32)                                                        \
-      hipLaunchKernelGGL((KERNEL<T, 32>), __VA_ARGS__);                        \
-    else if ((l) <= 48)                                                        \
-      hipLaunchKernelGGL((KERNEL<T, 48>), __VA_ARGS__);                        \
-    else if ((l) <= 64)                                                        \
-      hipLaunchKernelGGL((KERNEL<T, 64>), __VA_ARGS__);                        \
-    else                                                                       \
-      hipLaunchKernelGGL((KERNEL<T, 80>), __VA_ARGS__);                        \
-  } while (0)
-
 template <typename T>
-int launch_gemm_nn(const T* A, int64_t sA, int lda, const T* W, int64_t sW, int ldw, T* Y, int64_t sY, int ldy,
-                   int m, int kd, int l, int P, double* gpart, hipStream_t s) {
-  if (l > HT_MAX_WIDTH) HT_FAIL(HT_ERR_UNSUPPORTED, "sketch width above HT_MAX_WIDTH");
-  dim3 grid((unsigned)ceil_div(m, TM), (unsigned)P);
-  HT_WIDTH_DISPATCH(l, k_gemm_nn, grid, dim3(256), 0, s, A, sA, lda, W, sW, ldw, Y, sY, ldy, m, kd, l, gpart);
+int launch_gemm_nn(const T* A, const T* W, T* Y, const SliceDesc* sd, const int2* wk, const int2* items, int nitems,
+                   int lmax, double* gpart, hipStream_t s) {
+  if (lmax > HT_MAX_WIDTH) HT_FAIL(HT_ERR_UNSUPPORTED, "sketch width above HT_MAX_WIDTH");
+  if (nitems == 0) return HT_OK;
+  const dim3 grid((unsigned)nitems);
+  if (lmax <= 16)
+    hipLaunchKernelGGL((k_gemm_nn<T, 16, false>), grid, dim3(256), 0, s, A, W, Y, sd, wk, items, gpart);
+  else if (lmax <= 32)
+    hipLaunchKernelGGL((k_gemm_nn<T, 32, false>), grid, dim3(256), 0, s, A, W, Y, sd, wk, items, gpart);
+  else if (lmax <= 48)
+    hipLaunchKernelGGL((k_gemm_nn<T, 48, false>), grid, dim3(256), 0, s, A, W, Y, sd, wk, items, gpart);
+  else if (lmax <= 64)
+    hipLaunchKernelGGL((k_gemm_nn<T, 64, false>), grid, dim3(256), 0, s, A, W, Y, sd, wk, items, gpart);
+  else
+    hipLaunchKernelGGL((k_gemm_nn<T, 80, false>), grid, dim3(256), 0, s, A, W, Y, sd, wk, items, gpart);
   HT_CHECK_LAUNCH();
   return HT_OK;
 }
 
 template <typename T>
-int launch_gemm_tn(const T* A, int64_t sA, int lda, const T* Q, int64_t sQ, int ldq, T* Z, int64_t sZ, int ldz,
-                   int m, int n, int l, int P, double* gpart, hipStream_t s) {
-  if (l > HT_MAX_WIDTH) HT_FAIL(HT_ERR_UNSUPPORTED, "sketch width above HT_MAX_WIDTH");
-  dim3 grid((unsigned)ceil_div(n, TM), (unsigned)P);
-  HT_WIDTH_DISPATCH(l, k_gemm_tn, grid, dim3(256), 0, s, A, sA, lda, Q, sQ, ldq, Z, sZ, ldz, m, n, l, gpart);
+int launch_recon_qk(const T* Q, const T* K, T* QK, const SliceDesc* sd, const int2* wk, const int2* items, int nitems,
+                    int lmax, hipStream_t s) {
+  if (lmax > HT_MAX_WIDTH) HT_FAIL(HT_ERR_UNSUPPORTED, "sketch width above HT_MAX_WIDTH");
+  if (nitems == 0) return HT_OK;
+  const dim3 grid((unsigned)nitems);
+  double* const none = nullptr;
+  if (lmax <= 16)
+    hipLaunchKernelGGL((k_gemm_nn<T, 16, true>), grid, dim3(256), 0, s, Q, K, QK, sd, wk, items, none);
+  else if (lmax <= 32)
+    hipLaunchKernelGGL((k_gemm_nn<T, 32, true>), grid, dim3(256), 0, s, Q, K, QK, sd, wk, items, none);
+  else if (lmax <= 48)
+    hipLaunchKernelGGL((k_gemm_nn<T, 48, true>), grid, dim3(256), 0, s, Q, K, QK, sd, wk, items, none);
+  else if (lmax <= 64)
+    hipLaunchKernelGGL((k_gemm_nn<T, 64, true>), grid, dim3(256), 0, s, Q, K, QK, sd, wk, items, none);
+  else
+    hipLaunchKernelGGL((k_gemm_nn<T, 80, true>), grid, dim3(256), 0, s, Q, K, QK, sd, wk, items, none);
   HT_CHECK_LAUNCH();
   return HT_OK;
 }
 
 template <typename T>
-int launch_gemm_nt(const T* X, int64_t sX, int ldx, const T* W, int64_t sW, int ldw, T* C, int64_t sC, int ldc,
-                   int m, int n, int l, int P, hipStream_t s) {
-  dim3 grid((unsigned)ceil_div(m, 64), (unsigned)ceil_div(n, 64), (unsigned)P);
-  hipLaunchKernelGGL(k_gemm_nt<T>, grid, dim3(256), 0, s, X, sX, ldx, W, sW, ldw, C, sC, ldc, m, n, l);
+int launch_gemm_tn(const T* A, const T* Q, T* Z, const SliceDesc* sd, const int2* wk, const int2* items, int nitems,
+                   int lmax, double* gpart, hipStream_t s) {
+  if (lmax > HT_MAX_WIDTH) HT_FAIL(HT_ERR_UNSUPPORTED, "sketch width above HT_MAX_WIDTH");
+  if (nitems == 0) return HT_OK;
+  const dim3 grid((unsigned)nitems);
+  if (lmax <= 16)
+    hipLaunchKernelGGL((k_gemm_tn<T, 16>), grid, dim3(256), 0, s, A, Q, Z, sd, wk, items, gpart);
+  else if (lmax <= 32)
+    hipLaunchKernelGGL((k_gemm_tn<T, 32>), grid, dim3(256), 0, s, A, Q, Z, sd, wk, items, gpart);
+  else if (lmax <= 48)
+    hipLaunchKernelGGL((k_gemm_tn<T, 48>), grid, dim3(256), 0, s, A, Q, Z, sd, wk, items, gpart);
+  else if (lmax <= 64)
+    hipLaunchKernelGGL((k_gemm_tn<T, 64>), grid, dim3(256), 0, s, A, Q, Z, sd, wk, items, gpart);
+  else
+    hipLaunchKernelGGL((k_gemm_tn<T, 80>), grid, dim3(256), 0, s, A, Q, Z, sd, wk, items, gpart);
   HT_CHECK_LAUNCH();
   return HT_OK;
 }
 
-#define HT_INST(T)                                                                                              \
-  template int launch_gemm_nn<T>(const T*, int64_t, int, const T*, int64_t, int, T*, int64_t, int, int, int, int, \
-                                 int, double*, hipStream_t);                                                    \
-  template int launch_gemm_tn<T>(const T*, int64_t, int, const T*, int64_t, int, T*, int64_t, int, int, int, int, \
-                                 int, double*, hipStream_t);                                                    \
-  template int launch_gemm_nt<T>(const T*, int64_t, int, const T*, int64_t, int, T*, int64_t, int, int, int, int, \
-                                 int, hipStream_t);
+template <typename T>
+int launch_gemm_nt(const T* X, const T* W, T* C, const SliceDesc* sd, const int2* wk, const int2* items, int nitems,
+                   hipStream_t s) {
+  if (nitems == 0) return HT_OK;
+  hipLaunchKernelGGL(k_gemm_nt<T>, dim3((unsigned)nitems), dim3(256), 0, s, X, W, C, sd, wk, items);
+  HT_CHECK_LAUNCH();
+  return HT_OK;
+}
+
+#define HT_INST(T)                                                                                                  \
+  template int launch_gemm_nn<T>(const T*, const T*, T*, const SliceDesc*, const int2*, const int2*, int, int,     \
+                                 double*, hipStream_t);                                                             \
+  template int launch_recon_qk<T>(const T*, const T*, T*, const SliceDesc*, const int2*, const int2*, int, int,    \
+                                  hipStream_t);                                                                     \
+  template int launch_gemm_tn<T>(const T*, const T*, T*, const SliceDesc*, const int2*, const int2*, int, int,     \
+                                 double*, hipStream_t);                                                             \
+  template int launch_gemm_nt<T>(const T*, const T*, T*, const SliceDesc*, const int2*, const int2*, int,          \
+                                 hipStream_t);
 HT_INST(float)
 HT_INST(double)
 

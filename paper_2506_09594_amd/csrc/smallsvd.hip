@@ -1,7 +1,8 @@
 // Small projected SVD and shrinkage, one workgroup per slice, FP64.
 //
-// Inputs are Gram partials written by earlier kernels: those of the basis Q1
-// (the last CholeskyQR pass of the sketch) and those of Bt = A_j^T Q1.  The
+// One workgroup per slice of the slice table.  Inputs are Gram partials
+// written by earlier kernels: those of the basis Q1 (the last CholeskyQR pass
+// of the sketch) and those of Bt = A_j^T Q1.  The
 // second CholeskyQR step is applied here in the l x l space: with
 // R2 = chol(Q1^T Q1) the orthonormal basis is Q = Q1 R2^{-1}, so
 //   B = Q^T A_j = R2^{-T} Bt^T,   W = B B^T = R2^{-T} (Bt^T Bt) R2^{-1}.
@@ -69,13 +70,26 @@ __device__ __forceinline__ void schur2(double app, double aqq, double apq, doubl
 }
 
 template <typename T, int LB>
-__global__ __launch_bounds__(NT) void k_smallsvd(double* __restrict__ g2, int nt_q, double delta_rel,
-                                                 const double* __restrict__ gw, int nt_b, int l, int kkeep,
-                                                 double tau_host, const double* __restrict__ mu_dev, Penalty pen,
-                                                 T* __restrict__ Kall, double* __restrict__ sigma_out,
+__global__ __launch_bounds__(NT) void k_smallsvd(double* __restrict__ g2_all, const double* __restrict__ gw_all,
+                                                 const SliceDesc* __restrict__ sd, const int2* __restrict__ wk,
+                                                 int prod_rows, double tau_host, const double* __restrict__ tau_dev,
+                                                 const double* __restrict__ mu_dev, Penalty pen,
+                                                 T* __restrict__ Kall, double* __restrict__ sigma_out, int sigma_ld,
                                                  int* __restrict__ kept_out) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
+  __shared__ double s_scr;
+  __shared__ int s_rot[2], s_kept, s_step[2];  // flags double-buffered by parity
+
+  const int j = blockIdx.x;
+  const int tid = threadIdx.x;
+  const SliceDesc d = sd[j];
+  const int l = slice_width(d, wk, j), kkeep = slice_kept(d, wk, j);
   const int gp = l + 1;
+  const int nt_q = (d.n1 + 63) / 64, nt_b = (d.n2 + prod_rows - 1) / prod_rows;
+  const double delta_rel = 8.0 * (double)d.n1 * 2.220446049250313e-16;
+  const double tau = mu_dev ? 1.0 / (*mu_dev) : (tau_dev ? tau_dev[d.tensor] : tau_host);
+  const int ll = l * l;
+  double* gq = g2_all + d.g2;  // the slice's partials; reused to park R2^{-1}
   double* B0 = reinterpret_cast<double*>(smem_raw);  // G, then a Jacobi buffer
   double* B1 = B0 + (size_t)l * gp;                  // W~, then W
   double* V = B1 + (size_t)l * gp;                   // R2^{-1}, then eigenvectors
@@ -88,17 +102,9 @@ __global__ __launch_bounds__(NT) void k_smallsvd(double* __restrict__ g2, int nt
   int* perm = reinterpret_cast<int*>(rs + 64);
   int* rp = perm + LMAX;
   int* rq = rp + 64;
-  __shared__ double s_scr;
-  __shared__ int s_rot[2], s_kept, s_step[2];  // flags double-buffered by parity
-
-  const int j = blockIdx.x;
-  const int tid = threadIdx.x;
-  const double tau = mu_dev ? 1.0 / (*mu_dev) : tau_host;
-  const int ll = l * l;
-  double* gq = g2 + (int64_t)j * nt_q * ll;  // the slice's partials; reused to park R2^{-1}
 
   sum_gram_partials(B0, gp, gq, nt_q, l);
-  sum_gram_partials(B1, gp, gw + (int64_t)j * nt_b * ll, nt_b, l);
+  sum_gram_partials(B1, gp, gw_all + d.g1, nt_b, l);
   __syncthreads();
   if constexpr (LB <= 64) {
     // wave 0: R2 = chol(G2) and R2^{-1} in registers (lane b owns column b)
@@ -269,8 +275,10 @@ __global__ __launch_bounds__(NT) void k_smallsvd(double* __restrict__ g2, int nt
     }
     wv[i] = w;
     sig[i] = sv;
-    if (sigma_out) sigma_out[(int64_t)j * l + i] = sv;
+    if (sigma_out) sigma_out[(int64_t)j * sigma_ld + i] = sv;
   }
+  if (sigma_out)
+    for (int i = l + tid; i < sigma_ld; i += NT) sigma_out[(int64_t)j * sigma_ld + i] = 0.0;
   __syncthreads();
   double* Kb = Wn;  // free buffer
   double* Ri = Wc;  // R2^{-1} reloaded from global
@@ -293,7 +301,7 @@ __global__ __launch_bounds__(NT) void k_smallsvd(double* __restrict__ g2, int nt
     V[a * gp + b] = t;
   }
   __syncthreads();
-  T* K = Kall + (int64_t)j * ll;
+  T* K = Kall + d.kq;
   for (int idx = tid; idx < ll; idx += NT) {  // K' = R2^{-1} V, column-major
     const int a = idx % l, b = idx / l;
     double t = 0.0;
@@ -306,29 +314,29 @@ __global__ __launch_bounds__(NT) void k_smallsvd(double* __restrict__ g2, int nt
 }  // namespace
 
 template <typename T>
-int launch_smallsvd(double* g2, int ntiles_q, int m_q, const double* gw, int ntiles_b, int l, int k, int P,
-                    double tau, const double* mu_dev, Penalty pen, T* K, double* sigma_out, int* kept_out,
-                    hipStream_t s) {
-  if (l > HT_MAX_WIDTH) HT_FAIL(HT_ERR_UNSUPPORTED, "sketch width above HT_MAX_WIDTH");
-  const double delta_rel = 8.0 * (double)m_q * 2.220446049250313e-16;
+int launch_smallsvd(double* g2, const double* gw, const SliceDesc* sd, const int2* wk, int nslices, int lmax,
+                    int prod_rows, double tau, const double* tau_dev, const double* mu_dev, Penalty pen, T* K,
+                    double* sigma_out, int* kept_out, hipStream_t s) {
+  if (lmax > HT_MAX_WIDTH) HT_FAIL(HT_ERR_UNSUPPORTED, "sketch width above HT_MAX_WIDTH");
+  if (nslices == 0) return HT_OK;
   auto launch = [&](auto kern) -> int {
     int rc = ensure_dynamic_lds((const void*)kern, svd_lds_bytes(HT_MAX_WIDTH));
     if (rc) return rc;
-    hipLaunchKernelGGL(kern, dim3((unsigned)P), dim3(NT), svd_lds_bytes(l), s, g2, ntiles_q, delta_rel, gw,
-                       ntiles_b, l, k, tau, mu_dev, pen, K, sigma_out, kept_out);
+    hipLaunchKernelGGL(kern, dim3((unsigned)nslices), dim3(NT), svd_lds_bytes(lmax), s, g2, gw, sd, wk, prod_rows,
+                       tau, tau_dev, mu_dev, pen, K, sigma_out, lmax, kept_out);
     HT_CHECK_LAUNCH();
     return HT_OK;
   };
-  if (l <= 16) return launch(k_smallsvd<T, 16>);
-  if (l <= 32) return launch(k_smallsvd<T, 32>);
-  if (l <= 48) return launch(k_smallsvd<T, 48>);
-  if (l <= 64) return launch(k_smallsvd<T, 64>);
+  if (lmax <= 16) return launch(k_smallsvd<T, 16>);
+  if (lmax <= 32) return launch(k_smallsvd<T, 32>);
+  if (lmax <= 48) return launch(k_smallsvd<T, 48>);
+  if (lmax <= 64) return launch(k_smallsvd<T, 64>);
   return launch(k_smallsvd<T, 80>);
 }
 
-template int launch_smallsvd<float>(double*, int, int, const double*, int, int, int, int, double, const double*,
-                                    Penalty, float*, double*, int*, hipStream_t);
-template int launch_smallsvd<double>(double*, int, int, const double*, int, int, int, int, double, const double*,
-                                     Penalty, double*, double*, int*, hipStream_t);
+template int launch_smallsvd<float>(double*, const double*, const SliceDesc*, const int2*, int, int, int, double,
+                                    const double*, const double*, Penalty, float*, double*, int*, hipStream_t);
+template int launch_smallsvd<double>(double*, const double*, const SliceDesc*, const int2*, int, int, int, double,
+                                     const double*, const double*, Penalty, double*, double*, int*, hipStream_t);
 
 }  // namespace ht

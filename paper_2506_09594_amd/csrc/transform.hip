@@ -87,16 +87,25 @@ __device__ __forceinline__ void mode_exact(T* tile, int TP, int lgTP, int s, int
   }
 }
 
-// TO = T, or uint16_t for BF16 output (rounded to nearest even).
+// One workgroup per work item (tensor, first tube position).  TO = T, or
+// uint16_t for BF16 output (rounded to nearest even).
 template <typename T, typename TO>
-__global__ __launch_bounds__(256) void k_transform(const T* __restrict__ in, TO* __restrict__ out, int64_t NT,
-                                                   int P, int TP, int lgTP, int vec, ModeTable mt,
-                                                   const T* __restrict__ table) {
+__global__ __launch_bounds__(256) void k_transform(const T* __restrict__ in_all, TO* __restrict__ out_all,
+                                                   const TensorDesc* __restrict__ tds, const int2* __restrict__ items,
+                                                   const T* __restrict__ table, int inverse, int aligned) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T* tile = reinterpret_cast<T*>(smem_raw);
   constexpr int V = 16 / sizeof(T);  // elements per 16-byte access
   constexpr int UNR = 8;
-  const int64_t t0 = (int64_t)blockIdx.x * TP;
+  const int2 item = items[blockIdx.x];
+  const TensorDesc* td = tds + item.x;
+  const int64_t NT = td->NT;
+  const int P = td->P, TP = td->TP, lgTP = td->lgTP;
+  const ModeTable* mt = inverse ? &td->inv : &td->fwd;
+  const T* in = in_all + td->x;
+  TO* out = out_all + td->x;
+  const int vec = aligned && (NT % V == 0) && (TP % V == 0) && (td->x % V == 0);
+  const int64_t t0 = item.y;
   const int64_t rem = NT - t0;
   const int tp = rem < TP ? (int)rem : TP;
   const int total = TP * P;
@@ -143,10 +152,11 @@ __global__ __launch_bounds__(256) void k_transform(const T* __restrict__ in, TO*
   __syncthreads();
 
   // ---- modes ---------------------------------------------------------------
-  for (int m = 0; m < mt.nmodes; ++m) {
-    const int n = mt.n[m];
-    const int s = mt.stride[m];
-    const T* U = table + mt.off[m];
+  const int nmodes = mt->nmodes;
+  for (int m = 0; m < nmodes; ++m) {
+    const int n = mt->n[m];
+    const int s = mt->stride[m];
+    const T* U = table + mt->off[m];
     const int nfib = total / n;
     switch (n) {
       case 2: mode_exact<T, 2>(tile, TP, lgTP, s, nfib, U); break;
@@ -173,9 +183,24 @@ __global__ __launch_bounds__(256) void k_transform(const T* __restrict__ in, TO*
 
   // ---- store ---------------------------------------------------------------
   if constexpr (!std::is_same<TO, T>::value) {
-    for (int idx = tid; idx < total; idx += nt) {
-      const int j = idx >> lgTP, t = idx & (TP - 1);
-      if (t < tp) out[(int64_t)j * NT + t0 + t] = f32_to_bf16_rne((float)tile[idx]);
+    if (vec) {  // four BF16 values (8 bytes) per store
+      typedef unsigned short u16x4 __attribute__((ext_vector_type(4)));
+      const int nq = total / 4;
+      for (int q = tid; q < nq; q += nt) {
+        const int idx = 4 * q;
+        const int j = idx >> lgTP, t = idx & (TP - 1);
+        if (t < tp) {
+          u16x4 v;
+#pragma unroll
+          for (int e = 0; e < 4; ++e) v[e] = f32_to_bf16_rne((float)tile[idx + e]);
+          *reinterpret_cast<u16x4*>(out + (int64_t)j * NT + t0 + t) = v;
+        }
+      }
+    } else {
+      for (int idx = tid; idx < total; idx += nt) {
+        const int j = idx >> lgTP, t = idx & (TP - 1);
+        if (t < tp) out[(int64_t)j * NT + t0 + t] = f32_to_bf16_rne((float)tile[idx]);
+      }
     }
   } else if (vec) {
     using VT = __attribute__((ext_vector_type(V))) T;
@@ -198,8 +223,7 @@ __global__ __launch_bounds__(256) void k_transform(const T* __restrict__ in, TO*
   }
 }
 
-int transform_tile_width(int64_t P, size_t elem_bytes) {
-  const size_t budget = 64 * 1024;
+int transform_tile_width(int64_t P, size_t elem_bytes, size_t budget) {
   int64_t tp = 256;
   while (tp > 1 && (size_t)(tp * P) * elem_bytes > budget) tp >>= 1;
   if ((size_t)(tp * P) * elem_bytes > budget) return 0;
@@ -207,83 +231,73 @@ int transform_tile_width(int64_t P, size_t elem_bytes) {
 }
 
 template <typename T, typename TO>
-int launch_transform_impl(const T* in, TO* out, int64_t NT, int P, const ModeTable& mt, const T* table,
-                          hipStream_t stream) {
-  if (mt.nmodes == 0 && std::is_same<TO, T>::value) {
-    if ((const void*)in != (const void*)out)
-      HT_CHECK_HIP(hipMemcpyAsync(out, in, sizeof(T) * NT * P, hipMemcpyDeviceToDevice, stream));
-    return HT_OK;
-  }
-  const int TP = transform_tile_width(P, sizeof(T));
-  if (TP == 0) HT_FAIL(HT_ERR_UNSUPPORTED, "too many face slices for the LDS transform tile");
-  int lgTP = 0;
-  while ((1 << lgTP) < TP) ++lgTP;
-  constexpr int V = 16 / sizeof(T);
-  const int vec = (NT % V == 0) && (TP % V == 0) && (reinterpret_cast<uintptr_t>(in) % 16 == 0) &&
-                  (reinterpret_cast<uintptr_t>(out) % 16 == 0);
-  const size_t lds = sizeof(T) * (size_t)TP * P;
-  const int64_t blocks = ceil_div(NT, TP);
-  hipLaunchKernelGGL((k_transform<T, TO>), dim3((unsigned)blocks), dim3(256), lds, stream, in, out, NT, P, TP, lgTP,
-                     vec, mt, table);
+int launch_transform(const T* in, TO* out, const TensorDesc* tds, const int2* items, int nitems, size_t lds,
+                     const T* table, int inverse, hipStream_t stream) {
+  if (nitems == 0) return HT_OK;
+  if (lds > 160 * 1024) HT_FAIL(HT_ERR_UNSUPPORTED, "transform tile above the LDS size");
+  int rc = ensure_dynamic_lds((const void*)k_transform<T, TO>, 160 * 1024);
+  if (rc) return rc;
+  const int aligned = (reinterpret_cast<uintptr_t>(in) % 16 == 0) && (reinterpret_cast<uintptr_t>(out) % 16 == 0);
+  hipLaunchKernelGGL((k_transform<T, TO>), dim3((unsigned)nitems), dim3(256), lds, stream, in, out, tds, items, table,
+                     inverse, aligned);
   HT_CHECK_LAUNCH();
   return HT_OK;
 }
 
-template <typename T>
-int launch_transform(const T* in, T* out, int64_t NT, int P, const ModeTable& mt, const T* table,
-                     hipStream_t stream) {
-  return launch_transform_impl<T, T>(in, out, NT, P, mt, table, stream);
-}
-
-int launch_transform_bf16(const float* in, uint16_t* out, int64_t NT, int P, const ModeTable& mt,
-                          const float* table, hipStream_t stream) {
-  return launch_transform_impl<float, uint16_t>(in, out, NT, P, mt, table, stream);
-}
-
-template int launch_transform<float>(const float*, float*, int64_t, int, const ModeTable&, const float*, hipStream_t);
-template int launch_transform<double>(const double*, double*, int64_t, int, const ModeTable&, const double*,
-                                      hipStream_t);
+template int launch_transform<float, float>(const float*, float*, const TensorDesc*, const int2*, int, size_t,
+                                            const float*, int, hipStream_t);
+template int launch_transform<double, double>(const double*, double*, const TensorDesc*, const int2*, int, size_t,
+                                              const double*, int, hipStream_t);
+template int launch_transform<float, uint16_t>(const float*, uint16_t*, const TensorDesc*, const int2*, int, size_t,
+                                               const float*, int, hipStream_t);
 
 // ---------------------------------------------------------------------------
-// Gaussian sketch matrices Omega_j (n2 x l, column-major), one per slice,
-// keyed by the canonical slice index (identity for real transforms).
+// Gaussian sketch matrices Omega_s (n2 x l, column-major), one per slice,
+// keyed by (seed; group, slice index within the tensor, call, stream).  The
+// n2 * l entries of slice s go to its table offset, or to s * dense_stride when
+// dense_stride > 0; the draw of a narrower width is the prefix of a wider one.
 // ---------------------------------------------------------------------------
 template <typename T>
-__global__ __launch_bounds__(256) void k_omega(T* __restrict__ om, double* __restrict__ om64, int64_t per_slice,
-                                               uint32_t call, const int32_t* __restrict__ call_dev, uint32_t stream_id,
-                                               uint64_t seed, const int32_t* __restrict__ canon) {
-  const int j = blockIdx.y;
-  const uint32_t key = canon ? (uint32_t)canon[j] : (uint32_t)j;
+__global__ __launch_bounds__(256) void k_omega(T* __restrict__ om, double* __restrict__ om64,
+                                               const SliceDesc* __restrict__ sd, const int2* __restrict__ wk,
+                                               uint32_t call, const int32_t* __restrict__ call_dev,
+                                               uint32_t stream_base, uint64_t seed, int64_t dense_stride) {
+  const int s = blockIdx.x;
+  const SliceDesc d = sd[s];
+  const int64_t base = dense_stride > 0 ? (int64_t)s * dense_stride : d.z;
+  const int64_t per_slice = (int64_t)d.n2 * slice_width(d, wk, s);
   const uint32_t c = call_dev ? (uint32_t)(*call_dev) : call;
   const int64_t ngroups = (per_slice + 3) / 4;
-  for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < ngroups; g += (int64_t)gridDim.x * blockDim.x) {
+  for (int64_t g = (int64_t)blockIdx.y * blockDim.x + threadIdx.x; g < ngroups; g += (int64_t)gridDim.y * blockDim.x) {
     double z[4];
-    gaussian4((uint64_t)g, key, c, stream_id, seed, z);
+    gaussian4((uint64_t)g, (uint32_t)d.local, c, stream_base + (uint32_t)d.tensor, seed, z);
 #pragma unroll
     for (int lane = 0; lane < 4; ++lane) {
       const int64_t e = 4 * g + lane;
       if (e < per_slice) {
-        if (om) om[(int64_t)j * per_slice + e] = (T)z[lane];
-        if (om64) om64[(int64_t)j * per_slice + e] = z[lane];
+        if (om) om[base + e] = (T)z[lane];
+        if (om64) om64[base + e] = z[lane];
       }
     }
   }
 }
 
 template <typename T>
-int launch_omega(T* om, double* om64, int P, int64_t per_slice, uint32_t call, const int32_t* call_dev,
-                 uint32_t stream_id, uint64_t seed, const int32_t* canon, hipStream_t stream) {
-  const int64_t ngroups = (per_slice + 3) / 4;
-  const unsigned gx = (unsigned)std::min<int64_t>(ceil_div(ngroups, 256), 64);
-  hipLaunchKernelGGL(k_omega<T>, dim3(gx, (unsigned)P), dim3(256), 0, stream, om, om64, per_slice, call, call_dev,
-                     stream_id, seed, canon);
+int launch_omega(T* om, double* om64, const SliceDesc* sd, const int2* wk, int nslices, int64_t max_per_slice,
+                 uint32_t call, const int32_t* call_dev, uint32_t stream_base, uint64_t seed, int64_t dense_stride,
+                 hipStream_t stream) {
+  if (nslices == 0) return HT_OK;
+  const int64_t ngroups = (max_per_slice + 3) / 4;
+  const unsigned gy = (unsigned)std::max<int64_t>(1, std::min<int64_t>(ceil_div(ngroups, 256), 64));
+  hipLaunchKernelGGL(k_omega<T>, dim3((unsigned)nslices, gy), dim3(256), 0, stream, om, om64, sd, wk, call, call_dev,
+                     stream_base, seed, dense_stride);
   HT_CHECK_LAUNCH();
   return HT_OK;
 }
 
-template int launch_omega<float>(float*, double*, int, int64_t, uint32_t, const int32_t*, uint32_t, uint64_t,
-                                 const int32_t*, hipStream_t);
-template int launch_omega<double>(double*, double*, int, int64_t, uint32_t, const int32_t*, uint32_t, uint64_t,
-                                  const int32_t*, hipStream_t);
+template int launch_omega<float>(float*, double*, const SliceDesc*, const int2*, int, int64_t, uint32_t,
+                                 const int32_t*, uint32_t, uint64_t, int64_t, hipStream_t);
+template int launch_omega<double>(double*, double*, const SliceDesc*, const int2*, int, int64_t, uint32_t,
+                                  const int32_t*, uint32_t, uint64_t, int64_t, hipStream_t);
 
 }  // namespace ht

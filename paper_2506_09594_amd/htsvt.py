@@ -29,14 +29,15 @@ PRECISIONS = {"fp64": 0, "fp32": 1, "bf16": 2}
 PENALTIES = {"l1": 0, "mcp": 1, "scad": 2, "log": 3, "capped_l1": 4}
 MODELS = {"completion": 0, "rpca": 1}
 REGIONS = {"A": 0, "omega": 1, "Q": 2, "Bt": 3, "K": 4, "QK": 5, "C": 6, "Lnew": 7, "Xin": 8, "state": 9,
-           "gram": 10, "gram_q": 11}
+           "gram": 10, "gram_q": 11, "widths": 12, "call": 13}
 
 # Symbols the header declares (checked by the CPU test suite).
 EXPORTS = [
     "ht_version", "ht_last_error", "ht_plan_create", "ht_plan_destroy", "ht_plan_workspace_size",
     "ht_plan_info", "ht_plan_workspace_region", "ht_gnhtsvt", "ht_omega_fp64", "ht_transform",
     "ht_admm_workspace_size", "ht_admm_init", "ht_admm_iterate", "ht_admm_get_stats",
-    "ht_profile_enable", "ht_profile_read",
+    "ht_profile_enable", "ht_profile_read", "ht_batch_plan_create", "ht_batch_info", "ht_batch_tensor_info",
+    "ht_batch_gnhtsvt", "ht_plan_set_tuning", "ht_plan_get_tuning", "ht_plan_autotune", "ht_plan_graph_enable",
 ]
 STAGES = ["transform_fwd", "omega", "sketch_nn", "cholqr", "sketch_tn", "smallsvd", "recon_qk", "recon_nt",
           "transform_inv", "admm_update"]
@@ -101,6 +102,18 @@ _sig = {
     "ht_profile_enable": (ctypes.c_int, [_vp, ctypes.c_int]),
     "ht_profile_read": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int),
                                        ctypes.c_int]),
+    "ht_batch_plan_create": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(_PlanDesc), ctypes.POINTER(_vp)]),
+    "ht_batch_info": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int)]),
+    "ht_batch_tensor_info": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.POINTER(ctypes.c_int64),
+                                            ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64),
+                                            ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]),
+    "ht_batch_gnhtsvt": (ctypes.c_int, [_vp, _vp, _vp, _vp, ctypes.POINTER(_Penalty), ctypes.c_uint32,
+                                        _vp, ctypes.c_size_t, _vp, _vp, _vp]),
+    "ht_plan_set_tuning": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int]),
+    "ht_plan_get_tuning": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]),
+    "ht_plan_autotune": (ctypes.c_int, [_vp, _vp, _vp, _vp, ctypes.c_size_t, _vp, ctypes.c_int,
+                                        ctypes.POINTER(ctypes.c_double)]),
+    "ht_plan_graph_enable": (ctypes.c_int, [_vp, ctypes.c_int]),
 }
 for _name, (_res, _args) in _sig.items():
     _f = getattr(_lib, _name)
@@ -144,45 +157,82 @@ def from_device(t, dims):
     return t.detach().double().cpu().numpy().reshape(tuple(dims), order="F")
 
 
+def _make_desc(dims, transforms, r, p, q, precision, seed, stream_id, custom, keep):
+    dims = [int(n) for n in dims]
+    if not 2 <= len(dims) <= MAX_ORDER:
+        raise ValueError("order must be in [2, 8]")
+    transforms = transforms if transforms is not None else ["dct2"] * (len(dims) - 2)
+    d = _PlanDesc()
+    d.order = len(dims)
+    for i, n in enumerate(dims):
+        d.dims[i] = n
+    for k, kind in enumerate(transforms):
+        d.transform[k + 2] = TRANSFORMS[kind]
+        if kind == "custom":
+            U = np.ascontiguousarray(np.asarray(custom[k], dtype=np.float64))
+            keep.append(U)
+            d.custom[k + 2] = U.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    d.r, d.p, d.q = int(r), int(p), int(q)
+    d.precision = PRECISIONS[precision]
+    d.seed = int(seed)
+    d.stream_id = int(stream_id)
+    return d
+
+
 class Plan:
     """One tensor shape + transforms + sketch parameters on the current device."""
 
     def __init__(self, dims, transforms=None, r=5, p=5, q=1, precision="fp32", seed=0, stream_id=0, custom=None):
-        dims = [int(d) for d in dims]
-        if not 2 <= len(dims) <= MAX_ORDER:
-            raise ValueError("order must be in [2, 8]")
-        transforms = transforms if transforms is not None else ["dct2"] * (len(dims) - 2)
-        d = _PlanDesc()
-        d.order = len(dims)
         self._custom_keep = []
-        for i, n in enumerate(dims):
-            d.dims[i] = n
-        for k, kind in enumerate(transforms):
-            d.transform[k + 2] = TRANSFORMS[kind]
-            if kind == "custom":
-                U = np.ascontiguousarray(np.asarray(custom[k], dtype=np.float64))
-                self._custom_keep.append(U)
-                d.custom[k + 2] = U.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
-        d.r, d.p, d.q = int(r), int(p), int(q)
-        d.precision = PRECISIONS[precision]
-        d.seed = int(seed)
-        d.stream_id = int(stream_id)
+        d = _make_desc(dims, transforms, r, p, q, precision, seed, stream_id, custom, self._custom_keep)
         h = _vp()
         _check(_lib.ht_plan_create(ctypes.byref(d), ctypes.byref(h)))
         self._h = h
-        self.dims = tuple(dims)
-        self.transforms = list(transforms)
-        self.precision = precision
+        self.dims = tuple(int(n) for n in dims)
+        self.transforms = list(transforms) if transforms is not None else ["dct2"] * (len(dims) - 2)
         self.r, self.p, self.q = int(r), int(p), int(q)
+        self._finish(precision)
+
+    def _finish(self, precision):
+        self.precision = precision
+        h = self._h
         n_sl, w, k = ctypes.c_int64(), ctypes.c_int(), ctypes.c_int()
         _check(_lib.ht_plan_info(h, ctypes.byref(n_sl), ctypes.byref(w), ctypes.byref(k)))
         self.n_slices, self.width, self.kept = n_sl.value, w.value, k.value
-        self.N = int(np.prod(dims))
+        nn = ctypes.c_int64()
+        _check(_lib.ht_batch_info(h, ctypes.byref(nn), None))
+        self.N = nn.value
         sz = ctypes.c_size_t()
         _check(_lib.ht_plan_workspace_size(h, ctypes.byref(sz)))
         self.workspace_bytes = sz.value
         _check(_lib.ht_admm_workspace_size(h, ctypes.byref(sz)))
         self.admm_workspace_bytes = sz.value
+
+    def set_tuning(self, prod_rows=0, transform_lds_kib=0):
+        """Tile rows of the sketch products (64 or 128) and LDS budget of a
+        transform tile (32, 64 or 128 KiB); 0 keeps the current value."""
+        _check(_lib.ht_plan_set_tuning(self._h, int(prod_rows), int(transform_lds_kib)))
+
+    def tuning(self):
+        a, b = ctypes.c_int(), ctypes.c_int()
+        _check(_lib.ht_plan_get_tuning(self._h, ctypes.byref(a), ctypes.byref(b)))
+        return {"prod_rows": a.value, "transform_lds_kib": b.value}
+
+    def autotune(self, X, workspace=None, repeats=3):
+        """Time the tile choices on X and keep the fastest; returns (tuning, ms)."""
+        import torch
+        if workspace is None:
+            workspace = self.alloc_workspace()
+        out = torch.empty_like(X)
+        wp, wn = self._aligned(workspace)
+        ms = ctypes.c_double()
+        _check(_lib.ht_plan_autotune(self._h, _ptr(X), _ptr(out), wp, wn, _stream(), int(repeats), ctypes.byref(ms)))
+        return self.tuning(), ms.value
+
+    def graph(self, on=True):
+        """Record the launch sequence as a HIP graph on the next call and replay it
+        on later calls with the same buffers (the call index is updated in place)."""
+        _check(_lib.ht_plan_graph_enable(self._h, 1 if on else 0))
 
     @property
     def torch_dtype(self):
@@ -260,6 +310,76 @@ class Plan:
         if out is None:
             out = torch.empty_like(X)
         _check(_lib.ht_transform(self._h, _ptr(X), _ptr(out), 1 if inverse else 0, _stream()))
+        return out
+
+
+class BatchPlan(Plan):
+    """Many tensors of different shapes (orders, sizes, ranks) in one plan: every
+    stage of the t-SVT is one launch over all their slices.  The tensors live in
+    one packed device buffer, tensor t at element offset offsets[t], each in
+    Fortran order."""
+
+    def __init__(self, shapes, transforms=None, r=5, p=5, q=1, precision="fp32", seed=0, stream_id=0):
+        n = len(shapes)
+        rs = list(r) if np.ndim(r) else [r] * n
+        ps = list(p) if np.ndim(p) else [p] * n
+        trs = transforms if transforms is not None else [["dct2"] * (len(s) - 2) for s in shapes]
+        self._custom_keep = []
+        descs = (_PlanDesc * n)()
+        for t in range(n):
+            descs[t] = _make_desc(shapes[t], trs[t], rs[t], ps[t], q, precision, seed, stream_id, None,
+                                  self._custom_keep)
+        h = _vp()
+        _check(_lib.ht_batch_plan_create(n, descs, ctypes.byref(h)))
+        self._h = h
+        self.shapes = [tuple(int(v) for v in s) for s in shapes]
+        self.transforms = trs
+        self.q = int(q)
+        self._finish(precision)
+        self.offsets, self.numels, self.first_slice, self.widths, self.kepts = [], [], [], [], []
+        for t in range(n):
+            o, nm, f = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+            w, k = ctypes.c_int(), ctypes.c_int()
+            _check(_lib.ht_batch_tensor_info(h, t, ctypes.byref(o), ctypes.byref(nm), ctypes.byref(f),
+                                             ctypes.byref(w), ctypes.byref(k)))
+            self.offsets.append(o.value)
+            self.numels.append(nm.value)
+            self.first_slice.append(f.value)
+            self.widths.append(w.value)
+            self.kepts.append(k.value)
+
+    def pack(self, arrays):
+        """list of numpy tensors -> one packed flat CUDA tensor."""
+        import torch
+        flat = np.zeros(self.N, dtype=np.float64 if self.precision == "fp64" else np.float32)
+        for t, X in enumerate(arrays):
+            flat[self.offsets[t]: self.offsets[t] + self.numels[t]] = np.asarray(X).ravel(order="F")
+        return torch.from_numpy(flat).to(device="cuda")
+
+    def unpack(self, packed):
+        host = packed.detach().double().cpu().numpy()
+        return [host[o: o + n].reshape(s, order="F") for o, n, s in zip(self.offsets, self.numels, self.shapes)]
+
+    def gnhtsvt(self, X, tau, penalty=("l1", ()), call_index=0, out=None, workspace=None, stats=False):
+        """tau: one threshold per tensor (sequence or CUDA float64 tensor)."""
+        import torch
+        if out is None:
+            out = torch.empty_like(X)
+        if workspace is None:
+            workspace = self.alloc_workspace()
+        if not torch.is_tensor(tau):
+            tau = torch.tensor(np.asarray(tau, dtype=np.float64), device="cuda")
+        wp, wn = self._aligned(workspace)
+        sig = kept = None
+        if stats:
+            sig = torch.empty(self.n_slices * self.width, dtype=torch.float64, device=X.device)
+            kept = torch.empty(self.n_slices, dtype=torch.int32, device=X.device)
+        pen = _penalty(penalty)
+        _check(_lib.ht_batch_gnhtsvt(self._h, _ptr(X), _ptr(out), _ptr(tau), ctypes.byref(pen), int(call_index),
+                                     wp, wn, _stream(), _ptr(sig), _ptr(kept)))
+        self._tau_keep = tau
+        if stats:
+            return out, sig.view(self.n_slices, self.width), kept
         return out
 
 

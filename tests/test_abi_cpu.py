@@ -41,7 +41,7 @@ def test_every_declared_symbol_is_exported(lib):
 def test_binding_covers_header(lib):
     from paper_2506_09594_amd import htsvt
     assert sorted(htsvt.EXPORTS) == _declared()
-    assert htsvt.version() == 100
+    assert htsvt.version() == 200
 
 
 def test_invalid_descriptions_rejected_before_device_work(lib):
@@ -60,3 +60,21 @@ def test_invalid_descriptions_rejected_before_device_work(lib):
     assert lib.ht_plan_create(None, ctypes.byref(h)) == htsvt.ERR_INVALID_ARG
     assert lib.ht_gnhtsvt(None, None, None, ctypes.c_double(1.0), None, 0, None, 0, None, None, None) \
         == htsvt.ERR_INVALID_ARG
+
+
+def test_batch_descriptions_rejected_before_device_work(lib):
+    from paper_2506_09594_amd import htsvt
+    h = ctypes.c_void_p()
+    descs = (htsvt._PlanDesc * 2)()
+    for d in descs:
+        d.order, d.r, d.p, d.q, d.precision = 3, 4, 2, 1, 1
+        d.dims[0], d.dims[1], d.dims[2] = 8, 8, 4
+    assert lib.ht_batch_plan_create(0, descs, ctypes.byref(h)) == htsvt.ERR_INVALID_ARG
+    assert lib.ht_batch_plan_create(2, None, ctypes.byref(h)) == htsvt.ERR_INVALID_ARG
+    descs[1].precision = 2  # precision must agree across a batch
+    assert lib.ht_batch_plan_create(2, descs, ctypes.byref(h)) == htsvt.ERR_INVALID_ARG
+    assert b"agree" in htsvt._lib.ht_last_error()
+    descs[1].precision, descs[1].q = 1, 2  # and q
+    assert lib.ht_batch_plan_create(2, descs, ctypes.byref(h)) == htsvt.ERR_INVALID_ARG
+    assert lib.ht_plan_set_tuning(None, 64, 0) == htsvt.ERR_INVALID_ARG
+    assert lib.ht_plan_graph_enable(None, 1) == htsvt.ERR_INVALID_ARG

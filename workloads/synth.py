@@ -128,3 +128,18 @@ def to_fortran_flat(X):
 
 def from_fortran_flat(flat, dims):
     return np.asarray(flat).reshape(tuple(dims), order="F")
+
+
+def batch_shapes(n_tensors, seed, orders=(3, 4, 5), modes=(4, 8, 16), n_range=(64, 512), r_range=(5, 40)):
+    """Shapes and target ranks of a batch of uneven tensors: order uniform over
+    `orders`, every transformed mode uniform over `modes`, n1 and n2 uniform
+    integers in n_range, rank uniform in r_range (all bounds inclusive)."""
+    g = rng(seed, "shapes")
+    out = []
+    for _ in range(n_tensors):
+        d = int(g.choice(orders))
+        n1, n2 = (int(v) for v in g.integers(n_range[0], n_range[1] + 1, size=2))
+        rest = tuple(int(v) for v in g.choice(modes, size=d - 2))
+        r = int(g.integers(r_range[0], r_range[1] + 1))
+        out.append(((n1, n2) + rest, r))
+    return out
