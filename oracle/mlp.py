@@ -168,12 +168,14 @@ def features(sigma, kept_prev, l_prev, anorm2, tau, iteration, n1, n2):
 # ---------------------------------------------------------------------------
 def width_from_prediction(z, p, l_fix, k_fix):
     """Predicted surviving count s = exp(z) - 1; sketch width
-    l = clamp(ceil(s) + p, p + 1, l_fix), kept k = min(l - p, k_fix) (at least 1)."""
+    l = clamp(ceil(s) + p, p + 1, l_fix) and kept count k = min(k_fix, l), the
+    fixed method's k = min(r, l) at the new width: the p extra columns are the
+    margin of the prediction, and test (i) of the fallback fires only when all
+    k values survive, i.e. when the prediction fell short by more than p."""
     s = math.expm1(z) if z < 700.0 else math.inf
     l = math.ceil(s) + p if math.isfinite(s) else l_fix
     l = int(min(max(l, p + 1), l_fix))
-    k = int(max(1, min(l - p, k_fix)))
-    return l, k
+    return l, int(min(k_fix, l))
 
 
 def needs_fallback(l, k, kept, anorm2, sigma, tau, l_fix):

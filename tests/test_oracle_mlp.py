@@ -115,9 +115,10 @@ def test_features_degenerate_slice():
 
 def test_width_rule_clamps():
     p, l_fix, k_fix = 10, 74, 64
-    assert mlp.width_from_prediction(math.log(1 + 5.0), p, l_fix, k_fix) == (15, 5)
-    assert mlp.width_from_prediction(math.log(1 + 5.2), p, l_fix, k_fix) == (16, 6)  # ceil
-    assert mlp.width_from_prediction(-50.0, p, l_fix, k_fix) == (11, 1)  # at least p + 1
+    assert mlp.width_from_prediction(math.log(1 + 5.0), p, l_fix, k_fix) == (15, 15)
+    assert mlp.width_from_prediction(math.log(1 + 5.2), p, l_fix, k_fix) == (16, 16)  # ceil
+    assert mlp.width_from_prediction(-50.0, p, l_fix, k_fix) == (11, 11)  # at least p + 1
+    assert mlp.width_from_prediction(math.log(1 + 59.5), p, l_fix, k_fix) == (70, 64)  # k = min(k_fix, l)
     assert mlp.width_from_prediction(50.0, p, l_fix, k_fix) == (74, 64)  # at most the fixed width
     assert mlp.width_from_prediction(1e4, p, l_fix, k_fix) == (74, 64)  # overflow to inf
 
