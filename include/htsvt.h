@@ -134,8 +134,12 @@ int ht_plan_info(const ht_plan* plan, int64_t* n_slices, int* width, int* kept);
  * slice; the final R2 correction is applied in the l x l space),
  * 3 B^T = A^T Q1 (n2 x l per slice), 4 K' = R2^{-1} U diag(w) U^T R2^{-T}
  * (l x l per slice), 5 Q1 K', 6 reconstructed transformed slices C,
- * 7-9 solver buffers, 10-11 FP64 Gram partials, 12 per-slice widths,
- * 13 the call index of a replayed graph.  Thin blocks of slice j start at
+ * 7-9 solver buffers, 10-11 FP64 Gram partials, 12 per-slice widths of the
+ * first sketch pass (int pairs l, k), 13 the call index of a replayed graph,
+ * learned widths: 14 widths of the redo pass, 15 widths used (l, k),
+ * 16 singular values (P x l_max doubles), 17 kept counts (P ints),
+ * 18 ||A_j||^2 (previous, current; P x 2 doubles), 19 features (P x 32
+ * floats), 20 state (ints: history valid, predicted slices, redone slices).  Thin blocks of slice j start at
  * j * align4(rows * l) elements (align4 rounds up to a multiple of 4). */
 int ht_plan_workspace_region(const ht_plan* plan, int region, size_t* offset, size_t* bytes);
 
@@ -223,6 +227,74 @@ int ht_plan_autotune(ht_plan* plan, const void* X, void* out, void* workspace, s
  * the graph.  The stream must be a created stream (INVALID_ARG for the null
  * stream, which cannot be captured).  on = 0 drops the graph. */
 int ht_plan_graph_enable(ht_plan* plan, int on);
+
+/* ---------------------------------------------------------------------------
+ * Learned sketch widths.  A small MLP (32 inputs, two ReLU layers of 128, one
+ * output; FP32) predicts from the previous call's statistics of a slice how
+ * many of its singular values survive the shrinkage.  Features of slice j
+ * (from the previous call on the same workspace, and the current tau):
+ *   0-15  sigma_i / sigma_1, i = 1..16 (0 past the width or when sigma_1 = 0)
+ *   16    log10(||A_j||^2 + 1e-30) / 10           17  (||A_j||^2 - ||B_j||^2) / ||A_j||^2 in [0, 1]
+ *   18    tau / sigma_1 in [0, 10] (10 if sigma_1 = 0)
+ *   19    fraction of the sigma above tau         20  kept / width
+ *   21-24 log(sigma_k / sigma_{k+1}), k = 2, 4, 8, 16, in [0, 10] (10 when only
+ *         sigma_{k+1} is 0, 0 when both are or k >= width)
+ *   25    log10(1 / tau) / 10 (1 if tau = 0)      26  min(call index, 200) / 100
+ *   27    log(n1 / n2)    28 log2(min(n1, n2)) / 10    29 width / 64
+ *   30    (number of sigma above tau) / 64        31  0
+ * With z the network output, s = exp(z) - 1, the slice is sketched with
+ * l = clamp(ceil(s) + p, p + 1, l_fix) columns and keeps k = min(k_fix, l)
+ * values (l_fix, k_fix: the plan's fixed width and kept count).  It is redone at
+ * the fixed width when l < l_fix and either every kept value survived
+ * (kept >= k) or sqrt(||A_j||^2 - ||B_j||^2) > tau, so the fixed-width method
+ * stays the fallback.  The first call after a reset uses the fixed widths.
+ *
+ * Parameters: one flat FP32 device vector of ht_mlp_param_count() entries,
+ * W1 (128 x 32, row-major), b1 (128), W2 (128 x 128), b2 (128), W3 (128), b3.
+ * --------------------------------------------------------------------------- */
+
+/* mode 0: fixed widths (default).  mode 1: fixed widths, statistics and
+ * features recorded in the workspace (for collecting training traces).
+ * mode 2: predicted widths with the network theta (device, caller-owned,
+ * read when each call runs).  Applies to ht_gnhtsvt, ht_batch_gnhtsvt and the
+ * solver iterations on this plan. */
+int ht_plan_learned(ht_plan* plan, int mode, const float* theta);
+
+/* Forget the previous call's statistics and clear the counters (ht_admm_init
+ * does this too). */
+int ht_plan_learned_reset(const ht_plan* plan, void* workspace, size_t workspace_bytes, void* stream);
+
+/* Read (synchronizing the stream) whether statistics are recorded, and the
+ * cumulative numbers of slices sketched at a predicted width and of those
+ * redone at the fixed width since the last reset. */
+int ht_plan_learned_counts(const ht_plan* plan, const void* workspace, void* stream, int* valid, int* predicted,
+                           int* redone);
+
+/* Test hook: redo every slice sketched at a predicted width (the output is then
+ * the fixed-width method's). */
+int ht_plan_force_fallback(ht_plan* plan, int on);
+
+/* Number of network parameters, and device workspace bytes for a gradient or
+ * training step over n samples. */
+int ht_mlp_param_count(void);
+int ht_mlp_workspace_size(int n, size_t* bytes);
+
+/* z[i] = network(X[i, :]) for n samples (X: n x 32 row-major, device). */
+int ht_mlp_forward(const float* theta, const float* X, float* z, int n, void* stream);
+
+/* Gradient of the mean squared error (1/n) sum_i (z_i - y_i)^2 with respect to
+ * theta (grad: device, ht_mlp_param_count() floats) and the loss (device
+ * float, may be NULL).  Deterministic: partial sums in a fixed order. */
+int ht_mlp_grad(const float* theta, const float* X, const float* y, int n, float* grad, float* loss,
+                void* workspace, size_t workspace_bytes, void* stream);
+
+/* One Adam step (bias-corrected; step counts from 1) on theta with moment
+ * vectors m, v (device, zero before the first step) from the gradient of the
+ * mean squared error over the n samples; loss (device, may be NULL) receives
+ * the loss before the step. */
+int ht_mlp_train_step(float* theta, float* m, float* v, int step, const float* X, const float* y, int n,
+                      float lr, float beta1, float beta2, float eps, float* loss, void* workspace,
+                      size_t workspace_bytes, void* stream);
 
 /* Per-stage timing: when enabled, every kernel launch of the plan is bracketed
  * by HIP events recorded on the launch stream.  ht_profile_read waits for the

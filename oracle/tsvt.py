@@ -123,3 +123,20 @@ def tsvt_randomized(X, tau, penalty, transforms, r, p, q, omega_list, stats=None
         stats["tail_energy"] = np.array(tail_all)
     res = tr.inverse(tr.from_slices(out, X.shape), transforms)
     return _realify(res, X)
+
+
+def tsvt_randomized_widths(X, tau, penalty, transforms, widths, kepts, q, omega_list):
+    """The per-slice randomized GNHTSVT with a width l_j and kept count k_j of
+    its own for every slice j; Omega_j is the first l_j columns of the given
+    draw (a narrower draw is the prefix of a wider one)."""
+    LX = tr.to_slices(tr.forward(X, transforms))
+    out = np.zeros_like(LX, dtype=np.complex128)
+    for j in range(LX.shape[2]):
+        Aj = LX[:, :, j]
+        l, k = int(widths[j]), int(kepts[j])
+        Q, B = sketch_slice(Aj, omega_list[j][:, :l], q)
+        ub, s, vbh = np.linalg.svd(B, full_matrices=False)
+        st = _prox_vec(penalty, s[:k], tau)
+        out[:, :, j] = (Q @ (ub[:, :k] * st[None, :])) @ vbh[:k, :]
+    res = tr.inverse(tr.from_slices(out, X.shape), transforms)
+    return _realify(res, X)

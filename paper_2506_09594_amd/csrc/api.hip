@@ -49,7 +49,7 @@ using namespace ht;
 
 // Named regions of the workspace (for introspection by the tests).
 enum { WS_A = 0, WS_OMEGA, WS_Y, WS_Z, WS_K, WS_QK, WS_C, WS_LNEW, WS_XIN, WS_STATE, WS_GP1, WS_GP2, WS_WK, WS_CALL,
-       WS_COUNT };
+       WS_WK2, WS_WKF, WS_SIG, WS_KEPT, WS_ANORM, WS_FEAT, WS_LSTATE, WS_COUNT };
 
 // Optional per-stage timing with HIP events recorded on the launch stream.
 enum { ST_TRANSFORM_FWD = 0, ST_OMEGA, ST_SKETCH_NN, ST_CHOLQR, ST_SKETCH_TN, ST_SMALLSVD, ST_RECON_QK, ST_RECON_NT,
@@ -140,6 +140,9 @@ struct ht_plan {
   Profiler* prof;
   bool graph_on;
   GraphCache* graph;
+  int learn_mode;            // 0 off, 1 track (fixed widths, features recorded), 2 predicted widths
+  const float* learn_theta;  // network parameters (device, caller-owned)
+  int force_fallback;        // redo every predicted slice at the fixed width
 };
 
 namespace {
@@ -403,17 +406,25 @@ void layout(ht_plan* pl, int64_t nY, int64_t nZ, int64_t nK, int64_t nG1, int64_
   pl->size[WS_GP2] = (size_t)nG2 * sizeof(double);
   pl->size[WS_WK] = (size_t)pl->Ptot * sizeof(int2);
   pl->size[WS_CALL] = 256;
+  pl->size[WS_WK2] = (size_t)pl->Ptot * sizeof(int2);
+  pl->size[WS_WKF] = (size_t)pl->Ptot * sizeof(int2);
+  pl->size[WS_SIG] = (size_t)pl->Ptot * pl->lmax * sizeof(double);
+  pl->size[WS_KEPT] = (size_t)pl->Ptot * sizeof(int);
+  pl->size[WS_ANORM] = (size_t)pl->Ptot * 2 * sizeof(double);
+  pl->size[WS_FEAT] = (size_t)pl->Ptot * 32 * sizeof(float);
+  pl->size[WS_LSTATE] = 256;
   pl->size[WS_LNEW] = (size_t)pl->Ntot * es;
   pl->size[WS_XIN] = (size_t)pl->Ntot * es;
   pl->size[WS_STATE] = sizeof(AdmmState);
   // t-SVT regions first, then the solver-only regions
-  const int order_[] = {WS_A,   WS_OMEGA, WS_Y,   WS_Z,    WS_K,    WS_QK,   WS_C,
-                        WS_GP1, WS_GP2,   WS_WK,  WS_CALL, WS_LNEW, WS_XIN,  WS_STATE};
+  const int order_[] = {WS_A,   WS_OMEGA, WS_Y,    WS_Z,    WS_K,     WS_QK,   WS_C,      WS_GP1,  WS_GP2,
+                        WS_WK,  WS_CALL,  WS_WK2,  WS_WKF,  WS_SIG,   WS_KEPT, WS_ANORM,  WS_FEAT, WS_LSTATE,
+                        WS_LNEW, WS_XIN,  WS_STATE};
   size_t o = 0;
   for (int r : order_) {
     pl->off[r] = o;
     o += align256(pl->size[r]);
-    if (r == WS_CALL) pl->tsvt_bytes = o;
+    if (r == WS_LSTATE) pl->tsvt_bytes = o;
   }
   pl->admm_bytes = o;
 }
@@ -484,6 +495,8 @@ int build_plan(const ht_plan_desc* descs, int n, bool batch, ht_plan** out) {
       d.k = th.k;
       d.tensor = t;
       d.local = (int32_t)j;
+      d.p = th.p;
+      d.pad = 0;
       oY += align4(th.n1 * l);
       oZ += align4(th.n2 * l);
       oK += align4(l * l);
@@ -611,7 +624,6 @@ int run_tsvt(const ht_plan* pl, const T* X, T* out, double tau, const double* ta
   const int lmax = pl->lmax;
   const int P = (int)pl->Ptot;
   const SliceDesc* sd = pl->d_slices;
-  const int2* wk = nullptr;
   T* A = ws_ptr<T>(pl, ws, WS_A);
   T* Om = ws_ptr<T>(pl, ws, WS_OMEGA);
   T* Y = ws_ptr<T>(pl, ws, WS_Y);
@@ -626,6 +638,14 @@ int run_tsvt(const ht_plan* pl, const T* X, T* out, double tau, const double* ta
   const uint16_t* Ah = reinterpret_cast<const uint16_t*>(A);  // BF16 view of the transformed tensor
   const int rows = fp64 ? 64 : pl->prod_rows;
   const int ri = rows == 128 ? 1 : 0;
+  const int mode = pl->learn_mode;
+  int2* wk1 = ws_ptr<int2>(pl, ws, WS_WK);
+  int2* wk2 = ws_ptr<int2>(pl, ws, WS_WK2);
+  int2* wkf = ws_ptr<int2>(pl, ws, WS_WKF);
+  double* sig = ws_ptr<double>(pl, ws, WS_SIG);
+  int* kept = ws_ptr<int>(pl, ws, WS_KEPT);
+  double* anorm = ws_ptr<double>(pl, ws, WS_ANORM);
+  int* lstate = ws_ptr<int>(pl, ws, WS_LSTATE);
   int rc;
   if ((rc = timed(pl, ST_TRANSFORM_FWD, s, [&] {
          if (bf16)
@@ -635,11 +655,18 @@ int run_tsvt(const ht_plan* pl, const T* X, T* out, double tau, const double* ta
                                        0, s);
        })))
     return rc;
+  if (mode) {  // ||A_j||^2 and this call's widths
+    if ((rc = launch_anorm<T>(A, bf16 ? 1 : 0, sd, P, anorm, s))) return rc;
+    if ((rc = launch_width(pl->learn_theta, mode, sd, P, lmax, sig, kept, wkf, anorm, lstate, tau, tau_dev, mu_dev,
+                           call, call_dev, ws_ptr<float>(pl, ws, WS_FEAT), wk1, s)))
+      return rc;
+  }
   if ((rc = timed(pl, ST_OMEGA, s, [&] {
-         return launch_omega<T>(Om, nullptr, sd, wk, P, pl->max_n2l, call, call_dev, pl->stream_id, pl->seed, 0, s);
+         return launch_omega<T>(Om, nullptr, sd, nullptr, P, pl->max_n2l, call, call_dev, pl->stream_id, pl->seed, 0,
+                                s);
        })))
     return rc;
-  auto sketch_nn = [&](const T* W) {
+  auto sketch_nn = [&](const T* W, const int2* wk) {
     return timed(pl, ST_SKETCH_NN, s, [&] {
       const ItemList& L = pl->it_nn[ri];
       if (bf16)
@@ -650,7 +677,7 @@ int run_tsvt(const ht_plan* pl, const T* X, T* out, double tau, const double* ta
       return launch_gemm_nn<T>(A, W, Y, sd, wk, items(pl, L), L.n, lmax, gp1, s);
     });
   };
-  auto sketch_tn = [&]() {
+  auto sketch_tn = [&](const int2* wk) {
     return timed(pl, ST_SKETCH_TN, s, [&] {
       const ItemList& L = pl->it_tn[ri];
       if (bf16) return launch_bf16_tn(Ah, (const float*)Y, (float*)Z, sd, wk, items(pl, L), L.n, lmax, rows, gp1, s);
@@ -660,37 +687,60 @@ int run_tsvt(const ht_plan* pl, const T* X, T* out, double tau, const double* ta
       return launch_gemm_tn<T>(A, Y, Z, sd, wk, items(pl, L), L.n, lmax, gp1, s);
     });
   };
-  auto orth = [&](int which, double* gout) {
+  auto orth = [&](int which, double* gout, const int2* wk) {
     return timed(pl, ST_CHOLQR, s, [&] {
       const ItemList& L = which ? pl->it_oz : pl->it_oy;
       return launch_orth_apply<T>(which ? Z : Y, which, sd, wk, items(pl, L), L.n, lmax, gp1, rows, gout, s);
     });
   };
+  double* sig_dst = mode ? sig : sigma_out;
+  int* kept_dst = mode ? kept : kept_out;
+  // One sketch of every slice at the widths wk (a width of 0 skips the slice):
   // Y = A Omega, Q1 = orth(Y); q power steps Z = orth(A^T Q1), Q1 = orth(A Z);
-  // the last orthonormalization also writes the Gram partials of Q1.
-  if ((rc = sketch_nn(Om))) return rc;
-  if ((rc = orth(0, pl->q == 0 ? gp2 : nullptr))) return rc;
-  for (int it = 0; it < pl->q; ++it) {
-    if ((rc = sketch_tn())) return rc;
-    if ((rc = orth(1, nullptr))) return rc;
-    if ((rc = sketch_nn(Z))) return rc;
-    if ((rc = orth(0, it == pl->q - 1 ? gp2 : nullptr))) return rc;
+  // the last orthonormalization also writes the Gram partials of Q1; then
+  // Bt = A^T Q1 and the small SVD with the shrinkage -> K'.
+  auto sketch_all = [&](const int2* wk) -> int {
+    int r;
+    if ((r = sketch_nn(Om, wk))) return r;
+    if ((r = orth(0, pl->q == 0 ? gp2 : nullptr, wk))) return r;
+    for (int it = 0; it < pl->q; ++it) {
+      if ((r = sketch_tn(wk))) return r;
+      if ((r = orth(1, nullptr, wk))) return r;
+      if ((r = sketch_nn(Z, wk))) return r;
+      if ((r = orth(0, it == pl->q - 1 ? gp2 : nullptr, wk))) return r;
+    }
+    if ((r = sketch_tn(wk))) return r;
+    return timed(pl, ST_SMALLSVD, s, [&] {
+      return launch_smallsvd<T>(gp2, gp1, sd, wk, P, lmax, rows, tau, tau_dev, mu_dev, pen, K, sig_dst, kept_dst, s);
+    });
+  };
+  const int2* wk_final = nullptr;
+  if (mode == 0) {
+    if ((rc = sketch_all(nullptr))) return rc;
+  } else {
+    if ((rc = sketch_all(wk1))) return rc;
+    if (mode == 2) {
+      // slices whose predicted sketch could be truncated are redone at the fixed width
+      if ((rc = launch_fallback(sd, P, lmax, wk1, sig, kept, anorm, tau, tau_dev, mu_dev, pl->force_fallback, wk2,
+                                wkf, lstate, s)))
+        return rc;
+      if ((rc = sketch_all(wk2))) return rc;
+    } else if ((rc = launch_track_finalize(P, wk1, wkf, anorm, s))) {
+      return rc;
+    }
+    if ((rc = launch_lstate_set(lstate, 1, 0, s))) return rc;
+    wk_final = wkf;
+    if (sigma_out)
+      HT_CHECK_HIP(hipMemcpyAsync(sigma_out, sig, (size_t)P * lmax * sizeof(double), hipMemcpyDeviceToDevice, s));
+    if (kept_out) HT_CHECK_HIP(hipMemcpyAsync(kept_out, kept, (size_t)P * sizeof(int), hipMemcpyDeviceToDevice, s));
   }
-  // Bt = A^T Q1 with the Gram partials of Bt
-  if ((rc = sketch_tn())) return rc;
-  // second CholeskyQR step in the small space, small SVD, shrink -> K'
-  if ((rc = timed(pl, ST_SMALLSVD, s, [&] {
-         return launch_smallsvd<T>(gp2, gp1, sd, wk, P, lmax, rows, tau, tau_dev, mu_dev, pen, K, sigma_out, kept_out,
-                                   s);
-       })))
-    return rc;
   // C = (Q1 K') Bt^T, then the inverse transform
   if ((rc = timed(pl, ST_RECON_QK, s, [&] {
-         return launch_recon_qk<T>(Y, K, QK, sd, wk, items(pl, pl->it_qk), pl->it_qk.n, lmax, s);
+         return launch_recon_qk<T>(Y, K, QK, sd, wk_final, items(pl, pl->it_qk), pl->it_qk.n, lmax, s);
        })))
     return rc;
   if ((rc = timed(pl, ST_RECON_NT, s, [&] {
-         return launch_gemm_nt<T>(QK, Z, C, sd, wk, items(pl, pl->it_nt), pl->it_nt.n, s);
+         return launch_gemm_nt<T>(QK, Z, C, sd, wk_final, items(pl, pl->it_nt), pl->it_nt.n, s);
        })))
     return rc;
   return timed(pl, ST_TRANSFORM_INV, s, [&] {
@@ -1031,6 +1081,92 @@ int ht_transform(const ht_plan* pl, const void* X, void* out, int inverse, void*
                                         items(pl, pl->it_tf), pl->it_tf.n, pl->tf_lds, pl->table32, inv, s);
 }
 
+int ht_plan_learned(ht_plan* pl, int mode, const float* theta) {
+  if (!pl) HT_FAIL(HT_ERR_INVALID_ARG, "plan is NULL");
+  if (mode < 0 || mode > 2) HT_FAIL(HT_ERR_INVALID_ARG, "mode must be 0, 1 or 2");
+  if (mode == 2 && !theta) HT_FAIL(HT_ERR_INVALID_ARG, "predicted widths need the network parameters");
+  pl->learn_mode = mode;
+  pl->learn_theta = theta;
+  if (pl->graph) pl->graph->reset();
+  return HT_OK;
+}
+
+int ht_plan_learned_reset(const ht_plan* pl, void* ws, size_t ws_bytes, void* stream) {
+  if (!pl) HT_FAIL(HT_ERR_INVALID_ARG, "plan is NULL");
+  int rc;
+  if ((rc = check_ws(ws, ws_bytes, pl->tsvt_bytes))) return rc;
+  return launch_lstate_set(ws_ptr<int>(pl, ws, WS_LSTATE), 0, 1, static_cast<hipStream_t>(stream));
+}
+
+int ht_plan_learned_counts(const ht_plan* pl, const void* ws, void* stream, int* valid, int* predicted,
+                           int* redone) {
+  if (!pl || !ws) HT_FAIL(HT_ERR_INVALID_ARG, "plan/ws is NULL");
+  int st[3] = {0, 0, 0};
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  HT_CHECK_HIP(hipMemcpyAsync(st, static_cast<const char*>(ws) + pl->off[WS_LSTATE], sizeof(st),
+                              hipMemcpyDeviceToHost, s));
+  HT_CHECK_HIP(hipStreamSynchronize(s));
+  if (valid) *valid = st[0];
+  if (predicted) *predicted = st[1];
+  if (redone) *redone = st[2];
+  return HT_OK;
+}
+
+int ht_plan_force_fallback(ht_plan* pl, int on) {
+  if (!pl) HT_FAIL(HT_ERR_INVALID_ARG, "plan is NULL");
+  pl->force_fallback = on != 0;
+  if (pl->graph) pl->graph->reset();
+  return HT_OK;
+}
+
+int ht_mlp_param_count(void) { return mlp_param_count(); }
+
+int ht_mlp_workspace_size(int n, size_t* bytes) {
+  if (!bytes || n < 1) HT_FAIL(HT_ERR_INVALID_ARG, "need n >= 1 and bytes");
+  const size_t G = (size_t)mlp_grad_parts(n);
+  *bytes = align256(G * mlp_param_count() * sizeof(float)) + align256(G * sizeof(float));
+  return HT_OK;
+}
+
+int ht_mlp_forward(const float* theta, const float* X, float* z, int n, void* stream) {
+  if (!theta || !X || !z || n < 0) HT_FAIL(HT_ERR_INVALID_ARG, "bad MLP forward arguments");
+  return launch_mlp_forward(theta, X, z, n, static_cast<hipStream_t>(stream));
+}
+
+static int mlp_ws(int n, void* ws, size_t ws_bytes, float** part, float** lpart) {
+  size_t need = 0;
+  int rc;
+  if ((rc = ht_mlp_workspace_size(n, &need))) return rc;
+  if ((rc = check_ws(ws, ws_bytes, need))) return rc;
+  const size_t G = (size_t)mlp_grad_parts(n);
+  *part = static_cast<float*>(ws);
+  *lpart = reinterpret_cast<float*>(static_cast<char*>(ws) + align256(G * mlp_param_count() * sizeof(float)));
+  return HT_OK;
+}
+
+int ht_mlp_grad(const float* theta, const float* X, const float* y, int n, float* grad, float* loss, void* ws,
+                size_t ws_bytes, void* stream) {
+  if (!theta || !X || !y || !grad) HT_FAIL(HT_ERR_INVALID_ARG, "bad MLP gradient arguments");
+  float *part, *lpart;
+  int rc;
+  if ((rc = mlp_ws(n, ws, ws_bytes, &part, &lpart))) return rc;
+  return launch_mlp_grad_step(theta, X, y, n, part, lpart, grad, loss, nullptr, nullptr, nullptr, 0, 0.f, 0.f, 0.f,
+                              0.f, static_cast<hipStream_t>(stream));
+}
+
+int ht_mlp_train_step(float* theta, float* m, float* v, int step, const float* X, const float* y, int n, float lr,
+                      float beta1, float beta2, float eps, float* loss, void* ws, size_t ws_bytes, void* stream) {
+  if (!theta || !m || !v || !X || !y) HT_FAIL(HT_ERR_INVALID_ARG, "bad MLP training arguments");
+  if (step < 1) HT_FAIL(HT_ERR_INVALID_ARG, "Adam steps count from 1");
+  if (!(lr > 0.f) || !(beta1 >= 0.f && beta1 < 1.f) || !(beta2 >= 0.f && beta2 < 1.f) || !(eps > 0.f))
+    HT_FAIL(HT_ERR_INVALID_ARG, "bad Adam hyperparameters");
+  float *part, *lpart;
+  int rc;
+  if ((rc = mlp_ws(n, ws, ws_bytes, &part, &lpart))) return rc;
+  return launch_mlp_grad_step(theta, X, y, n, part, lpart, nullptr, loss, theta, m, v, step, lr, beta1, beta2, eps,
+                              static_cast<hipStream_t>(stream));
+}
+
 int ht_admm_workspace_size(const ht_plan* pl, size_t* bytes) {
   if (!pl || !bytes) HT_FAIL(HT_ERR_INVALID_ARG, "plan/bytes is NULL");
   *bytes = pl->admm_bytes;
@@ -1049,6 +1185,7 @@ int ht_admm_init(ht_plan* pl, const ht_admm_params* prm, void* L, void* E, void*
   HT_CHECK_HIP(hipMemsetAsync(L, 0, bytes, s));
   HT_CHECK_HIP(hipMemsetAsync(E, 0, bytes, s));
   HT_CHECK_HIP(hipMemsetAsync(Y, 0, bytes, s));
+  if ((rc = launch_lstate_set(ws_ptr<int>(pl, ws, WS_LSTATE), 0, 1, s))) return rc;
   return launch_admm_reset(ws_ptr<AdmmState>(pl, ws, WS_STATE), prm->mu0, s);
 }
 

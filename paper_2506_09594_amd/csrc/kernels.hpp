@@ -86,6 +86,36 @@ int launch_smallsvd(double* g2, const double* gw, const SliceDesc* sd, const int
                     int prod_rows, double tau, const double* tau_dev, const double* mu_dev, Penalty pen, T* K,
                     double* sigma_out, int* kept_out, hipStream_t s);
 
+// Learned widths (mlp.hip).  Network parameters: one flat FP32 vector of
+// mlp_param_count() entries.  Gradient steps use a partial buffer of
+// mlp_grad_parts(n) rows of mlp_param_count() floats plus as many loss partials.
+int mlp_param_count();
+int mlp_grad_parts(int n);
+int launch_mlp_forward(const float* th, const float* X, float* z, int n, hipStream_t s);
+// Gradient of the mean squared error (grad, loss optional) and, when th is not
+// null, one Adam step on th, m, v (th_in and th may alias).
+int launch_mlp_grad_step(const float* th_in, const float* X, const float* y, int n, float* part, float* lpart,
+                         float* grad, float* loss, float* th, float* m, float* v, int step, float lr, float beta1,
+                         float beta2, float eps, hipStream_t s);
+// ||A_s||_F^2 into anorm[2 s + 1] (A in T, or BF16 bits when bf16 != 0).
+template <typename T>
+int launch_anorm(const T* A, int bf16, const SliceDesc* sd, int nslices, double* anorm, hipStream_t s);
+// Features of every slice from the previous call (sig rows of lmax, kept,
+// widths used wk_prev, anorm[2 s]) and the widths of this call into wk
+// (mode 1: fixed widths; mode 2: predicted when lstate[0] says the previous
+// call's statistics are valid).
+int launch_width(const float* th, int mode, const SliceDesc* sd, int nslices, int lmax, const double* sig,
+                 const int* kept, const int2* wk_prev, const double* anorm, const int* lstate, double tau,
+                 const double* tau_dev, const double* mu_dev, uint32_t call, const int32_t* call_dev, float* feat,
+                 int2* wk, hipStream_t s);
+// Redo set wk2 (fixed width, or 0 = skip), final widths wkf, anorm[2 s] <-
+// anorm[2 s + 1], counters lstate[1] (predicted slices), lstate[2] (redone).
+int launch_fallback(const SliceDesc* sd, int nslices, int lmax, const int2* wk1, const double* sig, const int* kept,
+                    double* anorm, double tau, const double* tau_dev, const double* mu_dev, int force, int2* wk2,
+                    int2* wkf, int* lstate, hipStream_t s);
+int launch_track_finalize(int nslices, const int2* wk1, int2* wkf, double* anorm, hipStream_t s);
+int launch_lstate_set(int* lstate, int valid, int clear_counts, hipStream_t s);
+
 // ADMM update (see htsvt.h) and the per-iteration scalar bookkeeping.
 template <typename T>
 int launch_admm_input(const T* M, const T* E, const T* Y, const AdmmState* st, T* Xin, int64_t N, hipStream_t s);

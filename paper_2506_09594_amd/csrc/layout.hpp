@@ -46,10 +46,13 @@ struct SliceDesc {
   int32_t l, k;     // sketch width and number of kept singular values
   int32_t tensor;   // index of the tensor (the Philox stream word is stream_base + tensor)
   int32_t local;    // slice index within the tensor (the Philox counter word)
+  int32_t p;        // oversampling of the tensor (learned widths)
+  int32_t pad;
 };
 
 // Width and kept count of slice s: from the slice table, or from an optional
-// per-slice (l, k) array written on the device (learned widths).
+// per-slice (l, k) array written on the device (learned widths; l = 0 skips
+// the slice in that launch).
 __host__ __device__ inline int slice_width(const SliceDesc& d, const int2* wk, int s) {
   return wk ? wk[s].x : d.l;
 }

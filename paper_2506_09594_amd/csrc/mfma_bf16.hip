@@ -52,6 +52,7 @@ __global__ __launch_bounds__(64 * NW) void k_mfma_thin_bf16(const uint16_t* __re
   const int s = item.x, r0 = item.y;
   const SliceDesc d = sd[s];
   const int l = slice_width(d, wk, s);
+  if (l <= 0) return;  // slice not part of this pass
   const int lda = d.n1;
   const int M_out = TRANS ? d.n2 : d.n1;
   const int K = TRANS ? d.n1 : d.n2;

@@ -60,6 +60,7 @@ __global__ __launch_bounds__(TR) void k_orth_apply_regs(T* __restrict__ Yall, in
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const OrthItem o = orth_item(sd, wk, items, which, prod_rows);
   const int l = o.l, m = o.m, ldy = m, nparts = o.nparts;
+  if (l <= 0) return;  // slice not part of this pass
   const int gp = l + 1;
   double* S = reinterpret_cast<double*>(smem_raw);  // TR x gp (Gram of the result)
   const int row0 = o.row0;
@@ -131,6 +132,7 @@ __global__ __launch_bounds__(TR) void k_orth_apply(T* __restrict__ Yall, int whi
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const OrthItem o = orth_item(sd, wk, items, which, prod_rows);
   const int l = o.l, m = o.m, ldy = m, nparts = o.nparts;
+  if (l <= 0) return;  // slice not part of this pass
   const int gp = l + 1;
   double* G = reinterpret_cast<double*>(smem_raw);  // l x gp
   double* dR = G + (size_t)l * gp;                  // gp

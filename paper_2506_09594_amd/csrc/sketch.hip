@@ -60,6 +60,7 @@ __global__ __launch_bounds__(256) void k_gemm_nn(const T* __restrict__ Aall, con
   const int s = item.x, row0 = item.y;
   const SliceDesc d = sd[s];
   const int l = slice_width(d, wk, s);
+  if (l <= 0) return;  // slice not part of this pass
   const int m = d.n1, kd = RECON ? l : d.n2;
   const int lda = d.n1, ldw = RECON ? l : d.n2, ldy = d.n1;
   const T* Aj = Aall + (RECON ? d.y : d.a);
@@ -114,6 +115,7 @@ __global__ __launch_bounds__(256) void k_gemm_tn(const T* __restrict__ Aall, con
   const int s = item.x, col0 = item.y;
   const SliceDesc d = sd[s];
   const int l = slice_width(d, wk, s);
+  if (l <= 0) return;  // slice not part of this pass
   const int m = d.n1, n = d.n2;
   const int lda = m, ldq = m, ldz = n;
   const T* Aj = Aall + d.a;
@@ -169,6 +171,7 @@ __global__ __launch_bounds__(256) void k_gemm_nt(const T* __restrict__ Xall, con
   const int s = item.x;
   const SliceDesc d = sd[s];
   const int l = slice_width(d, wk, s);
+  if (l <= 0) return;  // slice not part of this pass
   const int m = d.n1, n = d.n2;
   const int nrt = (m + 63) / 64;
   const int row0 = (item.y % nrt) * 64, col0 = (item.y / nrt) * 64;

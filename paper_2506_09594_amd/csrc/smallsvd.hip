@@ -84,6 +84,7 @@ __global__ __launch_bounds__(NT) void k_smallsvd(double* __restrict__ g2_all, co
   const int tid = threadIdx.x;
   const SliceDesc d = sd[j];
   const int l = slice_width(d, wk, j), kkeep = slice_kept(d, wk, j);
+  if (l <= 0) return;  // slice not part of this pass
   const int gp = l + 1;
   const int nt_q = (d.n1 + 63) / 64, nt_b = (d.n2 + prod_rows - 1) / prod_rows;
   const double delta_rel = 8.0 * (double)d.n1 * 2.220446049250313e-16;

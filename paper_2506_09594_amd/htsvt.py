@@ -29,7 +29,8 @@ PRECISIONS = {"fp64": 0, "fp32": 1, "bf16": 2}
 PENALTIES = {"l1": 0, "mcp": 1, "scad": 2, "log": 3, "capped_l1": 4}
 MODELS = {"completion": 0, "rpca": 1}
 REGIONS = {"A": 0, "omega": 1, "Q": 2, "Bt": 3, "K": 4, "QK": 5, "C": 6, "Lnew": 7, "Xin": 8, "state": 9,
-           "gram": 10, "gram_q": 11, "widths": 12, "call": 13}
+           "gram": 10, "gram_q": 11, "widths": 12, "call": 13, "widths_redo": 14, "widths_used": 15,
+           "sigma": 16, "kept": 17, "anorm": 18, "features": 19, "learn_state": 20}
 
 # Symbols the header declares (checked by the CPU test suite).
 EXPORTS = [
@@ -38,6 +39,8 @@ EXPORTS = [
     "ht_admm_workspace_size", "ht_admm_init", "ht_admm_iterate", "ht_admm_get_stats",
     "ht_profile_enable", "ht_profile_read", "ht_batch_plan_create", "ht_batch_info", "ht_batch_tensor_info",
     "ht_batch_gnhtsvt", "ht_plan_set_tuning", "ht_plan_get_tuning", "ht_plan_autotune", "ht_plan_graph_enable",
+    "ht_plan_learned", "ht_plan_learned_reset", "ht_plan_learned_counts", "ht_plan_force_fallback",
+    "ht_mlp_param_count", "ht_mlp_workspace_size", "ht_mlp_forward", "ht_mlp_grad", "ht_mlp_train_step",
 ]
 STAGES = ["transform_fwd", "omega", "sketch_nn", "cholqr", "sketch_tn", "smallsvd", "recon_qk", "recon_nt",
           "transform_inv", "admm_update"]
@@ -114,6 +117,18 @@ _sig = {
     "ht_plan_autotune": (ctypes.c_int, [_vp, _vp, _vp, _vp, ctypes.c_size_t, _vp, ctypes.c_int,
                                         ctypes.POINTER(ctypes.c_double)]),
     "ht_plan_graph_enable": (ctypes.c_int, [_vp, ctypes.c_int]),
+    "ht_plan_learned": (ctypes.c_int, [_vp, ctypes.c_int, _vp]),
+    "ht_plan_learned_reset": (ctypes.c_int, [_vp, _vp, ctypes.c_size_t, _vp]),
+    "ht_plan_learned_counts": (ctypes.c_int, [_vp, _vp, _vp, ctypes.POINTER(ctypes.c_int),
+                                              ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]),
+    "ht_plan_force_fallback": (ctypes.c_int, [_vp, ctypes.c_int]),
+    "ht_mlp_param_count": (ctypes.c_int, []),
+    "ht_mlp_workspace_size": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(ctypes.c_size_t)]),
+    "ht_mlp_forward": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int, _vp]),
+    "ht_mlp_grad": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int, _vp, _vp, _vp, ctypes.c_size_t, _vp]),
+    "ht_mlp_train_step": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int, _vp, _vp, ctypes.c_int, ctypes.c_float,
+                                         ctypes.c_float, ctypes.c_float, ctypes.c_float, _vp, _vp, ctypes.c_size_t,
+                                         _vp]),
 }
 for _name, (_res, _args) in _sig.items():
     _f = getattr(_lib, _name)
@@ -228,6 +243,26 @@ class Plan:
         ms = ctypes.c_double()
         _check(_lib.ht_plan_autotune(self._h, _ptr(X), _ptr(out), wp, wn, _stream(), int(repeats), ctypes.byref(ms)))
         return self.tuning(), ms.value
+
+    def learned(self, mode, theta=None):
+        """0: fixed widths; 1: fixed widths with statistics/features recorded;
+        2: widths predicted by the network theta (flat FP32 CUDA tensor)."""
+        mode = {"off": 0, "track": 1, "predict": 2}.get(mode, mode)
+        self._theta_keep = theta
+        _check(_lib.ht_plan_learned(self._h, int(mode), _ptr(theta)))
+
+    def learned_reset(self, workspace):
+        wp, wn = self._aligned(workspace)
+        _check(_lib.ht_plan_learned_reset(self._h, wp, wn, _stream()))
+
+    def learned_counts(self, workspace):
+        wp, _wn = self._aligned(workspace)
+        a, b, c = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        _check(_lib.ht_plan_learned_counts(self._h, wp, _stream(), ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
+        return {"valid": a.value, "predicted": b.value, "redone": c.value}
+
+    def force_fallback(self, on=True):
+        _check(_lib.ht_plan_force_fallback(self._h, 1 if on else 0))
 
     def graph(self, on=True):
         """Record the launch sequence as a HIP graph on the next call and replay it
@@ -381,6 +416,55 @@ class BatchPlan(Plan):
         if stats:
             return out, sig.view(self.n_slices, self.width), kept
         return out
+
+
+class Mlp:
+    """The width-predicting network: parameters and Adam moments as flat FP32
+    CUDA tensors; forward, gradient and training steps run in the library."""
+
+    def __init__(self, theta):
+        import torch
+        self.n_params = _lib.ht_mlp_param_count()
+        theta = torch.as_tensor(np.asarray(theta, dtype=np.float32)) if not torch.is_tensor(theta) else theta
+        assert theta.numel() == self.n_params
+        self.theta = theta.to(device="cuda", dtype=torch.float32).contiguous()
+        self.m = torch.zeros_like(self.theta)
+        self.v = torch.zeros_like(self.theta)
+        self.step = 0
+        self._ws = None
+
+    def _workspace(self, n):
+        import torch
+        sz = ctypes.c_size_t()
+        _check(_lib.ht_mlp_workspace_size(int(n), ctypes.byref(sz)))
+        if self._ws is None or self._ws.numel() < sz.value + 256:
+            self._ws = torch.empty(sz.value + 256, dtype=torch.uint8, device="cuda")
+        return Plan._aligned(self._ws)
+
+    def forward(self, X):
+        import torch
+        z = torch.empty(X.shape[0], dtype=torch.float32, device="cuda")
+        _check(_lib.ht_mlp_forward(_ptr(self.theta), _ptr(X), _ptr(z), int(X.shape[0]), _stream()))
+        return z
+
+    def grad(self, X, y):
+        import torch
+        g = torch.empty_like(self.theta)
+        loss = torch.empty(1, dtype=torch.float32, device="cuda")
+        wp, wn = self._workspace(X.shape[0])
+        _check(_lib.ht_mlp_grad(_ptr(self.theta), _ptr(X), _ptr(y), int(X.shape[0]), _ptr(g), _ptr(loss), wp, wn,
+                                _stream()))
+        return g, loss
+
+    def train_step(self, X, y, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
+        import torch
+        self.step += 1
+        loss = torch.empty(1, dtype=torch.float32, device="cuda")
+        wp, wn = self._workspace(X.shape[0])
+        _check(_lib.ht_mlp_train_step(_ptr(self.theta), _ptr(self.m), _ptr(self.v), self.step, _ptr(X), _ptr(y),
+                                      int(X.shape[0]), float(lr), float(beta1), float(beta2), float(eps), _ptr(loss),
+                                      wp, wn, _stream()))
+        return loss
 
 
 class Admm:

@@ -139,3 +139,20 @@ def test_randomized_stats_and_truncation():
         ref[:, :, j] = (u[:, :3] * s[:3]) @ vh[:3]
     assert _rel(got, tr.inverse(tr.from_slices(ref, dims), T)) < 1e-12
     assert np.all(st["kept"] == 3)
+
+
+def test_per_slice_widths_reduce_to_the_fixed_method():
+    """With every slice at the plan's width and kept count, the per-slice-width
+    routine is the fixed-width routine; with a full-width sketch of an exactly
+    low-rank slice the result does not depend on the width either."""
+    dims, kinds = (20, 16, 6), ["dct2"]
+    X = synth.lowrank_tensor(dims, 3, kinds, seed=5)
+    T = tr.build_transforms(dims, kinds)
+    om = tsvt.omegas(dims, kinds, 6, 4, seed=1, call=0)
+    a = tsvt.tsvt_randomized(X, 0.5, ("l1", ()), T, 6, 4, 1, om)
+    b = tsvt.tsvt_randomized_widths(X, 0.5, ("l1", ()), T, [10] * 6, [6] * 6, 1, om)
+    assert np.array_equal(a, b)
+    # rank-3 slices: any width >= 3 with k >= 3 reproduces the exact operator
+    c = tsvt.tsvt_randomized_widths(X, 0.5, ("l1", ()), T, [3, 4, 5, 6, 8, 10], [3, 3, 4, 5, 6, 6], 1, om)
+    ex = tsvt.gnhtsvt_exact(X, 0.5, ("l1", ()), T)
+    assert np.linalg.norm(c - ex) <= 1e-10 * np.linalg.norm(ex)
