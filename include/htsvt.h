@@ -246,8 +246,9 @@ int ht_plan_graph_enable(ht_plan* plan, int on);
  * l = clamp(ceil(s) + p, p + 1, l_fix) columns and keeps k = min(k_fix, l)
  * values (l_fix, k_fix: the plan's fixed width and kept count).  It is redone at
  * the fixed width when l < l_fix and either every kept value survived
- * (kept >= k) or sqrt(||A_j||^2 - ||B_j||^2) > tau, so the fixed-width method
- * stays the fallback.  The first call after a reset uses the fixed widths.
+ * (kept >= k) or ||A_j||^2 - ||B_j||^2 > (min(n1, n2) - l) tau^2 (the
+ * residual then certainly holds a value above tau), so the fixed-width
+ * method stays the fallback.  The first call after a reset uses the fixed widths.
  *
  * Parameters: one flat FP32 device vector of ht_mlp_param_count() entries,
  * W1 (128 x 32, row-major), b1 (128), W2 (128 x 128), b2 (128), W3 (128), b3.

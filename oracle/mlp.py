@@ -12,11 +12,16 @@ previous iteration's sketch spectrum how many singular values of each slice
 survive the shrinkage; the slice is sketched with that many columns plus p,
 and redone at the fixed width when the result could be truncated:
 
-  (i)  every kept value survived the proximity operator (kept == k_j), or
-  (ii) the residual energy could hold a surviving value:
-       sqrt(||A_j||^2 - ||B_j||^2) > tau (the largest singular value of the
-       residual is at most its Frobenius norm; values <= tau are zeroed by the
-       L1 and MCP shrinkages used with the solvers).
+  (i)  every kept value survived the proximity operator (kept == k_j): the
+       sketch never reached below the threshold, so more values may survive;
+  (ii) the residual certainly holds a value above tau: its energy
+       ||A_j||^2 - ||B_j||^2 (the energy identity) exceeds (min(n1, n2) - l) tau^2,
+       i.e. the mean square of its at most min(n1, n2) - l singular values is
+       above tau^2, so the largest is too (values <= tau are zeroed by the L1
+       and MCP shrinkages used with the solvers).
+  The bound sqrt(energy) > tau, which is necessary for a missed value and
+  fires whenever the residual holds many small values, would leave a
+  completion iterate almost no slice at its predicted width.
 
 The paper gives no network, features or loss for this; the reading taken here
 (features from the last spectrum and energies, a 32-128-128-1 ReLU MLP, MSE on
@@ -178,11 +183,12 @@ def width_from_prediction(z, p, l_fix, k_fix):
     return l, int(min(k_fix, l))
 
 
-def needs_fallback(l, k, kept, anorm2, sigma, tau, l_fix):
-    """True when a slice sketched at width l < l_fix must be redone at l_fix."""
+def needs_fallback(l, k, kept, anorm2, sigma, tau, l_fix, n_min):
+    """True when a slice sketched at width l < l_fix must be redone at l_fix
+    (n_min = min(n1, n2))."""
     if l >= l_fix:
         return False
     if kept >= k:
         return True
     tail = anorm2 - float(np.sum(np.asarray(sigma[:l], dtype=np.float64) ** 2))
-    return math.sqrt(max(tail, 0.0)) > tau
+    return tail > (n_min - l) * tau * tau

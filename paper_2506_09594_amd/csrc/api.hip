@@ -690,7 +690,7 @@ int run_tsvt(const ht_plan* pl, const T* X, T* out, double tau, const double* ta
   auto orth = [&](int which, double* gout, const int2* wk) {
     return timed(pl, ST_CHOLQR, s, [&] {
       const ItemList& L = which ? pl->it_oz : pl->it_oy;
-      return launch_orth_apply<T>(which ? Z : Y, which, sd, wk, items(pl, L), L.n, lmax, gp1, rows, gout, s);
+      return launch_orth_apply<T>(which ? Z : Y, which, sd, wk, items(pl, L), L.n, lmax, P, gp1, rows, gout, s);
     });
   };
   double* sig_dst = mode ? sig : sigma_out;

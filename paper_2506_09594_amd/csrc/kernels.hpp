@@ -68,10 +68,11 @@ int launch_bf16_tn(const uint16_t* A, const float* Q, float* Z, const SliceDesc*
 // n1 rows, 1: Z of n2 rows) from the Gram partials of the producing product
 // (gin at the slice's g1 offset, prod_rows rows per partial).  Optionally
 // writes the Gram partials of the result (gout at the slice's g2 offset, one
-// per 64 rows).  Items are 64-row tiles.
+// per 64 rows).  Items are 64-row tiles.  Widths above 64 overwrite the first
+// partial of every slice with R^{-1}.
 template <typename T>
 int launch_orth_apply(T* Y, int which, const SliceDesc* sd, const int2* wk, const int2* items, int nitems, int lmax,
-                      const double* gin, int prod_rows, double* gout, hipStream_t s);
+                      int nslices, double* gin, int prod_rows, double* gout, hipStream_t s);
 
 // Small SVD and shrinkage in FP64, one workgroup per slice.  Inputs: Gram
 // partials of the basis Q1 (g2 at the slice's g2 offset, one per 64 rows of

@@ -17,8 +17,9 @@
 // Width rule: s = exp(z) - 1, l = clamp(ceil(s) + p, p + 1, l_fix),
 // k = min(k_fix, l).  Fallback: a slice sketched at l < l_fix is redone at the
 // fixed width when every kept value survived (kept >= k) or when the residual
-// energy could hold a surviving value, sqrt(||A_j||^2 - ||B_j||^2) > tau (the
-// energy identity behind the adaptive stopping test of Alg. 3).
+// certainly holds a value above tau: its energy ||A_j||^2 - ||B_j||^2 (the
+// energy identity behind the adaptive stopping test of Alg. 3) exceeds
+// (min(n1, n2) - l) tau^2, the most that many values <= tau can hold.
 #include "kernels.hpp"
 
 namespace ht {
@@ -358,7 +359,7 @@ __global__ __launch_bounds__(256) void k_fallback(const SliceDesc* __restrict__ 
     double b2 = 0.0;
     for (int i = 0; i < w.x; ++i) b2 += sig[(int64_t)s * lmax + i] * sig[(int64_t)s * lmax + i];
     const double tail = anorm[2 * s + 1] - b2;
-    redo = force || kept[s] >= w.y || sqrt(fmax(tail, 0.0)) > tau;
+    redo = force || kept[s] >= w.y || tail > (double)(min(d.n1, d.n2) - w.x) * tau * tau;
     atomicAdd(&lstate[1], 1);
     if (redo) atomicAdd(&lstate[2], 1);
   }

@@ -13,6 +13,10 @@
 // (its residual against the previous columns is at rounding level) becomes a
 // zero column of Q, which leaves the span of the kept columns intact.
 //
+// Slices wider than 64 factor once per slice in a separate kernel (one
+// workgroup of 256 threads per slice) and apply R^{-1} per tile; narrower
+// slices of the same launch take the register path.
+//
 // One pass of this CholeskyQR gives a basis whose span is exact to rounding and
 // whose orthogonality error is O(u_64 kappa(Y)^2); that suffices inside the
 // power iterations, where only the span matters.  For the final basis the
@@ -60,7 +64,7 @@ __global__ __launch_bounds__(TR) void k_orth_apply_regs(T* __restrict__ Yall, in
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const OrthItem o = orth_item(sd, wk, items, which, prod_rows);
   const int l = o.l, m = o.m, ldy = m, nparts = o.nparts;
-  if (l <= 0) return;  // slice not part of this pass
+  if (l <= 0 || l > LB) return;  // slice not part of this pass, or on the factor-once path
   const int gp = l + 1;
   double* S = reinterpret_cast<double*>(smem_raw);  // TR x gp (Gram of the result)
   const int row0 = o.row0;
@@ -124,43 +128,65 @@ __global__ __launch_bounds__(TR) void k_orth_apply_regs(T* __restrict__ Yall, in
   }
 }
 
-template <typename T, int LB>
-__global__ __launch_bounds__(TR) void k_orth_apply(T* __restrict__ Yall, int which, const SliceDesc* __restrict__ sd,
-                                                   const int2* __restrict__ wk, const int2* __restrict__ items,
-                                                   const double* __restrict__ gin_all, int prod_rows,
-                                                   double* __restrict__ gout_all) {
+// Widths above 64: one workgroup per slice factors G once (sum of the
+// partials, Cholesky with deflation, R^{-1}) and parks R^{-1} (row-major
+// l x l) in the slice's first Gram partial, which nothing reads afterwards.
+template <int LB>
+__global__ __launch_bounds__(256) void k_orth_factor(int which, const SliceDesc* __restrict__ sd,
+                                                     const int2* __restrict__ wk, double* __restrict__ gin_all,
+                                                     int prod_rows) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  const OrthItem o = orth_item(sd, wk, items, which, prod_rows);
-  const int l = o.l, m = o.m, ldy = m, nparts = o.nparts;
-  if (l <= 0) return;  // slice not part of this pass
+  __shared__ double s_scratch;
+  const int s = blockIdx.x;
+  const SliceDesc d = sd[s];
+  const int l = slice_width(d, wk, s);
+  if (l <= 64) return;  // not part of this pass, or on the register path
+  const int m = which ? d.n2 : d.n1;
+  const int nparts = (m + prod_rows - 1) / prod_rows;
   const int gp = l + 1;
   double* G = reinterpret_cast<double*>(smem_raw);  // l x gp
   double* dR = G + (size_t)l * gp;                  // gp
-  double* S = dR + gp;                               // TR x gp (Gram of the result)
-  __shared__ double s_scratch;
+  double* Rinv = dR + gp;                           // l x gp
+  double* part = gin_all + d.g1;
+  sum_gram_partials(G, gp, part, nparts, l);
+  __syncthreads();
+  chol_deflate(G, dR, gp, l, 8.0 * (double)m * 2.220446049250313e-16, &s_scratch);
+  tri_inverse<LB>(G, dR, gp, l, Rinv);
+  for (int idx = threadIdx.x; idx < l * l; idx += blockDim.x) part[idx] = Rinv[(idx / l) * gp + (idx % l)];
+}
+
+// Apply Q = Y R^{-1} per 64-row tile with R^{-1} from k_orth_factor (entries
+// read at wave-uniform addresses); lane i owns row i.
+template <typename T, int LB>
+__global__ __launch_bounds__(TR) void k_orth_apply_inv(T* __restrict__ Yall, int which,
+                                                       const SliceDesc* __restrict__ sd, const int2* __restrict__ wk,
+                                                       const int2* __restrict__ items,
+                                                       const double* __restrict__ gin_all, int prod_rows,
+                                                       double* __restrict__ gout_all) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const OrthItem o = orth_item(sd, wk, items, which, prod_rows);
+  const int l = o.l, m = o.m, ldy = m;
+  if (l <= 64) return;  // not part of this pass, or on the register path
+  const int gp = l + 1;
+  double* S = reinterpret_cast<double*>(smem_raw);  // TR x gp (Gram of the result)
   const int row0 = o.row0;
   const int rows = min(TR, m - row0);
   T* Y = Yall + o.off + row0;
+  const double* Ri = gin_all + o.g1;  // R^{-1}, row-major
   double* gout = gout_all ? gout_all + o.g2 + (int64_t)(row0 / TR) * l * l : nullptr;
   const int i = threadIdx.x;
   const bool valid = i < rows;
-
-  sum_gram_partials(G, gp, gin_all + o.g1, nparts, l);
   double y[LB];
 #pragma unroll
   for (int c = 0; c < LB; ++c) y[c] = (c < l && valid) ? (double)Y[i + (int64_t)c * ldy] : 0.0;
-  __syncthreads();
-  chol_deflate(G, dR, gp, l, 8.0 * (double)m * 2.220446049250313e-16, &s_scratch);
-
-  // q R = y: q_c = (y_c - sum_{a<c} q_a R[a][c]) / R[c][c]; skipped columns give q_c = 0
+  // q_c = sum_{a <= c} y_a Rinv[a][c], in place from the last column down
 #pragma unroll
-  for (int c = 0; c < LB; ++c) {
+  for (int c = LB - 1; c >= 0; --c) {
     if (c < l) {
-      double t = y[c];
+      double t = 0.0;
 #pragma unroll
-      for (int a = 0; a < c; ++a) t -= y[a] * G[c * gp + a];  // R[a][c], stored transposed
-      const double r = dR[c];
-      y[c] = (r != 0.0) ? t / r : 0.0;
+      for (int a = 0; a <= c; ++a) t += y[a] * Ri[a * l + c];
+      y[c] = t;
     }
   }
 #pragma unroll
@@ -177,13 +203,14 @@ __global__ __launch_bounds__(TR) void k_orth_apply(T* __restrict__ Yall, int whi
   }
 }
 
-size_t orth_lds_bytes(int l) { return ((size_t)l * (l + 1) + (size_t)(l + 1) + (size_t)TR * (l + 1)) * 8; }
+size_t orth_lds_bytes(int l) { return (size_t)TR * (l + 1) * 8; }
+size_t factor_lds_bytes(int l) { return (2 * (size_t)l * (l + 1) + (size_t)(l + 1)) * 8; }
 
 }  // namespace
 
 template <typename T>
 int launch_orth_apply(T* Y, int which, const SliceDesc* sd, const int2* wk, const int2* items, int nitems, int lmax,
-                      const double* gin, int prod_rows, double* gout, hipStream_t s) {
+                      int nslices, double* gin, int prod_rows, double* gout, hipStream_t s) {
   if (lmax > HT_MAX_WIDTH) HT_FAIL(HT_ERR_UNSUPPORTED, "sketch width above HT_MAX_WIDTH");
   if (nitems == 0) return HT_OK;
   const size_t lds = orth_lds_bytes(lmax);
@@ -198,12 +225,20 @@ int launch_orth_apply(T* Y, int which, const SliceDesc* sd, const int2* wk, cons
   if (lmax <= 32) return launch(k_orth_apply_regs<T, 32>);
   if (lmax <= 48) return launch(k_orth_apply_regs<T, 48>);
   if (lmax <= 64) return launch(k_orth_apply_regs<T, 64>);
-  return launch(k_orth_apply<T, 80>);
+  // slices up to 64 wide in registers; wider ones factor once per slice, then apply per tile
+  int rc = launch(k_orth_apply_regs<T, 64>);
+  if (rc) return rc;
+  rc = ensure_dynamic_lds((const void*)k_orth_factor<80>, factor_lds_bytes(HT_MAX_WIDTH));
+  if (rc) return rc;
+  hipLaunchKernelGGL(k_orth_factor<80>, dim3((unsigned)nslices), dim3(256), factor_lds_bytes(lmax), s, which, sd, wk,
+                     gin, prod_rows);
+  HT_CHECK_LAUNCH();
+  return launch(k_orth_apply_inv<T, 80>);
 }
 
-template int launch_orth_apply<float>(float*, int, const SliceDesc*, const int2*, const int2*, int, int, const double*,
+template int launch_orth_apply<float>(float*, int, const SliceDesc*, const int2*, const int2*, int, int, int, double*,
                                       int, double*, hipStream_t);
-template int launch_orth_apply<double>(double*, int, const SliceDesc*, const int2*, const int2*, int, int,
-                                       const double*, int, double*, hipStream_t);
+template int launch_orth_apply<double>(double*, int, const SliceDesc*, const int2*, const int2*, int, int, int,
+                                       double*, int, double*, hipStream_t);
 
 }  // namespace ht

@@ -101,8 +101,6 @@ __global__ __launch_bounds__(NT) void k_smallsvd(double* __restrict__ g2_all, co
   double* rc = sig + LMAX;
   double* rs = rc + 64;
   int* perm = reinterpret_cast<int*>(rs + 64);
-  int* rp = perm + LMAX;
-  int* rq = rp + 64;
 
   sum_gram_partials(B0, gp, gq, nt_q, l);
   sum_gram_partials(B1, gp, gw_all + d.g1, nt_b, l);
@@ -112,8 +110,13 @@ __global__ __launch_bounds__(NT) void k_smallsvd(double* __restrict__ g2_all, co
     if (tid < 64) chol_inverse_regs<LB>(B0, gp, l, delta_rel, V);
     __syncthreads();
   } else {
-    chol_deflate(B0, dR, gp, l, delta_rel, &s_scr);
-    tri_inverse<LB>(B0, dR, gp, l, V);  // V = R2^{-1} (upper)
+    if (l <= 64) {  // a narrow slice in a wide launch (uniform branch)
+      if (tid < 64) chol_inverse_regs<64>(B0, gp, l, delta_rel, V);
+      __syncthreads();
+    } else {
+      chol_deflate(B0, dR, gp, l, delta_rel, &s_scr);
+      tri_inverse<LB>(B0, dR, gp, l, V);  // V = R2^{-1} (upper)
+    }
   }
   for (int idx = tid; idx < ll; idx += NT) gq[idx] = V[(idx / l) * gp + (idx % l)];
 
@@ -184,6 +187,8 @@ __global__ __launch_bounds__(NT) void k_smallsvd(double* __restrict__ g2_all, co
   __syncthreads();
   double* Wc = B1;
   double* Wn = B0;
+  // Pair indices come from the schedule arithmetic, so after the barrier every
+  // load of the update (rotation parameters, W and V entries) issues at once.
   // A flag of parity b is cleared only after every thread has passed the
   // barriers that follow its last read, so no barrier is needed around it.
   int gstep = 0;
@@ -203,8 +208,6 @@ __global__ __launch_bounds__(NT) void k_smallsvd(double* __restrict__ g2_all, co
         if (q >= 0) schur2(Wc[p * gp + p], Wc[q * gp + q], Wc[p * gp + q], abs_tol, c, sn);
         rc[tid] = c;
         rs[tid] = sn;
-        rp[tid] = p;
-        rq[tid] = q;
         if (sn != 0.0) {
           s_step[fp] = 1;
           s_rot[sp] = 1;
@@ -216,30 +219,33 @@ __global__ __launch_bounds__(NT) void k_smallsvd(double* __restrict__ g2_all, co
       for (int u = 0; u < NBI; ++u) {
         if (bs[u] < 0) continue;
         const int st = bs[u], tt = bt[u];
-        const int ps = rp[st], qs = rq[st], pt = rp[tt], qt = rq[tt];
-        const double cs = rc[st], ss = rs[st], ct = rc[tt], sn = rs[tt];
+        int ps, qs, pt, qt;
+        rr_pair(step, st, L2, l, ps, qs);
+        rr_pair(step, tt, L2, l, pt, qt);
+        const double cs = rc[st], ss = rs[st], ct = rc[tt], snt = rs[tt];
         const double w00 = Wc[ps * gp + pt];
         const double w01 = qt >= 0 ? Wc[ps * gp + qt] : 0.0;
         const double w10 = qs >= 0 ? Wc[qs * gp + pt] : 0.0;
         const double w11 = (qs >= 0 && qt >= 0) ? Wc[qs * gp + qt] : 0.0;
         const double r00 = cs * w00 - ss * w10, r01 = cs * w01 - ss * w11;
         const double r10 = ss * w00 + cs * w10, r11 = ss * w01 + cs * w11;
-        Wn[ps * gp + pt] = ct * r00 - sn * r01;
-        if (qt >= 0) Wn[ps * gp + qt] = sn * r00 + ct * r01;
-        if (qs >= 0) Wn[qs * gp + pt] = ct * r10 - sn * r11;
-        if (qs >= 0 && qt >= 0) Wn[qs * gp + qt] = sn * r10 + ct * r11;
+        Wn[ps * gp + pt] = ct * r00 - snt * r01;
+        if (qt >= 0) Wn[ps * gp + qt] = snt * r00 + ct * r01;
+        if (qs >= 0) Wn[qs * gp + pt] = ct * r10 - snt * r11;
+        if (qs >= 0 && qt >= 0) Wn[qs * gp + qt] = snt * r10 + ct * r11;
       }
 #pragma unroll
       for (int u = 0; u < NVI; ++u) {
         if (vt[u] < 0) continue;
         const int tt = vt[u], x = vx[u];
-        const double sn = rs[tt];
-        if (sn != 0.0) {
-          const int pt = rp[tt], qt = rq[tt];
-          const double ct = rc[tt];
-          const double vp = V[x * gp + pt], vq = V[x * gp + qt];
-          V[x * gp + pt] = ct * vp - sn * vq;
-          V[x * gp + qt] = sn * vp + ct * vq;
+        int pt, qt;
+        rr_pair(step, tt, L2, l, pt, qt);
+        if (qt < 0) continue;  // the padding partner: no rotation
+        const double snt = rs[tt], ct = rc[tt];
+        const double vp = V[x * gp + pt], vq = V[x * gp + qt];
+        if (snt != 0.0) {
+          V[x * gp + pt] = ct * vp - snt * vq;
+          V[x * gp + qt] = snt * vp + ct * vq;
         }
       }
       double* tmp = Wc;

@@ -188,7 +188,7 @@ def test_predicted_widths_and_fallback_match_oracle(ht):
     kept = _region(plan, ws, "kept", torch.int32)[:P].cpu().numpy()
     an = _region(plan, ws, "anorm", torch.float64)[: 2 * P].cpu().numpy().reshape(P, 2)
     for j in np.where(~redo)[0]:
-        assert not omlp.needs_fallback(14, 14, int(kept[j]), an[j, 1], sig[j], tau, l_fix), j
+        assert not omlp.needs_fallback(14, 14, int(kept[j]), an[j, 1], sig[j], tau, l_fix, min(dims[:2])), j
     om = otsvt.omegas(dims, kinds, r, p, seed=seed, call=1, round_to=np.float32)
     ref = otsvt.tsvt_randomized_widths(X, tau, MCP, otr.build_transforms(dims, kinds), wkf[:, 0], wkf[:, 1], q, om)
     assert _rel(ht.from_device(out, dims), ref) < 1e-5
@@ -200,3 +200,60 @@ def test_predicted_widths_and_fallback_match_oracle(ht):
     torch.cuda.synchronize()
     assert torch.equal(forced, base)
     plan.force_fallback(False)
+
+
+def _completion(ht, dims, seed, r, p, sr=0.6, vartheta=1.05, ranks=(2, 20)):
+    import torch
+    kinds = ["dct2"] * (len(dims) - 2)
+    P = int(np.prod(dims[2:]))
+    rk = synth.rng(seed, "ranks").integers(ranks[0], ranks[1] + 1, size=P)
+    L = synth.slice_rank_tensor(dims, rk, kinds, seed)
+    mask = synth.observation_mask(dims, sr, seed)
+    M = np.where(mask, L, 0.0).astype(np.float32).astype(np.float64)
+    plan = ht.Plan(dims, kinds, r=r, p=p, q=2, precision="fp32", seed=seed)
+    mu0 = 1.0 / synth.max_slice_norm(M, kinds)
+    adm = ht.Admm(plan, "completion", phi=("mcp", (10.0,)), mu0=mu0, vartheta=vartheta, mu_max=1e10)
+    return plan, adm, L, ht.to_device(M, torch.float32), ht.to_device(mask.astype(np.uint8), torch.uint8)
+
+
+def test_trained_network_gain_in_the_solver(ht):
+    """Trained on the fixed-width solver's own traces (two seeded tensors), the
+    network lets a third tensor's completion run at a fraction of the fixed
+    width with the same final recovery error; the fallback redoes few slices."""
+    import torch
+    from oracle import solver as osolver
+    from paper_2506_09594_amd import rankpred
+    dims, r, p, n_iter = (64, 64, 4, 4), 30, 8, 60
+    X, y = [], []
+    for sd in (201, 202):
+        plan, adm, _, dM, dmask = _completion(ht, dims, sd, r, p)
+        f, t = rankpred.collect_traces(plan, adm, dM, dmask, n_iter)
+        X.append(f)
+        y.append(t)
+    X, y = np.concatenate(X), np.concatenate(y)
+    assert X.shape == (2 * 16 * (n_iter - 1), 32) and np.all(np.isfinite(X))
+    net = rankpred.init_network(3)
+    hist = rankpred.train(net, X, y, epochs=60, batch=256, lr=2e-3)
+    assert hist[-1] < 0.05 * hist[0]
+    res = {}
+    for mode in ("fixed", "predict"):
+        plan, adm, L, dM, dmask = _completion(ht, dims, 7, r, p)
+        dL, dE, dY = (torch.empty(plan.N, dtype=torch.float32, device="cuda") for _ in range(3))
+        ws = plan.alloc_workspace(admm=True)
+        if mode == "predict":
+            plan.learned("predict", net.theta)
+        adm.init(dL, dE, dY, ws)
+        widths = []
+        for _ in range(n_iter):
+            adm.iterate(dM, dmask, dL, dE, dY, 1, ws)
+            if mode == "predict":
+                widths.append(plan.region(ws, "widths_used", torch.int32)[: 2 * plan.n_slices].view(-1, 2)[:, 0]
+                              .float().mean().item())
+        torch.cuda.synchronize()
+        res[mode] = (osolver.rse(ht.from_device(dL, dims), L), plan.learned_counts(ws), widths, plan.width)
+    rse_fixed, rse_pred = res["fixed"][0], res["predict"][0]
+    counts, widths, l_fix = res["predict"][1], res["predict"][2], res["predict"][3]
+    assert rse_fixed < 1e-2  # a well-posed problem: the fixed method recovers the tensor
+    assert rse_pred <= 1.05 * rse_fixed + 1e-6
+    assert np.mean(widths[1:]) < 0.8 * l_fix  # the sketches shrink
+    assert counts["predicted"] > 0 and counts["redone"] < 0.25 * counts["predicted"]

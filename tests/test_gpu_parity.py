@@ -243,3 +243,12 @@ def test_admm_matches_oracle(ht, prec, model):
     assert st["iteration"] == n_iter
     assert st["mu"] == pytest.approx(min(mu_max, mu0 * vartheta ** n_iter), rel=1e-12)
     assert st["resid"] == pytest.approx(hist[-1]["resid"], rel=1e-6 if prec == "fp64" else 1e-2)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_tsvt_wide_sketch_with_deflation(ht, prec):
+    """Sketch width 70 (> 64: the factor-once orthonormalization path) on
+    rank-5 slices, so most sketch columns deflate; and a full-rank case."""
+    for rank, tau in ((5, 1.0), (80, 20.0)):
+        got, ref, _ = _run_case(ht, (100, 90, 3), ["dct2"], rank, 60, 10, 2, prec, tau=tau, pen="l1")
+        assert _rel(got, ref) < TOL[prec], f"rank {rank}"

@@ -126,10 +126,23 @@ def test_width_rule_clamps():
 def test_fallback_rule():
     sig = np.array([5.0, 3.0, 0.5, 0.1])
     # all kept survived -> redo
-    assert mlp.needs_fallback(4, 3, 3, 40.0, sig, 0.2, 74)
-    # two of three survive, residual energy 40 - 34.26 = 5.74 -> sqrt 2.4 > tau 2 -> redo
-    assert mlp.needs_fallback(4, 3, 2, 40.0, sig, 2.0, 74)
-    # same with tau 2.5: keep the predicted result
-    assert not mlp.needs_fallback(4, 3, 2, 40.0, sig, 2.5, 74)
+    assert mlp.needs_fallback(4, 3, 3, 40.0, sig, 0.2, 74, 6)
+    # two of three survive; residual energy 40 - 34.26 = 5.74 over 6 - 4 = 2
+    # remaining values: mean square 2.87 > tau^2 = 2.25 -> one is above tau -> redo
+    assert mlp.needs_fallback(4, 3, 2, 40.0, sig, 1.5, 74, 6)
+    # tau = 2: mean square 2.87 < 4, no value is certainly above tau -> keep
+    assert not mlp.needs_fallback(4, 3, 2, 40.0, sig, 2.0, 74, 6)
     # at the fixed width there is nothing to redo
-    assert not mlp.needs_fallback(74, 64, 64, 40.0, sig, 0.0, 74)
+    assert not mlp.needs_fallback(74, 64, 64, 40.0, sig, 0.0, 74, 128)
+
+
+def test_fallback_energy_test_is_certain():
+    """When the energy test fires, the residual has a singular value above tau
+    (checked on explicit residual spectra)."""
+    g = np.random.default_rng(11)
+    for _ in range(200):
+        rho = np.sort(g.exponential(1.0, size=g.integers(1, 20)))[::-1]
+        tau = g.uniform(0.1, 2.0)
+        fires = float(np.sum(rho ** 2)) > len(rho) * tau * tau
+        if fires:
+            assert rho[0] > tau
