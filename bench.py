@@ -99,6 +99,226 @@ def counter_traffic(stage):
     return int(m.group(1)) if m else None
 
 
+def _dct_matrix(n):
+    import numpy as np
+    k = np.arange(n)[:, None]
+    m = np.arange(n)[None, :]
+    U = np.cos(np.pi * (2 * m + 1) * k / (2 * n)) * np.sqrt(2.0 / n)
+    U[0] /= np.sqrt(2.0)
+    return U
+
+
+def batch_tensor(dims, rank, seed):
+    """One uneven-batch tensor on the GPU (FP32, Fortran order): Gaussian
+    transform-domain factors from the seeded generator, their face-wise
+    product, then the inverse orthonormal DCT along modes 3..d, in PyTorch
+    (data preparation only)."""
+    import numpy as np
+    import torch
+
+    from workloads import synth
+    n1, n2 = dims[:2]
+    modes = list(dims[2:])
+    P = int(np.prod(modes))
+    ga, gb = synth.rng(seed, "factor_a"), synth.rng(seed, "factor_b")
+    A = torch.from_numpy(ga.standard_normal((P, n1, rank)).astype(np.float32)).cuda()
+    B = torch.from_numpy(gb.standard_normal((P, rank, n2)).astype(np.float32)).cuda()
+    S = torch.bmm(A, B).transpose(1, 2).contiguous()  # slice j column-major
+    T = S.view(*reversed(modes), n2, n1)
+    nm = len(modes)
+    for k, n in enumerate(modes):  # mode k+3 is axis nm-1-k of the C-order view
+        U = torch.from_numpy(_dct_matrix(n).astype(np.float32)).cuda()
+        ax = nm - 1 - k
+        T = torch.movedim(torch.movedim(T, ax, -1) @ U, -1, ax)
+    return T.contiguous().view(-1)
+
+
+def bench_batch(args):
+    """64 tensors of orders 3-5 (n1, n2 uniform in [64, 512], modes 3..d in
+    {4, 8, 16}, rank uniform in [5, 40], DCT, p = 10, q = 2): one batched
+    BF16-mixed plan (one launch per stage, replayed as a graph) against the
+    plain form, per-tensor FP32 plans called one after another."""
+    import numpy as np
+    import torch
+
+    from paper_2506_09594_amd import htsvt as ht
+    from workloads import synth
+    spec = synth.batch_shapes(64, seed=3)
+    shapes = [s for s, _ in spec]
+    ranks = [r for _, r in spec]
+    n_el = sum(int(np.prod(s)) for s in shapes)
+    P_tot = sum(int(np.prod(s[2:])) for s in shapes)
+    pen = ("mcp", (100.0,))
+    taus = [5.0] * len(spec)
+    plan = ht.BatchPlan(shapes, r=ranks, p=10, q=2, precision="bf16", seed=3)
+    X = torch.zeros(plan.N, dtype=torch.float32, device="cuda")
+    for t, (s, r) in enumerate(spec):
+        X[plan.offsets[t]: plan.offsets[t] + plan.numels[t]] = batch_tensor(s, r, 1000 + t)
+    out = torch.zeros_like(X)
+    ws = plan.alloc_workspace()
+    tau = torch.tensor(taus, dtype=torch.float64, device="cuda")
+    tuning, _ = plan.autotune(X, workspace=ws, repeats=2)
+    side = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    with torch.cuda.stream(side):
+        plan.graph(True)
+        for i in range(args.warmup):
+            plan.gnhtsvt(X, tau, pen, call_index=i, out=out, workspace=ws)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(args.steps):
+            plan.gnhtsvt(X, tau, pen, call_index=args.warmup + i, out=out, workspace=ws)
+        torch.cuda.synchronize()
+        dt_batch = (time.perf_counter() - t0) / args.steps
+        plan.graph(False)
+    plan.profile(True)
+    plan.gnhtsvt(X, tau, pen, call_index=0, out=out, workspace=ws)
+    prof = plan.profile_read()
+    plan.profile(False)
+    # plain form: one FP32 plan per tensor, one call after another
+    plans = [ht.Plan(s, r=r, p=10, q=2, precision="fp32", seed=3, stream_id=t) for t, (s, r) in enumerate(spec)]
+    wsz = max(pl.workspace_bytes for pl in plans)
+    ws1 = torch.empty(wsz + 256, dtype=torch.uint8, device="cuda")
+    xs = [X[plan.offsets[t]: plan.offsets[t] + plan.numels[t]] for t in range(len(spec))]
+    outs = [torch.empty_like(x) for x in xs]
+
+    def plain_call(i):
+        for t, pl in enumerate(plans):
+            pl.gnhtsvt(xs[t], taus[t], pen, call_index=i, out=outs[t], workspace=ws1)
+    for i in range(args.warmup):
+        plain_call(i)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        plain_call(args.warmup + i)
+    torch.cuda.synchronize()
+    dt_plain = (time.perf_counter() - t0) / args.steps
+    # agreement of the two forms on the last call's sketch (same keys, BF16 vs FP32 rounding)
+    got = plan.gnhtsvt(X, tau, pen, call_index=args.warmup + args.steps - 1, out=out, workspace=ws)
+    torch.cuda.synchronize()
+    rel = max(float(torch.linalg.norm(got[plan.offsets[t]: plan.offsets[t] + plan.numels[t]] - outs[t]) /
+                    torch.linalg.norm(outs[t])) for t in range(len(spec)))
+    stages = {k: round(v[0], 4) for k, v in prof.items() if v[1]}
+    return {"metric": "frontal slices/sec of randomized t-SVT", "value": round(P_tot / dt_batch, 1),
+            "unit": "slices/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+            "ms_per_step": round(dt_batch * 1e3, 4), "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": "bf16-f32acc", "data": "synthetic",
+            "config": {"workload": "batch64_orders3to5_uneven_bf16", "tensors": len(spec), "slices": P_tot,
+                       "elements": n_el, "p": 10, "q": 2, "tuning": tuning, "graph": True},
+            "plain_fp32_per_tensor": {"ms_per_step": round(dt_plain * 1e3, 4),
+                                      "value": round(P_tot / dt_plain, 1), "launches_per_step": 13 * len(spec)},
+            "speedup_vs_plain": round(dt_plain / dt_batch, 3), "max_rel_diff_vs_plain": rel,
+            "stages_ms_one_call": stages}
+
+
+def _completion_problem(dims, ranks, sr, seed):
+    import numpy as np
+
+    from workloads import synth
+    kinds = ["dct2"] * (len(dims) - 2)
+    L = synth.slice_rank_tensor(dims, ranks, kinds, seed)
+    mask = synth.observation_mask(dims, sr, seed)
+    M = np.where(mask, L, 0.0).astype(np.float32).astype(np.float64)
+    return kinds, L, mask, M
+
+
+def _solve(dims, kinds, M, mask, r, p, prec, vartheta, n_iter, seed, theta=None, graph=False):
+    import torch
+
+    from paper_2506_09594_amd import htsvt as ht
+    from workloads import synth
+    plan = ht.Plan(dims, kinds, r=r, p=p, q=2, precision=prec, seed=seed)
+    mu0 = 1.0 / synth.max_slice_norm(M, kinds)
+    adm = ht.Admm(plan, "completion", phi=("mcp", (10.0,)), mu0=mu0, vartheta=vartheta, mu_max=1e10)
+    dM = ht.to_device(M, torch.float32)
+    dmask = ht.to_device(mask.astype("uint8"), torch.uint8)
+    dL, dE, dY = (torch.empty(plan.N, dtype=torch.float32, device="cuda") for _ in range(3))
+    ws = plan.alloc_workspace(admm=True)
+    if theta is not None:
+        plan.learned("predict", theta)
+    adm.init(dL, dE, dY, ws)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    adm.iterate(dM, dmask, dL, dE, dY, n_iter, ws)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / n_iter
+    counts = plan.learned_counts(ws) if theta is not None else None
+    return ht.from_device(dL, dims), dt, counts, plan
+
+
+def bench_solver(args):
+    """Completion solver iteration time against the plain FP32 form at equal
+    relative recovery error.  (a) 256x256x16x16 rank 20, 20% observed, 100
+    iterations: plain FP32 against BF16-mixed sketches.  (b) 128x128x8x8x8
+    with per-slice rank uniform in [4, 64], fixed r = 64, p = 10, 60%
+    observed, vartheta 1.05, 100 iterations: plain FP32 against predicted
+    widths (network trained on the plain method's traces of three
+    256x256x16x16 tensors of the same rank law)."""
+    import numpy as np
+
+    from oracle import solver as osolver
+    from paper_2506_09594_amd import rankpred
+    from paper_2506_09594_amd import htsvt as ht
+    from workloads import synth
+    res = {}
+    dims = (256, 256, 16, 16)
+    kinds = ["dct2", "dct2"]
+    L = synth.lowrank_tensor(dims, 20, kinds, seed=2)
+    mask = synth.observation_mask(dims, 0.2, 2)
+    M = np.where(mask, L, 0.0).astype(np.float32).astype(np.float64)
+    forms = {}
+    for name, prec in (("plain_fp32", "fp32"), ("bf16_mixed", "bf16")):
+        Lh, dt, _, _ = _solve(dims, kinds, M, mask, 20, 10, prec, 1.15, 100, 2)
+        forms[name] = {"ms_per_iter": round(dt * 1e3, 4), "rse": osolver.rse(Lh, L)}
+    res["rank20_256x256x16x16"] = forms
+    # learned widths
+    dims5 = (128, 128, 8, 8, 8)
+    X, y = [], []
+    for sd in (101, 102, 103):
+        d2 = (256, 256, 16, 16)
+        rk = synth.rng(sd, "ranks").integers(4, 65, size=256)
+        k2, _, m2, M2 = _completion_problem(d2, rk, 0.6, sd)
+        plan = ht.Plan(d2, k2, r=64, p=10, q=2, precision="fp32", seed=sd)
+        adm = ht.Admm(plan, "completion", phi=("mcp", (10.0,)), mu0=1.0 / synth.max_slice_norm(M2, k2),
+                      vartheta=1.05, mu_max=1e10)
+        import torch
+        f, tg = rankpred.collect_traces(plan, adm, ht.to_device(M2, torch.float32),
+                                        ht.to_device(m2.astype("uint8"), torch.uint8), 60)
+        X.append(f)
+        y.append(tg)
+    net = rankpred.init_network(5)
+    hist = rankpred.train(net, np.concatenate(X), np.concatenate(y), epochs=40, batch=2048, lr=1e-3)
+    rk5 = synth.rng(7, "ranks").integers(4, 65, size=512)
+    k5, L5, m5, M5 = _completion_problem(dims5, rk5, 0.6, 7)
+    forms = {}
+    for name, prec, theta in (("plain_fp32", "fp32", None), ("predicted_widths_fp32", "fp32", net.theta),
+                              ("predicted_widths_bf16", "bf16", net.theta)):
+        Lh, dt, counts, plan = _solve(dims5, k5, M5, m5, 64, 10, prec, 1.05, 100, 7, theta=theta)
+        forms[name] = {"ms_per_iter": round(dt * 1e3, 4), "rse": osolver.rse(Lh, L5)}
+        if counts:
+            forms[name]["slices_predicted"] = counts["predicted"]
+            forms[name]["slices_redone"] = counts["redone"]
+    forms["training"] = {"samples": int(sum(len(v) for v in y)), "loss_first_epoch": hist[0],
+                         "loss_last_epoch": hist[-1]}
+    res["slice_rank_4to64_128x128x8x8x8"] = forms
+    best = {}
+    for key, f in res.items():
+        base = f["plain_fp32"]
+        for name, v in f.items():
+            if name in ("plain_fp32", "training"):
+                continue
+            ok = v["rse"] <= 1.05 * base["rse"]
+            best[key + "/" + name] = {"speedup": round(base["ms_per_iter"] / v["ms_per_iter"], 3),
+                                      "equal_error": bool(ok)}
+    base0 = res["rank20_256x256x16x16"]["plain_fp32"]
+    return {"metric": "solver iteration time vs plain at equal relative error",
+            "value": base0["ms_per_iter"], "unit": "ms/iteration (plain FP32, 256x256x16x16)",
+            "n_gpus": 1, "steps": 100, "warmup": 0, "ms_per_step": base0["ms_per_iter"],
+            "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+            "data": "synthetic", "config": {"workload": "completion_solver_forms"}, "forms": res,
+            "speedups_at_equal_error": best}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -107,6 +327,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--precision", choices=["fp32", "bf16"], default="fp32",
                     help="fp32 (default) or the BF16-mixed path (BF16 transformed slices and sketch products)")
+    ap.add_argument("--workload", choices=["tsvt", "batch", "solver"], default="tsvt",
+                    help="tsvt (default): the 256x256x16x16 t-SVT line; batch: 64 uneven tensors in one plan "
+                         "against per-tensor plans; solver: completion iteration time against the plain FP32 form")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a plain 256 MiB device copy (known bytes) to calibrate HBM counters")
     args = ap.parse_args()
@@ -114,6 +337,12 @@ def main():
         print("bench.py measures one GPU only: the randomized t-SVT path runs on a single MI355X "
               "(multi-GPU sharding is a design note, not built); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
+    if args.workload == "batch":
+        print(json.dumps(bench_batch(args)), flush=True)
+        return
+    if args.workload == "solver":
+        print(json.dumps(bench_solver(args)), flush=True)
+        return
 
     import numpy as np
     import torch
@@ -136,13 +365,15 @@ def main():
         plan.gnhtsvt(dX, wl["tau"], wl["penalty"], call_index=i, out=dOut, workspace=ws)
     torch.cuda.synchronize()
 
-    plan.profile(True)
-    torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(args.steps):
         plan.gnhtsvt(dX, wl["tau"], wl["penalty"], call_index=args.warmup + i, out=dOut, workspace=ws)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
+    # per-stage durations from HIP events on the launch stream, in a second pass
+    plan.profile(True)
+    for i in range(args.steps):
+        plan.gnhtsvt(dX, wl["tau"], wl["penalty"], call_index=args.warmup + i, out=dOut, workspace=ws)
     prof = plan.profile_read()
     plan.profile(False)
 

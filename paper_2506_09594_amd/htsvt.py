@@ -20,6 +20,10 @@ LIB_PATH = os.path.join(_HERE, "libhtsvt.so")
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"libhtsvt.so not found at {LIB_PATH}; build it with paper_2506_09594_amd/build.py")
 
+# PyTorch's HIP runtime must be the one the library binds to: load torch first
+# so that the library resolves libamdhip64 to the copy already in the process.
+import torch  # noqa: E402,F401
+
 _lib = ctypes.CDLL(LIB_PATH)
 
 MAX_ORDER = 8
