@@ -56,7 +56,8 @@ enum {
 /* Transform of one mode k = 3..d (the matrices U_{n_k} of the transform L). */
 enum {
   HT_DCT2_ORTHO = 0,   /* orthonormal DCT-II, alpha = 1 */
-  HT_DFT_UNITARY = 1,  /* unitary DFT, alpha = 1 (complex slices; see below) */
+  HT_DFT_UNITARY = 1,  /* unitary DFT, alpha = 1; must be the kind of every mode 3..d
+                          (complex slices; see ht_plan_desc) */
   HT_CUSTOM_REAL = 2   /* caller-supplied real U with U U^T = alpha I */
 };
 
@@ -94,6 +95,18 @@ typedef struct {
  *  r, p, q     target rank r >= 1, oversampling p >= 0, power steps q >= 0;
  *              sketch width l = min(r + p, n1, n2) <= HT_MAX_WIDTH, kept k = min(r, l)
  *  precision   HT_FP64 / HT_FP32 / HT_BF16_MIXED
+ *  DFT         with HT_DFT_UNITARY on every mode 3..d the transformed slices
+ *              are complex; for real X slice partner(j) (every transform-domain
+ *              index negated modulo n_k) is the conjugate of slice j, so only
+ *              the canonical member of each pair (the smaller index) is
+ *              sketched, with the real Gaussian Omega keyed by that index, and
+ *              the partner's result is its conjugate (the output is real).  A
+ *              complex slice is sketched through its real embedding
+ *              [[Re, -Im], [Im, Re]] with blockdiag(Omega, Omega), so the plan
+ *              needs 2 l <= HT_MAX_WIDTH, reports width 2 l and kept 2 k, and
+ *              its singular values come in equal pairs.  Mixing DFT and real
+ *              kinds is UNSUPPORTED, as are ht_transform, ht_omega_fp64 and
+ *              learned widths on such plans.
  *  seed, stream_id  key of the Gaussian sketch generator (Philox4x32-10,
  *              counter (group, slice, call, stream_id), key = seed) */
 typedef struct {
@@ -125,7 +138,9 @@ int ht_plan_destroy(ht_plan* plan);
 /* Bytes of device workspace needed by ht_gnhtsvt on this plan. */
 int ht_plan_workspace_size(const ht_plan* plan, size_t* bytes);
 
-/* Number of face slices P = n3*...*nd and the sketch width l of the plan. */
+/* Number of sketched face slices (P = n3*...*nd, or the number of conjugate
+ * pairs and self-conjugate slices under the DFT), the largest sketch width
+ * and kept count of the plan. */
 int ht_plan_info(const ht_plan* plan, int64_t* n_slices, int* width, int* kept);
 
 /* Offset and size in bytes of a named region of the workspace, for

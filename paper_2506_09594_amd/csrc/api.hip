@@ -70,7 +70,11 @@ struct TensorHost {
   int64_t n1, n2, P, N;
   int r, p, l, k;
   int64_t x;       // offset in the packed buffers
+  int64_t a;       // offset of its slices in A / C
   int64_t slice0;  // first slice in the slice table
+  int cplx;        // unitary DFT on every transformed mode
+  int64_t nslots;  // slices kept in A (canonical members of conjugate pairs when cplx)
+  int64_t cmap;    // offset of its slot map (cplx)
   ModeTable fwd, inv;
 };
 
@@ -127,6 +131,9 @@ struct ht_plan {
   size_t tf_budget;  // LDS bytes of one transform tile
   size_t tf_lds;
   std::vector<SliceDesc> h_slices;
+  int64_t Atot;   // elements of the A / C regions
+  bool cplx;      // every tensor under the unitary DFT (complex slices)
+  int32_t* d_cmap;
   TensorDesc* d_tens;
   SliceDesc* d_slices;
   int2* d_items;
@@ -204,6 +211,7 @@ void free_plan(ht_plan* pl) {
   if (pl->d_tens) (void)hipFree(pl->d_tens);
   if (pl->d_slices) (void)hipFree(pl->d_slices);
   if (pl->d_items) (void)hipFree(pl->d_items);
+  if (pl->d_cmap) (void)hipFree(pl->d_cmap);
   delete pl;
 }
 
@@ -230,6 +238,15 @@ int add_tensor(const ht_plan_desc* d, std::vector<double>& tab, TensorHost& t) {
   t.l = (int)std::min<int64_t>(std::min<int64_t>((int64_t)d->r + d->p, t.n1), t.n2);
   t.k = std::min(d->r, t.l);
   if (t.l > HT_MAX_WIDTH) HT_FAIL(HT_ERR_UNSUPPORTED, "sketch width min(r+p, n1, n2) above HT_MAX_WIDTH");
+  int ndft = 0;
+  for (int m = 0; m < d->order - 2; ++m) ndft += d->transform[m + 2] == HT_DFT_UNITARY;
+  if (ndft > 0 && ndft != d->order - 2)
+    HT_FAIL(HT_ERR_UNSUPPORTED, "DFT_UNITARY must be the transform of every mode 3..d (no mixing with real kinds)");
+  t.cplx = ndft > 0;
+  if (t.cplx && 2 * t.l > HT_MAX_WIDTH)
+    HT_FAIL(HT_ERR_UNSUPPORTED, "complex slices are sketched through their real embedding: need 2 l <= HT_MAX_WIDTH");
+  if (t.cplx && (2 * t.n1 * t.n2 > (int64_t)INT32_MAX))
+    HT_FAIL(HT_ERR_UNSUPPORTED, "complex face slice above 2^31 elements");
   t.fwd.nmodes = t.inv.nmodes = d->order - 2;
   int stride = 1;
   for (int m = 0; m < d->order - 2; ++m) {
@@ -256,7 +273,26 @@ int add_tensor(const ht_plan_desc* d, std::vector<double>& tab, TensorHost& t) {
       if (!(alpha > 0.0) || err > 1e-10 * alpha)
         HT_FAIL(HT_ERR_INVALID_ARG, "CUSTOM_REAL matrix must satisfy U U^T = alpha I");
     } else if (kind == HT_DFT_UNITARY) {
-      HT_FAIL(HT_ERR_UNSUPPORTED, "DFT_UNITARY transforms are not implemented in this build");
+      // interleaved (re, im): forward F[k][m] = exp(-2 pi i k m / n) / sqrt(n), inverse F^H
+      const double sc = 1.0 / std::sqrt((double)n);
+      t.fwd.n[m] = t.inv.n[m] = n;
+      t.fwd.stride[m] = t.inv.stride[m] = stride;
+      stride *= n;
+      t.fwd.off[m] = (int)tab.size();
+      for (int a = 0; a < n; ++a)
+        for (int b = 0; b < n; ++b) {
+          const double ang = -2.0 * M_PI * (double)((int64_t)a * b % n) / n;
+          tab.push_back(std::cos(ang) * sc);
+          tab.push_back(std::sin(ang) * sc);
+        }
+      t.inv.off[m] = (int)tab.size();
+      for (int a = 0; a < n; ++a)
+        for (int b = 0; b < n; ++b) {  // conj(F[b][a])
+          const double ang = -2.0 * M_PI * (double)((int64_t)b * a % n) / n;
+          tab.push_back(std::cos(ang) * sc);
+          tab.push_back(-std::sin(ang) * sc);
+        }
+      continue;
     } else {
       HT_FAIL(HT_ERR_INVALID_ARG, "unknown transform kind");
     }
@@ -342,10 +378,11 @@ int tf_items(ht_plan* pl, size_t budget, std::vector<int2>& items, std::vector<i
   lds = 0;
   for (size_t t = 0; t < pl->tens.size(); ++t) {
     const TensorHost& th = pl->tens[t];
-    const int TP = transform_tile_width(th.P, es, budget);
+    const size_t tes = th.cplx ? 2 * es : es;  // complex tiles hold two planes
+    const int TP = transform_tile_width(th.P, tes, budget);
     if (TP == 0) HT_FAIL(HT_ERR_UNSUPPORTED, "too many face slices for the transform tile");
     tps.push_back(TP);
-    lds = std::max(lds, (size_t)TP * th.P * es);
+    lds = std::max(lds, (size_t)TP * th.P * tes);
     const int64_t NT = th.n1 * th.n2;
     for (int64_t t0 = 0; t0 < NT; t0 += TP) items.push_back(make_int2((int)t, (int)t0));
   }
@@ -359,7 +396,11 @@ int upload_tensors(ht_plan* pl, const std::vector<int>& tps) {
     TensorDesc& d = td[t];
     std::memset(&d, 0, sizeof(d));
     d.x = th.x;
+    d.a = th.a;
     d.NT = th.n1 * th.n2;
+    d.cmap = th.cmap;
+    d.cplx = th.cplx;
+    d.n1 = (int32_t)th.n1;
     d.P = (int32_t)th.P;
     d.TP = tps[t];
     int lg = 0;
@@ -395,13 +436,13 @@ constexpr size_t kTfBudgets[] = {32 * 1024, 64 * 1024, 128 * 1024};
 
 void layout(ht_plan* pl, int64_t nY, int64_t nZ, int64_t nK, int64_t nG1, int64_t nG2) {
   const size_t es = elem_bytes(pl->precision);
-  pl->size[WS_A] = (size_t)pl->Ntot * (pl->precision == HT_BF16_MIXED ? 2 : es);
+  pl->size[WS_A] = (size_t)pl->Atot * (pl->precision == HT_BF16_MIXED ? 2 : es);
   pl->size[WS_OMEGA] = (size_t)nZ * es;
   pl->size[WS_Y] = (size_t)nY * es;
   pl->size[WS_Z] = (size_t)nZ * es;
   pl->size[WS_K] = (size_t)nK * es;
   pl->size[WS_QK] = (size_t)nY * es;
-  pl->size[WS_C] = (size_t)pl->Ntot * es;
+  pl->size[WS_C] = (size_t)pl->Atot * es;
   pl->size[WS_GP1] = (size_t)nG1 * sizeof(double);
   pl->size[WS_GP2] = (size_t)nG2 * sizeof(double);
   pl->size[WS_WK] = (size_t)pl->Ptot * sizeof(int2);
@@ -448,8 +489,10 @@ int build_plan(const ht_plan_desc* descs, int n, bool batch, ht_plan** out) {
   pl->stream_id = d0.stream_id;
   if (hipGetDevice(&pl->device) != hipSuccess) pl->device = 0;
   std::vector<double> tab;
+  std::vector<int32_t> cmap;
   pl->tens.resize(n);
-  int64_t x = 0, P = 0;
+  int64_t x = 0, P = 0, Atot = 0;
+  int ncplx = 0;
   pl->lmax = 0;
   pl->kmax = 0;
   pl->max_n2l = 0;
@@ -463,45 +506,85 @@ int build_plan(const ht_plan_desc* descs, int n, bool batch, ht_plan** out) {
     th.x = x;
     th.slice0 = P;
     x += batch ? (th.N + 63) / 64 * 64 : th.N;  // 256-byte aligned tensors in a packed batch
-    P += th.P;
-    pl->lmax = std::max(pl->lmax, th.l);
-    pl->kmax = std::max(pl->kmax, th.k);
-    pl->max_n2l = std::max<int64_t>(pl->max_n2l, th.n2 * th.l);
+    const int f = th.cplx ? 2 : 1;                // complex slices: real embedding of twice the size
+    th.nslots = th.P;
+    if (th.cplx) {
+      // slot map: the canonical member of every conjugate pair (partner index =
+      // every transform-domain index negated modulo n_k) gets a slot
+      th.cmap = (int64_t)cmap.size();
+      cmap.resize(cmap.size() + th.P);
+      int32_t* cm = cmap.data() + th.cmap;
+      int64_t slots = 0;
+      for (int64_t j = 0; j < th.P; ++j) {
+        int64_t rem = j, pj = 0, stride = 1;
+        for (int m = 2; m < th.order; ++m) {
+          const int64_t nm = th.dims[m], i = rem % nm;
+          rem /= nm;
+          pj += ((nm - i) % nm) * stride;
+          stride *= nm;
+        }
+        if (pj >= j) {
+          cm[j] = (int32_t)slots++;
+        } else {
+          cm[j] = (int32_t)(cm[pj] | (int32_t)0x80000000u);
+        }
+      }
+      th.nslots = slots;
+    }
+    th.a = Atot;
+    Atot += th.nslots * f * th.n1 * th.n2;
+    Atot = (Atot + 63) / 64 * 64;
+    P += th.nslots;
+    pl->lmax = std::max(pl->lmax, f * th.l);
+    pl->kmax = std::max(pl->kmax, f * th.k);
+    pl->max_n2l = std::max<int64_t>(pl->max_n2l, (int64_t)f * th.n2 * f * th.l);
+    ncplx += th.cplx;
   }
+  if (ncplx != 0 && ncplx != n) {
+    free_plan(pl);
+    HT_FAIL(HT_ERR_UNSUPPORTED, "a batch mixes DFT and real transforms");
+  }
+  pl->cplx = ncplx > 0;
   if (P > (int64_t)INT32_MAX / 64) {
     free_plan(pl);
     HT_FAIL(HT_ERR_UNSUPPORTED, "too many face slices in one plan");
   }
   pl->Ntot = x;
   pl->Ptot = P;
+  pl->Atot = Atot;
 
-  // slice table
+  // slice table (complex slices: the real embedding of the n1 x n2 complex matrix)
   pl->h_slices.resize(P);
   int64_t oY = 0, oZ = 0, oK = 0, oG1 = 0, oG2 = 0;
   for (int t = 0; t < n; ++t) {
     const TensorHost& th = pl->tens[t];
-    const int64_t NT = th.n1 * th.n2, l = th.l;
-    for (int64_t j = 0; j < th.P; ++j) {
-      SliceDesc& d = pl->h_slices[th.slice0 + j];
-      d.a = th.x + j * NT;
+    const int f = th.cplx ? 2 : 1;
+    const int64_t NT = th.n1 * th.n2, l = f * th.l, n1 = f * th.n1, n2 = f * th.n2;
+    for (int64_t j = 0, s = 0; j < th.P; ++j) {
+      if (th.cplx && cmap[th.cmap + j] < 0) continue;  // a conjugate partner: no slot
+      SliceDesc& d = pl->h_slices[th.slice0 + s];
+      d.a = th.a + s * f * NT;
       d.y = oY;
       d.z = oZ;
       d.kq = oK;
       d.g1 = oG1;
       d.g2 = oG2;
-      d.n1 = (int32_t)th.n1;
-      d.n2 = (int32_t)th.n2;
-      d.l = th.l;
-      d.k = th.k;
+      d.n1 = (int32_t)n1;
+      d.n2 = (int32_t)n2;
+      d.l = (int32_t)l;
+      d.k = f * th.k;
       d.tensor = t;
-      d.local = (int32_t)j;
+      d.local = (int32_t)j;  // the Philox slice word: the canonical member's index
       d.p = th.p;
+      d.cplx = th.cplx;
+      d.nc = (int32_t)th.n2;
       d.pad = 0;
-      oY += align4(th.n1 * l);
-      oZ += align4(th.n2 * l);
+      oY += align4(n1 * l);
+      oZ += align4(n2 * l);
       oK += align4(l * l);
-      oG1 += ceil_div(std::max(th.n1, th.n2), 64) * l * l;
-      oG2 += ceil_div(th.n1, 64) * l * l;
+      oG1 += ceil_div(std::max(n1, n2), 64) * l * l;
+      oG2 += ceil_div(n1, 64) * l * l;
+      ++s;
     }
   }
   layout(pl, oY, oZ, oK, oG1, oG2);
@@ -558,6 +641,12 @@ int build_plan(const ht_plan_desc* descs, int n, bool batch, ht_plan** out) {
   if (!ok) {
     free_plan(pl);
     HT_FAIL(HT_ERR_ALLOC, "could not allocate or upload the plan tables");
+  }
+  if (!cmap.empty() && (hipMalloc(&pl->d_cmap, cmap.size() * sizeof(int32_t)) != hipSuccess ||
+                        hipMemcpy(pl->d_cmap, cmap.data(), cmap.size() * sizeof(int32_t), hipMemcpyHostToDevice) !=
+                            hipSuccess)) {
+    free_plan(pl);
+    HT_FAIL(HT_ERR_ALLOC, "could not upload the slot map");
   }
   if (hipMemcpy(pl->d_slices, pl->h_slices.data(), P * sizeof(SliceDesc), hipMemcpyHostToDevice) != hipSuccess ||
       hipMemcpy(pl->d_items, all.data(), all.size() * sizeof(int2), hipMemcpyHostToDevice) != hipSuccess) {
@@ -648,11 +737,18 @@ int run_tsvt(const ht_plan* pl, const T* X, T* out, double tau, const double* ta
   int* lstate = ws_ptr<int>(pl, ws, WS_LSTATE);
   int rc;
   if ((rc = timed(pl, ST_TRANSFORM_FWD, s, [&] {
+         const int2* it = items(pl, pl->it_tf);
+         if (pl->cplx) {
+           if (bf16)
+             return launch_transform_cplx<float, uint16_t>((const float*)X, (uint16_t*)A, pl->d_tens, it,
+                                                           pl->it_tf.n, pl->tf_lds, pl->table32, pl->d_cmap, 0, s);
+           return launch_transform_cplx<T, T>(X, A, pl->d_tens, it, pl->it_tf.n, pl->tf_lds, table<T>(pl),
+                                              pl->d_cmap, 0, s);
+         }
          if (bf16)
-           return launch_transform<float, uint16_t>((const float*)X, (uint16_t*)A, pl->d_tens, items(pl, pl->it_tf),
-                                                    pl->it_tf.n, pl->tf_lds, pl->table32, 0, s);
-         return launch_transform<T, T>(X, A, pl->d_tens, items(pl, pl->it_tf), pl->it_tf.n, pl->tf_lds, table<T>(pl),
-                                       0, s);
+           return launch_transform<float, uint16_t>((const float*)X, (uint16_t*)A, pl->d_tens, it, pl->it_tf.n,
+                                                    pl->tf_lds, pl->table32, 0, s);
+         return launch_transform<T, T>(X, A, pl->d_tens, it, pl->it_tf.n, pl->tf_lds, table<T>(pl), 0, s);
        })))
     return rc;
   if (mode) {  // ||A_j||^2 and this call's widths
@@ -744,6 +840,9 @@ int run_tsvt(const ht_plan* pl, const T* X, T* out, double tau, const double* ta
        })))
     return rc;
   return timed(pl, ST_TRANSFORM_INV, s, [&] {
+    if (pl->cplx)
+      return launch_transform_cplx<T, T>(C, out, pl->d_tens, items(pl, pl->it_tf), pl->it_tf.n, pl->tf_lds,
+                                         table<T>(pl), pl->d_cmap, 1, s);
     return launch_transform<T, T>(C, out, pl->d_tens, items(pl, pl->it_tf), pl->it_tf.n, pl->tf_lds, table<T>(pl), 1,
                                   s);
   });
@@ -1064,7 +1163,7 @@ int ht_batch_gnhtsvt(ht_plan* pl, const void* X, void* out, const double* tau_de
 
 int ht_omega_fp64(const ht_plan* pl, uint32_t call_index, double* dev_out, void* stream) {
   if (!pl || !dev_out) HT_FAIL(HT_ERR_INVALID_ARG, "plan/out is NULL");
-  if (pl->batch) HT_FAIL(HT_ERR_UNSUPPORTED, "ht_omega_fp64 takes a single-tensor plan");
+  if (pl->batch || pl->cplx) HT_FAIL(HT_ERR_UNSUPPORTED, "ht_omega_fp64 takes a single-tensor real plan");
   const TensorHost& th = pl->tens[0];
   return launch_omega<double>(nullptr, dev_out, pl->d_slices, nullptr, (int)pl->Ptot, pl->max_n2l, call_index, nullptr,
                               pl->stream_id, pl->seed, th.n2 * th.l, static_cast<hipStream_t>(stream));
@@ -1072,6 +1171,7 @@ int ht_omega_fp64(const ht_plan* pl, uint32_t call_index, double* dev_out, void*
 
 int ht_transform(const ht_plan* pl, const void* X, void* out, int inverse, void* stream) {
   if (!pl || !X || !out) HT_FAIL(HT_ERR_INVALID_ARG, "plan/X/out is NULL");
+  if (pl->cplx) HT_FAIL(HT_ERR_UNSUPPORTED, "ht_transform takes a real-transform plan");
   hipStream_t s = static_cast<hipStream_t>(stream);
   const int inv = inverse ? 1 : 0;
   if (pl->precision == HT_FP64)
@@ -1085,6 +1185,7 @@ int ht_plan_learned(ht_plan* pl, int mode, const float* theta) {
   if (!pl) HT_FAIL(HT_ERR_INVALID_ARG, "plan is NULL");
   if (mode < 0 || mode > 2) HT_FAIL(HT_ERR_INVALID_ARG, "mode must be 0, 1 or 2");
   if (mode == 2 && !theta) HT_FAIL(HT_ERR_INVALID_ARG, "predicted widths need the network parameters");
+  if (mode != 0 && pl->cplx) HT_FAIL(HT_ERR_UNSUPPORTED, "learned widths are not available for DFT plans");
   pl->learn_mode = mode;
   pl->learn_theta = theta;
   if (pl->graph) pl->graph->reset();

@@ -21,20 +21,33 @@ struct ModeTable {
   int off[HT_MAX_ORDER];     // offset of the n x n row-major matrix in the table
 };
 
-// One tensor of a plan (element offsets are into the packed X / A / C / out
-// buffers, which hold the tensors one after another, each in Fortran order).
+// One tensor of a plan.  X and out are packed buffers holding the tensors one
+// after another, each in Fortran order; A and C hold the transformed slices
+// the method works on.  For a real transform slice j of the tensor is the
+// n1 x n2 block at a + j n1 n2.  Under the unitary DFT on every mode 3..d only
+// one slice of each conjugate pair is kept (slot s of the tensor), stored as
+// the stacked real block [Re; Im] (2 n1 x n2, column-major) at a + 2 s n1 n2;
+// cmap[j] is the slot of slice j, with bit 31 set when j is the conjugate
+// partner of the slot's slice.
 struct TensorDesc {
-  int64_t x;      // offset of the tensor (and of its slice 0 in A and C)
+  int64_t x;      // offset of the tensor in X / out
+  int64_t a;      // offset of its slices in A / C
   int64_t NT;     // n1 * n2: elements per face slice
+  int64_t cmap;   // offset of its slot map in the plan's map (complex tensors)
   int32_t P;      // face slices
   int32_t TP;     // tube positions per transform tile (power of two)
   int32_t lgTP;
   int32_t slice0; // index of its first slice in the slice table
-  ModeTable fwd, inv;
+  int32_t cplx;   // unitary DFT on every transformed mode (complex slices)
+  int32_t n1;
+  ModeTable fwd, inv;  // complex matrices (interleaved re, im) when cplx
 };
 
 // One transformed face slice.  Thin blocks are laid out for the plan's
-// maximum width lmax; a slice uses the first l columns.
+// maximum width lmax; a slice uses the first l columns.  A complex slice
+// (cplx = 1) is handled through the real embedding of its n1o x n2o complex
+// matrix, [[Re, -Im], [Im, Re]]: here n1 = 2 n1o, n2 = 2 n2o, and l, k are
+// twice the complex width and kept count (singular values come in pairs).
 struct SliceDesc {
   int64_t a;   // offset of the n1 x n2 slice in A and C (elements)
   int64_t y;   // offset of its n1 x lmax block in Y and QK
@@ -47,8 +60,22 @@ struct SliceDesc {
   int32_t tensor;   // index of the tensor (the Philox stream word is stream_base + tensor)
   int32_t local;    // slice index within the tensor (the Philox counter word)
   int32_t p;        // oversampling of the tensor (learned widths)
+  int32_t cplx;     // complex slice (real embedding of the stacked block)
+  int32_t nc;       // columns of C written by the reconstruction (n2, or n2o)
   int32_t pad;
 };
+
+// Element (r, k) of the operand of slice d: the stored column-major block, or
+// for a complex slice the real embedding [[Ar, -Ai], [Ai, Ar]] of the stacked
+// block [Ar; Ai] (lda = 2 n1o rows, n2o columns), without forming it.
+__host__ __device__ inline int64_t embed_index(int r, int k, int lda, int cplx, int n1o, int n2o, bool& neg) {
+  neg = false;
+  if (cplx && k >= n2o) {
+    neg = r < n1o;
+    return (int64_t)(neg ? r + n1o : r - n1o) + (int64_t)(k - n2o) * lda;
+  }
+  return (int64_t)r + (int64_t)k * lda;
+}
 
 // Width and kept count of slice s: from the slice table, or from an optional
 // per-slice (l, k) array written on the device (learned widths; l = 0 skips

@@ -67,11 +67,23 @@ __global__ __launch_bounds__(64 * NW) void k_mfma_thin(const float* __restrict__
   const float* Aj = Aall + d.a;
   const float* Wj = Wall + woff;
   float* Yj = Yall + yoff;
-  const bool vecA = aligned && (lda % 4 == 0) && (d.a % 4 == 0);
+  const int cplx = d.cplx, n1o = d.n1 / 2, n2o = d.n2 / 2;
+  const bool vecA = aligned && (lda % 4 == 0) && (d.a % 4 == 0) && (!cplx || n1o % 4 == 0);
   const bool vecW = aligned && (ldw % 4 == 0) && (woff % 4 == 0);
   const int tid = threadIdx.x;
   const int wave = tid / 64, lane = tid % 64;
   const int LW = 32 * NB;
+  // element (r, k) of the slice operand (complex slices: the real embedding)
+  auto aval = [&](int r, int k) -> float {
+    bool neg;
+    const float v = Aj[embed_index(r, k, lda, cplx, n1o, n2o, neg)];
+    return neg ? -v : v;
+  };
+  auto avec = [&](int r, int k) -> f32x4 {  // rows r..r+3 of column k (no straddle when vecA)
+    bool neg;
+    const f32x4 v = *reinterpret_cast<const f32x4*>(Aj + embed_index(r, k, lda, cplx, n1o, n2o, neg));
+    return neg ? -v : v;
+  };
 
   // ---- global -> register staging of one K chunk --------------------------
   // A chunk: MT x KC values = 8 MT float4 groups; 4 per thread.
@@ -89,22 +101,22 @@ __global__ __launch_bounds__(64 * NW) void k_mfma_thin(const float* __restrict__
         const int kk = f / (MT / 4), row = (f % (MT / 4)) * 4;
         const int gr = r0 + row, gk = k0 + kk;
         if (vecA && gk < K && gr + 3 < M_out) {
-          ra[u] = *reinterpret_cast<const f32x4*>(Aj + gr + (int64_t)gk * lda);
+          ra[u] = avec(gr, gk);
         } else {
           f32x4 v;
 #pragma unroll
-          for (int e = 0; e < 4; ++e) v[e] = (gk < K && gr + e < M_out) ? Aj[gr + e + (int64_t)gk * lda] : 0.0f;
+          for (int e = 0; e < 4; ++e) v[e] = (gk < K && gr + e < M_out) ? aval(gr + e, gk) : 0.0f;
           ra[u] = v;
         }
       } else {
         const int row = f / (KC / 4), kk = (f % (KC / 4)) * 4;
         const int gc = r0 + row, gk = k0 + kk;
         if (vecA && gc < M_out && gk + 3 < K) {
-          ra[u] = *reinterpret_cast<const f32x4*>(Aj + gk + (int64_t)gc * lda);
+          ra[u] = avec(gk, gc);
         } else {
           f32x4 v;
 #pragma unroll
-          for (int e = 0; e < 4; ++e) v[e] = (gc < M_out && gk + e < K) ? Aj[gk + e + (int64_t)gc * lda] : 0.0f;
+          for (int e = 0; e < 4; ++e) v[e] = (gc < M_out && gk + e < K) ? aval(gk + e, gc) : 0.0f;
           ra[u] = v;
         }
       }

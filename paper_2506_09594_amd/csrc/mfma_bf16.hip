@@ -61,11 +61,25 @@ __global__ __launch_bounds__(64 * NW) void k_mfma_thin_bf16(const uint16_t* __re
   const uint16_t* Aj = Aall + d.a;
   const float* Wj = Wall + woff;
   float* Yj = Yall + yoff;
-  const bool vecA = aligned && (lda % 8 == 0) && (d.a % 8 == 0);
+  const int cplx = d.cplx, n1o = d.n1 / 2, n2o = d.n2 / 2;
+  const bool vecA = aligned && (lda % 8 == 0) && (d.a % 8 == 0) && (!cplx || n1o % 8 == 0);
   const bool vecW = aligned && (ldw % 4 == 0) && (woff % 4 == 0);
   const int tid = threadIdx.x;
   const int wave = tid / 64, lane = tid % 64;
   const int LW = 32 * NB;
+  // element (r, k) of the slice operand as BF16 bits (complex slices: the real
+  // embedding; a negation flips the sign bit)
+  auto aval = [&](int r, int k) -> uint16_t {
+    bool neg;
+    const uint16_t v = Aj[embed_index(r, k, lda, cplx, n1o, n2o, neg)];
+    return neg ? (uint16_t)(v ^ 0x8000u) : v;
+  };
+  auto avec = [&](int r, int k) -> u16x8 {  // rows r..r+7 of column k (no straddle when vecA)
+    bool neg;
+    u16x8 v = *reinterpret_cast<const u16x8*>(Aj + embed_index(r, k, lda, cplx, n1o, n2o, neg));
+    if (neg) v ^= (unsigned short)0x8000u;
+    return v;
+  };
 
   // A chunk: MT x 32 bf16 = 4 MT 16-byte groups of 8, two per thread.
   // nn: group = 8 consecutive rows of one column k;  tn: 8 consecutive k of one column.
@@ -82,19 +96,19 @@ __global__ __launch_bounds__(64 * NW) void k_mfma_thin_bf16(const uint16_t* __re
         const int kk = g / (MT / 8), row = (g % (MT / 8)) * 8;
         const int gr = r0 + row, gk = k0 + kk;
         if (vecA && gk < K && gr + 7 < M_out) {
-          v = *reinterpret_cast<const u16x8*>(Aj + gr + (int64_t)gk * lda);
+          v = avec(gr, gk);
         } else {
 #pragma unroll
-          for (int e = 0; e < 8; ++e) v[e] = (gk < K && gr + e < M_out) ? Aj[gr + e + (int64_t)gk * lda] : 0;
+          for (int e = 0; e < 8; ++e) v[e] = (gk < K && gr + e < M_out) ? aval(gr + e, gk) : 0;
         }
       } else {
         const int row = g / (KC / 8), kk = (g % (KC / 8)) * 8;
         const int gc = r0 + row, gk = k0 + kk;
         if (vecA && gc < M_out && gk + 7 < K) {
-          v = *reinterpret_cast<const u16x8*>(Aj + gk + (int64_t)gc * lda);
+          v = avec(gk, gc);
         } else {
 #pragma unroll
-          for (int e = 0; e < 8; ++e) v[e] = (gc < M_out && gk + e < K) ? Aj[gk + e + (int64_t)gc * lda] : 0;
+          for (int e = 0; e < 8; ++e) v[e] = (gc < M_out && gk + e < K) ? aval(gk + e, gc) : 0;
         }
       }
       ra[u] = v;

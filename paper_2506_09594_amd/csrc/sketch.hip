@@ -66,6 +66,7 @@ __global__ __launch_bounds__(256) void k_gemm_nn(const T* __restrict__ Aall, con
   const T* Aj = Aall + (RECON ? d.y : d.a);
   const T* Wj = Wall + (RECON ? d.kq : d.z);
   T* Yj = Yall + d.y;
+  const int cplx = RECON ? 0 : d.cplx, n1o = d.n1 / 2, n2o = d.n2 / 2;
   const int tr = threadIdx.x % TM, tc = threadIdx.x / TM;
   T acc[CPT];
 #pragma unroll
@@ -74,7 +75,13 @@ __global__ __launch_bounds__(256) void k_gemm_nn(const T* __restrict__ Aall, con
     for (int idx = threadIdx.x; idx < KC * TM; idx += 256) {
       const int kk = idx / TM, rr = idx % TM;
       const int gr = row0 + rr, gk = k0 + kk;
-      As[kk][rr] = (gr < m && gk < kd) ? Aj[gr + (int64_t)gk * lda] : T(0);
+      T v = T(0);
+      if (gr < m && gk < kd) {
+        bool neg;
+        v = Aj[embed_index(gr, gk, lda, cplx, n1o, n2o, neg)];
+        if (neg) v = -v;
+      }
+      As[kk][rr] = v;
     }
     for (int idx = threadIdx.x; idx < KC * LB; idx += 256) {
       const int c = idx / KC, kk = idx % KC;
@@ -121,6 +128,7 @@ __global__ __launch_bounds__(256) void k_gemm_tn(const T* __restrict__ Aall, con
   const T* Aj = Aall + d.a;
   const T* Qj = Qall + d.y;
   T* Zj = Zall + d.z;
+  const int cplx = d.cplx, n1o = d.n1 / 2, n2o = d.n2 / 2;
   const int tcol = threadIdx.x % TM, tc = threadIdx.x / TM;
   T acc[CPT];
 #pragma unroll
@@ -129,7 +137,13 @@ __global__ __launch_bounds__(256) void k_gemm_tn(const T* __restrict__ Aall, con
     for (int idx = threadIdx.x; idx < KC * TM; idx += 256) {
       const int kk = idx % KC, cc = idx / KC;
       const int gk = k0 + kk, gc = col0 + cc;
-      As[kk][cc] = (gk < m && gc < n) ? Aj[gk + (int64_t)gc * lda] : T(0);
+      T v = T(0);
+      if (gk < m && gc < n) {
+        bool neg;
+        v = Aj[embed_index(gk, gc, lda, cplx, n1o, n2o, neg)];
+        if (neg) v = -v;
+      }
+      As[kk][cc] = v;
     }
     for (int idx = threadIdx.x; idx < KC * LB; idx += 256) {
       const int kk = idx % KC, c = idx / KC;
@@ -172,13 +186,13 @@ __global__ __launch_bounds__(256) void k_gemm_nt(const T* __restrict__ Xall, con
   const SliceDesc d = sd[s];
   const int l = slice_width(d, wk, s);
   if (l <= 0) return;  // slice not part of this pass
-  const int m = d.n1, n = d.n2;
+  const int m = d.n1, n = d.nc;  // complex slices: the left block column [Re C; Im C]
   const int nrt = (m + 63) / 64;
   const int row0 = (item.y % nrt) * 64, col0 = (item.y / nrt) * 64;
   const T* Xj = Xall + d.y;
   const T* Wj = Wall + d.z;
   T* Cj = Call + d.a;
-  const int ldx = m, ldw = n, ldc = m;
+  const int ldx = m, ldw = d.n2, ldc = m;
   const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
   T acc[4][4];
 #pragma unroll

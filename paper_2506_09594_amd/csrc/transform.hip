@@ -102,9 +102,10 @@ __global__ __launch_bounds__(256) void k_transform(const T* __restrict__ in_all,
   const int64_t NT = td->NT;
   const int P = td->P, TP = td->TP, lgTP = td->lgTP;
   const ModeTable* mt = inverse ? &td->inv : &td->fwd;
-  const T* in = in_all + td->x;
-  TO* out = out_all + td->x;
-  const int vec = aligned && (NT % V == 0) && (TP % V == 0) && (td->x % V == 0);
+  // forward: X (packed, offset x) -> A (offset a); inverse: C (offset a) -> out (offset x)
+  const T* in = in_all + (inverse ? td->a : td->x);
+  TO* out = out_all + (inverse ? td->x : td->a);
+  const int vec = aligned && (NT % V == 0) && (TP % V == 0) && (td->x % V == 0) && (td->a % V == 0);
   const int64_t t0 = item.y;
   const int64_t rem = NT - t0;
   const int tp = rem < TP ? (int)rem : TP;
@@ -223,6 +224,156 @@ __global__ __launch_bounds__(256) void k_transform(const T* __restrict__ in_all,
   }
 }
 
+// ---------------------------------------------------------------------------
+// Unitary DFT on every mode 3..d (complex slices).  The tile holds TP tube
+// positions of all P slices as two planes (real, imaginary).  Forward: the
+// real X tile is transformed mode by mode with the complex matrices and the
+// canonical slice of every conjugate pair is stored as its stacked block
+// [Re; Im]; the partner (the conjugate, for real X) is not stored.  Inverse:
+// every slice is filled from its slot (conjugated for partners), the inverse
+// matrices are applied and the real part is stored (the imaginary part is
+// zero up to rounding for conjugate-symmetric data).
+// ---------------------------------------------------------------------------
+template <typename T, int NMAX>
+__device__ __forceinline__ void cplx_fiber(T* re, T* im, int base, int stride, int n, const T* __restrict__ M) {
+  T vr[NMAX], vi[NMAX];
+#pragma unroll
+  for (int b = 0; b < NMAX; ++b) {
+    vr[b] = (b < n) ? re[base + b * stride] : T(0);
+    vi[b] = (b < n) ? im[base + b * stride] : T(0);
+  }
+#pragma unroll
+  for (int a = 0; a < NMAX; ++a) {
+    if (a < n) {
+      T sr = T(0), si = T(0);
+#pragma unroll
+      for (int b = 0; b < NMAX; ++b) {
+        if (b < n) {
+          const T mr = M[2 * (a * n + b)], mi = M[2 * (a * n + b) + 1];
+          sr += mr * vr[b] - mi * vi[b];
+          si += mr * vi[b] + mi * vr[b];
+        }
+      }
+      re[base + a * stride] = sr;
+      im[base + a * stride] = si;
+    }
+  }
+}
+
+template <typename T, typename TO>
+__global__ __launch_bounds__(256) void k_transform_cplx(const T* __restrict__ in_all, TO* __restrict__ out_all,
+                                                        const TensorDesc* __restrict__ tds,
+                                                        const int2* __restrict__ items, const T* __restrict__ table,
+                                                        const int32_t* __restrict__ cmap_all, int inverse) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int2 item = items[blockIdx.x];
+  const TensorDesc* td = tds + item.x;
+  const int64_t NT = td->NT;
+  const int P = td->P, TP = td->TP, lgTP = td->lgTP, n1 = td->n1;
+  const ModeTable* mt = inverse ? &td->inv : &td->fwd;
+  const int32_t* cmap = cmap_all + td->cmap;
+  T* re = reinterpret_cast<T*>(smem_raw);
+  const int total = TP * P;
+  T* im = re + total;
+  const int64_t t0 = item.y;
+  const int64_t rem = NT - t0;
+  const int tp = rem < TP ? (int)rem : TP;
+  const int tid = threadIdx.x, nt = blockDim.x;
+  // ---- load --------------------------------------------------------------------
+  if (!inverse) {
+    const T* in = in_all + td->x;
+    for (int idx = tid; idx < total; idx += nt) {
+      const int j = idx >> lgTP, t = idx & (TP - 1);
+      re[idx] = (t < tp) ? in[(int64_t)j * NT + t0 + t] : T(0);
+      im[idx] = T(0);
+    }
+  } else {
+    const T* C = in_all + td->a;  // slots [Re; Im], 2 NT each
+    for (int idx = tid; idx < total; idx += nt) {
+      const int j = idx >> lgTP, t = idx & (TP - 1);
+      T vr = T(0), vi = T(0);
+      if (t < tp) {
+        const int32_t code = cmap[j];
+        const int slot = code & 0x7fffffff;
+        const int64_t tt = t0 + t;
+        const int64_t i1 = tt % n1, i2 = tt / n1;
+        const T* S = C + (int64_t)slot * 2 * NT + i1 + i2 * 2 * n1;
+        vr = S[0];
+        vi = S[n1];
+        if (code < 0) vi = -vi;  // conjugate partner
+      }
+      re[idx] = vr;
+      im[idx] = vi;
+    }
+  }
+  __syncthreads();
+  // ---- modes ---------------------------------------------------------------------
+  for (int m = 0; m < mt->nmodes; ++m) {
+    const int n = mt->n[m];
+    const int s = mt->stride[m];
+    const T* M = table + mt->off[m];
+    const int nfib = total / n;
+    for (int f = tid; f < nfib; f += nt) {
+      const int base = fiber_base(f, TP, lgTP, s, n);
+      if (n <= 8)
+        cplx_fiber<T, 8>(re, im, base, s * TP, n, M);
+      else if (n <= 16)
+        cplx_fiber<T, 16>(re, im, base, s * TP, n, M);
+      else if (n <= 32)
+        cplx_fiber<T, 32>(re, im, base, s * TP, n, M);
+      else
+        cplx_fiber<T, 64>(re, im, base, s * TP, n, M);
+    }
+    __syncthreads();
+  }
+  // ---- store ---------------------------------------------------------------------
+  if (!inverse) {
+    TO* A = out_all + td->a;
+    for (int idx = tid; idx < total; idx += nt) {
+      const int j = idx >> lgTP, t = idx & (TP - 1);
+      const int32_t code = cmap[j];
+      if (t < tp && code >= 0) {  // canonical member of its pair
+        const int64_t tt = t0 + t;
+        const int64_t i1 = tt % n1, i2 = tt / n1;
+        TO* S = A + (int64_t)code * 2 * NT + i1 + i2 * 2 * n1;
+        if constexpr (std::is_same<TO, T>::value) {
+          S[0] = re[idx];
+          S[n1] = im[idx];
+        } else {
+          S[0] = f32_to_bf16_rne((float)re[idx]);
+          S[n1] = f32_to_bf16_rne((float)im[idx]);
+        }
+      }
+    }
+  } else {
+    TO* out = out_all + td->x;
+    for (int idx = tid; idx < total; idx += nt) {
+      const int j = idx >> lgTP, t = idx & (TP - 1);
+      if (t < tp) out[(int64_t)j * NT + t0 + t] = (TO)re[idx];
+    }
+  }
+}
+
+template <typename T, typename TO>
+int launch_transform_cplx(const T* in, TO* out, const TensorDesc* tds, const int2* items, int nitems, size_t lds,
+                          const T* table, const int32_t* cmap, int inverse, hipStream_t stream) {
+  if (nitems == 0) return HT_OK;
+  if (lds > 160 * 1024) HT_FAIL(HT_ERR_UNSUPPORTED, "transform tile above the LDS size");
+  int rc = ensure_dynamic_lds((const void*)k_transform_cplx<T, TO>, 160 * 1024);
+  if (rc) return rc;
+  hipLaunchKernelGGL((k_transform_cplx<T, TO>), dim3((unsigned)nitems), dim3(256), lds, stream, in, out, tds, items,
+                     table, cmap, inverse);
+  HT_CHECK_LAUNCH();
+  return HT_OK;
+}
+
+template int launch_transform_cplx<float, float>(const float*, float*, const TensorDesc*, const int2*, int, size_t,
+                                                 const float*, const int32_t*, int, hipStream_t);
+template int launch_transform_cplx<double, double>(const double*, double*, const TensorDesc*, const int2*, int,
+                                                   size_t, const double*, const int32_t*, int, hipStream_t);
+template int launch_transform_cplx<float, uint16_t>(const float*, uint16_t*, const TensorDesc*, const int2*, int,
+                                                    size_t, const float*, const int32_t*, int, hipStream_t);
+
 int transform_tile_width(int64_t P, size_t elem_bytes, size_t budget) {
   int64_t tp = 256;
   while (tp > 1 && (size_t)(tp * P) * elem_bytes > budget) tp >>= 1;
@@ -265,7 +416,11 @@ __global__ __launch_bounds__(256) void k_omega(T* __restrict__ om, double* __res
   const int s = blockIdx.x;
   const SliceDesc d = sd[s];
   const int64_t base = dense_stride > 0 ? (int64_t)s * dense_stride : d.z;
-  const int64_t per_slice = (int64_t)d.n2 * slice_width(d, wk, s);
+  // complex slices: the real embedding of the real Gaussian Omega (n2o x lo)
+  // is blockdiag(Omega, Omega) (n2 x l = 2 n2o x 2 lo)
+  const int n2o = d.cplx ? d.n2 / 2 : d.n2;
+  const int lo = d.cplx ? slice_width(d, wk, s) / 2 : slice_width(d, wk, s);
+  const int64_t per_slice = (int64_t)n2o * lo;
   const uint32_t c = call_dev ? (uint32_t)(*call_dev) : call;
   const int64_t ngroups = (per_slice + 3) / 4;
   for (int64_t g = (int64_t)blockIdx.y * blockDim.x + threadIdx.x; g < ngroups; g += (int64_t)gridDim.y * blockDim.x) {
@@ -275,8 +430,26 @@ __global__ __launch_bounds__(256) void k_omega(T* __restrict__ om, double* __res
     for (int lane = 0; lane < 4; ++lane) {
       const int64_t e = 4 * g + lane;
       if (e < per_slice) {
-        if (om) om[base + e] = (T)z[lane];
-        if (om64) om64[base + e] = z[lane];
+        if (!d.cplx) {
+          if (om) om[base + e] = (T)z[lane];
+          if (om64) om64[base + e] = z[lane];
+        } else {
+          const int64_t r = e % n2o, col = e / n2o, ld = 2 * (int64_t)n2o;
+          const int64_t i00 = r + col * ld, i11 = (r + n2o) + (col + lo) * ld;
+          const int64_t i10 = (r + n2o) + col * ld, i01 = r + (col + lo) * ld;
+          if (om) {
+            om[base + i00] = (T)z[lane];
+            om[base + i11] = (T)z[lane];
+            om[base + i10] = T(0);
+            om[base + i01] = T(0);
+          }
+          if (om64) {
+            om64[base + i00] = z[lane];
+            om64[base + i11] = z[lane];
+            om64[base + i10] = 0.0;
+            om64[base + i01] = 0.0;
+          }
+        }
       }
     }
   }
