@@ -140,6 +140,9 @@ struct ht_plan {
   double* table64;
   float* table32;
   ItemList it_nn[2], it_tn[2], it_oy, it_oz, it_qk, it_nt, it_tf;  // [0]: 64-row tiles, [1]: 128-row tiles
+  ItemList it_nns;  // nn items of the streaming product (256-row tiles)
+  bool nn_stream;   // FP32 real slices the streaming nn product can take
+  int max_n2;
   int tf_capacity;
   size_t off[WS_COUNT];
   size_t size[WS_COUNT];
@@ -588,6 +591,15 @@ int build_plan(const ht_plan_desc* descs, int n, bool batch, ht_plan** out) {
     }
   }
   layout(pl, oY, oZ, oK, oG1, oG2);
+  // the streaming nn product: FP32, real slices with 16-byte aligned columns
+  pl->max_n2 = 0;
+  pl->nn_stream = pl->precision == HT_FP32 && pl->lmax <= 64;
+  for (const SliceDesc& d : pl->h_slices) {
+    pl->max_n2 = std::max(pl->max_n2, (int)d.n2);
+    // a 256-row tile of a short slice would leave most of its wavefronts idle
+    if (d.cplx || d.n1 % 4 != 0 || d.n1 < 3 * kStreamRows / 4 || d.a % 4 != 0 || d.y % 4 != 0) pl->nn_stream = false;
+  }
+  if (pl->max_n2 > kStreamMaxK) pl->nn_stream = false;
 
   // item lists (the transform list is sized for the smallest LDS budget)
   std::vector<std::vector<int2>> lists;
@@ -599,6 +611,7 @@ int build_plan(const ht_plan_desc* descs, int n, bool batch, ht_plan** out) {
   lists.push_back(row_items(pl, true, 64, false));   // orth Z
   lists.push_back(row_items(pl, false, 64, false));  // recon QK
   lists.push_back(nt_items(pl));                     // recon C
+  lists.push_back(row_items(pl, false, kStreamRows, true));  // nn, streaming product
   // the smallest LDS budget that fits every tensor sets the item capacity
   std::vector<int2> tfi;
   std::vector<int> tps;
@@ -616,7 +629,7 @@ int build_plan(const ht_plan_desc* descs, int n, bool batch, ht_plan** out) {
   }
   pl->tf_capacity = (int)tfi.size();
   ItemList* dst[] = {&pl->it_nn[0], &pl->it_tn[0], &pl->it_nn[1], &pl->it_tn[1], &pl->it_oy, &pl->it_oz,
-                     &pl->it_qk, &pl->it_nt};
+                     &pl->it_qk, &pl->it_nt, &pl->it_nns};
   std::vector<int2> all;
   for (size_t i = 0; i < lists.size(); ++i) {
     dst[i]->off = (int64_t)all.size();
@@ -767,6 +780,9 @@ int run_tsvt(const ht_plan* pl, const T* X, T* out, double tau, const double* ta
       const ItemList& L = pl->it_nn[ri];
       if (bf16)
         return launch_bf16_nn(Ah, (const float*)W, (float*)Y, sd, wk, items(pl, L), L.n, lmax, rows, gp1, s);
+      if (!fp64 && pl->nn_stream)
+        return launch_mfma_nn_stream((const float*)A, (const float*)W, (float*)Y, sd, wk, items(pl, pl->it_nns),
+                                     pl->it_nns.n, lmax, pl->max_n2, gp1, s);
       if (!fp64)
         return launch_mfma_nn((const float*)A, (const float*)W, (float*)Y, sd, wk, items(pl, L), L.n, lmax, rows, gp1,
                               s);
@@ -786,7 +802,7 @@ int run_tsvt(const ht_plan* pl, const T* X, T* out, double tau, const double* ta
   auto orth = [&](int which, double* gout, const int2* wk) {
     return timed(pl, ST_CHOLQR, s, [&] {
       const ItemList& L = which ? pl->it_oz : pl->it_oy;
-      return launch_orth_apply<T>(which ? Z : Y, which, sd, wk, items(pl, L), L.n, lmax, P, gp1, rows, gout, s);
+      return launch_orth_apply<T>(which ? Z : Y, which, sd, wk, items(pl, L), L.n, lmax, P, gp1, gout, s);
     });
   };
   double* sig_dst = mode ? sig : sigma_out;
@@ -807,7 +823,7 @@ int run_tsvt(const ht_plan* pl, const T* X, T* out, double tau, const double* ta
     }
     if ((r = sketch_tn(wk))) return r;
     return timed(pl, ST_SMALLSVD, s, [&] {
-      return launch_smallsvd<T>(gp2, gp1, sd, wk, P, lmax, rows, tau, tau_dev, mu_dev, pen, K, sig_dst, kept_dst, s);
+      return launch_smallsvd<T>(gp2, gp1, sd, wk, P, lmax, tau, tau_dev, mu_dev, pen, K, sig_dst, kept_dst, s);
     });
   };
   const int2* wk_final = nullptr;

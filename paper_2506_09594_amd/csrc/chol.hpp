@@ -213,32 +213,54 @@ __device__ inline void tri_inverse(const double* G, const double* dR, int gp, in
   __syncthreads();
 }
 
-// Gram partial of an LDS tile S (rows x l, pitch gp, rows beyond the data zero):
-// out[a*l + b] = out[b*l + a] = sum_i S[i][a] S[i][b].
-__device__ inline void tile_gram_to_global(const double* S, int gp, int rows, int l, double* __restrict__ out) {
-  const int npairs = l * (l + 1) / 2;
-  for (int p0 = 0; p0 < npairs; p0 += blockDim.x) {
-    int p = p0 + threadIdx.x;
-    if (p >= npairs) break;
-    int a = 0, row_len = l;
-    while (p >= row_len) {
-      p -= row_len;
-      ++a;
-      --row_len;
+// FP64 Gram partials of an LDS tile on the matrix cores: element (i, c) of the
+// tile is S[i * rs + c * cs] (rows i >= rows and columns c >= l read as zero),
+// and each slab of kGramRows = 64 rows gets its own l x l partial,
+//   out[h l l + a l + b] = sum_{i in slab h} S[i][a] S[i][b].
+// Consumers sum ceil(m / 64) partials per slice whatever tile the producer
+// used.  A wavefront takes (slab, 16 x 16 block of the upper triangle) units:
+// 16 steps of v_mfma_f64_16x16x4f64 (the FP32 products are exact in FP64),
+// operands loaded before the first step, and the block stored with its
+// mirror.  No barrier: S is only read.  Operand layout of the instruction:
+// lane t supplies A[t % 16][t / 16] and B[t / 16][t % 16]; accumulator v of
+// lane t is D[4 v + t / 16][t % 16].
+typedef double gram_d4 __attribute__((ext_vector_type(4)));
+template <typename TS>
+__device__ inline void tile_gram_mfma(const TS* S, int rs, int cs, int rows, int l, double* __restrict__ out) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwv = (blockDim.x + 63) >> 6;
+  const int nb = (l + 15) / 16, nblk = nb * (nb + 1) / 2;
+  const int nslab = (rows + kGramRows - 1) / kGramRows;
+  const int ll = l * l;
+  for (int unit = wave; unit < nslab * nblk; unit += nwv) {
+    const int h = unit / nblk;
+    int blk = unit % nblk, bi = 0, len = nb;
+    while (blk >= len) {
+      blk -= len;
+      ++bi;
+      --len;
     }
-    const int b = a + p;
-    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
-    int i = 0;
-    for (; i + 4 <= rows; i += 4) {
-      s0 += S[i * gp + a] * S[i * gp + b];
-      s1 += S[(i + 1) * gp + a] * S[(i + 1) * gp + b];
-      s2 += S[(i + 2) * gp + a] * S[(i + 2) * gp + b];
-      s3 += S[(i + 3) * gp + a] * S[(i + 3) * gp + b];
+    const int bj = bi + blk;
+    const int ci = 16 * bi + (lane & 15), cj = 16 * bj + (lane & 15), kq = lane >> 4;
+    double a[16], b[16];
+#pragma unroll
+    for (int st = 0; st < 16; ++st) {
+      const int row = h * kGramRows + 4 * st + kq;
+      const bool ok = row < rows;
+      a[st] = (ok && ci < l) ? (double)S[row * rs + ci * cs] : 0.0;
+      b[st] = (ok && cj < l) ? (double)S[row * rs + cj * cs] : 0.0;
     }
-    for (; i < rows; ++i) s0 += S[i * gp + a] * S[i * gp + b];
-    const double s = (s0 + s1) + (s2 + s3);
-    out[a * l + b] = s;
-    out[b * l + a] = s;
+    gram_d4 g = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int st = 0; st < 16; ++st) g = __builtin_amdgcn_mfma_f64_16x16x4f64(a[st], b[st], g, 0, 0, 0);
+    double* o = out + (int64_t)h * ll;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int i = 16 * bi + 4 * v + kq, j = 16 * bj + (lane & 15);
+      if (i < l && j < l) {
+        o[i * l + j] = g[v];
+        o[j * l + i] = g[v];
+      }
+    }
   }
 }
 

@@ -12,6 +12,10 @@
 
 namespace ht {
 
+// Rows per FP64 Gram partial: every producer of a thin block writes one l x l
+// partial per 64 rows of it, so a slice of m rows has ceil(m / 64) partials.
+constexpr int kGramRows = 64;
+
 // Work items.  Every per-slice launch takes an item list: item i of a product
 // or orthonormalization launch is (slice, first row of its tile); of the
 // transform, (tensor, first tube position); of the reconstruction nt product,
@@ -60,11 +64,16 @@ int launch_gemm_nt(const T* X, const T* W, T* C, const SliceDesc* sd, const int2
                    hipStream_t s);
 
 // FP32 and BF16 sketch products on the matrix cores; rows = 64 or 128 output
-// rows per workgroup (Gram partials per tile of that many rows).
+// rows per workgroup (Gram partials per 64 rows).  The streaming form of the
+// FP32 nn product takes 256-row items, real slices with n1 % 4 == 0, widths
+// up to 64 and n2 <= kStreamMaxK (its thin operand is staged in LDS whole).
 int launch_mfma_nn(const float* A, const float* W, float* Y, const SliceDesc* sd, const int2* wk, const int2* items,
                    int nitems, int lmax, int rows, double* gpart, hipStream_t s);
 int launch_mfma_tn(const float* A, const float* Q, float* Z, const SliceDesc* sd, const int2* wk, const int2* items,
                    int nitems, int lmax, int rows, double* gpart, hipStream_t s);
+constexpr int kStreamRows = 256, kStreamMaxK = 512;
+int launch_mfma_nn_stream(const float* A, const float* W, float* Y, const SliceDesc* sd, const int2* wk,
+                          const int2* items, int nitems, int lmax, int kmax, double* gpart, hipStream_t s);
 int launch_bf16_nn(const uint16_t* A, const float* W, float* Y, const SliceDesc* sd, const int2* wk,
                    const int2* items, int nitems, int lmax, int rows, double* gpart, hipStream_t s);
 int launch_bf16_tn(const uint16_t* A, const float* Q, float* Z, const SliceDesc* sd, const int2* wk,
@@ -72,17 +81,17 @@ int launch_bf16_tn(const uint16_t* A, const float* Q, float* Z, const SliceDesc*
 
 // One CholeskyQR pass with deflation, in place on the basis `which` (0: Y of
 // n1 rows, 1: Z of n2 rows) from the Gram partials of the producing product
-// (gin at the slice's g1 offset, prod_rows rows per partial).  Optionally
+// (gin at the slice's g1 offset, one per 64 rows).  Optionally
 // writes the Gram partials of the result (gout at the slice's g2 offset, one
 // per 64 rows).  Items are 64-row tiles.  Widths above 64 overwrite the first
 // partial of every slice with R^{-1}.
 template <typename T>
 int launch_orth_apply(T* Y, int which, const SliceDesc* sd, const int2* wk, const int2* items, int nitems, int lmax,
-                      int nslices, double* gin, int prod_rows, double* gout, hipStream_t s);
+                      int nslices, double* gin, double* gout, hipStream_t s);
 
 // Small SVD and shrinkage in FP64, one workgroup per slice.  Inputs: Gram
 // partials of the basis Q1 (g2 at the slice's g2 offset, one per 64 rows of
-// n1) and of Bt = A^T Q1 (gw at its g1 offset, one per prod_rows rows of n2).
+// n1) and of Bt = A^T Q1 (gw at its g1 offset, one per 64 rows of n2).
 // With R2 = chol(Q1^T Q1), B = R2^{-T} Bt^T, W = B B^T = U diag(s^2) U^T;
 // writes K' = R2^{-1} U diag(w) U^T R2^{-T} (l x l, at the slice's kq offset)
 // with w_i = prox(s_i)/s_i, i < k.  tau: 1 / *mu_dev if mu_dev, else
@@ -90,7 +99,7 @@ int launch_orth_apply(T* Y, int which, const SliceDesc* sd, const int2* wk, cons
 // slice's g2 partials are overwritten (scratch).  sigma_out rows have lmax entries.
 template <typename T>
 int launch_smallsvd(double* g2, const double* gw, const SliceDesc* sd, const int2* wk, int nslices, int lmax,
-                    int prod_rows, double tau, const double* tau_dev, const double* mu_dev, Penalty pen, T* K,
+                    double tau, const double* tau_dev, const double* mu_dev, Penalty pen, T* K,
                     double* sigma_out, int* kept_out, hipStream_t s);
 
 // Learned widths (mlp.hip).  Network parameters: one flat FP32 vector of

@@ -215,7 +215,150 @@ __global__ __launch_bounds__(64 * NW) void k_mfma_thin(const float* __restrict__
     const int i = idx % MT, c = idx / MT;
     if (i < rows) Yj[(r0 + i) + (int64_t)c * ldy] = (float)S[i * sp + c];
   }
-  if (gpart) tile_gram_to_global(S, sp, MT, l, gpart + d.g1 + (int64_t)(r0 / MT) * l * l);
+  if (gpart) tile_gram_mfma(S, sp, 1, rows, l, gpart + d.g1 + (int64_t)(r0 / kGramRows) * l * l);
+}
+
+// Streaming nn product for real FP32 slices (n1 % 4 == 0, n2 <= kStreamMaxK):
+// a workgroup of 8 wavefronts owns 256 output rows; wavefront (rw, ks) computes
+// rows 128 rw .. 128 rw + 127 over the ks-th quarter of the reduction.  A is
+// read straight from HBM into the MFMA operand registers: lane t loads rows
+// 4 (t % 32) .. +3 of column k (one 16-byte load), and element e of that
+// load feeds MFMA block e, whose row i stands for tile row 4 i + e.  Two
+// register buffers of U loads per lane are in flight at all times (the next
+// buffer is issued before the current one is consumed; loads past the end are
+// clamped to a valid address and their values zeroed), so each CU keeps about
+// 128 KB of reads outstanding.  The thin operand is staged in LDS whole.  The
+// four partial tiles are summed through one LDS tile, which then feeds the
+// coalesced store of Y and the Gram partials.
+template <int NB, int U>
+__global__ __launch_bounds__(512) void k_mfma_nn_stream(const float* __restrict__ Aall, const float* __restrict__ Wall,
+                                                       float* __restrict__ Yall, const SliceDesc* __restrict__ sd,
+                                                       const int2* __restrict__ wk, const int2* __restrict__ items,
+                                                       double* __restrict__ gpart) {
+  constexpr int RW = 2, KS = 4, VR = 4, NTH = 64 * RW * KS;
+  constexpr int ROWS = 32 * VR * RW, LW = 32 * NB, RP = ROWS + 4;
+  static_assert(ROWS == kStreamRows, "tile rows");
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  float* const Ws = reinterpret_cast<float*>(smem_raw);  // [K][LW], then the tile [LW][RP]
+  float* const Ts = Ws;
+  const int2 item = items[blockIdx.x];
+  const int s = item.x, r0 = item.y;
+  const SliceDesc d = sd[s];
+  const int l = slice_width(d, wk, s);
+  if (l <= 0) return;  // slice not part of this pass
+  const int M = d.n1, K = d.n2;
+  const float* A = Aall + d.a;
+  const float* W = Wall + d.z;
+  float* Y = Yall + d.y;
+  const int tid = threadIdx.x, wave = tid / 64, lane = tid % 64;
+  const int rw = wave % RW, ks = wave / RW;
+  const int half = lane / 32, li = lane % 32;
+  const int kper = ((K + KS - 1) / KS + 1) & ~1;
+  const int kb = min(K, ks * kper), ke = min(K, kb + kper);
+  const int rowl = r0 + 32 * VR * rw + VR * li;  // first of this lane's four rows
+  const bool rowok = rowl + VR - 1 < M;
+  const float* Arow = A + (rowok ? rowl : 0);
+  f32x4 bufA[U], bufB[U];
+  auto load = [&](f32x4* buf, int k0) {
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      int k = k0 + 2 * u + half;
+      k = k < ke ? k : ke - 1;
+      buf[u] = *reinterpret_cast<const f32x4*>(Arow + (int64_t)k * M);
+    }
+  };
+  if (kb < ke) {
+    load(bufA, kb);
+    load(bufB, kb + 2 * U);
+  }
+  for (int f = tid; f < K * LW; f += NTH) {
+    const int k = f % K, c = f / K;
+    Ws[k * LW + c] = (c < l) ? W[k + (int64_t)c * K] : 0.0f;
+  }
+  __syncthreads();
+  f32x16 acc[VR][NB];
+#pragma unroll
+  for (int e = 0; e < VR; ++e)
+#pragma unroll
+    for (int b = 0; b < NB; ++b)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[e][b][r] = 0.0f;
+  const int nbl = (l + 31) / 32;
+  auto compute = [&](const f32x4* buf, int k0) {
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int k = k0 + 2 * u + half;
+      const bool ok = k < ke && rowok;
+      const int kr = k < ke ? k : 0;
+      float bv[NB];
+#pragma unroll
+      for (int b = 0; b < NB; ++b) bv[b] = Ws[kr * LW + 32 * b + li];
+#pragma unroll
+      for (int e = 0; e < VR; ++e) {
+        const float av = ok ? buf[u][e] : 0.0f;
+#pragma unroll
+        for (int b = 0; b < NB; ++b)
+          if (b < nbl) acc[e][b] = __builtin_amdgcn_mfma_f32_32x32x2f32(av, bv[b], acc[e][b], 0, 0, 0);
+      }
+    }
+  };
+  for (int k0 = kb; k0 < ke; k0 += 4 * U) {
+    compute(bufA, k0);
+    if (k0 + 4 * U < ke) load(bufA, k0 + 4 * U);
+    compute(bufB, k0 + 2 * U);
+    if (k0 + 6 * U < ke) load(bufB, k0 + 6 * U);
+  }
+  // ---- sum the KS partial tiles through one LDS tile [LW][RP] -------------
+  auto tile_index = [&](int e, int b, int r) {
+    const int i = 8 * (r / 4) + 4 * half + (r % 4);
+    return (32 * b + li) * RP + 32 * VR * rw + VR * i + e;
+  };
+  __syncthreads();  // the thin operand is no longer read
+  for (int q = 1; q < KS; ++q) {
+    if (ks == q) {
+#pragma unroll
+      for (int e = 0; e < VR; ++e)
+#pragma unroll
+        for (int b = 0; b < NB; ++b)
+#pragma unroll
+          for (int r = 0; r < 16; ++r) Ts[tile_index(e, b, r)] = acc[e][b][r];
+    }
+    __syncthreads();
+    if (ks == 0) {
+#pragma unroll
+      for (int e = 0; e < VR; ++e)
+#pragma unroll
+        for (int b = 0; b < NB; ++b)
+#pragma unroll
+          for (int r = 0; r < 16; ++r) acc[e][b][r] += Ts[tile_index(e, b, r)];
+    }
+    __syncthreads();
+  }
+  if (ks == 0) {
+#pragma unroll
+    for (int e = 0; e < VR; ++e)
+#pragma unroll
+      for (int b = 0; b < NB; ++b)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) Ts[tile_index(e, b, r)] = acc[e][b][r];
+  }
+  __syncthreads();
+  const int rows = min(ROWS, M - r0);
+  for (int f = tid; f < l * (ROWS / 4); f += NTH) {
+    const int c = f / (ROWS / 4), q = (f % (ROWS / 4)) * 4;
+    if (q + 3 < rows)
+      *reinterpret_cast<f32x4*>(Y + r0 + q + (int64_t)c * M) = *reinterpret_cast<const f32x4*>(Ts + c * RP + q);
+    else
+      for (int e = 0; e < 4; ++e)
+        if (q + e < rows) Y[r0 + q + e + (int64_t)c * M] = Ts[c * RP + q + e];
+  }
+  if (gpart) tile_gram_mfma(Ts, 1, RP, rows, l, gpart + d.g1 + (int64_t)(r0 / kGramRows) * l * l);
+}
+
+template <int NB>
+size_t stream_lds_bytes(int kmax) {
+  const size_t w = (size_t)kmax * 32 * NB * 4, t = (size_t)32 * NB * (kStreamRows + 4) * 4;
+  return w > t ? w : t;
 }
 
 template <int NB, int NW, bool TRANS>
@@ -251,6 +394,23 @@ int launch_mfma_nn(const float* A, const float* W, float* Y, const SliceDesc* sd
                    int nitems, int lmax, int rows, double* gpart, hipStream_t s) {
   if (lmax > 96 || (rows != 64 && rows != 128)) HT_FAIL(HT_ERR_UNSUPPORTED, "matrix-core product: bad width or tile");
   return dispatch<false>(A, W, Y, sd, wk, items, nitems, lmax, rows, gpart, s);
+}
+
+int launch_mfma_nn_stream(const float* A, const float* W, float* Y, const SliceDesc* sd, const int2* wk,
+                          const int2* items, int nitems, int lmax, int kmax, double* gpart, hipStream_t s) {
+  if (lmax > 64 || kmax > kStreamMaxK || kmax < 1) HT_FAIL(HT_ERR_UNSUPPORTED, "streaming product: bad width or n2");
+  if (reinterpret_cast<uintptr_t>(A) % 16 != 0 || reinterpret_cast<uintptr_t>(Y) % 16 != 0)
+    HT_FAIL(HT_ERR_UNSUPPORTED, "streaming product: unaligned operands");
+  if (nitems == 0) return HT_OK;
+  auto launch = [&](auto kern, size_t lds, size_t lds_max) -> int {
+    int rc = ensure_dynamic_lds((const void*)kern, lds_max);
+    if (rc) return rc;
+    hipLaunchKernelGGL(kern, dim3((unsigned)nitems), dim3(512), lds, s, A, W, Y, sd, wk, items, gpart);
+    HT_CHECK_LAUNCH();
+    return HT_OK;
+  };
+  if (lmax <= 32) return launch(k_mfma_nn_stream<1, 8>, stream_lds_bytes<1>(kmax), stream_lds_bytes<1>(kStreamMaxK));
+  return launch(k_mfma_nn_stream<2, 8>, stream_lds_bytes<2>(kmax), stream_lds_bytes<2>(kStreamMaxK));
 }
 
 int launch_mfma_tn(const float* A, const float* Q, float* Z, const SliceDesc* sd, const int2* wk, const int2* items,

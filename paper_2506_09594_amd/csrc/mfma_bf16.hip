@@ -204,7 +204,7 @@ __global__ __launch_bounds__(64 * NW) void k_mfma_thin_bf16(const uint16_t* __re
     const int i = idx % MT, c = idx / MT;
     if (i < rows) Yj[(r0 + i) + (int64_t)c * ldy] = (float)S[i * sp + c];
   }
-  if (gpart) tile_gram_to_global(S, sp, MT, l, gpart + d.g1 + (int64_t)(r0 / MT) * l * l);
+  if (gpart) tile_gram_mfma(S, sp, 1, rows, l, gpart + d.g1 + (int64_t)(r0 / kGramRows) * l * l);
 }
 
 template <int NB, int NW, bool TRANS>

@@ -43,7 +43,7 @@ __device__ inline void tile_gram_epilogue(unsigned char* smem, const T* acc, int
     if (c < l) S[tr * gp + c] = (tr < rows) ? (double)acc[i] : 0.0;
   }
   __syncthreads();
-  tile_gram_to_global(S, gp, TM, l, out);
+  tile_gram_mfma(S, gp, 1, rows < TM ? rows : TM, l, out);
 }
 
 // RECON = false: Y = A W (sketch); RECON = true: QK = Q1 K'.
