@@ -87,6 +87,50 @@ __device__ __forceinline__ void mode_exact(T* tile, int TP, int lgTP, int s, int
   }
 }
 
+// Mode product on the matrix cores (FP32, n in {4, 8, 16}; used for n = 16):
+// for 16 tube positions t0..t0+15 and NB = 16 / n fibers of the mode at
+// consecutive "rest" indices, the fibers stacked along k form a 16 x 16
+// operand X and the new values are blockdiag(U, ..., U) X, four
+// v_mfma_f32_16x16x4f32 steps.
+// Lane l supplies A[l % 16][l / 16] and B[l / 16][l % 16] at each k step and
+// receives D[4 (l / 16) + v][l % 16].  A group is read and written back in
+// place by one wavefront; groups are disjoint.  Requires TP % 16 == 0 and
+// (P / n) % NB == 0 (checked by the caller).
+typedef float tf_f32x4 __attribute__((ext_vector_type(4)));
+template <int N>
+__device__ __forceinline__ void mode_mfma(float* tile, int TP, int s, int P, const float* __restrict__ U) {
+  constexpr int NB = 16 / N;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwv = blockDim.x >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  float ua[4];
+#pragma unroll
+  for (int kk = 0; kk < 4; ++kk) {
+    const int k = 4 * kk + lk;
+    ua[kk] = (li / N == k / N) ? U[(li % N) * N + (k % N)] : 0.0f;
+  }
+  const int ngt = TP >> 4, ngr = P / (N * NB);
+  for (int gidx = wave; gidx < ngt * ngr; gidx += nwv) {
+    const int tg = gidx % ngt, gr = gidx / ngt;
+    const int col = (tg << 4) + li;
+    // row (slice index) of element k' of the fiber at rest index r
+    auto jrow = [&](int r, int kp) { return (r % s) + s * (kp + N * (r / s)); };
+    float b[4];
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk) {
+      const int k = 4 * kk + lk;
+      b[kk] = tile[jrow(gr * NB + k / N, k % N) * TP + col];
+    }
+    tf_f32x4 d = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk) d = __builtin_amdgcn_mfma_f32_16x16x4f32(ua[kk], b[kk], d, 0, 0, 0);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int i = 4 * lk + v;
+      tile[jrow(gr * NB + i / N, i % N) * TP + col] = d[v];
+    }
+  }
+}
+
 // One workgroup per work item (tensor, first tube position).  TO = T, or
 // uint16_t for BF16 output (rounded to nearest even).
 template <typename T, typename TO>
@@ -159,6 +203,15 @@ __global__ __launch_bounds__(256) void k_transform(const T* __restrict__ in_all,
     const int s = mt->stride[m];
     const T* U = table + mt->off[m];
     const int nfib = total / n;
+    if constexpr (std::is_same<T, float>::value) {
+      // length-16 modes on the matrix cores; shorter ones stay on the vector
+      // units (block-diagonal packing would double their multiply-adds)
+      if (n == 16 && (TP & 15) == 0) {
+        mode_mfma<16>(tile, TP, s, P, U);
+        __syncthreads();
+        continue;
+      }
+    }
     switch (n) {
       case 2: mode_exact<T, 2>(tile, TP, lgTP, s, nfib, U); break;
       case 3: mode_exact<T, 3>(tile, TP, lgTP, s, nfib, U); break;
