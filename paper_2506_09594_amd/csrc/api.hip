@@ -852,6 +852,9 @@ int run_tsvt(const ht_plan* pl, const T* X, T* out, double tau, const double* ta
        })))
     return rc;
   if ((rc = timed(pl, ST_RECON_NT, s, [&] {
+         if (!fp64)
+           return launch_mfma_nt((const float*)QK, (const float*)Z, (float*)C, sd, wk_final, items(pl, pl->it_nt),
+                                 pl->it_nt.n, lmax, s);
          return launch_gemm_nt<T>(QK, Z, C, sd, wk_final, items(pl, pl->it_nt), pl->it_nt.n, s);
        })))
     return rc;

@@ -74,6 +74,9 @@ int launch_mfma_tn(const float* A, const float* Q, float* Z, const SliceDesc* sd
 constexpr int kStreamRows = 256, kStreamMaxK = 512;
 int launch_mfma_nn_stream(const float* A, const float* W, float* Y, const SliceDesc* sd, const int2* wk,
                           const int2* items, int nitems, int lmax, int kmax, double* gpart, hipStream_t s);
+// Reconstruction C = QK Bt^T on the matrix cores (FP32; items as launch_gemm_nt).
+int launch_mfma_nt(const float* X, const float* W, float* C, const SliceDesc* sd, const int2* wk, const int2* items,
+                   int nitems, int lmax, hipStream_t s);
 int launch_bf16_nn(const uint16_t* A, const float* W, float* Y, const SliceDesc* sd, const int2* wk,
                    const int2* items, int nitems, int lmax, int rows, double* gpart, hipStream_t s);
 int launch_bf16_tn(const uint16_t* A, const float* Q, float* Z, const SliceDesc* sd, const int2* wk,

@@ -361,6 +361,70 @@ size_t stream_lds_bytes(int kmax) {
   return w > t ? w : t;
 }
 
+// Reconstruction C_s (n1 x nc) = X_s (n1 x l) W_s^T (W_s n2 x l, first nc
+// rows) on the matrix cores: a 64 x 64 tile per work item (slice, tile index,
+// row tiles fastest), wavefront w computing the 32 x 32 block (w % 2, w / 2).
+// Operands load straight into the MFMA registers (lane t: rows / columns
+// t % 32 of the block at k = 2 s + t / 32, coalesced along the column-major
+// blocks), every load of the tile before the first step; the result goes
+// through LDS so that the column-major store is 16-byte and coalesced.
+template <int KMAX>
+__global__ __launch_bounds__(256) void k_mfma_nt(const float* __restrict__ Xall, const float* __restrict__ Wall,
+                                                 float* __restrict__ Call, const SliceDesc* __restrict__ sd,
+                                                 const int2* __restrict__ wk, const int2* __restrict__ items) {
+  constexpr int TP = 68;  // pitch of the [column][row] staging tile
+  __shared__ __align__(16) float Ts[64 * TP];
+  const int2 item = items[blockIdx.x];
+  const int s = item.x;
+  const SliceDesc d = sd[s];
+  const int l = slice_width(d, wk, s);
+  if (l <= 0) return;  // slice not part of this pass
+  const int m = d.n1, n = d.nc;
+  const int nrt = (m + 63) / 64;
+  const int row0 = (item.y % nrt) * 64, col0 = (item.y / nrt) * 64;
+  const float* X = Xall + d.y;
+  const float* W = Wall + d.z;
+  float* C = Call + d.a;
+  const int ldx = m, ldw = d.n2, ldc = m;
+  const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+  const int li = lane % 32, h = lane / 32;
+  const int br = 32 * (wave % 2), bc = 32 * (wave / 2);
+  const int gr = row0 + br + li, gc = col0 + bc + li;
+  const bool rok = gr < m, cok = gc < n;
+  constexpr int NS = (KMAX + 1) / 2;
+  float av[NS], bv[NS];
+#pragma unroll
+  for (int st = 0; st < NS; ++st) {
+    const int k = 2 * st + h;
+    av[st] = (k < l && rok) ? X[gr + (int64_t)k * ldx] : 0.0f;
+    bv[st] = (k < l && cok) ? W[gc + (int64_t)k * ldw] : 0.0f;
+  }
+  f32x16 acc;
+#pragma unroll
+  for (int r = 0; r < 16; ++r) acc[r] = 0.0f;
+#pragma unroll
+  for (int st = 0; st < NS; ++st)
+    if (2 * st < l) acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av[st], bv[st], acc, 0, 0, 0);
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    const int i = 8 * (r / 4) + 4 * h + (r % 4);
+    Ts[(bc + li) * TP + br + i] = acc[r];
+  }
+  __syncthreads();
+  const int rows = min(64, m - row0), cols = min(64, n - col0);
+  const bool vec = (ldc % 4 == 0) && (d.a % 4 == 0);
+  for (int f = threadIdx.x; f < 64 * 16; f += 256) {
+    const int c = f / 16, q = (f % 16) * 4;
+    if (c >= cols) continue;
+    float* dst = C + row0 + q + (int64_t)(col0 + c) * ldc;
+    if (vec && q + 3 < rows)
+      *reinterpret_cast<f32x4*>(dst) = *reinterpret_cast<const f32x4*>(Ts + c * TP + q);
+    else
+      for (int e = 0; e < 4; ++e)
+        if (q + e < rows) dst[e] = Ts[c * TP + q + e];
+  }
+}
+
 template <int NB, int NW, bool TRANS>
 int launch_thin(const float* A, const float* W, float* Y, const SliceDesc* sd, const int2* wk, const int2* items,
                 int nitems, double* gpart, hipStream_t s) {
@@ -411,6 +475,21 @@ int launch_mfma_nn_stream(const float* A, const float* W, float* Y, const SliceD
   };
   if (lmax <= 32) return launch(k_mfma_nn_stream<1, 8>, stream_lds_bytes<1>(kmax), stream_lds_bytes<1>(kStreamMaxK));
   return launch(k_mfma_nn_stream<2, 8>, stream_lds_bytes<2>(kmax), stream_lds_bytes<2>(kStreamMaxK));
+}
+
+int launch_mfma_nt(const float* X, const float* W, float* C, const SliceDesc* sd, const int2* wk, const int2* items,
+                   int nitems, int lmax, hipStream_t s) {
+  if (lmax > HT_MAX_WIDTH) HT_FAIL(HT_ERR_UNSUPPORTED, "sketch width above HT_MAX_WIDTH");
+  if (nitems == 0) return HT_OK;
+  const dim3 grid((unsigned)nitems);
+  if (lmax <= 32)
+    hipLaunchKernelGGL(k_mfma_nt<32>, grid, dim3(256), 0, s, X, W, C, sd, wk, items);
+  else if (lmax <= 64)
+    hipLaunchKernelGGL(k_mfma_nt<64>, grid, dim3(256), 0, s, X, W, C, sd, wk, items);
+  else
+    hipLaunchKernelGGL(k_mfma_nt<HT_MAX_WIDTH>, grid, dim3(256), 0, s, X, W, C, sd, wk, items);
+  HT_CHECK_LAUNCH();
+  return HT_OK;
 }
 
 int launch_mfma_tn(const float* A, const float* Q, float* Z, const SliceDesc* sd, const int2* wk, const int2* items,

@@ -136,6 +136,28 @@ def test_tsvt_fp32_matrix_core_shapes(ht, dims, kinds, rank, r, p, q):
     assert _rel(got, ref) < TOL["fp32"]
 
 
+@pytest.mark.parametrize("dims,kinds,rank,r,p,q", [
+    ((260, 300, 3, 2), ["dct2", "dct2"], 10, 10, 6, 2),   # streaming nn: a 256-row tile and a 4-row one, l = 16
+    ((448, 96, 5), ["dct2"], 30, 30, 10, 1),               # streaming nn: l = 40 (two column blocks), short reduction
+    ((256, 256, 4), ["dct2"], 20, 20, 10, 2),              # streaming nn at the headline slice size
+])
+def test_tsvt_fp32_streaming_product(ht, dims, kinds, rank, r, p, q):
+    """Slices of at least 192 rows take the streaming nn product (A read straight
+    into the matrix-core operands, Gram partials per 64 rows)."""
+    got, ref, _ = _run_case(ht, dims, kinds, rank, r, p, q, "fp32", tau=6.0, pen="mcp", noise=1e-2)
+    assert _rel(got, ref) < TOL["fp32"]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("r,p", [(8, 5), (6, 1), (20, 3)])
+def test_tsvt_odd_widths(ht, prec, r, p):
+    """Odd sketch widths l = r + p run the Jacobi sweeps with a zero padding row
+    and column for the idle player of the round-robin schedule."""
+    got, ref, plan = _run_case(ht, (70, 64, 6), ["dct2"], r, r, p, 1, prec, tau=4.0, pen="scad", noise=1e-2)
+    assert plan.width % 2 == 1
+    assert _rel(got, ref) < TOL[prec]
+
+
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 @pytest.mark.parametrize("dims,kinds,rank,r,p,q", [
     ((40, 30), [], 3, 3, 2, 1),              # order 2: one slice, no transform
