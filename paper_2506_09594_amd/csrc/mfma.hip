@@ -8,8 +8,8 @@
 // rows 32w..32w+31 as NB 32 x 32 MFMA blocks.  The reduction dimension is
 // walked in chunks of 32: the A chunk (MT x 32) and the thin-operand chunk
 // (32 x l) are fetched into registers (16-byte loads where the slice's columns
-// allow it) while the matrix cores work on the previous chunk in LDS (double
-// buffering).  MFMA operand layout (32x32x2, one block): lane t supplies
+// allow it) two chunks ahead, while the matrix cores work on the current chunk
+// in LDS (two LDS buffers, two register sets).  MFMA operand layout (32x32x2, one block): lane t supplies
 // A[t % 32][t / 32] and B[t / 32][t % 32]; accumulator r of lane t is
 // D[8 (r / 4) + 4 (t / 32) + r % 4][t % 32].
 //
@@ -91,9 +91,8 @@ __global__ __launch_bounds__(64 * NW) void k_mfma_thin(const float* __restrict__
   // tn: column-major A, rows k0..k0+31 (contiguous) for columns r0..r0+MT-1
   constexpr int NRA = MT * KC / 4 / NTH;
   constexpr int NRB = (KC * 32 * NB / 4 + NTH - 1) / NTH;
-  f32x4 ra[NRA];
-  f32x4 rb[NRB];
-  auto fetch = [&](int k0) {
+  f32x4 ra0[NRA], rb0[NRB], ra1[NRA], rb1[NRB];  // two chunks of loads in flight
+  auto fetch = [&](f32x4 (&ra)[NRA], f32x4 (&rb)[NRB], int k0) {
 #pragma unroll
     for (int u = 0; u < NRA; ++u) {
       const int f = tid + u * NTH;
@@ -138,7 +137,7 @@ __global__ __launch_bounds__(64 * NW) void k_mfma_thin(const float* __restrict__
       rb[u] = v;
     }
   };
-  auto stash = [&](int buf) {
+  auto stash = [&](const f32x4 (&ra)[NRA], const f32x4 (&rb)[NRB], int buf) {
     float* As = lds_f + buf * L::A_WORDS;
     float* Bs = lds_f + 2 * L::A_WORDS + buf * L::B_WORDS;
 #pragma unroll
@@ -172,14 +171,9 @@ __global__ __launch_bounds__(64 * NW) void k_mfma_thin(const float* __restrict__
 
   const int nchunks = (K + KC - 1) / KC;
   const int nbl = (l + 31) / 32;  // column blocks in use (uniform)
-  fetch(0);
-  stash(0);
-  __syncthreads();
   const int mrow = 32 * wave + (lane % 32);  // A-operand row of this lane within the tile
   const int khalf = lane / 32;
-  for (int ch = 0; ch < nchunks; ++ch) {
-    const int buf = ch & 1;
-    if (ch + 1 < nchunks) fetch((ch + 1) * KC);
+  auto compute = [&](int buf) {
     const float* As = lds_f + buf * L::A_WORDS;
     const float* Bs = lds_f + 2 * L::A_WORDS + buf * L::B_WORDS;
 #pragma unroll
@@ -194,7 +188,22 @@ __global__ __launch_bounds__(64 * NW) void k_mfma_thin(const float* __restrict__
         }
       }
     }
-    if (ch + 1 < nchunks) stash(buf ^ 1);
+  };
+  // chunk c sits in LDS buffer c & 1 while chunks c + 1 and c + 2 load into
+  // the register sets (unrolled by two so that the sets are fixed)
+  fetch(ra0, rb0, 0);
+  if (nchunks > 1) fetch(ra1, rb1, KC);
+  stash(ra0, rb0, 0);
+  __syncthreads();
+  for (int ch = 0; ch < nchunks; ch += 2) {
+    if (ch + 2 < nchunks) fetch(ra0, rb0, (ch + 2) * KC);
+    compute(0);
+    if (ch + 1 < nchunks) stash(ra1, rb1, 1);
+    __syncthreads();
+    if (ch + 1 >= nchunks) break;
+    if (ch + 3 < nchunks) fetch(ra1, rb1, (ch + 3) * KC);
+    compute(1);
+    if (ch + 2 < nchunks) stash(ra0, rb0, 0);
     __syncthreads();
   }
 
