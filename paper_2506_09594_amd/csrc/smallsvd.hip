@@ -43,7 +43,7 @@ size_t svd_lds_bytes(int l) {
 // Threads per workgroup: the Jacobi step has (l/2)^2 block items and l^2/2
 // rotation items of V.
 template <int LB>
-constexpr int svd_threads() { return LB <= 16 ? 256 : 512; }
+constexpr int svd_threads() { return LB <= 32 ? 256 : 512; }
 
 // Symmetric Schur rotation (c, s) that annihilates W[p][q] (Golub-Van Loan,
 // written as t = 2 apq sgn(d) / (|d| + sqrt(d^2 + 4 apq^2)), d = aqq - app);
