@@ -117,6 +117,9 @@ struct GraphCache {
   }
 };
 
+constexpr int kNumClasses = 5;
+constexpr int kClassBound[kNumClasses] = {16, 32, 48, 64, HT_MAX_WIDTH};
+
 struct ht_plan {
   bool batch;
   int precision, q;
@@ -141,6 +144,12 @@ struct ht_plan {
   float* table32;
   ItemList it_nn[2], it_tn[2], it_oy, it_oz, it_qk, it_nt, it_tf;  // [0]: 64-row tiles, [1]: 128-row tiles
   ItemList it_nns;  // nn items of the streaming product (256-row tiles)
+  // Width classes (bounds kClassBound) of plans whose slices differ in width:
+  // orthonormalization items and small-SVD slices per class, so that each
+  // launch is compiled for its own largest width (fixed widths only).
+  bool class_split;
+  int class_lmax[kNumClasses];
+  ItemList it_oyc[kNumClasses], it_ozc[kNumClasses], it_svc[kNumClasses];
   bool nn_stream;   // FP32 real slices the streaming nn product can take
   int max_n2;
   int tf_capacity;
@@ -612,6 +621,32 @@ int build_plan(const ht_plan_desc* descs, int n, bool batch, ht_plan** out) {
   lists.push_back(row_items(pl, false, 64, false));  // recon QK
   lists.push_back(nt_items(pl));                     // recon C
   lists.push_back(row_items(pl, false, kStreamRows, true));  // nn, streaming product
+  // width classes: orthonormalization items (Y, Z) and small-SVD slices
+  auto class_of = [&](int l) {
+    int c = 0;
+    while (c + 1 < kNumClasses && l > kClassBound[c]) ++c;
+    return c;
+  };
+  std::vector<int2> oyc[kNumClasses], ozc[kNumClasses], svc[kNumClasses];
+  {
+    const std::vector<int2>& oy = lists[4];
+    const std::vector<int2>& oz = lists[5];
+    for (const int2& it : oy) oyc[class_of(pl->h_slices[it.x].l)].push_back(it);
+    for (const int2& it : oz) ozc[class_of(pl->h_slices[it.x].l)].push_back(it);
+    for (int64_t j = 0; j < P; ++j) svc[class_of(pl->h_slices[j].l)].push_back(make_int2((int)j, 0));
+  }
+  int nused = 0;
+  for (int c = 0; c < kNumClasses; ++c) {
+    nused += !svc[c].empty();
+    pl->class_lmax[c] = 0;
+    for (const int2& it : svc[c]) pl->class_lmax[c] = std::max(pl->class_lmax[c], (int)pl->h_slices[it.x].l);
+  }
+  pl->class_split = nused > 1;
+  for (int c = 0; c < kNumClasses; ++c) {
+    lists.push_back(oyc[c]);
+    lists.push_back(ozc[c]);
+    lists.push_back(svc[c]);
+  }
   // the smallest LDS budget that fits every tensor sets the item capacity
   std::vector<int2> tfi;
   std::vector<int> tps;
@@ -629,7 +664,11 @@ int build_plan(const ht_plan_desc* descs, int n, bool batch, ht_plan** out) {
   }
   pl->tf_capacity = (int)tfi.size();
   ItemList* dst[] = {&pl->it_nn[0], &pl->it_tn[0], &pl->it_nn[1], &pl->it_tn[1], &pl->it_oy, &pl->it_oz,
-                     &pl->it_qk, &pl->it_nt, &pl->it_nns};
+                     &pl->it_qk, &pl->it_nt, &pl->it_nns,
+                     &pl->it_oyc[0], &pl->it_ozc[0], &pl->it_svc[0], &pl->it_oyc[1], &pl->it_ozc[1],
+                     &pl->it_svc[1], &pl->it_oyc[2], &pl->it_ozc[2], &pl->it_svc[2], &pl->it_oyc[3],
+                     &pl->it_ozc[3], &pl->it_svc[3], &pl->it_oyc[4], &pl->it_ozc[4], &pl->it_svc[4]};
+  static_assert(kNumClasses == 5, "item list table");
   std::vector<int2> all;
   for (size_t i = 0; i < lists.size(); ++i) {
     dst[i]->off = (int64_t)all.size();
@@ -801,6 +840,16 @@ int run_tsvt(const ht_plan* pl, const T* X, T* out, double tau, const double* ta
   };
   auto orth = [&](int which, double* gout, const int2* wk) {
     return timed(pl, ST_CHOLQR, s, [&] {
+      if (wk == nullptr && pl->class_split) {  // one launch per width class
+        for (int c = 0; c < kNumClasses; ++c) {
+          const ItemList& L = which ? pl->it_ozc[c] : pl->it_oyc[c];
+          if (L.n == 0) continue;
+          const int r = launch_orth_apply<T>(which ? Z : Y, which, sd, nullptr, items(pl, L), L.n,
+                                             pl->class_lmax[c], P, gp1, gout, s);
+          if (r) return r;
+        }
+        return (int)HT_OK;
+      }
       const ItemList& L = which ? pl->it_oz : pl->it_oy;
       return launch_orth_apply<T>(which ? Z : Y, which, sd, wk, items(pl, L), L.n, lmax, P, gp1, gout, s);
     });
@@ -823,7 +872,18 @@ int run_tsvt(const ht_plan* pl, const T* X, T* out, double tau, const double* ta
     }
     if ((r = sketch_tn(wk))) return r;
     return timed(pl, ST_SMALLSVD, s, [&] {
-      return launch_smallsvd<T>(gp2, gp1, sd, wk, P, lmax, tau, tau_dev, mu_dev, pen, K, sig_dst, kept_dst, s);
+      if (wk == nullptr && pl->class_split) {  // one launch per width class
+        for (int c = 0; c < kNumClasses; ++c) {
+          const ItemList& L = pl->it_svc[c];
+          if (L.n == 0) continue;
+          const int r = launch_smallsvd<T>(gp2, gp1, sd, nullptr, items(pl, L), L.n, pl->class_lmax[c], lmax, tau,
+                                           tau_dev, mu_dev, pen, K, sig_dst, kept_dst, s);
+          if (r) return r;
+        }
+        return (int)HT_OK;
+      }
+      return launch_smallsvd<T>(gp2, gp1, sd, wk, nullptr, P, lmax, lmax, tau, tau_dev, mu_dev, pen, K, sig_dst,
+                                kept_dst, s);
     });
   };
   const int2* wk_final = nullptr;

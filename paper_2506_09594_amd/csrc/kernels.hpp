@@ -99,11 +99,14 @@ int launch_orth_apply(T* Y, int which, const SliceDesc* sd, const int2* wk, cons
 // writes K' = R2^{-1} U diag(w) U^T R2^{-T} (l x l, at the slice's kq offset)
 // with w_i = prox(s_i)/s_i, i < k.  tau: 1 / *mu_dev if mu_dev, else
 // tau_dev[tensor] if tau_dev, else the scalar.  The first l*l doubles of every
-// slice's g2 partials are overwritten (scratch).  sigma_out rows have lmax entries.
+// slice's g2 partials are overwritten (scratch).  slices, when not null, lists
+// the slices of this launch (x = slice index; nslices entries; a width class),
+// else slices 0 .. nslices - 1.  lmax bounds the widths of the launch;
+// sigma_out rows have sigma_ld entries.
 template <typename T>
-int launch_smallsvd(double* g2, const double* gw, const SliceDesc* sd, const int2* wk, int nslices, int lmax,
-                    double tau, const double* tau_dev, const double* mu_dev, Penalty pen, T* K,
-                    double* sigma_out, int* kept_out, hipStream_t s);
+int launch_smallsvd(double* g2, const double* gw, const SliceDesc* sd, const int2* wk, const int2* slices, int nslices,
+                    int lmax, int sigma_ld, double tau, const double* tau_dev, const double* mu_dev, Penalty pen,
+                    T* K, double* sigma_out, int* kept_out, hipStream_t s);
 
 // Learned widths (mlp.hip).  Network parameters: one flat FP32 vector of
 // mlp_param_count() entries.  Gradient steps use a partial buffer of

@@ -110,7 +110,7 @@ __device__ __forceinline__ void rotate_block(double w00, double w01, double w10,
 template <typename T, int LB, int NT>
 __global__ __launch_bounds__(NT) void k_smallsvd(double* __restrict__ g2_all, const double* __restrict__ gw_all,
                                                  const SliceDesc* __restrict__ sd, const int2* __restrict__ wk,
-                                                 double tau_host, const double* __restrict__ tau_dev,
+                                                 const int2* __restrict__ slices, double tau_host, const double* __restrict__ tau_dev,
                                                  const double* __restrict__ mu_dev, Penalty pen,
                                                  T* __restrict__ Kall, double* __restrict__ sigma_out, int sigma_ld,
                                                  int* __restrict__ kept_out) {
@@ -119,7 +119,7 @@ __global__ __launch_bounds__(NT) void k_smallsvd(double* __restrict__ g2_all, co
   __shared__ int s_kept, s_flag[3];             // step flags, three-way rotation
   __shared__ JRot s_jr[2][LB / 2];              // rotations per pair, by step parity
 
-  const int j = blockIdx.x;
+  const int j = slices ? slices[blockIdx.x].x : (int)blockIdx.x;  // a class of slices, or all
   const int tid = threadIdx.x;
   const SliceDesc d = sd[j];
   const int l = slice_width(d, wk, j), kkeep = slice_kept(d, wk, j);
@@ -411,16 +411,16 @@ __global__ __launch_bounds__(NT) void k_smallsvd(double* __restrict__ g2_all, co
 }  // namespace
 
 template <typename T>
-int launch_smallsvd(double* g2, const double* gw, const SliceDesc* sd, const int2* wk, int nslices, int lmax,
-                    double tau, const double* tau_dev, const double* mu_dev, Penalty pen, T* K,
-                    double* sigma_out, int* kept_out, hipStream_t s) {
+int launch_smallsvd(double* g2, const double* gw, const SliceDesc* sd, const int2* wk, const int2* slices, int nslices,
+                    int lmax, int sigma_ld, double tau, const double* tau_dev, const double* mu_dev, Penalty pen,
+                    T* K, double* sigma_out, int* kept_out, hipStream_t s) {
   if (lmax > HT_MAX_WIDTH) HT_FAIL(HT_ERR_UNSUPPORTED, "sketch width above HT_MAX_WIDTH");
   if (nslices == 0) return HT_OK;
   auto launch = [&](auto kern, int nt) -> int {
     int rc = ensure_dynamic_lds((const void*)kern, svd_lds_bytes(HT_MAX_WIDTH));
     if (rc) return rc;
-    hipLaunchKernelGGL(kern, dim3((unsigned)nslices), dim3(nt), svd_lds_bytes(lmax), s, g2, gw, sd, wk,
-                       tau, tau_dev, mu_dev, pen, K, sigma_out, lmax, kept_out);
+    hipLaunchKernelGGL(kern, dim3((unsigned)nslices), dim3(nt), svd_lds_bytes(lmax), s, g2, gw, sd, wk, slices,
+                       tau, tau_dev, mu_dev, pen, K, sigma_out, sigma_ld, kept_out);
     HT_CHECK_LAUNCH();
     return HT_OK;
   };
@@ -431,9 +431,11 @@ int launch_smallsvd(double* g2, const double* gw, const SliceDesc* sd, const int
   return launch(k_smallsvd<T, 80, svd_threads<80>()>, svd_threads<80>());
 }
 
-template int launch_smallsvd<float>(double*, const double*, const SliceDesc*, const int2*, int, int, double,
-                                    const double*, const double*, Penalty, float*, double*, int*, hipStream_t);
-template int launch_smallsvd<double>(double*, const double*, const SliceDesc*, const int2*, int, int, double,
-                                     const double*, const double*, Penalty, double*, double*, int*, hipStream_t);
+template int launch_smallsvd<float>(double*, const double*, const SliceDesc*, const int2*, const int2*, int, int, int,
+                                    double, const double*, const double*, Penalty, float*, double*, int*,
+                                    hipStream_t);
+template int launch_smallsvd<double>(double*, const double*, const SliceDesc*, const int2*, const int2*, int, int,
+                                     int, double, const double*, const double*, Penalty, double*, double*, int*,
+                                     hipStream_t);
 
 }  // namespace ht
