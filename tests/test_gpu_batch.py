@@ -72,6 +72,26 @@ def test_batch_matches_oracle(ht, prec):
         assert _rel(got[t], ref[t]) < TOL[prec], f"tensor {t} shape {SHAPES[t]}"
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_batch_width_classes_match_oracle(ht, prec):
+    """Widths 10, 26, 42, 58, 74: one slice class per launch of the
+    orthonormalization and the small SVD (classes up to 16, 32, 48, 64, 76)."""
+    import torch
+    shapes = [(96, 96, 3), (80, 90, 2, 2), (128, 100, 2), (90, 120, 2), (100, 96, 3)]
+    ranks, ps = [5, 20, 36, 50, 66], [5, 6, 6, 8, 8]
+    taus = [1.0, 2.0, 3.0, 2.5, 1.5]
+    q, seed, sid = 1, 777, 2
+    xs = _inputs(shapes, ranks, prec, seed=5)
+    plan = ht.BatchPlan(shapes, r=ranks, p=ps, q=q, precision=prec, seed=seed, stream_id=sid)
+    assert plan.widths == [10, 26, 42, 58, 74]
+    out = plan.gnhtsvt(plan.pack(xs), taus, MCP, call_index=1)
+    torch.cuda.synchronize()
+    got = plan.unpack(out)
+    ref = _oracle(xs, shapes, ranks, ps, q, taus, MCP, seed, sid, 1, prec)
+    for t in range(len(shapes)):
+        assert _rel(got[t], ref[t]) < TOL[prec], f"tensor {t} shape {shapes[t]}"
+
+
 def test_batch_of_one_equals_single_plan(ht):
     import torch
     dims, kinds = (96, 80, 4, 4), ["dct2", "dct2"]
