@@ -144,6 +144,7 @@ struct ht_plan {
   float* table32;
   ItemList it_nn[2], it_tn[2], it_oy, it_oz, it_qk, it_nt, it_tf;  // [0]: 64-row tiles, [1]: 128-row tiles
   ItemList it_nns;  // nn items of the streaming product (256-row tiles)
+  ItemList it_t16;  // transform items when every tensor has two transformed modes of length 16 (else empty)
   // Width classes (bounds kClassBound) of plans whose slices differ in width:
   // orthonormalization items and small-SVD slices per class, so that each
   // launch is compiled for its own largest width (fixed widths only).
@@ -380,6 +381,25 @@ std::vector<int2> nt_items(const ht_plan* pl) {
     for (int t = 0; t < nt; ++t) groups[s].push_back(make_int2((int)s, t));
   }
   return xcd_grouped(groups, cost);
+}
+
+// Items of the two-modes-of-16 transform, or none when some tensor does not
+// qualify (FP64, complex slices, other mode lengths, ragged or huge slices).
+std::vector<int2> t16_items(const ht_plan* pl) {
+  std::vector<int2> items;
+  if (pl->precision == HT_FP64 || pl->cplx) return items;
+  for (const TensorHost& th : pl->tens) {
+    const int64_t NT = th.n1 * th.n2;
+    for (const ModeTable* mt : {&th.fwd, &th.inv})
+      if (mt->nmodes != 2 || mt->n[0] != 16 || mt->n[1] != 16 || mt->stride[0] * mt->stride[1] != 16)
+        return items;  // strides {1, 16}, or {16, 1} for the inverse (mode 4 first)
+    if (th.cplx || th.P != 256 || NT % 16 != 0 || NT >= (int64_t(1) << 24)) return items;
+  }
+  for (size_t t = 0; t < pl->tens.size(); ++t) {
+    const int64_t NT = pl->tens[t].n1 * pl->tens[t].n2;
+    for (int64_t t0 = 0; t0 < NT; t0 += 16 * kT16Groups) items.push_back(make_int2((int)t, (int)t0));
+  }
+  return items;
 }
 
 // Transform tiles of every tensor for an LDS budget; fills TP and the LDS size.
@@ -647,6 +667,7 @@ int build_plan(const ht_plan_desc* descs, int n, bool batch, ht_plan** out) {
     lists.push_back(ozc[c]);
     lists.push_back(svc[c]);
   }
+  lists.push_back(t16_items(pl));
   // the smallest LDS budget that fits every tensor sets the item capacity
   std::vector<int2> tfi;
   std::vector<int> tps;
@@ -667,7 +688,8 @@ int build_plan(const ht_plan_desc* descs, int n, bool batch, ht_plan** out) {
                      &pl->it_qk, &pl->it_nt, &pl->it_nns,
                      &pl->it_oyc[0], &pl->it_ozc[0], &pl->it_svc[0], &pl->it_oyc[1], &pl->it_ozc[1],
                      &pl->it_svc[1], &pl->it_oyc[2], &pl->it_ozc[2], &pl->it_svc[2], &pl->it_oyc[3],
-                     &pl->it_ozc[3], &pl->it_svc[3], &pl->it_oyc[4], &pl->it_ozc[4], &pl->it_svc[4]};
+                     &pl->it_ozc[3], &pl->it_svc[3], &pl->it_oyc[4], &pl->it_ozc[4], &pl->it_svc[4],
+                     &pl->it_t16};
   static_assert(kNumClasses == 5, "item list table");
   std::vector<int2> all;
   for (size_t i = 0; i < lists.size(); ++i) {
@@ -789,6 +811,14 @@ int run_tsvt(const ht_plan* pl, const T* X, T* out, double tau, const double* ta
   int* lstate = ws_ptr<int>(pl, ws, WS_LSTATE);
   int rc;
   if ((rc = timed(pl, ST_TRANSFORM_FWD, s, [&] {
+         if (pl->it_t16.n) {
+           const int2* i16 = items(pl, pl->it_t16);
+           if (bf16)
+             return launch_transform16<uint16_t>((const float*)X, (uint16_t*)A, pl->d_tens, i16, pl->it_t16.n,
+                                                 pl->table32, 0, s);
+           return launch_transform16<float>((const float*)X, (float*)A, pl->d_tens, i16, pl->it_t16.n, pl->table32,
+                                            0, s);
+         }
          const int2* it = items(pl, pl->it_tf);
          if (pl->cplx) {
            if (bf16)
@@ -919,6 +949,9 @@ int run_tsvt(const ht_plan* pl, const T* X, T* out, double tau, const double* ta
        })))
     return rc;
   return timed(pl, ST_TRANSFORM_INV, s, [&] {
+    if (pl->it_t16.n)
+      return launch_transform16<float>((const float*)C, (float*)out, pl->d_tens, items(pl, pl->it_t16), pl->it_t16.n,
+                                       pl->table32, 1, s);
     if (pl->cplx)
       return launch_transform_cplx<T, T>(C, out, pl->d_tens, items(pl, pl->it_tf), pl->it_tf.n, pl->tf_lds,
                                          table<T>(pl), pl->d_cmap, 1, s);
@@ -1256,6 +1289,9 @@ int ht_transform(const ht_plan* pl, const void* X, void* out, int inverse, void*
   if (pl->precision == HT_FP64)
     return launch_transform<double, double>(static_cast<const double*>(X), static_cast<double*>(out), pl->d_tens,
                                             items(pl, pl->it_tf), pl->it_tf.n, pl->tf_lds, pl->table64, inv, s);
+  if (pl->it_t16.n)
+    return launch_transform16<float>(static_cast<const float*>(X), static_cast<float*>(out), pl->d_tens,
+                                     items(pl, pl->it_t16), pl->it_t16.n, pl->table32, inv, s);
   return launch_transform<float, float>(static_cast<const float*>(X), static_cast<float*>(out), pl->d_tens,
                                         items(pl, pl->it_tf), pl->it_tf.n, pl->tf_lds, pl->table32, inv, s);
 }

@@ -35,6 +35,15 @@ template <typename T, typename TO>
 int launch_transform(const T* in, TO* out, const TensorDesc* tds, const int2* items, int nitems, size_t lds,
                      const T* table, int inverse, hipStream_t s);
 
+// FP32 transform of tensors whose transformed modes are exactly two of length
+// 16 (mode tables with n = {16, 16}, slice strides {1, 16} in either order); items are
+// (tensor, t0) with t0 a multiple of 16 kT16Groups, each taking tube
+// positions t0 .. t0 + 16 kT16Groups - 1 (NT a multiple of 16).
+constexpr int kT16Groups = 2;
+template <typename TO>
+int launch_transform16(const float* in, TO* out, const TensorDesc* tds, const int2* items, int nitems,
+                       const float* table, int inverse, hipStream_t s);
+
 // Same for tensors under the unitary DFT (complex slices, see TensorDesc):
 // forward stores the canonical slots of A, inverse reads the slots of C.
 template <typename T, typename TO>

@@ -278,6 +278,125 @@ __global__ __launch_bounds__(256) void k_transform(const T* __restrict__ in_all,
 }
 
 // ---------------------------------------------------------------------------
+// Two transformed modes of length 16 (P = 256, slice j = i3 + 16 i4), FP32.
+// Every wavefront works alone (no workgroup barrier): it takes kT16Groups
+// groups of 16 consecutive tube positions t0 + c, c < 16.  Lane (g, c) with
+// g = lane / 16 loads X(t0 + c, i3 + 16 i4) for i3 = 4 g + kk (kk < 4) and all
+// 16 values of i4 straight from HBM (16 lanes read 64 contiguous bytes).
+// Mode 3 is sixteen 16 x 16 x 16 products on the matrix cores (one per i4,
+// four v_mfma_f32_16x16x4f32 steps), contracting i3 in the order 4 g + kk so
+// that every lane already holds its B operand; lane (g, c) receives
+// Y(t0 + c, i3' = 4 g + v, i4).  One pass through a private LDS region of the
+// wavefront (pitch kT16Pitch floats per tube position, 16-byte accesses)
+// hands lane (g, c) the four values i4 = 4 g + kk of every i3'; mode 4 is
+// another sixteen products with the same contraction order, and lane (g, c)
+// stores A(t0 + c, i3' + 16 (4 g + v)).  HBM traffic is one read and one write
+// of the tensor; the second group of an item reuses the other half of each
+// 128-byte line the first group fetched.
+// ---------------------------------------------------------------------------
+constexpr int kT16Pitch = 16 * 16 + 4;
+constexpr int kT16Waves = 4;
+
+template <typename TO>
+__device__ __forceinline__ TO t16_cast(float v) {
+  if constexpr (std::is_same<TO, float>::value)
+    return v;
+  else
+    return f32_to_bf16_rne(v);
+}
+
+template <typename TO>
+__global__ __launch_bounds__(64 * kT16Waves) void k_transform16(const float* __restrict__ in_all,
+                                                                TO* __restrict__ out_all,
+                                                                const TensorDesc* __restrict__ tds,
+                                                                const int2* __restrict__ items, int nitems,
+                                                                const float* __restrict__ table, int inverse) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  // the wavefront index as a scalar, so that item, tensor and every row base
+  // below live in scalar registers and a lane keeps only 32-bit offsets
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+  const int it = blockIdx.x * kT16Waves + wave;
+  if (it >= nitems) return;
+  const int2 item = items[it];
+  const TensorDesc* td = tds + item.x;
+  const int64_t NT = td->NT;
+  const ModeTable* mt = inverse ? &td->inv : &td->fwd;
+  const float* in = in_all + (inverse ? td->a : td->x);
+  TO* out = out_all + (inverse ? td->x : td->a);
+  const int m3 = mt->stride[0] == 1 ? 0 : 1;  // table entry of mode 3 (the inverse lists mode 4 first)
+  const float* U3 = table + mt->off[m3];
+  const float* U4 = table + mt->off[1 - m3];
+  const int g = lane >> 4, c = lane & 15;
+  float ua[4], ub[4];  // A operands: U[c][4 g + kk]
+#pragma unroll
+  for (int kk = 0; kk < 4; ++kk) {
+    ua[kk] = U3[c * 16 + 4 * g + kk];
+    ub[kk] = U4[c * 16 + 4 * g + kk];
+  }
+  float* xw = reinterpret_cast<float*>(smem_raw) + wave * 16 * kT16Pitch + c * kT16Pitch;
+  for (int gi = 0; gi < kT16Groups; ++gi) {
+    const int64_t t0 = (int64_t)item.y + 16 * gi;
+    if (t0 >= NT) break;  // uniform over the wavefront
+    float x[16][4];
+#pragma unroll
+    for (int i4 = 0; i4 < 16; ++i4) {
+      const float* src = in + t0 + (int64_t)(16 * i4) * NT;  // uniform
+#pragma unroll
+      for (int kk = 0; kk < 4; ++kk) x[i4][kk] = src[(uint32_t)((4 * g + kk) * (uint32_t)NT + c)];
+    }
+    // mode 3; four consecutive i4 give one 16-byte LDS store per v
+#pragma unroll
+    for (int w = 0; w < 4; ++w) {
+      tf_f32x4 d[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        d[q] = tf_f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+        for (int kk = 0; kk < 4; ++kk) d[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(ua[kk], x[4 * w + q][kk], d[q], 0, 0, 0);
+      }
+#pragma unroll
+      for (int v = 0; v < 4; ++v)
+        *reinterpret_cast<tf_f32x4*>(xw + (4 * g + v) * 16 + 4 * w) = tf_f32x4{d[0][v], d[1][v], d[2][v], d[3][v]};
+    }
+    // the stores above reach the LDS before the loads below (same wavefront)
+    asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+    const uint32_t so = (uint32_t)(64 * g) * (uint32_t)NT + c;
+#pragma unroll
+    for (int i3 = 0; i3 < 16; ++i3) {
+      const tf_f32x4 y = *reinterpret_cast<const tf_f32x4*>(xw + i3 * 16 + 4 * g);
+      tf_f32x4 e = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+      for (int kk = 0; kk < 4; ++kk) e = __builtin_amdgcn_mfma_f32_16x16x4f32(ub[kk], y[kk], e, 0, 0, 0);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) out[t0 + (int64_t)(i3 + 16 * v) * NT + so] = t16_cast<TO>(e[v]);
+    }
+    // the next group's LDS stores follow this group's LDS loads
+    asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+  }
+}
+
+size_t transform16_lds_bytes() { return (size_t)kT16Waves * 16 * kT16Pitch * sizeof(float); }
+
+template <typename TO>
+int launch_transform16(const float* in, TO* out, const TensorDesc* tds, const int2* items, int nitems,
+                       const float* table, int inverse, hipStream_t stream) {
+  if (nitems == 0) return HT_OK;
+  const size_t lds = transform16_lds_bytes();
+  int rc = ensure_dynamic_lds((const void*)k_transform16<TO>, lds);
+  if (rc) return rc;
+  const unsigned grid = (unsigned)((nitems + kT16Waves - 1) / kT16Waves);
+  hipLaunchKernelGGL((k_transform16<TO>), dim3(grid), dim3(64 * kT16Waves), lds, stream, in, out, tds, items, nitems,
+                     table, inverse);
+  HT_CHECK_LAUNCH();
+  return HT_OK;
+}
+
+template int launch_transform16<float>(const float*, float*, const TensorDesc*, const int2*, int, const float*, int,
+                                       hipStream_t);
+template int launch_transform16<uint16_t>(const float*, uint16_t*, const TensorDesc*, const int2*, int, const float*,
+                                          int, hipStream_t);
+
+// ---------------------------------------------------------------------------
 // Unitary DFT on every mode 3..d (complex slices).  The tile holds TP tube
 // positions of all P slices as two planes (real, imaginary).  Forward: the
 // real X tile is transformed mode by mode with the complex matrices and the

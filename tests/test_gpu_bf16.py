@@ -42,9 +42,10 @@ def _run(ht, dims, kinds, rank, r, p, q, tau, pen, seed=1, noise=0.0, call=0):
     return got, ref
 
 
-def test_bf16_transformed_slices_are_rounded_transform(ht):
+@pytest.mark.parametrize("dims", [(96, 80, 4, 4), (36, 20, 16, 16)])
+def test_bf16_transformed_slices_are_rounded_transform(ht, dims):
     import torch
-    dims, kinds = (96, 80, 4, 4), ["dct2", "dct2"]
+    kinds = ["dct2", "dct2"]
     X = synth.lowrank_tensor(dims, 8, kinds, seed=2).astype(np.float32).astype(np.float64)
     plan = ht.Plan(dims, kinds, r=8, p=6, q=1, precision="bf16", seed=5)
     ws = plan.alloc_workspace()

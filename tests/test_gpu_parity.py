@@ -68,7 +68,10 @@ def test_omega_matches_oracle_generator(ht):
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 @pytest.mark.parametrize("dims,kinds", [((60, 50, 20), ["dct2"]), ((33, 17, 5, 3), ["dct2", "dct2"]),
-                                        ((20, 9, 4, 3, 2), ["dct2", "dct2", "dct2"]), ((70, 65, 33), ["dct2"])])
+                                        ((20, 9, 4, 3, 2), ["dct2", "dct2", "dct2"]), ((70, 65, 33), ["dct2"]),
+                                        # two modes of 16: 45 groups of 16 tube positions (a ragged last item
+                                        # and a partly filled last workgroup), and an even count
+                                        ((36, 20, 16, 16), ["dct2", "dct2"]), ((48, 40, 16, 16), ["dct2", "dct2"])])
 def test_transform_matches_oracle(ht, prec, dims, kinds):
     import torch
     rng = np.random.default_rng(0)
@@ -95,6 +98,28 @@ def test_custom_transform_nonunitary(ht):
     torch.cuda.synchronize()
     T = otr.build_transforms(dims, [("custom", U)])
     assert _rel(ht.from_device(fwd, dims), otr.forward(X, T)) < 1e-14
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_custom_transform_two_modes_of_16(ht, prec):
+    """Different non-symmetric matrices with U U^T = alpha I (alpha 2.89 and 0.36) on
+    modes 3 and 4 (length 16): a transposed or swapped mode matrix, or a wrong
+    inverse, fails."""
+    import torch
+    rng = np.random.default_rng(5)
+    U3 = 1.7 * np.linalg.qr(rng.standard_normal((16, 16)))[0]
+    U4 = 0.6 * np.linalg.qr(rng.standard_normal((16, 16)))[0]
+    dims = (32, 24, 16, 16)
+    X = rng.standard_normal(dims).astype(_np_dtype(prec)).astype(np.float64)
+    plan = ht.Plan(dims, ["custom", "custom"], r=3, p=2, q=1, precision=prec, custom=[U3, U4])
+    dX = ht.to_device(X, plan.torch_dtype)
+    fwd = plan.transform(dX)
+    back = plan.transform(fwd, inverse=True)
+    torch.cuda.synchronize()
+    T = otr.build_transforms(dims, [("custom", U3), ("custom", U4)])
+    tol = 1e-13 if prec == "fp64" else 2e-6
+    assert _rel(ht.from_device(fwd, dims), otr.forward(X, T)) < tol
+    assert _rel(ht.from_device(back, dims), X) < tol
 
 
 @pytest.mark.parametrize("pen", list(PEN))
