@@ -393,13 +393,20 @@ std::vector<int2> t16_items(const ht_plan* pl) {
     for (const ModeTable* mt : {&th.fwd, &th.inv})
       if (mt->nmodes != 2 || mt->n[0] != 16 || mt->n[1] != 16 || mt->stride[0] * mt->stride[1] != 16)
         return items;  // strides {1, 16}, or {16, 1} for the inverse (mode 4 first)
-    if (th.cplx || th.P != 256 || NT % 16 != 0 || NT >= (int64_t(1) << 24)) return items;
+    if (th.cplx || th.P != 256 || NT % 16 != 0 || NT >= (int64_t(1) << 24) || th.x % 2 || th.a % 2) return items;
   }
   for (size_t t = 0; t < pl->tens.size(); ++t) {
     const int64_t NT = pl->tens[t].n1 * pl->tens[t].n2;
-    for (int64_t t0 = 0; t0 < NT; t0 += 16 * kT16Groups) items.push_back(make_int2((int)t, (int)t0));
+    for (int64_t t0 = 0; t0 < NT; t0 += kT16Tube) items.push_back(make_int2((int)t, (int)t0));
   }
   return items;
+}
+
+// The two-modes-of-16 transform applies to this plan and to these buffers
+// (8-byte pairs in, 8- or 4-byte pairs out).
+bool use_t16(const ht_plan* pl, const void* in, const void* out, size_t out_elem) {
+  return pl->it_t16.n > 0 && reinterpret_cast<uintptr_t>(in) % 8 == 0 &&
+         reinterpret_cast<uintptr_t>(out) % (2 * out_elem) == 0;
 }
 
 // Transform tiles of every tensor for an LDS budget; fills TP and the LDS size.
@@ -811,7 +818,7 @@ int run_tsvt(const ht_plan* pl, const T* X, T* out, double tau, const double* ta
   int* lstate = ws_ptr<int>(pl, ws, WS_LSTATE);
   int rc;
   if ((rc = timed(pl, ST_TRANSFORM_FWD, s, [&] {
-         if (pl->it_t16.n) {
+         if (use_t16(pl, X, A, bf16 ? 2 : 4)) {
            const int2* i16 = items(pl, pl->it_t16);
            if (bf16)
              return launch_transform16<uint16_t>((const float*)X, (uint16_t*)A, pl->d_tens, i16, pl->it_t16.n,
@@ -949,7 +956,7 @@ int run_tsvt(const ht_plan* pl, const T* X, T* out, double tau, const double* ta
        })))
     return rc;
   return timed(pl, ST_TRANSFORM_INV, s, [&] {
-    if (pl->it_t16.n)
+    if (use_t16(pl, C, out, 4))
       return launch_transform16<float>((const float*)C, (float*)out, pl->d_tens, items(pl, pl->it_t16), pl->it_t16.n,
                                        pl->table32, 1, s);
     if (pl->cplx)
@@ -1289,7 +1296,7 @@ int ht_transform(const ht_plan* pl, const void* X, void* out, int inverse, void*
   if (pl->precision == HT_FP64)
     return launch_transform<double, double>(static_cast<const double*>(X), static_cast<double*>(out), pl->d_tens,
                                             items(pl, pl->it_tf), pl->it_tf.n, pl->tf_lds, pl->table64, inv, s);
-  if (pl->it_t16.n)
+  if (use_t16(pl, X, out, 4))
     return launch_transform16<float>(static_cast<const float*>(X), static_cast<float*>(out), pl->d_tens,
                                      items(pl, pl->it_t16), pl->it_t16.n, pl->table32, inv, s);
   return launch_transform<float, float>(static_cast<const float*>(X), static_cast<float*>(out), pl->d_tens,

@@ -36,10 +36,12 @@ int launch_transform(const T* in, TO* out, const TensorDesc* tds, const int2* it
                      const T* table, int inverse, hipStream_t s);
 
 // FP32 transform of tensors whose transformed modes are exactly two of length
-// 16 (mode tables with n = {16, 16}, slice strides {1, 16} in either order); items are
-// (tensor, t0) with t0 a multiple of 16 kT16Groups, each taking tube
-// positions t0 .. t0 + 16 kT16Groups - 1 (NT a multiple of 16).
-constexpr int kT16Groups = 2;
+// 16 (mode tables with n = {16, 16}, slice strides {1, 16} in either order);
+// items are (tensor, t0) with t0 a multiple of kT16Tube, each taking tube
+// positions t0 .. t0 + kT16Tube - 1 (fewer at the end; NT a multiple of 16,
+// tensor offsets even).  in and out must be 8-byte (BF16 out: 4-byte) aligned,
+// else HT_ERR_UNSUPPORTED.
+constexpr int kT16Tube = 32;
 template <typename TO>
 int launch_transform16(const float* in, TO* out, const TensorDesc* tds, const int2* items, int nitems,
                        const float* table, int inverse, hipStream_t s);

@@ -279,39 +279,76 @@ __global__ __launch_bounds__(256) void k_transform(const T* __restrict__ in_all,
 
 // ---------------------------------------------------------------------------
 // Two transformed modes of length 16 (P = 256, slice j = i3 + 16 i4), FP32.
-// Every wavefront works alone (no workgroup barrier): it takes kT16Groups
-// groups of 16 consecutive tube positions t0 + c, c < 16.  Lane (g, c) with
-// g = lane / 16 loads X(t0 + c, i3 + 16 i4) for i3 = 4 g + kk (kk < 4) and all
-// 16 values of i4 straight from HBM (16 lanes read 64 contiguous bytes).
-// Mode 3 is sixteen 16 x 16 x 16 products on the matrix cores (one per i4,
-// four v_mfma_f32_16x16x4f32 steps), contracting i3 in the order 4 g + kk so
-// that every lane already holds its B operand; lane (g, c) receives
-// Y(t0 + c, i3' = 4 g + v, i4).  One pass through a private LDS region of the
+// Every wavefront works alone (no workgroup barrier) on an item of 32
+// consecutive tube positions t0 .. t0 + 31, as two blocks of 16: lane (g, c)
+// with g = lane / 16, c = lane % 16 reads the pair t0 + 2c, t0 + 2c + 1 with
+// one 8-byte load (16 lanes cover a 128-byte line) for slice rows
+// i3 = 4 g + kk (kk < 4) and all 16 values of i4: element 0 of the pair
+// belongs to block 0, element 1 to block 1.  Per block, mode 3 is sixteen
+// 16 x 16 x 16 products on the matrix cores (one per i4, four
+// v_mfma_f32_16x16x4f32 steps), contracting i3 in the order 4 g + kk so that
+// every lane already holds its B operand; lane (g, c) receives
+// Y(i3' = 4 g + v, i4).  One pass through a private LDS region of the
 // wavefront (pitch kT16Pitch floats per tube position, 16-byte accesses)
 // hands lane (g, c) the four values i4 = 4 g + kk of every i3'; mode 4 is
-// another sixteen products with the same contraction order, and lane (g, c)
-// stores A(t0 + c, i3' + 16 (4 g + v)).  HBM traffic is one read and one write
-// of the tensor; the second group of an item reuses the other half of each
-// 128-byte line the first group fetched.
+// another sixteen products with the same contraction order and gives
+// A(i3' + 16 (4 g + v)).  Block 0's results wait in registers until block 1's
+// are ready, and each pair leaves with one 8-byte store.  HBM traffic is one
+// read and one write of the tensor.  A last item of 16 positions masks the
+// lanes whose pair lies past the end (their columns stay zero and are not
+// stored; columns of the products never mix).
 // ---------------------------------------------------------------------------
 constexpr int kT16Pitch = 16 * 16 + 4;
-constexpr int kT16Waves = 4;
+constexpr int kT16Waves = 2;
 
 template <typename TO>
-__device__ __forceinline__ TO t16_cast(float v) {
-  if constexpr (std::is_same<TO, float>::value)
-    return v;
-  else
-    return f32_to_bf16_rne(v);
+struct T16Pair;
+template <>
+struct T16Pair<float> {
+  typedef float __attribute__((ext_vector_type(2))) type;
+  static __device__ __forceinline__ type make(float a, float b) { return type{a, b}; }
+};
+template <>
+struct T16Pair<uint16_t> {
+  typedef unsigned short __attribute__((ext_vector_type(2))) type;
+  static __device__ __forceinline__ type make(float a, float b) { return type{f32_to_bf16_rne(a), f32_to_bf16_rne(b)}; }
+};
+
+// Mode 3 of one block (x: the lane's 64 values) into the exchange region.
+__device__ __forceinline__ void t16_mode3(const float (&x)[16][4], const float (&ua)[4], float* xw, int g) {
+#pragma unroll
+  for (int w = 0; w < 4; ++w) {
+    tf_f32x4 d[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      d[q] = tf_f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+      for (int kk = 0; kk < 4; ++kk) d[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(ua[kk], x[4 * w + q][kk], d[q], 0, 0, 0);
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v)
+      *reinterpret_cast<tf_f32x4*>(xw + (4 * g + v) * 16 + 4 * w) = tf_f32x4{d[0][v], d[1][v], d[2][v], d[3][v]};
+  }
+  // the stores above reach the LDS before the loads that follow (same wavefront)
+  asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+}
+
+// Mode 4 of chain i3' from the exchange region.
+__device__ __forceinline__ tf_f32x4 t16_mode4(const float (&ub)[4], const float* xw, int i3, int g) {
+  const tf_f32x4 y = *reinterpret_cast<const tf_f32x4*>(xw + i3 * 16 + 4 * g);
+  tf_f32x4 e = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+  for (int kk = 0; kk < 4; ++kk) e = __builtin_amdgcn_mfma_f32_16x16x4f32(ub[kk], y[kk], e, 0, 0, 0);
+  return e;
 }
 
 template <typename TO>
-__global__ __launch_bounds__(64 * kT16Waves) void k_transform16(const float* __restrict__ in_all,
-                                                                TO* __restrict__ out_all,
-                                                                const TensorDesc* __restrict__ tds,
-                                                                const int2* __restrict__ items, int nitems,
-                                                                const float* __restrict__ table, int inverse) {
+__global__ __launch_bounds__(64 * kT16Waves) __attribute__((amdgpu_waves_per_eu(2))) void k_transform16(
+    const float* __restrict__ in_all, TO* __restrict__ out_all, const TensorDesc* __restrict__ tds,
+    const int2* __restrict__ items, int nitems, const float* __restrict__ table, int inverse) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
+  typedef typename T16Pair<TO>::type PT;
+  typedef float __attribute__((ext_vector_type(2))) f32x2;
   // the wavefront index as a scalar, so that item, tensor and every row base
   // below live in scalar registers and a lane keeps only 32-bit offsets
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
@@ -327,6 +364,8 @@ __global__ __launch_bounds__(64 * kT16Waves) void k_transform16(const float* __r
   const float* U3 = table + mt->off[m3];
   const float* U4 = table + mt->off[1 - m3];
   const int g = lane >> 4, c = lane & 15;
+  const int64_t t0 = item.y;
+  const bool live = t0 + 2 * c < NT;  // false only in a last item of 16 positions
   float ua[4], ub[4];  // A operands: U[c][4 g + kk]
 #pragma unroll
   for (int kk = 0; kk < 4; ++kk) {
@@ -334,44 +373,36 @@ __global__ __launch_bounds__(64 * kT16Waves) void k_transform16(const float* __r
     ub[kk] = U4[c * 16 + 4 * g + kk];
   }
   float* xw = reinterpret_cast<float*>(smem_raw) + wave * 16 * kT16Pitch + c * kT16Pitch;
-  for (int gi = 0; gi < kT16Groups; ++gi) {
-    const int64_t t0 = (int64_t)item.y + 16 * gi;
-    if (t0 >= NT) break;  // uniform over the wavefront
-    float x[16][4];
+  float x0[16][4], x1[16][4];
 #pragma unroll
-    for (int i4 = 0; i4 < 16; ++i4) {
-      const float* src = in + t0 + (int64_t)(16 * i4) * NT;  // uniform
+  for (int i4 = 0; i4 < 16; ++i4) {
+    const float* src = in + t0 + (int64_t)(16 * i4) * NT;  // uniform
 #pragma unroll
-      for (int kk = 0; kk < 4; ++kk) x[i4][kk] = src[(uint32_t)((4 * g + kk) * (uint32_t)NT + c)];
+    for (int kk = 0; kk < 4; ++kk) {
+      f32x2 v = {0.0f, 0.0f};
+      if (live) v = *reinterpret_cast<const f32x2*>(src + (uint32_t)((4 * g + kk) * (uint32_t)NT + 2 * c));
+      x0[i4][kk] = v[0];
+      x1[i4][kk] = v[1];
     }
-    // mode 3; four consecutive i4 give one 16-byte LDS store per v
+  }
+  float e0[16][4];
+  t16_mode3(x0, ua, xw, g);
 #pragma unroll
-    for (int w = 0; w < 4; ++w) {
-      tf_f32x4 d[4];
+  for (int i3 = 0; i3 < 16; ++i3) {
+    const tf_f32x4 e = t16_mode4(ub, xw, i3, g);
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        d[q] = tf_f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+    for (int v = 0; v < 4; ++v) e0[i3][v] = e[v];
+  }
+  // block 1's LDS stores follow block 0's LDS loads
+  asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+  t16_mode3(x1, ua, xw, g);
+  const uint32_t so = (uint32_t)(64 * g) * (uint32_t)NT + 2 * c;
 #pragma unroll
-        for (int kk = 0; kk < 4; ++kk) d[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(ua[kk], x[4 * w + q][kk], d[q], 0, 0, 0);
-      }
+  for (int i3 = 0; i3 < 16; ++i3) {
+    const tf_f32x4 e = t16_mode4(ub, xw, i3, g);
 #pragma unroll
-      for (int v = 0; v < 4; ++v)
-        *reinterpret_cast<tf_f32x4*>(xw + (4 * g + v) * 16 + 4 * w) = tf_f32x4{d[0][v], d[1][v], d[2][v], d[3][v]};
-    }
-    // the stores above reach the LDS before the loads below (same wavefront)
-    asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
-    const uint32_t so = (uint32_t)(64 * g) * (uint32_t)NT + c;
-#pragma unroll
-    for (int i3 = 0; i3 < 16; ++i3) {
-      const tf_f32x4 y = *reinterpret_cast<const tf_f32x4*>(xw + i3 * 16 + 4 * g);
-      tf_f32x4 e = {0.0f, 0.0f, 0.0f, 0.0f};
-#pragma unroll
-      for (int kk = 0; kk < 4; ++kk) e = __builtin_amdgcn_mfma_f32_16x16x4f32(ub[kk], y[kk], e, 0, 0, 0);
-#pragma unroll
-      for (int v = 0; v < 4; ++v) out[t0 + (int64_t)(i3 + 16 * v) * NT + so] = t16_cast<TO>(e[v]);
-    }
-    // the next group's LDS stores follow this group's LDS loads
-    asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+    for (int v = 0; v < 4; ++v)
+      if (live) *reinterpret_cast<PT*>(out + t0 + (int64_t)(i3 + 16 * v) * NT + so) = T16Pair<TO>::make(e0[i3][v], e[v]);
   }
 }
 
@@ -381,6 +412,8 @@ template <typename TO>
 int launch_transform16(const float* in, TO* out, const TensorDesc* tds, const int2* items, int nitems,
                        const float* table, int inverse, hipStream_t stream) {
   if (nitems == 0) return HT_OK;
+  if (reinterpret_cast<uintptr_t>(in) % 8 != 0 || reinterpret_cast<uintptr_t>(out) % (2 * sizeof(TO)) != 0)
+    HT_FAIL(HT_ERR_UNSUPPORTED, "two-modes-of-16 transform: unaligned buffers");
   const size_t lds = transform16_lds_bytes();
   int rc = ensure_dynamic_lds((const void*)k_transform16<TO>, lds);
   if (rc) return rc;
