@@ -26,6 +26,8 @@
 // the round-robin schedule, whose rotations are the identity, so no item
 // branches on it.  W is scaled to unit maximum diagonal first, so the rotation
 // formulas cannot overflow.
+#include <type_traits>
+
 #include "chol.hpp"
 
 namespace ht {
@@ -47,12 +49,12 @@ constexpr int svd_threads() { return LB <= 32 ? 256 : 512; }
 
 // Symmetric Schur rotation (c, s) that annihilates W[p][q] (Golub-Van Loan,
 // written as t = 2 apq sgn(d) / (|d| + sqrt(d^2 + 4 apq^2)), d = aqq - app);
-// identity when the entry is below the rounding-level thresholds.  Entries are
-// at most 1 in magnitude (W is normalized), so nothing overflows.
-__device__ __forceinline__ void schur2(double app, double aqq, double apq, double abs_tol, double& c, double& s) {
+// identity when |apq| is at most tol, or at most tol * sqrt(|app aqq|).  Entries
+// are at most 1 in magnitude (W is normalized), so nothing overflows.
+__device__ __forceinline__ void schur2(double app, double aqq, double apq, double tol, double& c, double& s) {
   c = 1.0;
   s = 0.0;
-  if (fabs(apq) > abs_tol && apq * apq > 1e-30 * fabs(app * aqq)) {
+  if (fabs(apq) > tol && apq * apq > tol * tol * fabs(app * aqq)) {
     const double d = aqq - app;
     const double h = sqrt(d * d + 4.0 * apq * apq);
     const double t = 2.0 * apq * (d >= 0.0 ? 1.0 : -1.0) * fast_rcp(fabs(d) + h);
@@ -195,14 +197,16 @@ __global__ __launch_bounds__(NT) void k_smallsvd(double* __restrict__ g2_all, co
     if (tid == 0) s_scr = md;
   }
   __syncthreads();
-  // A pair is rotated only when its off-diagonal entry is above both 1e-15
-  // relative to sqrt(|app aqq|) and 1e-15 * max diag: below that it is at the
-  // rounding level of W and rotating it would not change the result.
+  // A pair is rotated only when its off-diagonal entry is above both tol
+  // relative to sqrt(|app aqq|) and tol * max diag.  FP64 output: tol = 1e-15,
+  // the rounding level of W.  FP32 output: tol = 1e-10; a skipped entry moves
+  // an eigenvalue by about apq^2 / gap and a vector by about apq / gap, far
+  // below the single-precision rounding of B and of the result.
   const double scale = s_scr > 0.0 ? s_scr : 1.0;  // W <- W / max diag
   const double inv_scale = 1.0 / scale;
   for (int idx = tid; idx < ll; idx += NT) B1[(idx / l) * gp + (idx % l)] *= inv_scale;
   __syncthreads();
-  const double abs_tol = 1e-15;
+  const double abs_tol = std::is_same<T, double>::value ? 1e-15 : 1e-10;
 
   // ---- parallel cyclic Jacobi, ping-pong between B1 and B0 -----------------
   const int half = L2 / 2;
