@@ -52,12 +52,23 @@ __device__ __forceinline__ void chol_regs(double (&g)[LB], int l, double delta) 
         const double inv_r = fast_rsqrt(d);
         const double rjb = g[j] * inv_r;  // R[j][b] on lane b >= j (R[j][j] on lane j)
         if (lane >= j) g[j] = rjb;
+        // every a up to LB, without a test against l: a guard here becomes a
+        // branch per entry and serializes the broadcasts.  Rows a >= l are
+        // never read afterwards; their entries stay finite (the column lanes
+        // past l hold copies of column 0).
+        // up to 32 columns: eight broadcasts, then their updates (no wait
+        // states between a broadcast and its use); wider kernels already run
+        // short of scalar registers and update one entry at a time
+        constexpr int NB = LB <= 32 ? 8 : 1;
 #pragma unroll
-        for (int a = j + 1; a < LB; ++a) {
-          if (a < l) {
-            const double rja = readlane_d(rjb, a);
-            g[a] -= rja * rjb;
-          }
+        for (int a0 = j + 1; a0 < LB; a0 += NB) {
+          double r[NB];
+#pragma unroll
+          for (int u = 0; u < NB; ++u)
+            if (a0 + u < LB) r[u] = readlane_d(rjb, a0 + u);
+#pragma unroll
+          for (int u = 0; u < NB; ++u)
+            if (a0 + u < LB) g[a0 + u] -= r[u] * rjb;
         }
       } else {
         if (lane >= j) g[j] = 0.0;

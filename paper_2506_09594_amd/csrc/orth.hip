@@ -104,6 +104,13 @@ __global__ __launch_bounds__(TR) void k_orth_fused(T* __restrict__ Yall, int whi
   const double delta = 8.0 * (double)m * 2.220446049250313e-16 * dmax;
   chol_regs<LB>(g, l, dmax > 0.0 ? delta : 1.0);
 
+  // 1 / R[c][c] on lane c (0 for a skipped column), all lanes at once, so no
+  // reciprocal sits on the chain of the substitution below
+  double rdiag = 0.0;
+#pragma unroll
+  for (int a = 0; a < LB; ++a)
+    if (a == lane) rdiag = g[a];
+  const double rinv = (rdiag != 0.0) ? fast_rcp(rdiag) : 0.0;
   // q R = y: q_c = (y_c - sum_{a<c} q_a R[a][c]) / R[c][c]; R[a][c] is g[a] on lane c
 #pragma unroll
   for (int c = 0; c < LB; ++c) {
@@ -111,8 +118,7 @@ __global__ __launch_bounds__(TR) void k_orth_fused(T* __restrict__ Yall, int whi
       double t = y[c];
 #pragma unroll
       for (int a = 0; a < c; ++a) t -= y[a] * readlane_d(g[a], c);
-      const double rcc = readlane_d(g[c], c);
-      y[c] = (rcc != 0.0) ? t * fast_rcp(rcc) : 0.0;
+      y[c] = t * readlane_d(rinv, c);
     }
   }
 #pragma unroll
