@@ -122,6 +122,35 @@ def test_custom_transform_two_modes_of_16(ht, prec):
     assert _rel(ht.from_device(back, dims), X) < tol
 
 
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_tsvt_repeated_singular_values(ht, prec):
+    """Transformed slices with clusters of equal singular values (6 x 8, 6 x 5, 4 x 2):
+    inside a cluster the singular vectors are arbitrary, so the rotations the
+    small SVD skips (threshold 1e-10 relative for FP32 output, 1e-15 for FP64) must
+    leave K' = U diag(w) U^T unchanged; the shrink weights differ between clusters
+    (MCP) and the last cluster falls below tau."""
+    import torch
+    dims, kinds = (96, 80, 4, 4), ["dct2", "dct2"]
+    n1, n2, P = dims[0], dims[1], 16
+    g = np.random.default_rng(21)
+    sv = np.array([8.0] * 6 + [5.0] * 6 + [2.0] * 4)
+    S = np.zeros((n1, n2, P))
+    for j in range(P):
+        U = np.linalg.qr(g.standard_normal((n1, sv.size)))[0]
+        V = np.linalg.qr(g.standard_normal((n2, sv.size)))[0]
+        S[:, :, j] = (U * sv) @ V.T
+    T = otr.build_transforms(dims, kinds)
+    X = otr.inverse(S.reshape(dims, order="F"), T)
+    Xs = X.astype(_np_dtype(prec)).astype(np.float64)
+    r, p, q, tau, seed = 16, 8, 2, 3.0, 4
+    plan = ht.Plan(dims, kinds, r=r, p=p, q=q, precision=prec, seed=seed)
+    out = plan.gnhtsvt(ht.to_device(Xs, plan.torch_dtype), tau, PEN["mcp"])
+    torch.cuda.synchronize()
+    om = otsvt.omegas(dims, kinds, r, p, seed=seed, round_to=_np_dtype(prec) if prec != "fp64" else None)
+    ref = otsvt.tsvt_randomized(Xs, tau, PEN["mcp"], T, r, p, q, om)
+    assert _rel(ht.from_device(out, dims), ref) < TOL[prec]
+
+
 @pytest.mark.parametrize("pen", list(PEN))
 def test_tsvt_fp64_config_small(ht, pen):
     """60x50x20 under DCT on mode 3, tubal rank 5 plus noise std 1e-3, r=5 p=5 q=1."""
