@@ -145,7 +145,10 @@ int ht_plan_info(const ht_plan* plan, int64_t* n_slices, int* width, int* kept);
 
 /* Offset and size in bytes of a named region of the workspace, for
  * inspecting intermediate results after a call: 0 transformed tensor A,
- * 1 sketch matrices Omega, 2 basis Q1 of the last CholeskyQR pass (n1 x l per
+ * 1 sketch matrices Omega (left unwritten by FP32 plans whose slices are all
+ * real with n1 >= 192, n1 a multiple of 4, n2 <= 512 and l <= 64: there the
+ * first product draws Omega in place),
+ * 2 basis Q1 of the last CholeskyQR pass (n1 x l per
  * slice; the final R2 correction is applied in the l x l space),
  * 3 B^T = A^T Q1 (n2 x l per slice), 4 K' = R2^{-1} U diag(w) U^T R2^{-T}
  * (l x l per slice), 5 Q1 K', 6 reconstructed transformed slices C,

@@ -846,10 +846,13 @@ int run_tsvt(const ht_plan* pl, const T* X, T* out, double tau, const double* ta
                            call, call_dev, ws_ptr<float>(pl, ws, WS_FEAT), wk1, s)))
       return rc;
   }
-  if ((rc = timed(pl, ST_OMEGA, s, [&] {
-         return launch_omega<T>(Om, nullptr, sd, nullptr, P, pl->max_n2l, call, call_dev, pl->stream_id, pl->seed, 0,
-                                s);
-       })))
+  // the streaming product draws Omega itself; every other path reads it
+  const OmegaKey okey{call, call_dev, pl->stream_id, pl->seed};
+  const bool om_inline = !fp64 && pl->nn_stream;
+  if (!om_inline && (rc = timed(pl, ST_OMEGA, s, [&] {
+                       return launch_omega<T>(Om, nullptr, sd, nullptr, P, pl->max_n2l, call, call_dev, pl->stream_id,
+                                              pl->seed, 0, s);
+                     })))
     return rc;
   auto sketch_nn = [&](const T* W, const int2* wk) {
     return timed(pl, ST_SKETCH_NN, s, [&] {
@@ -857,8 +860,8 @@ int run_tsvt(const ht_plan* pl, const T* X, T* out, double tau, const double* ta
       if (bf16)
         return launch_bf16_nn(Ah, (const float*)W, (float*)Y, sd, wk, items(pl, L), L.n, lmax, rows, gp1, s);
       if (!fp64 && pl->nn_stream)
-        return launch_mfma_nn_stream((const float*)A, (const float*)W, (float*)Y, sd, wk, items(pl, pl->it_nns),
-                                     pl->it_nns.n, lmax, pl->max_n2, gp1, s);
+        return launch_mfma_nn_stream((const float*)A, W == Om ? nullptr : (const float*)W, (float*)Y, sd, wk,
+                                     items(pl, pl->it_nns), pl->it_nns.n, lmax, pl->max_n2, gp1, okey, s);
       if (!fp64)
         return launch_mfma_nn((const float*)A, (const float*)W, (float*)Y, sd, wk, items(pl, L), L.n, lmax, rows, gp1,
                               s);

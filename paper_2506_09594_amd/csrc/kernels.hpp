@@ -83,8 +83,19 @@ int launch_mfma_nn(const float* A, const float* W, float* Y, const SliceDesc* sd
 int launch_mfma_tn(const float* A, const float* Q, float* Z, const SliceDesc* sd, const int2* wk, const int2* items,
                    int nitems, int lmax, int rows, double* gpart, hipStream_t s);
 constexpr int kStreamRows = 256, kStreamMaxK = 512;
+// Key of the Gaussian sketch draws (as launch_omega): call index (*call_dev
+// when set), stream base added to the tensor index, seed.
+struct OmegaKey {
+  uint32_t call;
+  const int32_t* call_dev;
+  uint32_t stream_base;
+  uint64_t seed;
+};
+// W == nullptr: the sketch Omega_s is drawn inside the product (the same values
+// launch_omega writes, rounded to FP32) from `key` instead of read.
 int launch_mfma_nn_stream(const float* A, const float* W, float* Y, const SliceDesc* sd, const int2* wk,
-                          const int2* items, int nitems, int lmax, int kmax, double* gpart, hipStream_t s);
+                          const int2* items, int nitems, int lmax, int kmax, double* gpart, const OmegaKey& key,
+                          hipStream_t s);
 // Reconstruction C = QK Bt^T on the matrix cores (FP32; items as launch_gemm_nt).
 int launch_mfma_nt(const float* X, const float* W, float* C, const SliceDesc* sd, const int2* wk, const int2* items,
                    int nitems, int lmax, hipStream_t s);

@@ -236,14 +236,17 @@ __global__ __launch_bounds__(64 * NW) void k_mfma_thin(const float* __restrict__
 // register buffers of U loads per lane are in flight at all times (the next
 // buffer is issued before the current one is consumed; loads past the end are
 // clamped to a valid address and their values zeroed), so each CU keeps about
-// 128 KB of reads outstanding.  The thin operand is staged in LDS whole.  The
+// 128 KB of reads outstanding.  The thin operand is staged in LDS whole; with
+// W null it is the Gaussian sketch, drawn here while the first loads of A are
+// in flight (element e = k + c n2 of Omega_s is draw e % 4 of group e / 4 of
+// the slice's key, as the sketch generator writes it).  The
 // four partial tiles are summed through one LDS tile, which then feeds the
 // coalesced store of Y and the Gram partials.
 template <int NB, int U>
 __global__ __launch_bounds__(512) void k_mfma_nn_stream(const float* __restrict__ Aall, const float* __restrict__ Wall,
                                                        float* __restrict__ Yall, const SliceDesc* __restrict__ sd,
                                                        const int2* __restrict__ wk, const int2* __restrict__ items,
-                                                       double* __restrict__ gpart) {
+                                                       double* __restrict__ gpart, OmegaKey key) {
   constexpr int RW = 2, KS = 4, VR = 4, NTH = 64 * RW * KS;
   constexpr int ROWS = 32 * VR * RW, LW = 32 * NB, RP = ROWS + 4;
   static_assert(ROWS == kStreamRows, "tile rows");
@@ -280,9 +283,24 @@ __global__ __launch_bounds__(512) void k_mfma_nn_stream(const float* __restrict_
     load(bufA, kb);
     load(bufB, kb + 2 * U);
   }
-  for (int f = tid; f < K * LW; f += NTH) {
-    const int k = f % K, c = f / K;
-    Ws[k * LW + c] = (c < l) ? W[k + (int64_t)c * K] : 0.0f;
+  if (W) {
+    for (int f = tid; f < K * LW; f += NTH) {
+      const int k = f % K, c = f / K;
+      Ws[k * LW + c] = (c < l) ? W[k + (int64_t)c * K] : 0.0f;
+    }
+  } else {
+    const uint32_t call = key.call_dev ? (uint32_t)(*key.call_dev) : key.call;
+    const int ne = K * l;
+    for (int gi = tid; gi < (ne + 3) / 4; gi += NTH) {
+      double z[4];
+      gaussian4((uint64_t)gi, (uint32_t)d.local, call, key.stream_base + (uint32_t)d.tensor, key.seed, z);
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int e = 4 * gi + u;
+        if (e < ne) Ws[(e % K) * LW + e / K] = (float)z[u];
+      }
+    }
+    for (int f = tid; f < K * (LW - l); f += NTH) Ws[(f % K) * LW + l + f / K] = 0.0f;
   }
   __syncthreads();
   f32x16 acc[VR][NB];
@@ -470,7 +488,8 @@ int launch_mfma_nn(const float* A, const float* W, float* Y, const SliceDesc* sd
 }
 
 int launch_mfma_nn_stream(const float* A, const float* W, float* Y, const SliceDesc* sd, const int2* wk,
-                          const int2* items, int nitems, int lmax, int kmax, double* gpart, hipStream_t s) {
+                          const int2* items, int nitems, int lmax, int kmax, double* gpart, const OmegaKey& key,
+                          hipStream_t s) {
   if (lmax > 64 || kmax > kStreamMaxK || kmax < 1) HT_FAIL(HT_ERR_UNSUPPORTED, "streaming product: bad width or n2");
   if (reinterpret_cast<uintptr_t>(A) % 16 != 0 || reinterpret_cast<uintptr_t>(Y) % 16 != 0)
     HT_FAIL(HT_ERR_UNSUPPORTED, "streaming product: unaligned operands");
@@ -478,7 +497,7 @@ int launch_mfma_nn_stream(const float* A, const float* W, float* Y, const SliceD
   auto launch = [&](auto kern, size_t lds, size_t lds_max) -> int {
     int rc = ensure_dynamic_lds((const void*)kern, lds_max);
     if (rc) return rc;
-    hipLaunchKernelGGL(kern, dim3((unsigned)nitems), dim3(512), lds, s, A, W, Y, sd, wk, items, gpart);
+    hipLaunchKernelGGL(kern, dim3((unsigned)nitems), dim3(512), lds, s, A, W, Y, sd, wk, items, gpart, key);
     HT_CHECK_LAUNCH();
     return HT_OK;
   };
