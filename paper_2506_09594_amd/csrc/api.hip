@@ -948,6 +948,9 @@ int run_tsvt(const ht_plan* pl, const T* X, T* out, double tau, const double* ta
   }
   // C = (Q1 K') Bt^T, then the inverse transform
   if ((rc = timed(pl, ST_RECON_QK, s, [&] {
+         if (!fp64 && lmax <= 64)
+           return launch_mfma_qk((const float*)Y, (const float*)K, (float*)QK, sd, wk_final, items(pl, pl->it_qk),
+                                 pl->it_qk.n, lmax, s);
          return launch_recon_qk<T>(Y, K, QK, sd, wk_final, items(pl, pl->it_qk), pl->it_qk.n, lmax, s);
        })))
     return rc;

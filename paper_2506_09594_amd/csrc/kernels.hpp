@@ -96,6 +96,10 @@ struct OmegaKey {
 int launch_mfma_nn_stream(const float* A, const float* W, float* Y, const SliceDesc* sd, const int2* wk,
                           const int2* items, int nitems, int lmax, int kmax, double* gpart, const OmegaKey& key,
                           hipStream_t s);
+// Q1 K' on the matrix cores (FP32, widths up to 64; items as launch_recon_qk:
+// slice and first row of a 64-row tile).
+int launch_mfma_qk(const float* Q, const float* K, float* QK, const SliceDesc* sd, const int2* wk, const int2* items,
+                   int nitems, int lmax, hipStream_t s);
 // Reconstruction C = QK Bt^T on the matrix cores (FP32; items as launch_gemm_nt).
 int launch_mfma_nt(const float* X, const float* W, float* C, const SliceDesc* sd, const int2* wk, const int2* items,
                    int nitems, int lmax, hipStream_t s);

@@ -452,6 +452,63 @@ __global__ __launch_bounds__(256) void k_mfma_nt(const float* __restrict__ Xall,
   }
 }
 
+// Q1 K' (n1 x l per slice) on the matrix cores, FP32, l <= KMAX <= 64: one
+// 64-row tile per work item (slice, first row), wavefront w computing the
+// 32 x 32 block (rows 32 (w % 2), columns 32 (w / 2)); lane t supplies
+// Q1[row t % 32][k] and K'[k][column t % 32] at k = 2 s + t / 32, and the
+// block goes through LDS for coalesced 16-byte column stores.
+template <int KMAX>
+__global__ __launch_bounds__(4 * KMAX) void k_mfma_qk(const float* __restrict__ Qall, const float* __restrict__ Kall,
+                                                      float* __restrict__ QKall, const SliceDesc* __restrict__ sd,
+                                                      const int2* __restrict__ wk, const int2* __restrict__ items) {
+  constexpr int NT = 4 * KMAX, TP = 68, NS = KMAX / 2;
+  __shared__ __align__(16) float Ts[KMAX * TP];  // [column][row]
+  const int2 item = items[blockIdx.x];
+  const int s = item.x, row0 = item.y;
+  const SliceDesc d = sd[s];
+  const int l = slice_width(d, wk, s);
+  if (l <= 0) return;  // slice not part of this pass
+  const int m = d.n1;
+  const float* Q = Qall + d.y;
+  const float* Kq = Kall + d.kq;  // K' column-major, l x l
+  float* QK = QKall + d.y;
+  const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+  const int li = lane % 32, h = lane / 32;
+  const int br = 32 * (wave % 2), bc = 32 * (wave / 2);
+  const int gr = row0 + br + li, gc = bc + li;
+  const bool rok = gr < m, cok = gc < l;
+  float av[NS], bv[NS];
+#pragma unroll
+  for (int st = 0; st < NS; ++st) {
+    const int k = 2 * st + h;
+    av[st] = (k < l && rok) ? Q[gr + (int64_t)k * m] : 0.0f;
+    bv[st] = (k < l && cok) ? Kq[k + gc * l] : 0.0f;
+  }
+  f32x16 acc;
+#pragma unroll
+  for (int r = 0; r < 16; ++r) acc[r] = 0.0f;
+#pragma unroll
+  for (int st = 0; st < NS; ++st)
+    if (2 * st < l) acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av[st], bv[st], acc, 0, 0, 0);
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    const int i = 8 * (r / 4) + 4 * h + (r % 4);
+    Ts[(bc + li) * TP + br + i] = acc[r];
+  }
+  __syncthreads();
+  const int rows = min(64, m - row0);
+  const bool vec = (m % 4 == 0) && (d.y % 4 == 0);
+  for (int f = threadIdx.x; f < l * 16; f += NT) {
+    const int c = f / 16, q = (f % 16) * 4;
+    float* dst = QK + row0 + q + (int64_t)c * m;
+    if (vec && q + 3 < rows)
+      *reinterpret_cast<f32x4*>(dst) = *reinterpret_cast<const f32x4*>(Ts + c * TP + q);
+    else
+      for (int e = 0; e < 4; ++e)
+        if (q + e < rows) dst[e] = Ts[c * TP + q + e];
+  }
+}
+
 template <int NB, int NW, bool TRANS>
 int launch_thin(const float* A, const float* W, float* Y, const SliceDesc* sd, const int2* wk, const int2* items,
                 int nitems, double* gpart, hipStream_t s) {
@@ -516,6 +573,19 @@ int launch_mfma_nt(const float* X, const float* W, float* C, const SliceDesc* sd
     hipLaunchKernelGGL(k_mfma_nt<64>, grid, dim3(256), 0, s, X, W, C, sd, wk, items);
   else
     hipLaunchKernelGGL(k_mfma_nt<HT_MAX_WIDTH>, grid, dim3(256), 0, s, X, W, C, sd, wk, items);
+  HT_CHECK_LAUNCH();
+  return HT_OK;
+}
+
+int launch_mfma_qk(const float* Q, const float* K, float* QK, const SliceDesc* sd, const int2* wk, const int2* items,
+                   int nitems, int lmax, hipStream_t s) {
+  if (lmax > 64) HT_FAIL(HT_ERR_UNSUPPORTED, "matrix-core Q1 K': width above 64");
+  if (nitems == 0) return HT_OK;
+  const dim3 grid((unsigned)nitems);
+  if (lmax <= 32)
+    hipLaunchKernelGGL(k_mfma_qk<32>, grid, dim3(128), 0, s, Q, K, QK, sd, wk, items);
+  else
+    hipLaunchKernelGGL(k_mfma_qk<64>, grid, dim3(256), 0, s, Q, K, QK, sd, wk, items);
   HT_CHECK_LAUNCH();
   return HT_OK;
 }
