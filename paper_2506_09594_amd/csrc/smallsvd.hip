@@ -119,6 +119,7 @@ __global__ __launch_bounds__(NT) void k_smallsvd(double* __restrict__ g2_all, co
   extern __shared__ __align__(16) unsigned char smem_raw[];
   __shared__ double s_scr;
   __shared__ int s_kept, s_flag[3];             // step flags, three-way rotation
+  __shared__ int s_open;                        // some pair of the current W still rotates
   __shared__ JRot s_jr[2][LB / 2];              // rotations per pair, by step parity
 
   const int j = slices ? slices[blockIdx.x].x : (int)blockIdx.x;  // a class of slices, or all
@@ -345,6 +346,21 @@ __global__ __launch_bounds__(NT) void k_smallsvd(double* __restrict__ g2_all, co
       still = 0;
     } else if (++still >= m) {
       break;
+    } else if (still == 1) {
+      // The first quiet step after rotations: W is unchanged from here on
+      // unless some pair passes the rotation test, so testing every pair now
+      // decides what the remaining m - 1 steps of the check would find.
+      if (tid == 0) s_open = 0;
+      __syncthreads();
+      for (int idx = tid; idx < ll; idx += NT) {
+        const int p = idx / l, q = idx % l;
+        if (p < q) {
+          const double apq = Wc[p * gp + q];
+          if (fabs(apq) > abs_tol && apq * apq > abs_tol * abs_tol * fabs(Wc[p * gp + p] * Wc[q * gp + q])) s_open = 1;
+        }
+      }
+      __syncthreads();
+      if (s_open == 0) break;
     }
     step = ns;
   }
