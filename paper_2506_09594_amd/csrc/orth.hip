@@ -85,13 +85,23 @@ __global__ __launch_bounds__(TR) void k_orth_fused(T* __restrict__ Yall, int whi
   for (int t = 0; t < nparts; ++t) {
     double v[LB];
 #pragma unroll
-    for (int a = 0; a < LB; ++a) v[a] = (a < l) ? part[(int64_t)t * ll + a * l + bcol] : 0.0;
+    for (int a = 0; a < LB; ++a) {
+      const double pv = part[(int64_t)t * ll + (a < l ? a : l - 1) * l + bcol];
+      v[a] = (a < l) ? pv : 0.0;
+    }
 #pragma unroll
     for (int a = 0; a < LB; ++a) g[a] += v[a];
   }
+  // every load unconditional (row and column clamped into the tile) so that
+  // all of them are in flight at once; a guarded load compiles to a branch
+  // and a wait per column
+  const int lrow = valid ? lane : rows - 1;
   double y[LB];
 #pragma unroll
-  for (int c = 0; c < LB; ++c) y[c] = (c < l && valid) ? (double)Y[lane + (int64_t)c * ldy] : 0.0;
+  for (int c = 0; c < LB; ++c) {
+    const T v = Y[lrow + (int64_t)(c < l ? c : l - 1) * ldy];
+    y[c] = (c < l && valid) ? (double)v : 0.0;
+  }
 
   // pivot threshold from the largest diagonal entry
   double dmax = (lane < l) ? g[0] : 0.0;
