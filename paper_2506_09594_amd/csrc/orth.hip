@@ -195,9 +195,27 @@ __global__ __launch_bounds__(TR) void k_orth_apply(T* __restrict__ Yall, int whi
   double* gout = gout_all ? gout_all + o.g2 + (int64_t)(row0 / TR) * l * l : nullptr;
   const int i = threadIdx.x;
   const bool valid = i < rows;
-  for (int idx = i; idx < ll; idx += TR) Ri[idx] = Rg[idx];
+  // loads in batches of eight with clamped indices, so that each batch is in
+  // flight together (a guarded load in a runtime loop waits once per element)
+  constexpr int LBT = 8;
+  for (int idx0 = i; idx0 < ll; idx0 += LBT * TR) {
+    double v[LBT];
+#pragma unroll
+    for (int u = 0; u < LBT; ++u) v[u] = Rg[min(idx0 + u * TR, ll - 1)];
+#pragma unroll
+    for (int u = 0; u < LBT; ++u)
+      if (idx0 + u * TR < ll) Ri[idx0 + u * TR] = v[u];
+  }
   double* yi = S + i * gp;
-  for (int c = 0; c < l; ++c) yi[c] = valid ? (double)Y[i + (int64_t)c * ldy] : 0.0;
+  const int lrow = valid ? i : rows - 1;
+  for (int c0 = 0; c0 < l; c0 += LBT) {
+    T v[LBT];
+#pragma unroll
+    for (int u = 0; u < LBT; ++u) v[u] = Y[lrow + (int64_t)min(c0 + u, l - 1) * ldy];
+#pragma unroll
+    for (int u = 0; u < LBT; ++u)
+      if (c0 + u < l) yi[c0 + u] = valid ? (double)v[u] : 0.0;
+  }
   __syncthreads();
   for (int c = l - 1; c >= 0; --c) {
     double t0 = 0.0, t1 = 0.0;
