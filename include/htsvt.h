@@ -55,10 +55,15 @@ enum {
 
 /* Transform of one mode k = 3..d (the matrices U_{n_k} of the transform L). */
 enum {
-  HT_DCT2_ORTHO = 0,   /* orthonormal DCT-II, alpha = 1 */
-  HT_DFT_UNITARY = 1,  /* unitary DFT, alpha = 1; must be the kind of every mode 3..d
-                          (complex slices; see ht_plan_desc) */
-  HT_CUSTOM_REAL = 2   /* caller-supplied real U with U U^T = alpha I */
+  HT_DCT2_ORTHO = 0,      /* orthonormal DCT-II, alpha = 1 */
+  HT_DFT_UNITARY = 1,     /* unitary DFT F[k][m] = exp(-2 pi i k m / n) / sqrt(n), alpha = 1 */
+  HT_CUSTOM_REAL = 2,     /* caller-supplied real U with U U^T = alpha I */
+  HT_DFT_UNNORMALIZED = 3 /* plain DFT F[k][m] = exp(-2 pi i k m / n), alpha = n (the FFT of
+                             the experiments, Sec. VI); the inverse is F^H / n.  The threshold
+                             tau applies unscaled to the transform-domain singular values.
+                             The two DFT kinds may be mixed across modes, but a DFT kind must
+                             be the transform of every mode 3..d (complex slices; see
+                             ht_plan_desc) */
 };
 
 /* Arithmetic of the path. */
@@ -69,17 +74,21 @@ enum {
                          with FP32 accumulation; Gram/Cholesky/eigen FP64 */
 };
 
-/* Penalty Phi of the low-rank term or psi of the sparse term.  Every penalty is
- * normalized to slope 1 at 0 except LOG; parameters are absolute:
+/* Penalty Phi of the low-rank term or psi of the sparse term (the family of the
+ * Assumption on Phi, Sec. IV-A).  Every penalty is normalized to slope 1 at 0
+ * except LOG; parameters are absolute except FIRM's ratio:
  *   L1         phi(x) = x
  *   MCP        phi(x) = x - x^2/(2 p0) (x <= p0), p0/2 beyond          (p0 = gamma > 0)
  *   SCAD       phi(x) = x (x <= p1), (2 p0 p1 x - x^2 - p1^2)/(2 (p0-1) p1) (x <= p0 p1),
  *              (p0+1) p1 / 2 beyond                                   (p0 = a > 2, p1 = b > 0)
  *   LOG        phi(x) = log(1 + x / p0)                                (p0 = eps > 0)
  *   CAPPED_L1  phi(x) = min(x, p0)                                     (p0 = theta > 0)
+ *   FIRM       firm shrinkage (Gao-Bruce) with thresholds (mu, a mu):    (p0 = a > 1)
+ *              Prox(v) = 0 (v <= mu), a (v - mu)/(a - 1) (v <= a mu), v beyond; the
+ *              proximity operator of MCP with gamma = a mu at the same mu
  * Prox_{phi,mu}(v) = argmin_x mu*phi(x) + (x - v)^2/2 (the proximity operator of
  * Sec. IV-B); ties between two global minimizers resolve to the smaller |x|. */
-enum { HT_PEN_L1 = 0, HT_PEN_MCP = 1, HT_PEN_SCAD = 2, HT_PEN_LOG = 3, HT_PEN_CAPPED_L1 = 4 };
+enum { HT_PEN_L1 = 0, HT_PEN_MCP = 1, HT_PEN_SCAD = 2, HT_PEN_LOG = 3, HT_PEN_CAPPED_L1 = 4, HT_PEN_FIRM = 5 };
 
 typedef struct {
   int kind;
@@ -131,9 +140,22 @@ const char* ht_last_error(void);
 
 /* Create a plan on the current HIP device.  Validates the description and
  * uploads the transform tables.  Errors: INVALID_ARG (bad sizes/ranks/kinds),
- * UNSUPPORTED (a valid request this build does not implement), HIP, ALLOC. */
+ * UNSUPPORTED (a valid request this build does not implement), HIP, ALLOC.
+ * The plan is the library's device context: it records the device that was
+ * current at creation and owns the tables there; every later call on the plan
+ * must run with that device current (INVALID_ARG otherwise). */
 int ht_plan_create(const ht_plan_desc* desc, ht_plan** out);
 int ht_plan_destroy(ht_plan* plan);
+
+/* HIP device ordinal the plan was created on. */
+int ht_plan_device(const ht_plan* plan, int* device);
+
+/* Non-finite detection.  Every t-SVT call records, per slice, whether the FP64
+ * Gram matrices of its sketch held a NaN or an infinity (any non-finite entry
+ * of the transformed slice reaches them).  This call waits for the stream, and
+ * returns HT_ERR_NONFINITE when some slice of the last call on this workspace
+ * was flagged (n_bad, optional: how many), HT_OK otherwise. */
+int ht_plan_status(const ht_plan* plan, const void* workspace, void* stream, int64_t* n_bad);
 
 /* Bytes of device workspace needed by ht_gnhtsvt on this plan. */
 int ht_plan_workspace_size(const ht_plan* plan, size_t* bytes);
@@ -264,9 +286,13 @@ int ht_plan_graph_enable(ht_plan* plan, int on);
  * l = clamp(ceil(s) + p, p + 1, l_fix) columns and keeps k = min(k_fix, l)
  * values (l_fix, k_fix: the plan's fixed width and kept count).  It is redone at
  * the fixed width when l < l_fix and either every kept value survived
- * (kept >= k) or ||A_j||^2 - ||B_j||^2 > (min(n1, n2) - l) tau^2 (the
- * residual then certainly holds a value above tau), so the fixed-width
- * method stays the fallback.  The first call after a reset uses the fixed widths.
+ * (kept >= k) or ||A_j||^2 - ||B_j||^2 > (min(n1, n2) - l) t0^2, where t0 =
+ * sup{v : Prox_{Phi,tau}(v) = 0} is the penalty's zero threshold (tau for L1,
+ * FIRM and MCP with gamma > tau; sqrt(gamma tau) for MCP with gamma <= tau;
+ * min(tau, sqrt(2 tau theta)) for capped-L1; by bisection on the prox for SCAD
+ * and LOG): the residual then certainly holds a value that would survive.  The
+ * fixed-width method stays the fallback.  The first call after a reset uses the
+ * fixed widths.
  *
  * Parameters: one flat FP32 device vector of ht_mlp_param_count() entries,
  * W1 (128 x 32, row-major), b1 (128), W2 (128 x 128), b2 (128), W3 (128), b3.
@@ -347,7 +373,9 @@ typedef struct {
 typedef struct {
   int32_t iteration;    /* iterations completed */
   double mu;            /* mu for the next iteration */
-  double dL, dE, resid; /* stopping terms of the last iteration (inf-norms) */
+  double dL, dE, resid; /* stopping terms of the last iteration (inf-norms; NaN propagates) */
+  double rse;           /* ||L - L*||_F / ||L*||_F after the last ht_admm_iterate call
+                           against the registered ground truth L* (NaN if none) */
 } ht_admm_stats;
 
 /* Workspace for the ADMM calls (includes the t-SVT workspace). */
@@ -364,7 +392,15 @@ int ht_admm_iterate(ht_plan* plan, const ht_admm_params* prm, const void* M, con
                     void* L, void* E, void* Y, int n_iter, void* workspace, size_t workspace_bytes,
                     void* stream);
 
-/* Copy the solver scalars to the host (synchronizes the stream). */
+/* Register a ground truth L* (device, storage type, N elements, caller-owned;
+ * NULL clears it): every later ht_admm_iterate call ends with the relative
+ * recovery error ||L - L*||_F / ||L*||_F (the RSE of the experiments), summed in
+ * FP64 in a fixed order, into the solver state. */
+int ht_admm_set_truth(ht_plan* plan, const void* truth);
+
+/* Copy the solver scalars to the host (synchronizes the stream).  Returns
+ * HT_ERR_NONFINITE (with *out filled) when a stopping term is NaN or infinite
+ * or a slice of the last t-SVT was flagged non-finite. */
 int ht_admm_get_stats(const ht_plan* plan, const void* workspace, void* stream, ht_admm_stats* out);
 
 #ifdef __cplusplus

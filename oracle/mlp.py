@@ -31,6 +31,8 @@ import math
 
 import numpy as np
 
+from . import prox as proxmod
+
 N_IN, N_H = 32, 128
 SHAPES = {"W1": (N_H, N_IN), "b1": (N_H,), "W2": (N_H, N_H), "b2": (N_H,), "W3": (1, N_H), "b3": (1,)}
 ORDER = ["W1", "b1", "W2", "b2", "W3", "b3"]
@@ -183,12 +185,17 @@ def width_from_prediction(z, p, l_fix, k_fix):
     return l, int(min(k_fix, l))
 
 
-def needs_fallback(l, k, kept, anorm2, sigma, tau, l_fix, n_min):
+def needs_fallback(l, k, kept, anorm2, sigma, tau, l_fix, n_min, penalty=("l1", ())):
     """True when a slice sketched at width l < l_fix must be redone at l_fix
-    (n_min = min(n1, n2))."""
+    (n_min = min(n1, n2)): (i) every kept value survived the shrinkage, or (ii)
+    the residual energy ||A||^2 - ||B||^2 exceeds (n_min - l) t0^2 with t0 the
+    penalty's zero threshold (a value above t0 survives the prox), so the
+    residual certainly holds a value that would survive."""
     if l >= l_fix:
         return False
     if kept >= k:
         return True
+    kind, params = penalty
+    t0 = proxmod.zero_threshold(kind, tau, params)
     tail = anorm2 - float(np.sum(np.asarray(sigma[:l], dtype=np.float64) ** 2))
-    return tail > (n_min - l) * tau * tau
+    return tail > (n_min - l) * t0 * t0

@@ -19,20 +19,36 @@ smaller magnitude).  Penalties and their parameters (all absolute):
               slope at 0 is 1 like the other penalties; a > 2)
   log(e)      phi(x) = log(1 + x/e)
   capped_l1(t) phi(x) = min(x, t)
+  firm(a)     firm shrinkage with thresholds (mu, a mu), a > 1 (Gao-Bruce
+              1997, named among the penalties of the Assumption on Phi): the
+              penalty is MCP with gamma = a mu at the threshold mu it is used
+              with, so phi depends on mu (reading: the paper lists firm
+              thresholding among its proximity operators; its two thresholds
+              scale with the one the solver sets)
+
+The zero threshold t0 = sup{v >= 0 : Prox(v) = 0} of every penalty is found
+by bisection on prox_scalar itself (the prox is nondecreasing).
 
 Pins: dense 1-D brute force of the defining minimization for every penalty and
-parameter set, l1 = soft threshold, monotonicity (tests/test_oracle_prox.py).
+parameter set, l1 = soft threshold, firm = the Gao-Bruce formula, monotonicity,
+closed forms of the zero threshold where the prox has one
+(tests/test_oracle_prox.py).
 """
 import math
 
 import numpy as np
 
-PENALTIES = ("l1", "mcp", "scad", "log", "capped_l1")
+PENALTIES = ("l1", "mcp", "scad", "log", "capped_l1", "firm")
 
 
-def phi(kind, x, params=()):
-    """Penalty value at x >= 0."""
+def phi(kind, x, params=(), mu=None):
+    """Penalty value at x >= 0 (firm needs the threshold mu it is used with)."""
     x = abs(float(x))
+    if kind == "firm":
+        if mu is None:
+            raise ValueError("the firm penalty depends on the threshold mu")
+        (a,) = params
+        return phi("mcp", x, (a * mu,))
     if kind == "l1":
         return x
     if kind == "mcp":
@@ -55,12 +71,15 @@ def phi(kind, x, params=()):
 
 
 def _objective(kind, params, mu, v, x):
-    return mu * phi(kind, x, params) + 0.5 * (x - v) ** 2
+    return mu * phi(kind, x, params, mu) + 0.5 * (x - v) ** 2
 
 
 def _candidates(kind, params, mu, v):
     """Candidate minimizers on [0, inf) for v >= 0."""
     c = [0.0, v]
+    if kind == "firm":
+        (a,) = params
+        return _candidates("mcp", (a * mu,), mu, v)
     if kind == "l1":
         c.append(max(v - mu, 0.0))
     elif kind == "mcp":
@@ -107,6 +126,27 @@ def prox_scalar(kind, v, mu, params=()):
         if best_f is None or f < best_f - 1e-15 * max(1.0, abs(best_f)):
             best_x, best_f = x, f
     return s * best_x
+
+
+def zero_threshold(kind, mu, params=()):
+    """t0 = sup{v >= 0 : Prox_{phi,mu}(v) = 0}, by bisection on prox_scalar
+    (doubling from mu until the prox is nonzero, then halving the bracket)."""
+    if mu <= 0.0:
+        return 0.0
+    lo, hi = 0.0, float(mu)
+    for _ in range(64):
+        if prox_scalar(kind, hi, mu, params) != 0.0:
+            break
+        lo, hi = hi, 2.0 * hi
+    for _ in range(200):
+        mid = 0.5 * (lo + hi)
+        if not lo < mid < hi:
+            break
+        if prox_scalar(kind, mid, mu, params) == 0.0:
+            lo = mid
+        else:
+            hi = mid
+    return lo
 
 
 def prox(kind, v, mu, params=()):

@@ -58,7 +58,7 @@ def objective(G, A, tau, penalty, transforms):
     total = 0.0
     for j in range(LG.shape[2]):
         for s in np.linalg.svd(LG[:, :, j], compute_uv=False):
-            total += proxmod.phi(kind, s, params)
+            total += proxmod.phi(kind, s, params, tau)
     return tau * total / tr.rho(transforms) + 0.5 * np.linalg.norm((G - A).ravel()) ** 2
 
 

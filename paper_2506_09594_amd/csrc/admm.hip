@@ -9,9 +9,13 @@ namespace {
 
 __device__ __forceinline__ unsigned long long dbits(double x) { return (unsigned long long)__double_as_longlong(x); }
 
+// Maximum that keeps a NaN (fmax drops it): a NaN iterate must show in the
+// stopping terms instead of letting a stopping rule converge on it.
+__device__ __forceinline__ double nan_max(double a, double b) { return (b > a || b != b) ? b : a; }
+
 __device__ __forceinline__ double wave_max(double v) {
 #pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
+  for (int off = 32; off > 0; off >>= 1) v = nan_max(v, __shfl_xor(v, off, 64));
   return v;
 }
 
@@ -47,9 +51,9 @@ __global__ __launch_bounds__(256) void k_admm_update(const T* __restrict__ M, co
       en = h;
     const double r = m - ln - en;
     const double yn = y + mu * r;
-    mdl = fmax(mdl, fabs(ln - lo));
-    mde = fmax(mde, fabs(en - e));
-    mres = fmax(mres, fabs(r));
+    mdl = nan_max(mdl, fabs(ln - lo));
+    mde = nan_max(mde, fabs(en - e));
+    mres = nan_max(mres, fabs(r));
     L[i] = (T)ln;
     E[i] = (T)en;
     Y[i] = (T)yn;
@@ -69,13 +73,15 @@ __global__ __launch_bounds__(256) void k_admm_update(const T* __restrict__ M, co
   if (threadIdx.x == 0) {
     double a = red[0][0], b = red[1][0], c = red[2][0];
     for (int w = 1; w < (int)(blockDim.x / 64); ++w) {
-      a = fmax(a, red[0][w]);
-      b = fmax(b, red[1][w]);
-      c = fmax(c, red[2][w]);
+      a = nan_max(a, red[0][w]);
+      b = nan_max(b, red[1][w]);
+      c = nan_max(c, red[2][w]);
     }
-    atomicMax(&st->red_dL, dbits(a));
-    atomicMax(&st->red_dE, dbits(b));
-    atomicMax(&st->red_res, dbits(c));
+    // the values are >= 0 or a NaN with the sign bit clear (fabs), so the bit
+    // patterns order like the values with NaN above +inf
+    atomicMax(&st->red_dL, dbits(fabs(a)));
+    atomicMax(&st->red_dE, dbits(fabs(b)));
+    atomicMax(&st->red_res, dbits(fabs(c)));
   }
 }
 
@@ -96,6 +102,50 @@ __global__ void k_admm_reset(AdmmState* st, double mu0) {
   st->pad0 = 0;
   st->dL = st->dE = st->resid = 0.0;
   st->red_dL = st->red_dE = st->red_res = 0ull;
+  st->rse = __longlong_as_double(0x7ff8000000000000ll);
+}
+
+// RSE against the ground truth: block b sums (L - L*)^2 and L*^2 over its
+// grid-stride share in FP64 (fixed order within the block), the last kernel
+// adds the block partials in index order.
+template <typename T>
+__global__ __launch_bounds__(256) void k_rse_part(const T* __restrict__ L, const T* __restrict__ truth, int64_t N,
+                                                  double* __restrict__ part) {
+  double e2 = 0.0, t2 = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < N; i += (int64_t)gridDim.x * blockDim.x) {
+    const double t = (double)truth[i], d = (double)L[i] - t;
+    e2 = fma(d, d, e2);
+    t2 = fma(t, t, t2);
+  }
+  __shared__ double red[2][256];
+  red[0][threadIdx.x] = e2;
+  red[1][threadIdx.x] = t2;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h) {
+      red[0][threadIdx.x] += red[0][threadIdx.x + h];
+      red[1][threadIdx.x] += red[1][threadIdx.x + h];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    part[2 * blockIdx.x] = red[0][0];
+    part[2 * blockIdx.x + 1] = red[1][0];
+  }
+}
+
+__global__ void k_rse_final(const double* __restrict__ part, int nblocks, AdmmState* st) {
+  if (threadIdx.x != 0) return;
+  double e2 = 0.0, t2 = 0.0;
+  for (int b = 0; b < nblocks; ++b) {
+    e2 += part[2 * b];
+    t2 += part[2 * b + 1];
+  }
+  st->rse = sqrt(e2) / sqrt(t2);
+}
+
+__global__ void k_rse_none(AdmmState* st) {
+  if (threadIdx.x == 0) st->rse = __longlong_as_double(0x7ff8000000000000ll);
 }
 
 unsigned elementwise_blocks(int64_t N) {
@@ -133,6 +183,24 @@ int launch_admm_reset(AdmmState* st, double mu0, hipStream_t s) {
   HT_CHECK_LAUNCH();
   return HT_OK;
 }
+
+template <typename T>
+int launch_admm_rse(const T* L, const T* truth, int64_t N, double* part, int nblocks, AdmmState* st, hipStream_t s) {
+  if (!truth) {
+    hipLaunchKernelGGL(k_rse_none, dim3(1), dim3(64), 0, s, st);
+    HT_CHECK_LAUNCH();
+    return HT_OK;
+  }
+  const int nb = (int)std::min<int64_t>(std::max<int64_t>(ceil_div(N, 256), 1), nblocks);
+  hipLaunchKernelGGL(k_rse_part<T>, dim3(nb), dim3(256), 0, s, L, truth, N, part);
+  HT_CHECK_LAUNCH();
+  hipLaunchKernelGGL(k_rse_final, dim3(1), dim3(64), 0, s, part, nb, st);
+  HT_CHECK_LAUNCH();
+  return HT_OK;
+}
+
+template int launch_admm_rse<float>(const float*, const float*, int64_t, double*, int, AdmmState*, hipStream_t);
+template int launch_admm_rse<double>(const double*, const double*, int64_t, double*, int, AdmmState*, hipStream_t);
 
 template int launch_admm_input<float>(const float*, const float*, const float*, const AdmmState*, float*, int64_t,
                                       hipStream_t);

@@ -49,7 +49,10 @@ using namespace ht;
 
 // Named regions of the workspace (for introspection by the tests).
 enum { WS_A = 0, WS_OMEGA, WS_Y, WS_Z, WS_K, WS_QK, WS_C, WS_LNEW, WS_XIN, WS_STATE, WS_GP1, WS_GP2, WS_WK, WS_CALL,
-       WS_WK2, WS_WKF, WS_SIG, WS_KEPT, WS_ANORM, WS_FEAT, WS_LSTATE, WS_COUNT };
+       WS_WK2, WS_WKF, WS_SIG, WS_KEPT, WS_ANORM, WS_FEAT, WS_LSTATE, WS_STATUS, WS_RED, WS_COUNT };
+
+// Block partials of the RSE reduction of the solver (two doubles per block).
+constexpr int kRseBlocks = 1024;
 
 // Optional per-stage timing with HIP events recorded on the launch stream.
 enum { ST_TRANSFORM_FWD = 0, ST_OMEGA, ST_SKETCH_NN, ST_CHOLQR, ST_SKETCH_TN, ST_SMALLSVD, ST_RECON_QK, ST_RECON_NT,
@@ -163,6 +166,7 @@ struct ht_plan {
   int learn_mode;            // 0 off, 1 track (fixed widths, features recorded), 2 predicted widths
   const float* learn_theta;  // network parameters (device, caller-owned)
   int force_fallback;        // redo every predicted slice at the fixed width
+  const void* truth;         // ground truth of the solver's RSE (device, caller-owned) or null
 };
 
 namespace {
@@ -188,6 +192,9 @@ int check_penalty(const ht_penalty* pen) {
       return HT_OK;
     case HT_PEN_CAPPED_L1:
       if (!(a > 0.0) || !std::isfinite(a)) HT_FAIL(HT_ERR_INVALID_ARG, "CAPPED_L1 needs theta = p0 > 0");
+      return HT_OK;
+    case HT_PEN_FIRM:
+      if (!(a > 1.0) || !std::isfinite(a)) HT_FAIL(HT_ERR_INVALID_ARG, "FIRM needs the threshold ratio a = p0 > 1");
       return HT_OK;
     default:
       HT_FAIL(HT_ERR_INVALID_ARG, "unknown penalty kind");
@@ -252,9 +259,10 @@ int add_tensor(const ht_plan_desc* d, std::vector<double>& tab, TensorHost& t) {
   t.k = std::min(d->r, t.l);
   if (t.l > HT_MAX_WIDTH) HT_FAIL(HT_ERR_UNSUPPORTED, "sketch width min(r+p, n1, n2) above HT_MAX_WIDTH");
   int ndft = 0;
-  for (int m = 0; m < d->order - 2; ++m) ndft += d->transform[m + 2] == HT_DFT_UNITARY;
+  for (int m = 0; m < d->order - 2; ++m)
+    ndft += d->transform[m + 2] == HT_DFT_UNITARY || d->transform[m + 2] == HT_DFT_UNNORMALIZED;
   if (ndft > 0 && ndft != d->order - 2)
-    HT_FAIL(HT_ERR_UNSUPPORTED, "DFT_UNITARY must be the transform of every mode 3..d (no mixing with real kinds)");
+    HT_FAIL(HT_ERR_UNSUPPORTED, "a DFT must be the transform of every mode 3..d (no mixing with real kinds)");
   t.cplx = ndft > 0;
   if (t.cplx && 2 * t.l > HT_MAX_WIDTH)
     HT_FAIL(HT_ERR_UNSUPPORTED, "complex slices are sketched through their real embedding: need 2 l <= HT_MAX_WIDTH");
@@ -285,9 +293,12 @@ int add_tensor(const ht_plan_desc* d, std::vector<double>& tab, TensorHost& t) {
         }
       if (!(alpha > 0.0) || err > 1e-10 * alpha)
         HT_FAIL(HT_ERR_INVALID_ARG, "CUSTOM_REAL matrix must satisfy U U^T = alpha I");
-    } else if (kind == HT_DFT_UNITARY) {
-      // interleaved (re, im): forward F[k][m] = exp(-2 pi i k m / n) / sqrt(n), inverse F^H
-      const double sc = 1.0 / std::sqrt((double)n);
+    } else if (kind == HT_DFT_UNITARY || kind == HT_DFT_UNNORMALIZED) {
+      // interleaved (re, im): forward F[k][m] = exp(-2 pi i k m / n) s_f, inverse
+      // F^H s_i with (s_f, s_i) = (1/sqrt n, 1/sqrt n) unitary, (1, 1/n) unnormalized
+      const bool unit = kind == HT_DFT_UNITARY;
+      const double sc = unit ? 1.0 / std::sqrt((double)n) : 1.0;
+      const double sci = unit ? sc : 1.0 / n;
       t.fwd.n[m] = t.inv.n[m] = n;
       t.fwd.stride[m] = t.inv.stride[m] = stride;
       stride *= n;
@@ -302,8 +313,8 @@ int add_tensor(const ht_plan_desc* d, std::vector<double>& tab, TensorHost& t) {
       for (int a = 0; a < n; ++a)
         for (int b = 0; b < n; ++b) {  // conj(F[b][a])
           const double ang = -2.0 * M_PI * (double)((int64_t)b * a % n) / n;
-          tab.push_back(std::cos(ang) * sc);
-          tab.push_back(-std::sin(ang) * sc);
+          tab.push_back(std::cos(ang) * sci);
+          tab.push_back(-std::sin(ang) * sci);
         }
       continue;
     } else {
@@ -493,18 +504,20 @@ void layout(ht_plan* pl, int64_t nY, int64_t nZ, int64_t nK, int64_t nG1, int64_
   pl->size[WS_ANORM] = (size_t)pl->Ptot * 2 * sizeof(double);
   pl->size[WS_FEAT] = (size_t)pl->Ptot * 32 * sizeof(float);
   pl->size[WS_LSTATE] = 256;
+  pl->size[WS_STATUS] = (size_t)pl->Ptot * sizeof(int);
+  pl->size[WS_RED] = (size_t)kRseBlocks * 2 * sizeof(double);
   pl->size[WS_LNEW] = (size_t)pl->Ntot * es;
   pl->size[WS_XIN] = (size_t)pl->Ntot * es;
   pl->size[WS_STATE] = sizeof(AdmmState);
   // t-SVT regions first, then the solver-only regions
   const int order_[] = {WS_A,   WS_OMEGA, WS_Y,    WS_Z,    WS_K,     WS_QK,   WS_C,      WS_GP1,  WS_GP2,
                         WS_WK,  WS_CALL,  WS_WK2,  WS_WKF,  WS_SIG,   WS_KEPT, WS_ANORM,  WS_FEAT, WS_LSTATE,
-                        WS_LNEW, WS_XIN,  WS_STATE};
+                        WS_STATUS, WS_LNEW, WS_XIN, WS_STATE, WS_RED};
   size_t o = 0;
   for (int r : order_) {
     pl->off[r] = o;
     o += align256(pl->size[r]);
-    if (r == WS_LSTATE) pl->tsvt_bytes = o;
+    if (r == WS_STATUS) pl->tsvt_bytes = o;
   }
   pl->admm_bytes = o;
 }
@@ -816,6 +829,7 @@ int run_tsvt(const ht_plan* pl, const T* X, T* out, double tau, const double* ta
   int* kept = ws_ptr<int>(pl, ws, WS_KEPT);
   double* anorm = ws_ptr<double>(pl, ws, WS_ANORM);
   int* lstate = ws_ptr<int>(pl, ws, WS_LSTATE);
+  int* status = ws_ptr<int>(pl, ws, WS_STATUS);
   int rc;
   if ((rc = timed(pl, ST_TRANSFORM_FWD, s, [&] {
          if (use_t16(pl, X, A, bf16 ? 2 : 4)) {
@@ -917,13 +931,13 @@ int run_tsvt(const ht_plan* pl, const T* X, T* out, double tau, const double* ta
           const ItemList& L = pl->it_svc[c];
           if (L.n == 0) continue;
           const int r = launch_smallsvd<T>(gp2, gp1, sd, nullptr, items(pl, L), L.n, pl->class_lmax[c], lmax, tau,
-                                           tau_dev, mu_dev, pen, K, sig_dst, kept_dst, s);
+                                           tau_dev, mu_dev, pen, K, sig_dst, kept_dst, status, s);
           if (r) return r;
         }
         return (int)HT_OK;
       }
       return launch_smallsvd<T>(gp2, gp1, sd, wk, nullptr, P, lmax, lmax, tau, tau_dev, mu_dev, pen, K, sig_dst,
-                                kept_dst, s);
+                                kept_dst, status, s);
     });
   };
   const int2* wk_final = nullptr;
@@ -933,8 +947,8 @@ int run_tsvt(const ht_plan* pl, const T* X, T* out, double tau, const double* ta
     if ((rc = sketch_all(wk1))) return rc;
     if (mode == 2) {
       // slices whose predicted sketch could be truncated are redone at the fixed width
-      if ((rc = launch_fallback(sd, P, lmax, wk1, sig, kept, anorm, tau, tau_dev, mu_dev, pl->force_fallback, wk2,
-                                wkf, lstate, s)))
+      if ((rc = launch_fallback(sd, P, lmax, wk1, sig, kept, anorm, tau, tau_dev, mu_dev, pen, pl->force_fallback,
+                                wk2, wkf, lstate, s)))
         return rc;
       if ((rc = sketch_all(wk2))) return rc;
     } else if ((rc = launch_track_finalize(P, wk1, wkf, anorm, s))) {
@@ -1048,6 +1062,17 @@ int run_admm(const ht_plan* pl, const ht_admm_params* prm, const T* M, const uin
       return rc;
     if ((rc = launch_admm_finalize(st, prm->vartheta, prm->mu_max, s))) return rc;
   }
+  return launch_admm_rse<T>(L, static_cast<const T*>(pl->truth), pl->Ntot, ws_ptr<double>(pl, ws, WS_RED), kRseBlocks,
+                            st, s);
+}
+
+// Every call on a plan runs on the device the plan was created on.
+int check_device(const ht_plan* pl) {
+  int dev = -1;
+  HT_CHECK_HIP(hipGetDevice(&dev));
+  if (dev != pl->device)
+    HT_FAIL(HT_ERR_INVALID_ARG, "the current HIP device " + std::to_string(dev) + " is not the plan's device " +
+                                    std::to_string(pl->device));
   return HT_OK;
 }
 
@@ -1070,7 +1095,7 @@ int check_admm_params(const ht_admm_params* prm) {
 
 extern "C" {
 
-int ht_version(void) { return 200; }
+int ht_version(void) { return 300; }
 
 const char* ht_last_error(void) { return g_last_error.c_str(); }
 
@@ -1087,6 +1112,29 @@ int ht_batch_plan_create(int n_tensors, const ht_plan_desc* descs, ht_plan** out
 
 int ht_plan_destroy(ht_plan* pl) {
   free_plan(pl);
+  return HT_OK;
+}
+
+int ht_plan_device(const ht_plan* pl, int* device) {
+  if (!pl || !device) HT_FAIL(HT_ERR_INVALID_ARG, "plan/device is NULL");
+  *device = pl->device;
+  return HT_OK;
+}
+
+int ht_plan_status(const ht_plan* pl, const void* ws, void* stream, int64_t* n_bad) {
+  if (!pl || !ws) HT_FAIL(HT_ERR_INVALID_ARG, "plan/ws is NULL");
+  int rc;
+  if ((rc = check_device(pl))) return rc;
+  std::vector<int> st((size_t)pl->Ptot);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (!st.empty())
+    HT_CHECK_HIP(hipMemcpyAsync(st.data(), static_cast<const char*>(ws) + pl->off[WS_STATUS], st.size() * sizeof(int),
+                                hipMemcpyDeviceToHost, s));
+  HT_CHECK_HIP(hipStreamSynchronize(s));
+  int64_t bad = 0;
+  for (int v : st) bad += v != 0;
+  if (n_bad) *n_bad = bad;
+  if (bad) HT_FAIL(HT_ERR_NONFINITE, std::to_string(bad) + " slice(s) of the last t-SVT met a NaN or an infinity");
   return HT_OK;
 }
 
@@ -1271,6 +1319,7 @@ int ht_gnhtsvt(ht_plan* pl, const void* X, void* out, double tau, const ht_penal
   if (!(tau >= 0.0) || !std::isfinite(tau)) HT_FAIL(HT_ERR_INVALID_ARG, "tau must be finite and >= 0");
   int rc;
   if ((rc = check_penalty(penalty))) return rc;
+  if ((rc = check_device(pl))) return rc;
   if ((rc = check_ws(ws, ws_bytes, pl->tsvt_bytes))) return rc;
   return run_tsvt_any(pl, X, out, tau, nullptr, penalty, call_index, ws, static_cast<hipStream_t>(stream), sigma_out,
                       kept_out);
@@ -1281,6 +1330,7 @@ int ht_batch_gnhtsvt(ht_plan* pl, const void* X, void* out, const double* tau_de
   if (!pl || !X || !out || !tau_dev) HT_FAIL(HT_ERR_INVALID_ARG, "plan/X/out/tau is NULL");
   int rc;
   if ((rc = check_penalty(penalty))) return rc;
+  if ((rc = check_device(pl))) return rc;
   if ((rc = check_ws(ws, ws_bytes, pl->tsvt_bytes))) return rc;
   return run_tsvt_any(pl, X, out, 0.0, tau_dev, penalty, call_index, ws, static_cast<hipStream_t>(stream), sigma_out,
                       kept_out);
@@ -1425,6 +1475,7 @@ int ht_admm_iterate(ht_plan* pl, const ht_admm_params* prm, const void* M, const
   if (n_iter < 0) HT_FAIL(HT_ERR_INVALID_ARG, "n_iter must be >= 0");
   int rc;
   if ((rc = check_admm_params(prm))) return rc;
+  if ((rc = check_device(pl))) return rc;
   if ((rc = check_ws(ws, ws_bytes, pl->admm_bytes))) return rc;
   hipStream_t s = static_cast<hipStream_t>(stream);
   if (pl->precision == HT_FP64)
@@ -1434,18 +1485,37 @@ int ht_admm_iterate(ht_plan* pl, const ht_admm_params* prm, const void* M, const
                          static_cast<float*>(Y), n_iter, ws, s);
 }
 
+int ht_admm_set_truth(ht_plan* pl, const void* truth) {
+  if (!pl) HT_FAIL(HT_ERR_INVALID_ARG, "plan is NULL");
+  if (pl->batch) HT_FAIL(HT_ERR_UNSUPPORTED, "the solver takes a single-tensor plan");
+  pl->truth = truth;
+  return HT_OK;
+}
+
 int ht_admm_get_stats(const ht_plan* pl, const void* ws, void* stream, ht_admm_stats* out) {
   if (!pl || !ws || !out) HT_FAIL(HT_ERR_INVALID_ARG, "plan/ws/out is NULL");
+  int rc;
+  if ((rc = check_device(pl))) return rc;
   AdmmState st;
   hipStream_t s = static_cast<hipStream_t>(stream);
   HT_CHECK_HIP(hipMemcpyAsync(&st, static_cast<const char*>(ws) + pl->off[WS_STATE], sizeof(st),
                               hipMemcpyDeviceToHost, s));
+  std::vector<int> status((size_t)pl->Ptot);
+  if (!status.empty())
+    HT_CHECK_HIP(hipMemcpyAsync(status.data(), static_cast<const char*>(ws) + pl->off[WS_STATUS],
+                                status.size() * sizeof(int), hipMemcpyDeviceToHost, s));
   HT_CHECK_HIP(hipStreamSynchronize(s));
   out->iteration = st.iteration;
   out->mu = st.mu;
   out->dL = st.dL;
   out->dE = st.dE;
   out->resid = st.resid;
+  out->rse = st.rse;
+  int64_t bad = 0;
+  for (int v : status) bad += v != 0;
+  if (st.iteration > 0 && (!std::isfinite(st.dL) || !std::isfinite(st.dE) || !std::isfinite(st.resid) || bad))
+    HT_FAIL(HT_ERR_NONFINITE, "the solver met a NaN or an infinity (stopping terms or " + std::to_string(bad) +
+                                  " flagged slice(s))");
   return HT_OK;
 }
 

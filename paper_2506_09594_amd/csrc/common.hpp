@@ -52,7 +52,8 @@ struct AdmmState {
   int32_t iteration;
   int32_t pad0;
   double dL, dE, resid;                       // stopping terms of the last iteration
-  unsigned long long red_dL, red_dE, red_res;  // running max (bit patterns of non-negative doubles)
+  unsigned long long red_dL, red_dE, red_res;  // running max (bit patterns of non-negative doubles; NaN is largest)
+  double rse;                                  // recovery error against the registered truth (NaN if none)
 };
 
 }  // namespace ht

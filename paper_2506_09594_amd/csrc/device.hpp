@@ -77,7 +77,7 @@ __device__ __forceinline__ double pen_value(const Penalty& p, double x) {
     }
     case HT_PEN_LOG:
       return log1p(x / p.p0);
-    default:  // HT_PEN_CAPPED_L1
+    default:  // HT_PEN_CAPPED_L1 (FIRM has its closed-form prox and never gets here)
       return fmin(x, p.p0);
   }
 }
@@ -125,6 +125,12 @@ __device__ inline double prox_pos(const Penalty& p, double v, double mu) {
       prox_consider(p, mu, v, fmax(v, a * b), bx, bf);
       return bx;
     }
+    case HT_PEN_FIRM: {  // firm shrinkage with thresholds (mu, a mu), a = p0 > 1
+      const double a = p.p0;
+      if (v <= mu) return 0.0;
+      if (v <= a * mu) return a * (v - mu) / (a - 1.0);
+      return v;
+    }
     case HT_PEN_LOG: {
       const double e = p.p0;
       double bx = 0.0, bf = prox_obj(p, mu, v, 0.0);
@@ -141,6 +147,40 @@ __device__ inline double prox_pos(const Penalty& p, double v, double mu) {
       prox_consider(p, mu, v, fmin(fmax(v - mu, 0.0), t), bx, bf);
       prox_consider(p, mu, v, fmax(v, t), bx, bf);
       return bx;
+    }
+  }
+}
+
+// Zero threshold of the proximity operator: t0 = sup{v >= 0 : Prox_{phi,mu}(v) = 0}
+// (the operator is nondecreasing, so every v <= t0 maps to 0 and every v > t0
+// to a positive value).  Closed forms where the prox has one (L1, FIRM: mu;
+// MCP: mu for gamma > mu, else sqrt(gamma mu); capped-L1: min(mu, sqrt(2 mu
+// theta))), bisection on prox_pos itself otherwise (SCAD, LOG).
+__device__ inline double prox_zero_threshold(const Penalty& p, double mu) {
+  if (!(mu > 0.0)) return 0.0;
+  switch (p.kind) {
+    case HT_PEN_L1:
+    case HT_PEN_FIRM:
+      return mu;
+    case HT_PEN_MCP:
+      return p.p0 > mu ? mu : sqrt(p.p0 * mu);
+    case HT_PEN_CAPPED_L1:
+      return fmin(mu, sqrt(2.0 * mu * p.p0));
+    default: {
+      double lo = 0.0, hi = mu;
+      for (int i = 0; i < 64 && prox_pos(p, hi, mu) == 0.0; ++i) {
+        lo = hi;
+        hi *= 2.0;
+      }
+      for (int i = 0; i < 80; ++i) {
+        const double mid = 0.5 * (lo + hi);
+        if (!(mid > lo && mid < hi)) break;
+        if (prox_pos(p, mid, mu) == 0.0)
+          lo = mid;
+        else
+          hi = mid;
+      }
+      return lo;
     }
   }
 }

@@ -128,11 +128,12 @@ int launch_orth_apply(T* Y, int which, const SliceDesc* sd, const int2* wk, cons
 // slice's g2 partials are overwritten (scratch).  slices, when not null, lists
 // the slices of this launch (x = slice index; nslices entries; a width class),
 // else slices 0 .. nslices - 1.  lmax bounds the widths of the launch;
-// sigma_out rows have sigma_ld entries.
+// sigma_out rows have sigma_ld entries.  status (optional): per slice, 1 when
+// a Gram matrix held a NaN or an infinity, else 0.
 template <typename T>
 int launch_smallsvd(double* g2, const double* gw, const SliceDesc* sd, const int2* wk, const int2* slices, int nslices,
                     int lmax, int sigma_ld, double tau, const double* tau_dev, const double* mu_dev, Penalty pen,
-                    T* K, double* sigma_out, int* kept_out, hipStream_t s);
+                    T* K, double* sigma_out, int* kept_out, int* status, hipStream_t s);
 
 // Learned widths (mlp.hip).  Network parameters: one flat FP32 vector of
 // mlp_param_count() entries.  Gradient steps use a partial buffer of
@@ -159,8 +160,8 @@ int launch_width(const float* th, int mode, const SliceDesc* sd, int nslices, in
 // Redo set wk2 (fixed width, or 0 = skip), final widths wkf, anorm[2 s] <-
 // anorm[2 s + 1], counters lstate[1] (predicted slices), lstate[2] (redone).
 int launch_fallback(const SliceDesc* sd, int nslices, int lmax, const int2* wk1, const double* sig, const int* kept,
-                    double* anorm, double tau, const double* tau_dev, const double* mu_dev, int force, int2* wk2,
-                    int2* wkf, int* lstate, hipStream_t s);
+                    double* anorm, double tau, const double* tau_dev, const double* mu_dev, Penalty pen, int force,
+                    int2* wk2, int2* wkf, int* lstate, hipStream_t s);
 int launch_track_finalize(int nslices, const int2* wk1, int2* wkf, double* anorm, hipStream_t s);
 int launch_lstate_set(int* lstate, int valid, int clear_counts, hipStream_t s);
 
@@ -173,5 +174,9 @@ int launch_admm_update(const T* M, const uint8_t* mask, const T* Lnew, T* L, T* 
                        double mu_max, hipStream_t s);
 int launch_admm_finalize(AdmmState* st, double vartheta, double mu_max, hipStream_t s);
 int launch_admm_reset(AdmmState* st, double mu0, hipStream_t s);
+// st->rse = ||L - truth||_F / ||truth||_F (FP64 block partials in part, 2 per
+// block, nblocks blocks, summed in a fixed order), or NaN when truth is null.
+template <typename T>
+int launch_admm_rse(const T* L, const T* truth, int64_t N, double* part, int nblocks, AdmmState* st, hipStream_t s);
 
 }  // namespace ht

@@ -347,19 +347,22 @@ __global__ __launch_bounds__(256) void k_fallback(const SliceDesc* __restrict__ 
                                                   const int2* __restrict__ wk1, const double* __restrict__ sig,
                                                   const int* __restrict__ kept, double* __restrict__ anorm,
                                                   double tau_host, const double* __restrict__ tau_dev,
-                                                  const double* __restrict__ mu_dev, int force, int2* __restrict__ wk2,
-                                                  int2* __restrict__ wkf, int* __restrict__ lstate) {
+                                                  const double* __restrict__ mu_dev, Penalty pen, int force,
+                                                  int2* __restrict__ wk2, int2* __restrict__ wkf,
+                                                  int* __restrict__ lstate) {
   const int s = blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= nslices) return;
   const SliceDesc d = sd[s];
   const int2 w = wk1[s];
   bool redo = false;
   if (w.x < d.l) {
-    const double tau = current_tau(tau_host, tau_dev, mu_dev, d.tensor);
+    // the residual certainly holds a value that would survive when its energy
+    // exceeds (number of residual values) x (zero threshold of the prox)^2
+    const double t0 = prox_zero_threshold(pen, current_tau(tau_host, tau_dev, mu_dev, d.tensor));
     double b2 = 0.0;
     for (int i = 0; i < w.x; ++i) b2 += sig[(int64_t)s * lmax + i] * sig[(int64_t)s * lmax + i];
     const double tail = anorm[2 * s + 1] - b2;
-    redo = force || kept[s] >= w.y || tail > (double)(min(d.n1, d.n2) - w.x) * tau * tau;
+    redo = force || kept[s] >= w.y || tail > (double)(min(d.n1, d.n2) - w.x) * t0 * t0;
     atomicAdd(&lstate[1], 1);
     if (redo) atomicAdd(&lstate[2], 1);
   }
@@ -436,11 +439,11 @@ int launch_width(const float* th, int mode, const SliceDesc* sd, int nslices, in
 }
 
 int launch_fallback(const SliceDesc* sd, int nslices, int lmax, const int2* wk1, const double* sig, const int* kept,
-                    double* anorm, double tau, const double* tau_dev, const double* mu_dev, int force, int2* wk2,
-                    int2* wkf, int* lstate, hipStream_t s) {
+                    double* anorm, double tau, const double* tau_dev, const double* mu_dev, Penalty pen, int force,
+                    int2* wk2, int2* wkf, int* lstate, hipStream_t s) {
   if (nslices == 0) return HT_OK;
   hipLaunchKernelGGL(k_fallback, dim3((unsigned)ceil_div(nslices, 256)), dim3(256), 0, s, sd, nslices, lmax, wk1, sig,
-                     kept, anorm, tau, tau_dev, mu_dev, force, wk2, wkf, lstate);
+                     kept, anorm, tau, tau_dev, mu_dev, pen, force, wk2, wkf, lstate);
   HT_CHECK_LAUNCH();
   return HT_OK;
 }

@@ -115,7 +115,7 @@ __global__ __launch_bounds__(NT) void k_smallsvd(double* __restrict__ g2_all, co
                                                  const int2* __restrict__ slices, double tau_host, const double* __restrict__ tau_dev,
                                                  const double* __restrict__ mu_dev, Penalty pen,
                                                  T* __restrict__ Kall, double* __restrict__ sigma_out, int sigma_ld,
-                                                 int* __restrict__ kept_out) {
+                                                 int* __restrict__ kept_out, int* __restrict__ status) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   __shared__ double s_scr;
   __shared__ int s_kept, s_flag[3];             // step flags, three-way rotation
@@ -146,6 +146,12 @@ __global__ __launch_bounds__(NT) void k_smallsvd(double* __restrict__ g2_all, co
   sum_gram_partials(B0, gp, gq, nt_q, l);
   sum_gram_partials(B1, gp, gw_all + d.g1, nt_b, l);
   __syncthreads();
+  if (status && tid < 64) {  // a non-finite entry of the slice reaches a diagonal entry of the Gram sums
+    bool bad = false;
+    for (int a = tid; a < l; a += 64) bad |= !isfinite(B0[a * gp + a]) || !isfinite(B1[a * gp + a]);
+    const bool any_bad = __ballot(bad) != 0;
+    if (tid == 0) status[j] = any_bad ? 1 : 0;
+  }
   if constexpr (LB <= 64) {
     // wave 0: R2 = chol(G2) and R2^{-1} in registers (lane b owns column b)
     if (tid < 64) chol_inverse_regs<LB>(B0, gp, l, delta_rel, V);
@@ -433,14 +439,14 @@ __global__ __launch_bounds__(NT) void k_smallsvd(double* __restrict__ g2_all, co
 template <typename T>
 int launch_smallsvd(double* g2, const double* gw, const SliceDesc* sd, const int2* wk, const int2* slices, int nslices,
                     int lmax, int sigma_ld, double tau, const double* tau_dev, const double* mu_dev, Penalty pen,
-                    T* K, double* sigma_out, int* kept_out, hipStream_t s) {
+                    T* K, double* sigma_out, int* kept_out, int* status, hipStream_t s) {
   if (lmax > HT_MAX_WIDTH) HT_FAIL(HT_ERR_UNSUPPORTED, "sketch width above HT_MAX_WIDTH");
   if (nslices == 0) return HT_OK;
   auto launch = [&](auto kern, int nt) -> int {
     int rc = ensure_dynamic_lds((const void*)kern, svd_lds_bytes(HT_MAX_WIDTH));
     if (rc) return rc;
     hipLaunchKernelGGL(kern, dim3((unsigned)nslices), dim3(nt), svd_lds_bytes(lmax), s, g2, gw, sd, wk, slices,
-                       tau, tau_dev, mu_dev, pen, K, sigma_out, sigma_ld, kept_out);
+                       tau, tau_dev, mu_dev, pen, K, sigma_out, sigma_ld, kept_out, status);
     HT_CHECK_LAUNCH();
     return HT_OK;
   };
@@ -452,10 +458,10 @@ int launch_smallsvd(double* g2, const double* gw, const SliceDesc* sd, const int
 }
 
 template int launch_smallsvd<float>(double*, const double*, const SliceDesc*, const int2*, const int2*, int, int, int,
-                                    double, const double*, const double*, Penalty, float*, double*, int*,
+                                    double, const double*, const double*, Penalty, float*, double*, int*, int*,
                                     hipStream_t);
 template int launch_smallsvd<double>(double*, const double*, const SliceDesc*, const int2*, const int2*, int, int,
-                                     int, double, const double*, const double*, Penalty, double*, double*, int*,
+                                     int, double, const double*, const double*, Penalty, double*, double*, int*, int*,
                                      hipStream_t);
 
 }  // namespace ht

@@ -28,13 +28,13 @@ _lib = ctypes.CDLL(LIB_PATH)
 
 MAX_ORDER = 8
 OK, ERR_INVALID_ARG, ERR_UNSUPPORTED, ERR_NONFINITE, ERR_WORKSPACE, ERR_HIP, ERR_ALLOC = 0, -1, -2, -3, -4, -5, -6
-TRANSFORMS = {"dct2": 0, "dft": 1, "custom": 2}
+TRANSFORMS = {"dct2": 0, "dft": 1, "custom": 2, "dft_unnormalized": 3}
 PRECISIONS = {"fp64": 0, "fp32": 1, "bf16": 2}
-PENALTIES = {"l1": 0, "mcp": 1, "scad": 2, "log": 3, "capped_l1": 4}
+PENALTIES = {"l1": 0, "mcp": 1, "scad": 2, "log": 3, "capped_l1": 4, "firm": 5}
 MODELS = {"completion": 0, "rpca": 1}
 REGIONS = {"A": 0, "omega": 1, "Q": 2, "Bt": 3, "K": 4, "QK": 5, "C": 6, "Lnew": 7, "Xin": 8, "state": 9,
            "gram": 10, "gram_q": 11, "widths": 12, "call": 13, "widths_redo": 14, "widths_used": 15,
-           "sigma": 16, "kept": 17, "anorm": 18, "features": 19, "learn_state": 20}
+           "sigma": 16, "kept": 17, "anorm": 18, "features": 19, "learn_state": 20, "status": 21, "rse_part": 22}
 
 # Symbols the header declares (checked by the CPU test suite).
 EXPORTS = [
@@ -45,6 +45,7 @@ EXPORTS = [
     "ht_batch_gnhtsvt", "ht_plan_set_tuning", "ht_plan_get_tuning", "ht_plan_autotune", "ht_plan_graph_enable",
     "ht_plan_learned", "ht_plan_learned_reset", "ht_plan_learned_counts", "ht_plan_force_fallback",
     "ht_mlp_param_count", "ht_mlp_workspace_size", "ht_mlp_forward", "ht_mlp_grad", "ht_mlp_train_step",
+    "ht_plan_device", "ht_plan_status", "ht_admm_set_truth",
 ]
 STAGES = ["transform_fwd", "omega", "sketch_nn", "cholqr", "sketch_tn", "smallsvd", "recon_qk", "recon_nt",
           "transform_inv", "admm_update"]
@@ -83,7 +84,7 @@ class _AdmmParams(ctypes.Structure):
 
 class _AdmmStats(ctypes.Structure):
     _fields_ = [("iteration", ctypes.c_int32), ("mu", ctypes.c_double), ("dL", ctypes.c_double),
-                ("dE", ctypes.c_double), ("resid", ctypes.c_double)]
+                ("dE", ctypes.c_double), ("resid", ctypes.c_double), ("rse", ctypes.c_double)]
 
 
 _vp = ctypes.c_void_p
@@ -133,6 +134,9 @@ _sig = {
     "ht_mlp_train_step": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int, _vp, _vp, ctypes.c_int, ctypes.c_float,
                                          ctypes.c_float, ctypes.c_float, ctypes.c_float, _vp, _vp, ctypes.c_size_t,
                                          _vp]),
+    "ht_plan_device": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_int)]),
+    "ht_plan_status": (ctypes.c_int, [_vp, _vp, _vp, ctypes.POINTER(ctypes.c_int64)]),
+    "ht_admm_set_truth": (ctypes.c_int, [_vp, _vp]),
 }
 for _name, (_res, _args) in _sig.items():
     _f = getattr(_lib, _name)
@@ -157,6 +161,27 @@ def _penalty(pen):
 
 def _ptr(t):
     return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def check_tensor(t, name, dtype, numel, optional=False):
+    """Raise ValueError unless t is a contiguous CUDA tensor of the given dtype
+    holding at least numel elements (the library reads and writes exactly the
+    plan's element count through the raw pointer)."""
+    import torch
+    if t is None:
+        if optional:
+            return
+        raise ValueError(f"{name} is required")
+    if not torch.is_tensor(t):
+        raise ValueError(f"{name} must be a torch tensor")
+    if t.dtype != dtype:
+        raise ValueError(f"{name} must be {dtype} for this plan, not {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous (Fortran-order flat storage)")
+    if t.numel() < numel:
+        raise ValueError(f"{name} holds {t.numel()} elements, the plan needs {numel}")
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a CUDA tensor (the library takes device pointers)")
 
 
 def _stream():
@@ -240,9 +265,11 @@ class Plan:
     def autotune(self, X, workspace=None, repeats=3):
         """Time the tile choices on X and keep the fastest; returns (tuning, ms)."""
         import torch
+        check_tensor(X, "X", self.torch_dtype, self.N)
         if workspace is None:
             workspace = self.alloc_workspace()
         out = torch.empty_like(X)
+        self._check_io(X, out, workspace, self.workspace_bytes)
         wp, wn = self._aligned(workspace)
         ms = ctypes.c_double()
         _check(_lib.ht_plan_autotune(self._h, _ptr(X), _ptr(out), wp, wn, _stream(), int(repeats), ctypes.byref(ms)))
@@ -267,6 +294,19 @@ class Plan:
 
     def force_fallback(self, on=True):
         _check(_lib.ht_plan_force_fallback(self._h, 1 if on else 0))
+
+    def device(self):
+        d = ctypes.c_int()
+        _check(_lib.ht_plan_device(self._h, ctypes.byref(d)))
+        return d.value
+
+    def status(self, workspace):
+        """Number of slices of the last t-SVT on this workspace whose Gram matrices
+        held a NaN or an infinity (raises HtError ERR_NONFINITE when nonzero)."""
+        wp, _wn = self._aligned(workspace)
+        n = ctypes.c_int64()
+        _check(_lib.ht_plan_status(self._h, wp, _stream(), ctypes.byref(n)))
+        return n.value
 
     def graph(self, on=True):
         """Record the launch sequence as a HIP graph on the next call and replay it
@@ -309,12 +349,20 @@ class Plan:
         raw = ws[base + off.value: base + off.value + nb.value]
         return raw.view(dtype)
 
+    def _check_io(self, X, out, workspace, need):
+        import torch
+        check_tensor(X, "X", self.torch_dtype, self.N)
+        check_tensor(out, "out", self.torch_dtype, self.N)
+        check_tensor(workspace, "workspace", torch.uint8, 0)  # its size is checked by the library
+
     def gnhtsvt(self, X, tau, penalty=("l1", ()), call_index=0, out=None, workspace=None, stats=False):
         import torch
+        check_tensor(X, "X", self.torch_dtype, self.N)
         if out is None:
             out = torch.empty_like(X)
         if workspace is None:
             workspace = self.alloc_workspace()
+        self._check_io(X, out, workspace, self.workspace_bytes)
         wp, wn = self._aligned(workspace)
         sig = kept = None
         if stats:
@@ -346,8 +394,10 @@ class Plan:
 
     def transform(self, X, inverse=False, out=None):
         import torch
+        check_tensor(X, "X", self.torch_dtype, self.N)
         if out is None:
             out = torch.empty_like(X)
+        check_tensor(out, "out", self.torch_dtype, self.N)
         _check(_lib.ht_transform(self._h, _ptr(X), _ptr(out), 1 if inverse else 0, _stream()))
         return out
 
@@ -402,12 +452,15 @@ class BatchPlan(Plan):
     def gnhtsvt(self, X, tau, penalty=("l1", ()), call_index=0, out=None, workspace=None, stats=False):
         """tau: one threshold per tensor (sequence or CUDA float64 tensor)."""
         import torch
+        check_tensor(X, "X", self.torch_dtype, self.N)
         if out is None:
             out = torch.empty_like(X)
         if workspace is None:
             workspace = self.alloc_workspace()
         if not torch.is_tensor(tau):
             tau = torch.tensor(np.asarray(tau, dtype=np.float64), device="cuda")
+        self._check_io(X, out, workspace, self.workspace_bytes)
+        check_tensor(tau, "tau", torch.float64, len(self.shapes))
         wp, wn = self._aligned(workspace)
         sig = kept = None
         if stats:
@@ -480,17 +533,39 @@ class Admm:
         self.prm = _AdmmParams(MODELS[model], _penalty(phi), _penalty(psi), float(lam), float(mu0),
                                float(vartheta), float(mu_max))
 
+    def _check_state(self, L, E, Y, workspace):
+        import torch
+        dt, N = self.plan.torch_dtype, self.plan.N
+        for t, name in ((L, "L"), (E, "E"), (Y, "Y")):
+            check_tensor(t, name, dt, N)
+        check_tensor(workspace, "workspace", torch.uint8, 0)  # its size is checked by the library
+
     def init(self, L, E, Y, workspace):
+        self._check_state(L, E, Y, workspace)
         wp, wn = Plan._aligned(workspace)
         _check(_lib.ht_admm_init(self.plan._h, ctypes.byref(self.prm), _ptr(L), _ptr(E), _ptr(Y), wp, wn, _stream()))
 
     def iterate(self, M, mask, L, E, Y, n_iter, workspace):
+        import torch
+        self._check_state(L, E, Y, workspace)
+        check_tensor(M, "M", self.plan.torch_dtype, self.plan.N)
+        check_tensor(mask, "mask", torch.uint8, self.plan.N)
         wp, wn = Plan._aligned(workspace)
         _check(_lib.ht_admm_iterate(self.plan._h, ctypes.byref(self.prm), _ptr(M), _ptr(mask), _ptr(L), _ptr(E),
                                     _ptr(Y), int(n_iter), wp, wn, _stream()))
 
+    def set_truth(self, truth):
+        """Register the ground truth L* (None clears it): every later iterate()
+        call ends with the RSE ||L - L*||_F / ||L*||_F in the solver state."""
+        if truth is not None:
+            check_tensor(truth, "truth", self.plan.torch_dtype, self.plan.N)
+        self._truth_keep = truth
+        _check(_lib.ht_admm_set_truth(self.plan._h, _ptr(truth)))
+
     def stats(self, workspace):
+        """Solver scalars; raises HtError ERR_NONFINITE when a stopping term is
+        NaN or infinite or a slice met a non-finite value."""
         wp, _wn = Plan._aligned(workspace)
         st = _AdmmStats()
         _check(_lib.ht_admm_get_stats(self.plan._h, wp, _stream(), ctypes.byref(st)))
-        return {"iteration": st.iteration, "mu": st.mu, "dL": st.dL, "dE": st.dE, "resid": st.resid}
+        return {"iteration": st.iteration, "mu": st.mu, "dL": st.dL, "dE": st.dE, "resid": st.resid, "rse": st.rse}

@@ -7,6 +7,8 @@ import ctypes
 import os
 import re
 
+import numpy as np
+
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -41,7 +43,7 @@ def test_every_declared_symbol_is_exported(lib):
 def test_binding_covers_header(lib):
     from paper_2506_09594_amd import htsvt
     assert sorted(htsvt.EXPORTS) == _declared()
-    assert htsvt.version() == 200
+    assert htsvt.version() == 300
 
 
 def test_invalid_descriptions_rejected_before_device_work(lib):
@@ -78,3 +80,90 @@ def test_batch_descriptions_rejected_before_device_work(lib):
     assert lib.ht_batch_plan_create(2, descs, ctypes.byref(h)) == htsvt.ERR_INVALID_ARG
     assert lib.ht_plan_set_tuning(None, 64, 0) == htsvt.ERR_INVALID_ARG
     assert lib.ht_plan_graph_enable(None, 1) == htsvt.ERR_INVALID_ARG
+
+
+def test_error_codes_reachable_without_a_gpu(lib):
+    """Every error code but NONFINITE (which needs a computed slice; see the GPU
+    tests) comes back through the ABI with a message, before or at the first
+    device call."""
+    from paper_2506_09594_amd import htsvt
+    lib = htsvt._lib  # with argument types (size_t and double arguments)
+    h = ctypes.c_void_p()
+    d = htsvt._make_desc((20, 20, 4), ["dct2"], 4, 2, 1, "fp32", 0, 0, None, [])
+    # a valid description: the device tables cannot be allocated without a GPU
+    assert lib.ht_plan_create(ctypes.byref(d), ctypes.byref(h)) == htsvt.ERR_ALLOC
+    # a valid request this build does not take: sketch width above HT_MAX_WIDTH
+    d = htsvt._make_desc((200, 200, 4), ["dct2"], 70, 10, 1, "fp32", 0, 0, None, [])
+    assert lib.ht_plan_create(ctypes.byref(d), ctypes.byref(h)) == htsvt.ERR_UNSUPPORTED
+    assert b"HT_MAX_WIDTH" in htsvt._lib.ht_last_error()
+    # a DFT mode next to a real one
+    d = htsvt._make_desc((20, 20, 4, 4), ["dct2", "dft_unnormalized"], 4, 2, 1, "fp32", 0, 0, None, [])
+    assert lib.ht_plan_create(ctypes.byref(d), ctypes.byref(h)) == htsvt.ERR_UNSUPPORTED
+    fake = ctypes.c_void_p(0x1000)
+    # a misaligned workspace
+    assert lib.ht_mlp_grad(fake, fake, fake, 1, fake, None, ctypes.c_void_p(0x1001), 1 << 20, None) \
+        == htsvt.ERR_WORKSPACE
+    assert b"aligned" in htsvt._lib.ht_last_error()
+    # too small a workspace
+    assert lib.ht_mlp_grad(fake, fake, fake, 1, fake, None, ctypes.c_void_p(0x1000), 16, None) \
+        == htsvt.ERR_WORKSPACE
+    # the HIP runtime's own failure (no device here) is reported as HIP
+    assert lib.ht_mlp_forward(fake, fake, fake, 1, None) == htsvt.ERR_HIP
+    assert b"kernel launch failed" in htsvt._lib.ht_last_error()
+    # invalid arguments
+    assert lib.ht_mlp_train_step(fake, fake, fake, 0, fake, fake, 1, ctypes.c_float(1e-3), ctypes.c_float(0.9),
+                                 ctypes.c_float(0.999), ctypes.c_float(1e-8), None, fake, 1 << 20, None) \
+        == htsvt.ERR_INVALID_ARG
+    assert lib.ht_plan_status(None, fake, None, None) == htsvt.ERR_INVALID_ARG
+    assert lib.ht_plan_device(None, None) == htsvt.ERR_INVALID_ARG
+    assert lib.ht_admm_set_truth(None, None) == htsvt.ERR_INVALID_ARG
+
+
+def _fake_plan(htsvt, precision="fp32", N=24):
+    """A Plan object without a device plan behind it: the binding's argument
+    checks run before any call into the library."""
+    p = htsvt.Plan.__new__(htsvt.Plan)
+    p._h = None
+    p.precision, p.N = precision, N
+    p.workspace_bytes = p.admm_workspace_bytes = 1024
+    p.n_slices, p.width = 2, 3
+    return p
+
+
+def test_binding_rejects_misuse_before_the_library(lib):
+    import torch
+    from paper_2506_09594_amd import htsvt
+    p = _fake_plan(htsvt)
+    good = torch.zeros(24, dtype=torch.float32)
+    ws = torch.zeros(2048, dtype=torch.uint8)
+    cases = [
+        (torch.zeros(24, dtype=torch.float64), "float32"),          # an FP64 tensor on an FP32 plan
+        (torch.zeros(23, dtype=torch.float32), "elements"),         # too short
+        (torch.zeros(48, dtype=torch.float32)[::2], "contiguous"),  # strided
+        (good, "CUDA"),                                             # host memory
+        (np.zeros(24, dtype=np.float32), "torch tensor"),
+    ]
+    for X, msg in cases:
+        with pytest.raises(ValueError, match=msg):
+            p.gnhtsvt(X, 1.0, out=good, workspace=ws)
+        with pytest.raises(ValueError, match=msg):
+            p.transform(X)
+    with pytest.raises(ValueError, match="float64"):
+        _fake_plan(htsvt, "fp64").gnhtsvt(good, 1.0)
+    adm = htsvt.Admm.__new__(htsvt.Admm)
+    adm.plan = p
+    with pytest.raises(ValueError, match="L must be"):
+        adm.init(torch.zeros(24, dtype=torch.float64), good, good, ws)
+    with pytest.raises(ValueError, match="L holds"):
+        adm.iterate(good, torch.zeros(24, dtype=torch.uint8), torch.zeros(3, dtype=torch.float32), good, good, 1, ws)
+    with pytest.raises(ValueError, match="workspace must be torch.uint8"):
+        htsvt.check_tensor(torch.zeros(8, dtype=torch.float32), "workspace", torch.uint8, 0)
+    with pytest.raises(ValueError, match="truth"):
+        adm.set_truth(torch.zeros(2, dtype=torch.float32))
+
+
+def test_binding_exposes_new_kinds(lib):
+    from paper_2506_09594_amd import htsvt
+    assert htsvt.TRANSFORMS["dft_unnormalized"] == 3
+    assert htsvt.PENALTIES["firm"] == 5
+    assert htsvt.REGIONS["status"] == 21

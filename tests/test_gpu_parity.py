@@ -17,7 +17,7 @@ pytestmark = pytest.mark.gpu
 
 TOL = {"fp64": 1e-10, "fp32": 1e-5}
 PEN = {"l1": ("l1", ()), "mcp": ("mcp", (40.0,)), "scad": ("scad", (3.7, 6.0)), "log": ("log", (5.0,)),
-       "capped_l1": ("capped_l1", (30.0,))}
+       "capped_l1": ("capped_l1", (30.0,)), "firm": ("firm", (2.5,))}
 
 
 @pytest.fixture(scope="module")

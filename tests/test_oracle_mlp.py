@@ -146,3 +146,35 @@ def test_fallback_energy_test_is_certain():
         fires = float(np.sum(rho ** 2)) > len(rho) * tau * tau
         if fires:
             assert rho[0] > tau
+
+
+def test_fallback_uses_the_zero_threshold_of_the_penalty():
+    """MCP with gamma <= tau hard-thresholds at sqrt(gamma tau) < tau: values in
+    (sqrt(gamma tau), tau] survive, so the certain-miss test must use that
+    threshold.  Residual energy 5.74 over 2 residual values: certainly one above
+    sqrt(2.5) = 1.58 but not certainly one above tau = 2."""
+    sig = np.array([5.0, 3.0, 0.5, 0.1])
+    assert not mlp.needs_fallback(4, 3, 2, 40.0, sig, 2.0, 74, 6, ("l1", ()))
+    assert mlp.needs_fallback(4, 3, 2, 40.0, sig, 2.0, 74, 6, ("mcp", (1.25,)))
+    # gamma above tau: the firm regime keeps tau as the threshold
+    assert not mlp.needs_fallback(4, 3, 2, 40.0, sig, 2.0, 74, 6, ("mcp", (5.0,)))
+
+
+def test_fallback_energy_test_is_certain_for_every_penalty():
+    """When the energy test fires, the residual holds a value the prox keeps
+    (explicit residual spectra, every penalty)."""
+    from oracle import prox
+    g = np.random.default_rng(12)
+    pens = [("l1", ()), ("mcp", (0.5,)), ("mcp", (4.0,)), ("scad", (3.7, 0.4)), ("log", (0.5,)),
+            ("capped_l1", (0.3,)), ("firm", (2.0,))]
+    fired = 0
+    for _ in range(300):
+        kind, params = pens[g.integers(len(pens))]
+        rho = np.sort(g.exponential(1.0, size=g.integers(1, 12)))[::-1]
+        tau = g.uniform(0.1, 2.0)
+        sig = np.array([10.0, 8.0])  # the sketched values; two kept, one survived
+        an = float(np.sum(sig ** 2) + np.sum(rho ** 2))
+        if mlp.needs_fallback(2, 2, 1, an, sig, tau, 74, 2 + len(rho), (kind, params)):
+            fired += 1
+            assert prox.prox_scalar(kind, rho[0], tau, params) > 0.0
+    assert fired > 20

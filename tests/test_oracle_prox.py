@@ -86,3 +86,63 @@ def test_prox_monotone_and_shrinking(kind, params):
 def test_mu_zero_is_identity():
     for kind, params in CASES:
         assert P.prox_scalar(kind, 1.7, 0.0, params) == 1.7
+
+
+def test_firm_is_gao_bruce_threshold():
+    """FIRM(a) at threshold mu: 0 up to mu, a (|v| - mu)/(a - 1) up to a mu, v beyond."""
+    for a in (1.5, 3.0, 10.0):
+        for mu in (0.2, 1.0, 4.0):
+            for v in np.linspace(-6 * a * mu, 6 * a * mu, 301):
+                t = abs(v)
+                if abs(t - mu) < 1e-12 or abs(t - a * mu) < 1e-12:
+                    continue
+                ref = 0.0 if t <= mu else (np.sign(v) * a * (t - mu) / (a - 1) if t <= a * mu else v)
+                assert P.prox_scalar("firm", v, mu, (a,)) == pytest.approx(ref, abs=1e-12)
+
+
+@pytest.mark.parametrize("a", [1.2, 2.5, 8.0])
+@pytest.mark.parametrize("mu", [0.1, 0.7, 2.0])
+def test_firm_prox_matches_bruteforce(a, mu):
+    rng = np.random.default_rng(int(100 * a + 10 * mu))
+    for v in np.concatenate([rng.uniform(-6, 6, 25), [0.0, mu, a * mu]]):
+        x = P.prox_scalar("firm", v, mu, (a,))
+        xb = P.prox_bruteforce("firm", v, mu, (a,))
+        assert P._objective("firm", (a,), mu, abs(v), abs(x)) <= P._objective("firm", (a,), mu, abs(v), abs(xb)) + 1e-9
+
+
+def test_firm_needs_its_threshold():
+    with pytest.raises(ValueError):
+        P.phi("firm", 1.0, (2.0,))
+    assert P.phi("firm", 1.0, (2.0,), 1.0) == P.phi("mcp", 1.0, (2.0,))
+
+
+@pytest.mark.parametrize("mu", [0.05, 0.8, 3.0])
+def test_zero_threshold_closed_forms(mu):
+    """Where the prox has a closed form, the bisection lands on its threshold
+    (to within the oracle prox's tie tolerance: objective differences below
+    1e-15 resolve to the smaller magnitude, which moves a continuous threshold
+    by at most sqrt(2e-15) ~ 5e-8)."""
+    t = P.zero_threshold
+    tol = dict(rel=1e-9, abs=1e-7)
+    assert t("l1", mu) == pytest.approx(mu, **tol)
+    assert t("firm", mu, (3.0,)) == pytest.approx(mu, **tol)
+    assert t("mcp", mu, (5.0 * mu,)) == pytest.approx(mu, **tol)             # firm regime, gamma > mu
+    assert t("mcp", mu, (0.3 * mu,)) == pytest.approx(np.sqrt(0.3) * mu, **tol)  # hard threshold sqrt(g mu)
+    for th in (0.1 * mu, mu, 4 * mu):
+        assert t("capped_l1", mu, (th,)) == pytest.approx(min(mu, np.sqrt(2 * mu * th)), **tol)
+    assert t("l1", 0.0) == 0.0
+
+
+@pytest.mark.parametrize("kind,params", CASES + [("firm", (2.0,)), ("firm", (1.1,))])
+@pytest.mark.parametrize("mu", [0.3, 1.7])
+def test_zero_threshold_is_the_boundary_of_the_prox(kind, params, mu):
+    """Every v below t0 maps to 0 and every v above it survives (dense grid),
+    i.e. t0 is the threshold that decides which singular values survive."""
+    t0 = P.zero_threshold(kind, mu, params)
+    assert t0 > 0.0
+    assert P.prox_scalar(kind, t0 * (1 - 1e-7), mu, params) == 0.0
+    assert P.prox_scalar(kind, t0 * (1 + 1e-6), mu, params) > 0.0
+    vs = np.linspace(0.0, 3.0 * t0, 601)
+    surv = np.array([P.prox_scalar(kind, v, mu, params) > 0.0 for v in vs])
+    first = vs[np.argmax(surv)]
+    assert abs(first - t0) <= vs[1] - vs[0] + 1e-12
