@@ -1,16 +1,25 @@
 #!/usr/bin/env python3
 """Throughput of the randomized high-order t-SVT on one MI355X.
 
-Workload: a 256 x 256 x 16 x 16 FP32 tensor (256 transformed face slices of
-256 x 256) of tubal rank 20 built from Gaussian t-product factors under the
-orthonormal DCT on modes 3 and 4; randomized t-SVT with r = 20, p = 10, q = 2
-and MCP shrinkage.  One step = one full randomized t-SVT (forward transform,
-sketch, power iterations, CholeskyQR, small SVD, shrink, reconstruction,
-inverse transform) on the resident input.
+Default workload (the largest single-GPU one): the robust-PCA tensor of order 4,
+1024 x 1024 x 32 x 8 in FP32 storage, whose low-tubal-rank part of rank 50 is
+built from Gaussian t-product factors under the unitary DFT on modes 3 and 4,
+plus 10% outliers uniform in [-1, 1]; randomized t-SVT with r = 50, p = 10,
+q = 2 and BF16 sketch products (FP32 accumulation; FP64 CholeskyQR and small
+SVD).  The DFT turns the 256 face slices into complex ones, 130 of which are
+sketched (the others are their conjugates).  One step = one full randomized
+t-SVT (forward transform, sketch, power iterations, CholeskyQR, small SVD,
+shrink, reconstruction, inverse transform) on the resident input; the value
+counts all 256 face slices per step.
+
+`--workload tsvt` runs the 256 x 256 x 16 x 16 FP32 rank-20 DCT tensor instead
+(r = 20, p = 10, q = 2).
 
 Prints one JSON line: frontal slices per second, the roofline of the dominant
-kernel (HIP-event durations on the launch stream), and the FP64 oracle timed
-on the host CPU over a bounded sample of the same workload.
+HBM-streaming kernel (HIP-event durations on the launch stream), the FP64
+oracle timed on the host CPU over a bounded sample of the same workload, and
+the completion solver's iteration time in its plain FP32 and BF16-mixed forms
+with the final relative error of each.
 """
 import argparse
 import json
@@ -25,39 +34,104 @@ if ROOT not in sys.path:
 HBM_PEAK_GBS = 8000.0
 FP64_VECTOR_TFLOPS = 78.6
 
-WORKLOAD = {
-    "name": "tsvt_256x256x16x16_fp32_rank20_dct",
-    "dims": (256, 256, 16, 16), "kinds": ["dct2", "dct2"], "rank": 20, "r": 20, "p": 10, "q": 2,
-    "tau": 50.0, "penalty": ("mcp", (100.0,)), "precision": "fp32", "seed": 2,
+WORKLOADS = {
+    "rpca": {
+        "name": "rpca_dft_1024x1024x32x8_rank50_bf16",
+        "dims": (1024, 1024, 32, 8), "kinds": ["dft", "dft"], "rank": 50, "outliers": 0.1, "r": 50, "p": 10,
+        "q": 2, "tau": 400.0, "penalty": ("mcp", (4000.0,)), "precision": "bf16", "seed": 9,
+        "transform": "unitary dft on modes 3,4",
+    },
+    "tsvt": {
+        "name": "tsvt_256x256x16x16_fp32_rank20_dct",
+        "dims": (256, 256, 16, 16), "kinds": ["dct2", "dct2"], "rank": 20, "outliers": 0.0, "r": 20, "p": 10,
+        "q": 2, "tau": 50.0, "penalty": ("mcp", (100.0,)), "precision": "fp32", "seed": 2,
+        "transform": "dct2 on modes 3,4",
+    },
 }
 
 
-def stage_bytes(stage, plan, es):
-    """Algorithmic HBM bytes of one launch of a stage (read once, write once); the
-    transformed tensor is 2 bytes per entry in the BF16-mixed path."""
+def stage_bytes(stage, plan, es, cplx):
+    """Algorithmic HBM bytes of one launch of a stage (read once, write once).
+    The transformed tensor is 2 bytes per entry in the BF16-mixed path.  Complex
+    slices (DFT) count their real and imaginary parts (stacked blocks of
+    2 n1 x n2 and 2 n x l); only the sketched (canonical) slices are stored."""
     n1, n2 = plan.dims[0], plan.dims[1]
     P, l, N = plan.n_slices, plan.width, plan.N
     ea = 2 if plan.precision == "bf16" else es
+    f = 2 if cplx else 1
     if stage == "transform_fwd":
-        return N * (es + ea)
+        return N * es + P * f * n1 * n2 * ea
     if stage == "transform_inv":
-        return 2 * N * es
+        return P * f * n1 * n2 * es + N * es
     if stage in ("sketch_nn", "sketch_tn"):
-        return P * (n1 * n2 * ea + (n1 + n2) * l * es)
+        return P * f * (n1 * n2 * ea + (n1 + n2) * l * es)
     if stage == "recon_nt":
-        return P * (n1 * n2 + (n1 + n2) * l) * es
+        return P * f * (n1 * n2 + (n1 + n2) * l) * es
     if stage == "recon_qk":
-        return P * (2 * n1 * l + l * l) * es
+        return P * f * (2 * n1 * l + f * l * l) * es
     if stage == "omega":
         return P * n2 * l * es
     return None
 
 
+def rpca_input(wl):
+    """The robust-PCA tensor on the GPU (FP32, Fortran order), from seeded
+    torch generators (data preparation only): Gaussian factors of the
+    transformed domain, their face-wise product under the unitary DFT on modes
+    3..d (torch.fft with orthonormal scaling), the real part of the inverse,
+    then round(frac N) outliers uniform in [-1, 1] added at positions drawn
+    uniformly without replacement."""
+    import torch
+    dims, r = wl["dims"], wl["rank"]
+    n1, n2 = dims[:2]
+    modes = list(dims[2:])
+    g = torch.Generator(device="cuda")
+    g.manual_seed(wl["seed"])
+    # C-order views with the transformed modes first: (nd, ..., n3, n1, r) and (nd, ..., n3, r, n2)
+    A = torch.randn(*reversed(modes), n1, r, generator=g, device="cuda", dtype=torch.float32)
+    B = torch.randn(*reversed(modes), r, n2, generator=g, device="cuda", dtype=torch.float32)
+    axes = tuple(range(len(modes)))
+    FA = torch.fft.fftn(A, dim=axes, norm="ortho")
+    FB = torch.fft.fftn(B, dim=axes, norm="ortho")
+    del A, B
+    FC = torch.matmul(FA, FB)
+    del FA, FB
+    X = torch.fft.ifftn(FC, dim=axes, norm="ortho").real
+    del FC
+    X = X.transpose(-1, -2).contiguous().view(-1)  # slice j column-major: i1 fastest
+    N = X.numel()
+    m = int(round(wl["outliers"] * N))
+    if m:
+        pos = torch.randperm(N, generator=g, device="cuda")[:m]
+        X[pos] += torch.rand(m, generator=g, device="cuda", dtype=torch.float32) * 2.0 - 1.0
+        del pos
+    torch.cuda.synchronize()
+    return X
+
+
+def _host_info():
+    import platform
+    model = platform.processor() or ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"nproc": os.cpu_count(), "cpu_model": model}
+
+
 def cpu_baseline(X, wl, budget_s=10.0):
-    """The FP64 oracle on the host: whole randomized t-SVTs of the workload, repeated
-    until about budget_s seconds of CPU work (each call draws its own sketch)."""
+    """The FP64 oracle on the host, timed on a bounded sample of the workload.
+    Small tensors: whole randomized t-SVTs until about budget_s seconds.  The
+    DFT workload (too large for whole calls): sampled canonical slices, each the
+    oracle's transformed slice by the definition plus its randomized estimate,
+    until about budget_s seconds (slices per second of that work).  Timed with
+    the BLAS threads the host offers and again with one thread."""
     import numpy as np
-    from threadpoolctl import threadpool_info
+    from threadpoolctl import threadpool_info, threadpool_limits
 
     from oracle import transforms as otr, tsvt as otsvt
 
@@ -65,26 +139,52 @@ def cpu_baseline(X, wl, budget_s=10.0):
     T = otr.build_transforms(dims, kinds)
     X64 = X.astype(np.float64)
     P = int(np.prod(dims[2:]))
-    calls, t0 = 0, time.perf_counter()
-    while True:
-        om = otsvt.omegas(dims, kinds, wl["r"], wl["p"], seed=wl["seed"], call=calls, round_to=np.float32)
-        otsvt.tsvt_randomized(X64, wl["tau"], wl["penalty"], T, wl["r"], wl["p"], wl["q"], om)
-        calls += 1
-        dt = time.perf_counter() - t0
-        if dt >= budget_s or calls >= 50:
-            break
+    k = min(wl["r"], wl["r"] + wl["p"], dims[0], dims[1])
+    whole = wl["kinds"][0] != "dft"
+
+    def run(budget):
+        done, t0 = 0, time.perf_counter()
+        calls = 0
+        while True:
+            om = otsvt.omegas(dims, kinds, wl["r"], wl["p"], seed=wl["seed"], call=calls, round_to=np.float32)
+            if whole:
+                otsvt.tsvt_randomized(X64, wl["tau"], wl["penalty"], T, wl["r"], wl["p"], wl["q"], om)
+                done += P
+            else:
+                j = [1, 37, 0, 16 + 32 * 4][calls % 4]
+                otsvt.tsvt_slice(otr.forward_slice(X64, T, j), wl["tau"], wl["penalty"], k, wl["q"], om[j])
+                done += 1
+            calls += 1
+            dt = time.perf_counter() - t0
+            if dt >= budget or calls >= 50:
+                return done, dt
+    done, dt = run(budget_s)
     threads = max((d.get("num_threads", 1) for d in threadpool_info()), default=1)
-    return {"value": round(calls * P / dt, 2), "unit": "slices/s", "cores": int(threads), "kind": "oracle",
-            "sample": f"{calls} full randomized t-SVTs of the workload ({P} slices each, FP64 numpy/LAPACK, "
-                      f"{dt:.1f} s incl. transforms and sketch draws)"}
+    with threadpool_limits(limits=1):
+        done1, dt1 = run(budget_s / 2)
+    unit = "whole randomized t-SVTs of the workload" if whole else "sampled canonical slices (transformed slice " \
+        "by the definition + randomized estimate)"
+    return {"value": round(done / dt, 3), "unit": "slices/s", "cores": int(threads), "kind": "oracle",
+            "sample": f"{done} slices in {dt:.1f} s: {unit}, FP64 numpy/LAPACK",
+            "one_thread": {"value": round(done1 / dt1, 3), "sample": f"{done1} slices in {dt1:.1f} s"},
+            **_host_info()}
 
 
-def counter_traffic(stage):
-    """HBM bytes per launch of a sketch product from the committed rocprofv3 counter
-    summary, or None if the summary is missing or the kernel sources changed since."""
+COUNTER_FILES = {
+    "tsvt_256x256x16x16_fp32_rank20_dct": "sketch_256x256x16x16_fp32_hbm_counters.md",
+    "rpca_dft_1024x1024x32x8_rank50_bf16": "sketch_1024x1024x32x8_dft_bf16_hbm_counters.md",
+}
+
+
+def counter_traffic(stage, workload):
+    """HBM bytes per launch of a stage from the committed rocprofv3 counter
+    summary of the workload, or None if the summary is missing or the kernel
+    sources changed since it was taken."""
     import hashlib
     import re
-    path = os.path.join(ROOT, "profiles", "sketch_256x256x16x16_fp32_hbm_counters.md")
+    if workload not in COUNTER_FILES:
+        return None
+    path = os.path.join(ROOT, "profiles", COUNTER_FILES[workload])
     if not os.path.exists(path):
         return None
     text = open(path).read()
@@ -319,17 +419,44 @@ def bench_solver(args):
             "speedups_at_equal_error": best}
 
 
+def solver_forms(steps=100):
+    """Completion solver on the 256 x 256 x 16 x 16 rank-20 DCT tensor, 20%
+    observed, 100 iterations: iteration time and final relative recovery error
+    of the plain FP32 form and of BF16-mixed sketches (equal error: within 5% of
+    the plain form's)."""
+    import numpy as np
+
+    from oracle import solver as osolver
+    from workloads import synth
+    dims, kinds = (256, 256, 16, 16), ["dct2", "dct2"]
+    L = synth.lowrank_tensor(dims, 20, kinds, seed=2)
+    mask = synth.observation_mask(dims, 0.2, 2)
+    M = np.where(mask, L, 0.0).astype(np.float32).astype(np.float64)
+    forms = {}
+    for name, prec in (("plain_fp32", "fp32"), ("bf16_mixed", "bf16")):
+        Lh, dt, _, _ = _solve(dims, kinds, M, mask, 20, 10, prec, 1.15, steps, 2)
+        forms[name] = {"ms_per_iter": round(dt * 1e3, 4), "rse": osolver.rse(Lh, L)}
+    base = forms["plain_fp32"]
+    for name, v in forms.items():
+        if name != "plain_fp32":
+            v["speedup_vs_plain"] = round(base["ms_per_iter"] / v["ms_per_iter"], 3)
+            v["equal_error"] = bool(v["rse"] <= 1.05 * base["rse"])
+    return {"workload": "completion_256x256x16x16_rank20_sr0.2_100it", "iterations": steps, "forms": forms}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--precision", choices=["fp32", "bf16"], default="fp32",
-                    help="fp32 (default) or the BF16-mixed path (BF16 transformed slices and sketch products)")
-    ap.add_argument("--workload", choices=["tsvt", "batch", "solver"], default="tsvt",
-                    help="tsvt (default): the 256x256x16x16 t-SVT line; batch: 64 uneven tensors in one plan "
-                         "against per-tensor plans; solver: completion iteration time against the plain FP32 form")
+    ap.add_argument("--no-solver", action="store_true", help="skip the completion solver comparison")
+    ap.add_argument("--precision", choices=["fp32", "bf16"], default=None,
+                    help="override the workload's precision (fp32, or the BF16-mixed path)")
+    ap.add_argument("--workload", choices=["rpca", "tsvt", "batch", "solver"], default="rpca",
+                    help="rpca (default): the 1024x1024x32x8 DFT t-SVT line; tsvt: the 256x256x16x16 DCT line; "
+                         "batch: 64 uneven tensors in one plan against per-tensor plans; solver: completion "
+                         "iteration time against the plain FP32 form")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a plain 256 MiB device copy (known bytes) to calibrate HBM counters")
     args = ap.parse_args()
@@ -350,17 +477,22 @@ def main():
     from paper_2506_09594_amd import htsvt as ht
     from workloads import synth
 
-    wl = dict(WORKLOAD)
-    if args.precision != wl["precision"]:
+    wl = dict(WORKLOADS[args.workload])
+    if args.precision and args.precision != wl["precision"]:
+        wl["name"] = wl["name"].replace("_" + wl["precision"], "_" + args.precision)
         wl["precision"] = args.precision
-        wl["name"] = wl["name"].replace("_fp32_", "_" + args.precision + "_")
+    cplx = wl["kinds"][0] == "dft"
     torch.cuda.set_device(0)
-    X = synth.lowrank_tensor(wl["dims"], wl["rank"], wl["kinds"], seed=wl["seed"]).astype(np.float32)
+    if cplx:
+        dX = rpca_input(wl)
+    else:
+        dX = ht.to_device(synth.lowrank_tensor(wl["dims"], wl["rank"], wl["kinds"], seed=wl["seed"]).astype(
+            np.float32), torch.float32)
     plan = ht.Plan(wl["dims"], wl["kinds"], r=wl["r"], p=wl["p"], q=wl["q"], precision=wl["precision"],
                    seed=wl["seed"])
-    dX = ht.to_device(X, torch.float32)
     dOut = torch.empty_like(dX)
     ws = plan.alloc_workspace()
+    P_logical = int(np.prod(wl["dims"][2:]))
     for i in range(args.warmup):
         plan.gnhtsvt(dX, wl["tau"], wl["penalty"], call_index=i, out=dOut, workspace=ws)
     torch.cuda.synchronize()
@@ -378,19 +510,19 @@ def main():
     plan.profile(False)
 
     ms_per_step = 1e3 * dt / args.steps
-    value = plan.n_slices / (dt / args.steps)
+    value = P_logical / (dt / args.steps)
     es = 4
     stages = {k: {"ms_per_launch": (v[0] / v[1]) if v[1] else 0.0, "launches_per_step": v[1] / args.steps,
                   "ms_per_step": v[0] / args.steps} for k, v in prof.items() if v[1]}
     # dominant HBM-streaming kernel: the largest per-step total among stages with an algorithmic byte count
-    hbm_stages = [k for k in stages if stage_bytes(k, plan, es) is not None]
+    hbm_stages = [k for k in stages if stage_bytes(k, plan, es, cplx) is not None]
     dom = max(hbm_stages, key=lambda k: stages[k]["ms_per_step"])
     ms = stages[dom]["ms_per_launch"]
-    achieved = stage_bytes(dom, plan, es) / (ms * 1e-3) / 1e9
+    nbytes = stage_bytes(dom, plan, es, cplx)
+    achieved = nbytes / (ms * 1e-3) / 1e9
     roof = {"kernel": dom, "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": counter_traffic(dom) if wl["precision"] == "fp32" else None,
-            "algorithmic_bytes_per_launch": stage_bytes(dom, plan, es), "ms_per_launch": round(ms, 5)}
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": counter_traffic(dom, wl["name"]),
+            "algorithmic_bytes_per_launch": nbytes, "ms_per_launch": round(ms, 5)}
     if args.calib_copy:
         src = torch.empty(64 * 1024 * 1024, dtype=torch.float32, device="cuda").fill_(1.0)
         dst = torch.empty_like(src)
@@ -411,11 +543,17 @@ def main():
         "dtype": "f32" if wl["precision"] == "fp32" else "bf16-f32acc",
         "data": "synthetic",
         "config": {"workload": wl["name"], "dims": list(wl["dims"]), "r": wl["r"], "p": wl["p"], "q": wl["q"],
-                   "transform": "dct2 on modes 3,4", "penalty": "mcp", "slices_per_step": plan.n_slices},
+                   "transform": wl["transform"], "penalty": wl["penalty"][0], "slices_per_step": P_logical,
+                   "sketched_slices_per_step": plan.n_slices},
         "roofline": roof,
         "stages": {k: {kk: round(vv, 5) for kk, vv in v.items()} for k, v in stages.items()},
     }
+    del dOut, ws
+    if not args.no_solver:
+        line["solver"] = solver_forms()
     if not args.no_cpu:
+        X = dX.cpu().numpy().reshape(wl["dims"], order="F")
+        del dX
         line["cpu_baseline"] = cpu_baseline(X, wl)
     print(json.dumps(line), flush=True)
 

@@ -104,18 +104,19 @@ typedef struct {
  *  r, p, q     target rank r >= 1, oversampling p >= 0, power steps q >= 0;
  *              sketch width l = min(r + p, n1, n2) <= HT_MAX_WIDTH, kept k = min(r, l)
  *  precision   HT_FP64 / HT_FP32 / HT_BF16_MIXED
- *  DFT         with HT_DFT_UNITARY on every mode 3..d the transformed slices
- *              are complex; for real X slice partner(j) (every transform-domain
- *              index negated modulo n_k) is the conjugate of slice j, so only
- *              the canonical member of each pair (the smaller index) is
- *              sketched, with the real Gaussian Omega keyed by that index, and
- *              the partner's result is its conjugate (the output is real).  A
- *              complex slice is sketched through its real embedding
- *              [[Re, -Im], [Im, Re]] with blockdiag(Omega, Omega), so the plan
- *              needs 2 l <= HT_MAX_WIDTH, reports width 2 l and kept 2 k, and
- *              its singular values come in equal pairs.  Mixing DFT and real
- *              kinds is UNSUPPORTED, as are ht_transform, ht_omega_fp64 and
- *              learned widths on such plans.
+ *  DFT         with a DFT kind (HT_DFT_UNITARY or HT_DFT_UNNORMALIZED) on every
+ *              mode 3..d the transformed slices are complex; for real X slice
+ *              partner(j) (every transform-domain index negated modulo n_k) is
+ *              the conjugate of slice j, so only the canonical member of each
+ *              pair (the smaller index) is sketched, with the real Gaussian
+ *              Omega (n2 x l) keyed by that index, and the partner's result is
+ *              its conjugate (the output is real).  Every product is the
+ *              complex one (conjugate transposes where the method transposes);
+ *              CholeskyQR and the small SVD run in complex FP64.  Complex slices
+ *              need l <= 64.  n_slices, width and kept (ht_plan_info) count
+ *              canonical slices and complex columns.  Mixing DFT and real kinds
+ *              is UNSUPPORTED, as are ht_transform, ht_omega_fp64 and learned
+ *              widths on such plans.
  *  seed, stream_id  key of the Gaussian sketch generator (Philox4x32-10,
  *              counter (group, slice, call, stream_id), key = seed) */
 typedef struct {
@@ -180,7 +181,9 @@ int ht_plan_info(const ht_plan* plan, int64_t* n_slices, int* width, int* kept);
  * 16 singular values (P x l_max doubles), 17 kept counts (P ints),
  * 18 ||A_j||^2 (previous, current; P x 2 doubles), 19 features (P x 32
  * floats), 20 state (ints: history valid, predicted slices, redone slices).  Thin blocks of slice j start at
- * j * align4(rows * l) elements (align4 rounds up to a multiple of 4). */
+ * j * align4(rows * l) elements (align4 rounds up to a multiple of 4).  A
+ * complex slice keeps its real and imaginary parts stacked: A and C blocks of
+ * 2 n1 x n2, thin blocks of 2 rows x l, K' of 2 l x l (column-major). */
 int ht_plan_workspace_region(const ht_plan* plan, int region, size_t* offset, size_t* bytes);
 
 /* Randomized GNHTSVT (Def. 4.3 computed slice-wise on sketches):

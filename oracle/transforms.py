@@ -102,6 +102,23 @@ def inverse(X, transforms):
     return Y
 
 
+def forward_slice(X, transforms, j):
+    """Transformed face slice j of L(X) alone, by the definition of the mode
+    products: L(X)^<j> = sum_{j'} (prod_k U_k[i_k, i'_k]) X^<j'>, with j and j'
+    split into mode indices as in slice_index.  The coefficient vector over j'
+    is the Kronecker product of the rows U_d[i_d], ..., U_3[i_3] (i_3 fastest)."""
+    dims = X.shape
+    idx = np.unravel_index(int(j), dims[2:], order="F")
+    coef = np.ones(1, dtype=np.complex128)
+    for k in reversed(range(len(transforms))):
+        coef = np.kron(coef, transforms[k][0][idx[k], :])
+    P = int(np.prod(dims[2:]))
+    S = np.asarray(X).reshape((dims[0], dims[1], P), order="F")
+    if not np.iscomplexobj(S):  # real data: the real and imaginary coefficients apart
+        return np.tensordot(S, coef.real, axes=([2], [0])) + 1j * np.tensordot(S, coef.imag, axes=([2], [0]))
+    return np.tensordot(S, coef, axes=([2], [0]))
+
+
 def rho(transforms):
     """rho = alpha_3 * ... * alpha_d."""
     r = 1.0

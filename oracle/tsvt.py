@@ -76,6 +76,21 @@ def sketch_slice(Aj, Om, q):
     return Q, Q.conj().T @ Aj
 
 
+def tsvt_slice(Aj, tau, penalty, k, q, Om, info=None):
+    """The randomized estimate C_j = Q U_B[:, :k] diag(Prox(s[:k])) V_B[:, :k]^H
+    of one transformed slice A_j with sketch matrix Om (n2 x l).  info, if a
+    dict, receives 'sigma' (the l singular values of B), 'kept' and
+    'tail_energy' ||A_j||_F^2 - ||B||_F^2."""
+    Q, B = sketch_slice(Aj, Om, q)
+    ub, s, vbh = np.linalg.svd(B, full_matrices=False)
+    st = _prox_vec(penalty, s[:k], tau)
+    if info is not None:
+        info["sigma"] = s
+        info["kept"] = int(np.count_nonzero(st))
+        info["tail_energy"] = np.linalg.norm(Aj) ** 2 - np.linalg.norm(B) ** 2
+    return (Q @ (ub[:, :k] * st[None, :])) @ vbh[:k, :]
+
+
 def omegas(dims, kinds, r, p, seed, call=0, stream=0, round_to=None):
     """Omega_j for every slice: n2 x l Gaussians keyed by the canonical slice index."""
     n1, n2 = dims[0], dims[1]
@@ -109,13 +124,12 @@ def tsvt_randomized(X, tau, penalty, transforms, r, p, q, omega_list, stats=None
         Aj = LX[:, :, j]
         Om = omega_list[j]
         assert Om.shape == (n2, l)
-        Q, B = sketch_slice(Aj, Om, q)
-        ub, s, vbh = np.linalg.svd(B, full_matrices=False)
-        st = _prox_vec(penalty, s[:k], tau)
-        out[:, :, j] = (Q @ (ub[:, :k] * st[None, :])) @ vbh[:k, :]
+        info = {}
+        out[:, :, j] = tsvt_slice(Aj, tau, penalty, k, q, Om, info)
+        s = info["sigma"]
         sig_all.append(np.pad(s, (0, l - len(s))))
-        kept_all.append(int(np.count_nonzero(st)))
-        tail_all.append(np.linalg.norm(Aj) ** 2 - np.linalg.norm(B) ** 2)
+        kept_all.append(info["kept"])
+        tail_all.append(info["tail_energy"])
     if stats is not None:
         stats["sigma"] = np.array(sig_all)
         stats["k"] = k
@@ -132,11 +146,7 @@ def tsvt_randomized_widths(X, tau, penalty, transforms, widths, kepts, q, omega_
     LX = tr.to_slices(tr.forward(X, transforms))
     out = np.zeros_like(LX, dtype=np.complex128)
     for j in range(LX.shape[2]):
-        Aj = LX[:, :, j]
         l, k = int(widths[j]), int(kepts[j])
-        Q, B = sketch_slice(Aj, omega_list[j][:, :l], q)
-        ub, s, vbh = np.linalg.svd(B, full_matrices=False)
-        st = _prox_vec(penalty, s[:k], tau)
-        out[:, :, j] = (Q @ (ub[:, :k] * st[None, :])) @ vbh[:k, :]
+        out[:, :, j] = tsvt_slice(LX[:, :, j], tau, penalty, k, q, omega_list[j][:, :l])
     res = tr.inverse(tr.from_slices(out, X.shape), transforms)
     return _realify(res, X)

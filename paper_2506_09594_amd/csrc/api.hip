@@ -264,8 +264,8 @@ int add_tensor(const ht_plan_desc* d, std::vector<double>& tab, TensorHost& t) {
   if (ndft > 0 && ndft != d->order - 2)
     HT_FAIL(HT_ERR_UNSUPPORTED, "a DFT must be the transform of every mode 3..d (no mixing with real kinds)");
   t.cplx = ndft > 0;
-  if (t.cplx && 2 * t.l > HT_MAX_WIDTH)
-    HT_FAIL(HT_ERR_UNSUPPORTED, "complex slices are sketched through their real embedding: need 2 l <= HT_MAX_WIDTH");
+  if (t.cplx && t.l > kMaxComplexWidth)
+    HT_FAIL(HT_ERR_UNSUPPORTED, "complex slices need a sketch width l = min(r + p, n1, n2) <= 64");
   if (t.cplx && (2 * t.n1 * t.n2 > (int64_t)INT32_MAX))
     HT_FAIL(HT_ERR_UNSUPPORTED, "complex face slice above 2^31 elements");
   t.fwd.nmodes = t.inv.nmodes = d->order - 2;
@@ -587,9 +587,9 @@ int build_plan(const ht_plan_desc* descs, int n, bool batch, ht_plan** out) {
     Atot += th.nslots * f * th.n1 * th.n2;
     Atot = (Atot + 63) / 64 * 64;
     P += th.nslots;
-    pl->lmax = std::max(pl->lmax, f * th.l);
-    pl->kmax = std::max(pl->kmax, f * th.k);
-    pl->max_n2l = std::max<int64_t>(pl->max_n2l, (int64_t)f * th.n2 * f * th.l);
+    pl->lmax = std::max(pl->lmax, th.l);
+    pl->kmax = std::max(pl->kmax, th.k);
+    pl->max_n2l = std::max<int64_t>(pl->max_n2l, (int64_t)th.n2 * th.l);  // the real Omega
     ncplx += th.cplx;
   }
   if (ncplx != 0 && ncplx != n) {
@@ -605,13 +605,13 @@ int build_plan(const ht_plan_desc* descs, int n, bool batch, ht_plan** out) {
   pl->Ptot = P;
   pl->Atot = Atot;
 
-  // slice table (complex slices: the real embedding of the n1 x n2 complex matrix)
+  // slice table (complex slices: stacked real and imaginary parts, f = 2)
   pl->h_slices.resize(P);
   int64_t oY = 0, oZ = 0, oK = 0, oG1 = 0, oG2 = 0;
   for (int t = 0; t < n; ++t) {
     const TensorHost& th = pl->tens[t];
     const int f = th.cplx ? 2 : 1;
-    const int64_t NT = th.n1 * th.n2, l = f * th.l, n1 = f * th.n1, n2 = f * th.n2;
+    const int64_t NT = th.n1 * th.n2, l = th.l, n1 = th.n1, n2 = th.n2;
     for (int64_t j = 0, s = 0; j < th.P; ++j) {
       if (th.cplx && cmap[th.cmap + j] < 0) continue;  // a conjugate partner: no slot
       SliceDesc& d = pl->h_slices[th.slice0 + s];
@@ -624,18 +624,18 @@ int build_plan(const ht_plan_desc* descs, int n, bool batch, ht_plan** out) {
       d.n1 = (int32_t)n1;
       d.n2 = (int32_t)n2;
       d.l = (int32_t)l;
-      d.k = f * th.k;
+      d.k = th.k;
       d.tensor = t;
       d.local = (int32_t)j;  // the Philox slice word: the canonical member's index
       d.p = th.p;
       d.cplx = th.cplx;
       d.nc = (int32_t)th.n2;
       d.pad = 0;
-      oY += align4(n1 * l);
-      oZ += align4(n2 * l);
-      oK += align4(l * l);
-      oG1 += ceil_div(std::max(n1, n2), 64) * l * l;
-      oG2 += ceil_div(n1, 64) * l * l;
+      oY += align4(f * n1 * l);
+      oZ += align4(f * n2 * l);
+      oK += align4(f * l * l);
+      oG1 += ceil_div(std::max(n1, n2), 64) * f * l * l;
+      oG2 += ceil_div(n1, 64) * f * l * l;
       ++s;
     }
   }
@@ -681,7 +681,7 @@ int build_plan(const ht_plan_desc* descs, int n, bool batch, ht_plan** out) {
     pl->class_lmax[c] = 0;
     for (const int2& it : svc[c]) pl->class_lmax[c] = std::max(pl->class_lmax[c], (int)pl->h_slices[it.x].l);
   }
-  pl->class_split = nused > 1;
+  pl->class_split = nused > 1 && !pl->cplx;
   for (int c = 0; c < kNumClasses; ++c) {
     lists.push_back(oyc[c]);
     lists.push_back(ozc[c]);
@@ -868,8 +868,18 @@ int run_tsvt(const ht_plan* pl, const T* X, T* out, double tau, const double* ta
                                               pl->seed, 0, s);
                      })))
     return rc;
+  const bool cplx = pl->cplx;
   auto sketch_nn = [&](const T* W, const int2* wk) {
     return timed(pl, ST_SKETCH_NN, s, [&] {
+      if (cplx) {  // items of 64 complex rows
+        const ItemList& L = pl->it_nn[0];
+        if (bf16)
+          return launch_bf16_cnn(Ah, (const float*)W, (float*)Y, W == Om, sd, wk, items(pl, L), L.n, lmax, gp1, s);
+        if (!fp64)
+          return launch_mfma_cnn((const float*)A, (const float*)W, (float*)Y, W == Om, sd, wk, items(pl, L), L.n,
+                                 lmax, gp1, s);
+        return launch_cgemm<T>(A, W, Y, 0, W == Om, sd, wk, items(pl, L), L.n, lmax, gp1, s);
+      }
       const ItemList& L = pl->it_nn[ri];
       if (bf16)
         return launch_bf16_nn(Ah, (const float*)W, (float*)Y, sd, wk, items(pl, L), L.n, lmax, rows, gp1, s);
@@ -884,6 +894,14 @@ int run_tsvt(const ht_plan* pl, const T* X, T* out, double tau, const double* ta
   };
   auto sketch_tn = [&](const int2* wk) {
     return timed(pl, ST_SKETCH_TN, s, [&] {
+      if (cplx) {
+        const ItemList& L = pl->it_tn[0];
+        if (bf16) return launch_bf16_ctn(Ah, (const float*)Y, (float*)Z, sd, wk, items(pl, L), L.n, lmax, gp1, s);
+        if (!fp64)
+          return launch_mfma_ctn((const float*)A, (const float*)Y, (float*)Z, sd, wk, items(pl, L), L.n, lmax, gp1,
+                                 s);
+        return launch_cgemm<T>(A, Y, Z, 1, 0, sd, wk, items(pl, L), L.n, lmax, gp1, s);
+      }
       const ItemList& L = pl->it_tn[ri];
       if (bf16) return launch_bf16_tn(Ah, (const float*)Y, (float*)Z, sd, wk, items(pl, L), L.n, lmax, rows, gp1, s);
       if (!fp64)
@@ -894,6 +912,10 @@ int run_tsvt(const ht_plan* pl, const T* X, T* out, double tau, const double* ta
   };
   auto orth = [&](int which, double* gout, const int2* wk) {
     return timed(pl, ST_CHOLQR, s, [&] {
+      if (cplx) {
+        const ItemList& L = which ? pl->it_oz : pl->it_oy;
+        return launch_corth<T>(which ? Z : Y, which, sd, wk, items(pl, L), L.n, lmax, P, gp1, gout, s);
+      }
       if (wk == nullptr && pl->class_split) {  // one launch per width class
         for (int c = 0; c < kNumClasses; ++c) {
           const ItemList& L = which ? pl->it_ozc[c] : pl->it_oyc[c];
@@ -926,6 +948,9 @@ int run_tsvt(const ht_plan* pl, const T* X, T* out, double tau, const double* ta
     }
     if ((r = sketch_tn(wk))) return r;
     return timed(pl, ST_SMALLSVD, s, [&] {
+      if (cplx)
+        return launch_csvd<T>(gp2, gp1, sd, wk, nullptr, P, lmax, lmax, tau, tau_dev, mu_dev, pen, K, sig_dst,
+                              kept_dst, status, s);
       if (wk == nullptr && pl->class_split) {  // one launch per width class
         for (int c = 0; c < kNumClasses; ++c) {
           const ItemList& L = pl->it_svc[c];
@@ -962,6 +987,12 @@ int run_tsvt(const ht_plan* pl, const T* X, T* out, double tau, const double* ta
   }
   // C = (Q1 K') Bt^T, then the inverse transform
   if ((rc = timed(pl, ST_RECON_QK, s, [&] {
+         if (cplx) {
+           if (!fp64)
+             return launch_mfma_cqk((const float*)Y, (const float*)K, (float*)QK, sd, wk_final, items(pl, pl->it_qk),
+                                    pl->it_qk.n, lmax, s);
+           return launch_crecon<T>(Y, K, QK, 0, sd, wk_final, items(pl, pl->it_qk), pl->it_qk.n, s);
+         }
          if (!fp64 && lmax <= 64)
            return launch_mfma_qk((const float*)Y, (const float*)K, (float*)QK, sd, wk_final, items(pl, pl->it_qk),
                                  pl->it_qk.n, lmax, s);
@@ -969,6 +1000,12 @@ int run_tsvt(const ht_plan* pl, const T* X, T* out, double tau, const double* ta
        })))
     return rc;
   if ((rc = timed(pl, ST_RECON_NT, s, [&] {
+         if (cplx) {
+           if (!fp64)
+             return launch_mfma_cnt((const float*)QK, (const float*)Z, (float*)C, sd, wk_final, items(pl, pl->it_nt),
+                                    pl->it_nt.n, lmax, s);
+           return launch_crecon<T>(QK, Z, C, 1, sd, wk_final, items(pl, pl->it_nt), pl->it_nt.n, s);
+         }
          if (!fp64)
            return launch_mfma_nt((const float*)QK, (const float*)Z, (float*)C, sd, wk_final, items(pl, pl->it_nt),
                                  pl->it_nt.n, lmax, s);

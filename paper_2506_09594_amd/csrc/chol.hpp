@@ -275,4 +275,62 @@ __device__ inline void tile_gram_mfma(const TS* S, int rs, int cs, int rows, int
   }
 }
 
+// Complex Gram partial of an LDS tile of 64 complex rows kept as 128 real
+// rows: row i < 64 is the real part of complex row i, row 64 + i its
+// imaginary part (element (i, c) at S[i * rs + c * cs]; rows past the slice
+// and columns c >= l hold zeros).  With Y = Yr + i Yi the tile's rows,
+//   out[a l + b]       = (Yr^T Yr + Yi^T Yi)[a][b] = Re (Y^H Y)  (both triangles)
+//   out[l^2 + a l + b] = (Yr^T Yi)[a][b] = M,  and Im (Y^H Y) = M - M^T.
+// Units: 16 x 16 blocks of the upper triangle of the real part (32 steps of
+// v_mfma_f64_16x16x4f64 over the 128 rows) and every 16 x 16 block of M (16
+// steps over the 64 row pairs); operand layout as tile_gram_mfma.
+template <typename TS>
+__device__ inline void tile_cgram_mfma(const TS* S, int rs, int cs, int l, double* __restrict__ out) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwv = (blockDim.x + 63) >> 6;
+  const int nb = (l + 15) / 16, nsym = nb * (nb + 1) / 2;
+  const int ll = l * l;
+  for (int unit = wave; unit < nsym + nb * nb; unit += nwv) {
+    const bool cross = unit >= nsym;
+    int bi = 0, bj = 0;
+    if (!cross) {
+      int blk = unit, len = nb;
+      while (blk >= len) {
+        blk -= len;
+        ++bi;
+        --len;
+      }
+      bj = bi + blk;
+    } else {
+      bi = (unit - nsym) / nb;
+      bj = (unit - nsym) % nb;
+    }
+    const int ci = 16 * bi + (lane & 15), cj = 16 * bj + (lane & 15), kq = lane >> 4;
+    gram_d4 g = {0.0, 0.0, 0.0, 0.0};
+    for (int part = 0; part < (cross ? 1 : 2); ++part) {
+      double a[16], b[16];
+#pragma unroll
+      for (int st = 0; st < 16; ++st) {
+        const int row = 64 * part + 4 * st + kq;
+        const int rowb = cross ? 64 + row : row;
+        a[st] = (ci < l) ? (double)S[row * rs + ci * cs] : 0.0;
+        b[st] = (cj < l) ? (double)S[rowb * rs + cj * cs] : 0.0;
+      }
+#pragma unroll
+      for (int st = 0; st < 16; ++st) g = __builtin_amdgcn_mfma_f64_16x16x4f64(a[st], b[st], g, 0, 0, 0);
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int i = 16 * bi + 4 * v + kq, j = 16 * bj + (lane & 15);
+      if (i < l && j < l) {
+        if (cross) {
+          out[ll + i * l + j] = g[v];
+        } else {
+          out[i * l + j] = g[v];
+          out[j * l + i] = g[v];
+        }
+      }
+    }
+  }
+}
+
 }  // namespace ht

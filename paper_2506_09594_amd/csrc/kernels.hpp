@@ -16,6 +16,10 @@ namespace ht {
 // partial per 64 rows of it, so a slice of m rows has ceil(m / 64) partials.
 constexpr int kGramRows = 64;
 
+// Largest sketch width of a complex slice (its l x l kernels hold two FP64
+// planes per matrix).
+constexpr int kMaxComplexWidth = 64;
+
 // Work items.  Every per-slice launch takes an item list: item i of a product
 // or orthonormalization launch is (slice, first row of its tile); of the
 // transform, (tensor, first tube position); of the reconstruction nt product,
@@ -108,6 +112,23 @@ int launch_bf16_nn(const uint16_t* A, const float* W, float* Y, const SliceDesc*
 int launch_bf16_tn(const uint16_t* A, const float* Q, float* Z, const SliceDesc* sd, const int2* wk,
                    const int2* items, int nitems, int lmax, int rows, double* gpart, hipStream_t s);
 
+// Complex slices (stacked layout) on the matrix cores, l <= kMaxComplexWidth,
+// items of 64 complex rows: nn Y = A W (wreal: W is the real Omega, n2 x l),
+// tn Z = A^H Q, with complex Gram partials; reconstruction QK = Q1 K' (items
+// of 64 complex rows) and C = QK Bt^H (64 x 64 tiles as launch_mfma_nt).
+int launch_mfma_cnn(const float* A, const float* W, float* Y, int wreal, const SliceDesc* sd, const int2* wk,
+                    const int2* items, int nitems, int lmax, double* gpart, hipStream_t s);
+int launch_mfma_ctn(const float* A, const float* Q, float* Z, const SliceDesc* sd, const int2* wk, const int2* items,
+                    int nitems, int lmax, double* gpart, hipStream_t s);
+int launch_bf16_cnn(const uint16_t* A, const float* W, float* Y, int wreal, const SliceDesc* sd, const int2* wk,
+                    const int2* items, int nitems, int lmax, double* gpart, hipStream_t s);
+int launch_bf16_ctn(const uint16_t* A, const float* Q, float* Z, const SliceDesc* sd, const int2* wk,
+                    const int2* items, int nitems, int lmax, double* gpart, hipStream_t s);
+int launch_mfma_cqk(const float* Q, const float* K, float* QK, const SliceDesc* sd, const int2* wk, const int2* items,
+                    int nitems, int lmax, hipStream_t s);
+int launch_mfma_cnt(const float* X, const float* W, float* C, const SliceDesc* sd, const int2* wk, const int2* items,
+                    int nitems, int lmax, hipStream_t s);
+
 // One CholeskyQR pass with deflation, in place on the basis `which` (0: Y of
 // n1 rows, 1: Z of n2 rows) from the Gram partials of the producing product
 // (gin at the slice's g1 offset, one per 64 rows).  Optionally
@@ -134,6 +155,32 @@ template <typename T>
 int launch_smallsvd(double* g2, const double* gw, const SliceDesc* sd, const int2* wk, const int2* slices, int nslices,
                     int lmax, int sigma_ld, double tau, const double* tau_dev, const double* mu_dev, Penalty pen,
                     T* K, double* sigma_out, int* kept_out, int* status, hipStream_t s);
+
+// Complex slices (unitary or plain DFT on every mode 3..d; cplx.hip): the
+// stacked [Re; Im] storage described in layout.hpp, widths up to
+// kMaxComplexWidth.  Gram partials: one per 64 complex rows, 2 l^2 doubles.
+// CholeskyQR with deflation of the complex basis `which` (0: Y, 1: Z): one
+// factor launch per slice (R^{-1} parked over the first partial of gin), then
+// Q = Y R^{-1} per 64-complex-row item; gout as launch_orth_apply.
+template <typename T>
+int launch_corth(T* Y, int which, const SliceDesc* sd, const int2* wk, const int2* items, int nitems, int lmax,
+                 int nslices, double* gin, double* gout, hipStream_t s);
+// Small SVD and shrinkage of complex slices (arguments as launch_smallsvd;
+// K' is written stacked, 2 l x l).
+template <typename T>
+int launch_csvd(double* g2, const double* gw, const SliceDesc* sd, const int2* wk, const int2* slices, int nslices,
+                int lmax, int sigma_ld, double tau, const double* tau_dev, const double* mu_dev, Penalty pen, T* K,
+                double* sigma_out, int* kept_out, int* status, hipStream_t s);
+// Complex sketch products on the vector units: trans = 0: Y = A W (wreal: W is
+// the real Omega, n2 x l), trans = 1: Z = A^H Q; items of 64 complex rows.
+template <typename T>
+int launch_cgemm(const T* A, const T* W, T* Y, int trans, int wreal, const SliceDesc* sd, const int2* wk,
+                 const int2* items, int nitems, int lmax, double* gpart, hipStream_t s);
+// Complex reconstruction on the vector units: mode 0: QK = Q1 K' (items of 64
+// complex rows), mode 1: C = QK Bt^H (64 x 64 tiles as launch_gemm_nt).
+template <typename T>
+int launch_crecon(const T* X, const T* W, T* C, int mode, const SliceDesc* sd, const int2* wk, const int2* items,
+                  int nitems, hipStream_t s);
 
 // Learned widths (mlp.hip).  Network parameters: one flat FP32 vector of
 // mlp_param_count() entries.  Gradient steps use a partial buffer of

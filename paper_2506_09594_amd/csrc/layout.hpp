@@ -45,9 +45,9 @@ struct TensorDesc {
 
 // One transformed face slice.  Thin blocks are laid out for the plan's
 // maximum width lmax; a slice uses the first l columns.  A complex slice
-// (cplx = 1) is handled through the real embedding of its n1o x n2o complex
-// matrix, [[Re, -Im], [Im, Re]]: here n1 = 2 n1o, n2 = 2 n2o, and l, k are
-// twice the complex width and kept count (singular values come in pairs).
+// (cplx = 1, DFT on every transformed mode) of n1 x n2 complex entries is the
+// stacked real block [Re; Im] (2 n1 x n2) at a; its thin blocks are stacked
+// too (Y: 2 n1 x l, Z: 2 n2 x l, K: 2 l x l) and l, k count complex columns.
 struct SliceDesc {
   int64_t a;   // offset of the n1 x n2 slice in A and C (elements)
   int64_t y;   // offset of its n1 x lmax block in Y and QK
@@ -55,19 +55,20 @@ struct SliceDesc {
   int64_t kq;  // offset of its lmax x lmax block in K
   int64_t g1;  // offset (doubles) of its product Gram partials (ceil(max(n1,n2)/64) tiles)
   int64_t g2;  // offset (doubles) of its basis Gram partials (ceil(n1/64) tiles)
-  int32_t n1, n2;
+  int32_t n1, n2;   // rows and columns (complex entries for a complex slice)
   int32_t l, k;     // sketch width and number of kept singular values
   int32_t tensor;   // index of the tensor (the Philox stream word is stream_base + tensor)
   int32_t local;    // slice index within the tensor (the Philox counter word)
   int32_t p;        // oversampling of the tensor (learned widths)
-  int32_t cplx;     // complex slice (real embedding of the stacked block)
-  int32_t nc;       // columns of C written by the reconstruction (n2, or n2o)
+  int32_t cplx;     // complex slice (stacked real and imaginary parts)
+  int32_t nc;       // columns of C written by the reconstruction (n2)
   int32_t pad;
 };
 
-// Element (r, k) of the operand of slice d: the stored column-major block, or
-// for a complex slice the real embedding [[Ar, -Ai], [Ai, Ar]] of the stacked
-// block [Ar; Ai] (lda = 2 n1o rows, n2o columns), without forming it.
+// Element (r, k) of the real embedding [[Ar, -Ai], [Ai, Ar]] (2 n1o x 2 n2o)
+// of a complex matrix stored as the stacked block [Ar; Ai] (lda = 2 n1o rows,
+// n2o columns), without forming it; cplx = 0: the stored block itself.  The
+// embedding times a stacked [Wr; Wi] is the stacked complex product.
 __host__ __device__ inline int64_t embed_index(int r, int k, int lda, int cplx, int n1o, int n2o, bool& neg) {
   neg = false;
   if (cplx && k >= n2o) {

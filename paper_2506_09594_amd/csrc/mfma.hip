@@ -42,14 +42,21 @@ struct MfmaLds {
 };
 
 // TRANS = false: nn (A rows are output rows); TRANS = true: tn (A columns are
-// output rows).
-template <int NB, int NW, bool TRANS>
+// output rows).  CPLX: complex slices in the stacked layout (NW = 4): A enters
+// through its real embedding, so that the product with a stacked thin operand
+// is the stacked complex product (nn: Y = A W, or with wreal the real Omega
+// against the stored block; tn: Z = A^H Q), and the tile's 128 rows are 64
+// complex rows, their real parts then their imaginary parts, whose complex
+// Gram partial the epilogue writes.
+template <int NB, int NW, bool TRANS, bool CPLX>
 __global__ __launch_bounds__(64 * NW) void k_mfma_thin(const float* __restrict__ Aall, const float* __restrict__ Wall,
                                                        float* __restrict__ Yall, const SliceDesc* __restrict__ sd,
                                                        const int2* __restrict__ wk, const int2* __restrict__ items,
-                                                       double* __restrict__ gpart, int aligned) {
+                                                       double* __restrict__ gpart, int aligned, int wreal) {
   using L = MfmaLds<NB, NW>;
   constexpr int MT = L::MT;
+  constexpr int HM = MT / 2;  // complex rows of a tile
+  static_assert(!CPLX || MT == 128, "complex tiles hold 64 complex rows");
   constexpr int NTH = 64 * NW;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   float* const lds_f = reinterpret_cast<float*>(smem_raw);
@@ -59,29 +66,32 @@ __global__ __launch_bounds__(64 * NW) void k_mfma_thin(const float* __restrict__
   const SliceDesc d = sd[s];
   const int l = slice_width(d, wk, s);
   if (l <= 0) return;  // slice not part of this pass
-  const int lda = d.n1;
-  const int M_out = TRANS ? d.n2 : d.n1;
-  const int K = TRANS ? d.n1 : d.n2;
+  const int mo = TRANS ? d.n2 : d.n1;  // output rows (complex rows when CPLX)
+  const int lda = CPLX ? 2 * d.n1 : d.n1;
+  const int M_out = CPLX ? 2 * mo : mo;
+  const int K = CPLX ? (TRANS ? 2 * d.n1 : (wreal ? d.n2 : 2 * d.n2)) : (TRANS ? d.n1 : d.n2);
   const int ldw = K, ldy = M_out;
   const int64_t woff = TRANS ? d.y : d.z, yoff = TRANS ? d.z : d.y;
   const float* Aj = Aall + d.a;
   const float* Wj = Wall + woff;
   float* Yj = Yall + yoff;
-  const int cplx = d.cplx, n1o = d.n1 / 2, n2o = d.n2 / 2;
-  const bool vecA = aligned && (lda % 4 == 0) && (d.a % 4 == 0) && (!cplx || n1o % 4 == 0);
+  const bool vecA = aligned && (lda % 4 == 0) && (d.a % 4 == 0) && (!CPLX || d.n1 % 4 == 0);
   const bool vecW = aligned && (ldw % 4 == 0) && (woff % 4 == 0);
   const int tid = threadIdx.x;
   const int wave = tid / 64, lane = tid % 64;
   const int LW = 32 * NB;
+  // stacked output row of tile row i, and whether it exists
+  auto orow = [&](int i) -> int { return CPLX ? (i >= HM ? mo + r0 + i - HM : r0 + i) : r0 + i; };
+  auto ovalid = [&](int i) -> bool { return CPLX ? r0 + (i >= HM ? i - HM : i) < mo : r0 + i < M_out; };
   // element (r, k) of the slice operand (complex slices: the real embedding)
   auto aval = [&](int r, int k) -> float {
     bool neg;
-    const float v = Aj[embed_index(r, k, lda, cplx, n1o, n2o, neg)];
+    const float v = Aj[embed_index(r, k, lda, CPLX, d.n1, d.n2, neg)];
     return neg ? -v : v;
   };
   auto avec = [&](int r, int k) -> f32x4 {  // rows r..r+3 of column k (no straddle when vecA)
     bool neg;
-    const f32x4 v = *reinterpret_cast<const f32x4*>(Aj + embed_index(r, k, lda, cplx, n1o, n2o, neg));
+    const f32x4 v = *reinterpret_cast<const f32x4*>(Aj + embed_index(r, k, lda, CPLX, d.n1, d.n2, neg));
     return neg ? -v : v;
   };
 
@@ -97,25 +107,25 @@ __global__ __launch_bounds__(64 * NW) void k_mfma_thin(const float* __restrict__
     for (int u = 0; u < NRA; ++u) {
       const int f = tid + u * NTH;
       if (!TRANS) {
-        const int kk = f / (MT / 4), row = (f % (MT / 4)) * 4;
-        const int gr = r0 + row, gk = k0 + kk;
-        if (vecA && gk < K && gr + 3 < M_out) {
+        const int kk = f / (MT / 4), row = (f % (MT / 4)) * 4;  // four rows within one half of a complex tile
+        const int gr = orow(row), gk = k0 + kk;
+        if (vecA && gk < K && ovalid(row + 3)) {
           ra[u] = avec(gr, gk);
         } else {
           f32x4 v;
 #pragma unroll
-          for (int e = 0; e < 4; ++e) v[e] = (gk < K && gr + e < M_out) ? aval(gr + e, gk) : 0.0f;
+          for (int e = 0; e < 4; ++e) v[e] = (gk < K && ovalid(row + e)) ? aval(gr + e, gk) : 0.0f;
           ra[u] = v;
         }
       } else {
         const int row = f / (KC / 4), kk = (f % (KC / 4)) * 4;
-        const int gc = r0 + row, gk = k0 + kk;
-        if (vecA && gc < M_out && gk + 3 < K) {
+        const int gc = orow(row), gk = k0 + kk;
+        if (vecA && ovalid(row) && gk + 3 < K) {
           ra[u] = avec(gk, gc);
         } else {
           f32x4 v;
 #pragma unroll
-          for (int e = 0; e < 4; ++e) v[e] = (gc < M_out && gk + e < K) ? aval(gk + e, gc) : 0.0f;
+          for (int e = 0; e < 4; ++e) v[e] = (ovalid(row) && gk + e < K) ? aval(gk + e, gc) : 0.0f;
           ra[u] = v;
         }
       }
@@ -210,21 +220,25 @@ __global__ __launch_bounds__(64 * NW) void k_mfma_thin(const float* __restrict__
   // ---- epilogue: tile to LDS (as double), coalesced store, Gram partial ----
   double* S = reinterpret_cast<double*>(smem_raw);
   const int sp = LW + 1;
-  const int rows = min(MT, M_out - r0);
 #pragma unroll
   for (int b = 0; b < NB; ++b)
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
       const int i = 32 * wave + 8 * (r / 4) + 4 * (lane / 32) + (r % 4);
       const int c = 32 * b + (lane % 32);
-      S[i * sp + c] = (i < rows && c < l) ? (double)acc[b][r] : 0.0;
+      S[i * sp + c] = (ovalid(i) && c < l) ? (double)acc[b][r] : 0.0;
     }
   __syncthreads();
   for (int idx = tid; idx < MT * l; idx += NTH) {
     const int i = idx % MT, c = idx / MT;
-    if (i < rows) Yj[(r0 + i) + (int64_t)c * ldy] = (float)S[i * sp + c];
+    if (ovalid(i)) Yj[orow(i) + (int64_t)c * ldy] = (float)S[i * sp + c];
   }
-  if (gpart) tile_gram_mfma(S, sp, 1, rows, l, gpart + d.g1 + (int64_t)(r0 / kGramRows) * l * l);
+  if (gpart) {
+    if (CPLX)
+      tile_cgram_mfma(S, sp, 1, l, gpart + d.g1 + (int64_t)(r0 / kGramRows) * 2 * l * l);
+    else
+      tile_gram_mfma(S, sp, 1, min(MT, M_out - r0), l, gpart + d.g1 + (int64_t)(r0 / kGramRows) * l * l);
+  }
 }
 
 // Streaming nn product for real FP32 slices (n1 % 4 == 0, n2 <= kStreamMaxK):
@@ -509,18 +523,106 @@ __global__ __launch_bounds__(4 * KMAX) void k_mfma_qk(const float* __restrict__ 
   }
 }
 
-template <int NB, int NW, bool TRANS>
+template <int NB, int NW, bool TRANS, bool CPLX = false>
 int launch_thin(const float* A, const float* W, float* Y, const SliceDesc* sd, const int2* wk, const int2* items,
-                int nitems, double* gpart, hipStream_t s) {
+                int nitems, double* gpart, hipStream_t s, int wreal = 0) {
   using L = MfmaLds<NB, NW>;
   if (nitems == 0) return HT_OK;
-  int rc = ensure_dynamic_lds((const void*)k_mfma_thin<NB, NW, TRANS>, L::BYTES);
+  int rc = ensure_dynamic_lds((const void*)k_mfma_thin<NB, NW, TRANS, CPLX>, L::BYTES);
   if (rc) return rc;
   const int aligned = (reinterpret_cast<uintptr_t>(A) % 16 == 0) && (reinterpret_cast<uintptr_t>(W) % 16 == 0);
-  hipLaunchKernelGGL((k_mfma_thin<NB, NW, TRANS>), dim3((unsigned)nitems), dim3(64 * NW), L::BYTES, s, A, W, Y, sd,
-                     wk, items, gpart, aligned);
+  hipLaunchKernelGGL((k_mfma_thin<NB, NW, TRANS, CPLX>), dim3((unsigned)nitems), dim3(64 * NW), L::BYTES, s, A, W, Y,
+                     sd, wk, items, gpart, aligned, wreal);
   HT_CHECK_LAUNCH();
   return HT_OK;
+}
+
+// Complex reconstruction on the matrix cores (FP32, complex slices in the
+// stacked layout, l <= 64):
+//   MODE 0: QK = Q1 K', a work item is 64 complex rows and all l columns;
+//   MODE 1: C = QK Bt^H, a work item is a 64 x 64 tile (complex rows; row tiles
+//           fastest, as the real reconstruction).
+// With the left factor X = Xr + i Xi and the right one B encoded as the real
+// 2 l x n matrix E = [Re B; -Im B], Re(X B) = [Xr, Xi] E and Im(X B) =
+// [Xi, -Xr] E.  Wavefront w computes the 32 x 32 block (rows 32 (w % 2),
+// columns 32 (w / 2)) of both parts on v_mfma_f32_32x32x2_f32: lane t supplies
+// row t % 32 of X and column t % 32 of E at k = 2 st + t / 32, every load
+// before the first step; the blocks go through LDS for coalesced stores.
+template <int MODE>
+__global__ __launch_bounds__(256) void k_mfma_cmul(const float* __restrict__ Xall, const float* __restrict__ Wall,
+                                                   float* __restrict__ Call, const SliceDesc* __restrict__ sd,
+                                                   const int2* __restrict__ wk, const int2* __restrict__ items) {
+  constexpr int TP = 68, NS = 64;  // staging pitch; steps for K = 2 l <= 128
+  __shared__ __align__(16) float Ts[2][64 * TP];  // [part][column][row]
+  const int2 item = items[blockIdx.x];
+  const int s = item.x;
+  const SliceDesc d = sd[s];
+  const int l = slice_width(d, wk, s);
+  if (l <= 0) return;  // slice not part of this pass
+  const int n1 = d.n1, n2 = d.n2, ldx = 2 * n1, K2 = 2 * l;
+  const int nrt = (n1 + 63) / 64;
+  const int row0 = MODE == 0 ? item.y : (item.y % nrt) * 64;
+  const int col0 = MODE == 0 ? 0 : (item.y / nrt) * 64;
+  const int ncols = MODE == 0 ? l : n2;
+  const float* X = Xall + d.y;                       // Q1 (MODE 0) or Q1 K' (MODE 1)
+  const float* W = Wall + (MODE == 0 ? d.kq : d.z);  // K' (2 l x l) or Bt (2 n2 x l)
+  float* C = Call + (MODE == 0 ? d.y : d.a);
+  const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+  const int li = lane % 32, h = lane / 32;
+  const int br = 32 * (wave % 2), bc = 32 * (wave / 2);
+  const int gr = row0 + br + li, gc = col0 + bc + li;
+  const bool rok = gr < n1, cok = gc < ncols;
+  const int lr = rok ? gr : 0, lc = cok ? gc : 0;
+  float are[NS], aim[NS], bv[NS];
+#pragma unroll
+  for (int st = 0; st < NS; ++st) {
+    const int k = 2 * st + h;
+    const bool kh = k >= l;
+    const int kk = min(kh ? k - l : k, l - 1);
+    const float xr = X[lr + (int64_t)kk * ldx], xi = X[n1 + lr + (int64_t)kk * ldx];
+    float e;
+    if (MODE == 0) {
+      const float v = W[(kh ? l : 0) + kk + (int64_t)lc * K2];
+      e = kh ? -v : v;
+    } else {
+      e = W[(kh ? n2 : 0) + lc + (int64_t)kk * 2 * n2];
+    }
+    const bool ok = k < K2;
+    are[st] = (ok && rok) ? (kh ? xi : xr) : 0.0f;
+    aim[st] = (ok && rok) ? (kh ? -xr : xi) : 0.0f;
+    bv[st] = (ok && cok) ? e : 0.0f;
+  }
+  f32x16 accr, acci;
+#pragma unroll
+  for (int r = 0; r < 16; ++r) accr[r] = acci[r] = 0.0f;
+#pragma unroll
+  for (int st = 0; st < NS; ++st)
+    if (2 * st < K2) {
+      accr = __builtin_amdgcn_mfma_f32_32x32x2f32(are[st], bv[st], accr, 0, 0, 0);
+      acci = __builtin_amdgcn_mfma_f32_32x32x2f32(aim[st], bv[st], acci, 0, 0, 0);
+    }
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    const int i = 8 * (r / 4) + 4 * h + (r % 4);
+    Ts[0][(bc + li) * TP + br + i] = accr[r];
+    Ts[1][(bc + li) * TP + br + i] = acci[r];
+  }
+  __syncthreads();
+  const int rows = min(64, n1 - row0), cols = min(64, ncols - col0);
+  const int64_t base = (MODE == 0 ? d.y : d.a);
+  const bool vec = (ldx % 4 == 0) && (n1 % 4 == 0) && (base % 4 == 0) && (row0 % 4 == 0);
+  for (int f = threadIdx.x; f < 2 * 64 * 16; f += 256) {
+    const int part = f / (64 * 16), g = f % (64 * 16);
+    const int c = g / 16, q = (g % 16) * 4;
+    if (c >= cols) continue;
+    float* dst = C + (part ? n1 : 0) + row0 + q + (int64_t)(col0 + c) * ldx;
+    const float* src = Ts[part] + c * TP + q;
+    if (vec && q + 3 < rows)
+      *reinterpret_cast<f32x4*>(dst) = *reinterpret_cast<const f32x4*>(src);
+    else
+      for (int e = 0; e < 4; ++e)
+        if (q + e < rows) dst[e] = src[e];
+  }
 }
 
 template <bool TRANS>
@@ -586,6 +688,38 @@ int launch_mfma_qk(const float* Q, const float* K, float* QK, const SliceDesc* s
     hipLaunchKernelGGL(k_mfma_qk<32>, grid, dim3(128), 0, s, Q, K, QK, sd, wk, items);
   else
     hipLaunchKernelGGL(k_mfma_qk<64>, grid, dim3(256), 0, s, Q, K, QK, sd, wk, items);
+  HT_CHECK_LAUNCH();
+  return HT_OK;
+}
+
+int launch_mfma_cnn(const float* A, const float* W, float* Y, int wreal, const SliceDesc* sd, const int2* wk,
+                    const int2* items, int nitems, int lmax, double* gpart, hipStream_t s) {
+  if (lmax > kMaxComplexWidth) HT_FAIL(HT_ERR_UNSUPPORTED, "complex sketch width above 64");
+  if (lmax <= 32) return launch_thin<1, 4, false, true>(A, W, Y, sd, wk, items, nitems, gpart, s, wreal);
+  return launch_thin<2, 4, false, true>(A, W, Y, sd, wk, items, nitems, gpart, s, wreal);
+}
+
+int launch_mfma_ctn(const float* A, const float* Q, float* Z, const SliceDesc* sd, const int2* wk, const int2* items,
+                    int nitems, int lmax, double* gpart, hipStream_t s) {
+  if (lmax > kMaxComplexWidth) HT_FAIL(HT_ERR_UNSUPPORTED, "complex sketch width above 64");
+  if (lmax <= 32) return launch_thin<1, 4, true, true>(A, Q, Z, sd, wk, items, nitems, gpart, s);
+  return launch_thin<2, 4, true, true>(A, Q, Z, sd, wk, items, nitems, gpart, s);
+}
+
+int launch_mfma_cqk(const float* Q, const float* K, float* QK, const SliceDesc* sd, const int2* wk, const int2* items,
+                    int nitems, int lmax, hipStream_t s) {
+  if (lmax > kMaxComplexWidth) HT_FAIL(HT_ERR_UNSUPPORTED, "complex sketch width above 64");
+  if (nitems == 0) return HT_OK;
+  hipLaunchKernelGGL(k_mfma_cmul<0>, dim3((unsigned)nitems), dim3(256), 0, s, Q, K, QK, sd, wk, items);
+  HT_CHECK_LAUNCH();
+  return HT_OK;
+}
+
+int launch_mfma_cnt(const float* X, const float* W, float* C, const SliceDesc* sd, const int2* wk, const int2* items,
+                    int nitems, int lmax, hipStream_t s) {
+  if (lmax > kMaxComplexWidth) HT_FAIL(HT_ERR_UNSUPPORTED, "complex sketch width above 64");
+  if (nitems == 0) return HT_OK;
+  hipLaunchKernelGGL(k_mfma_cmul<1>, dim3((unsigned)nitems), dim3(256), 0, s, X, W, C, sd, wk, items);
   HT_CHECK_LAUNCH();
   return HT_OK;
 }

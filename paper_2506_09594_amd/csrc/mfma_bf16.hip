@@ -37,14 +37,18 @@ struct Bf16Lds {
   static constexpr int BYTES = MAIN_BYTES > EPI_BYTES ? MAIN_BYTES : EPI_BYTES;
 };
 
-template <int NB, int NW, bool TRANS>
+// CPLX: complex slices in the stacked layout, as the FP32 kernel (NW = 4;
+// 64 complex rows per tile; wreal: the real Omega against the stored block).
+template <int NB, int NW, bool TRANS, bool CPLX>
 __global__ __launch_bounds__(64 * NW) void k_mfma_thin_bf16(const uint16_t* __restrict__ Aall,
                                                             const float* __restrict__ Wall, float* __restrict__ Yall,
                                                             const SliceDesc* __restrict__ sd,
                                                             const int2* __restrict__ wk, const int2* __restrict__ items,
-                                                            double* __restrict__ gpart, int aligned) {
+                                                            double* __restrict__ gpart, int aligned, int wreal) {
   using L = Bf16Lds<NB, NW>;
   constexpr int MT = L::MT;
+  constexpr int HM = MT / 2;
+  static_assert(!CPLX || MT == 128, "complex tiles hold 64 complex rows");
   constexpr int NTH = 64 * NW;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   uint16_t* const lds_h = reinterpret_cast<uint16_t*>(smem_raw);
@@ -53,30 +57,32 @@ __global__ __launch_bounds__(64 * NW) void k_mfma_thin_bf16(const uint16_t* __re
   const SliceDesc d = sd[s];
   const int l = slice_width(d, wk, s);
   if (l <= 0) return;  // slice not part of this pass
-  const int lda = d.n1;
-  const int M_out = TRANS ? d.n2 : d.n1;
-  const int K = TRANS ? d.n1 : d.n2;
+  const int mo = TRANS ? d.n2 : d.n1;
+  const int lda = CPLX ? 2 * d.n1 : d.n1;
+  const int M_out = CPLX ? 2 * mo : mo;
+  const int K = CPLX ? (TRANS ? 2 * d.n1 : (wreal ? d.n2 : 2 * d.n2)) : (TRANS ? d.n1 : d.n2);
   const int ldw = K, ldy = M_out;
   const int64_t woff = TRANS ? d.y : d.z, yoff = TRANS ? d.z : d.y;
   const uint16_t* Aj = Aall + d.a;
   const float* Wj = Wall + woff;
   float* Yj = Yall + yoff;
-  const int cplx = d.cplx, n1o = d.n1 / 2, n2o = d.n2 / 2;
-  const bool vecA = aligned && (lda % 8 == 0) && (d.a % 8 == 0) && (!cplx || n1o % 8 == 0);
+  const bool vecA = aligned && (lda % 8 == 0) && (d.a % 8 == 0) && (!CPLX || d.n1 % 8 == 0);
   const bool vecW = aligned && (ldw % 4 == 0) && (woff % 4 == 0);
   const int tid = threadIdx.x;
   const int wave = tid / 64, lane = tid % 64;
   const int LW = 32 * NB;
+  auto orow = [&](int i) -> int { return CPLX ? (i >= HM ? mo + r0 + i - HM : r0 + i) : r0 + i; };
+  auto ovalid = [&](int i) -> bool { return CPLX ? r0 + (i >= HM ? i - HM : i) < mo : r0 + i < M_out; };
   // element (r, k) of the slice operand as BF16 bits (complex slices: the real
   // embedding; a negation flips the sign bit)
   auto aval = [&](int r, int k) -> uint16_t {
     bool neg;
-    const uint16_t v = Aj[embed_index(r, k, lda, cplx, n1o, n2o, neg)];
+    const uint16_t v = Aj[embed_index(r, k, lda, CPLX, d.n1, d.n2, neg)];
     return neg ? (uint16_t)(v ^ 0x8000u) : v;
   };
   auto avec = [&](int r, int k) -> u16x8 {  // rows r..r+7 of column k (no straddle when vecA)
     bool neg;
-    u16x8 v = *reinterpret_cast<const u16x8*>(Aj + embed_index(r, k, lda, cplx, n1o, n2o, neg));
+    u16x8 v = *reinterpret_cast<const u16x8*>(Aj + embed_index(r, k, lda, CPLX, d.n1, d.n2, neg));
     if (neg) v ^= (unsigned short)0x8000u;
     return v;
   };
@@ -93,22 +99,22 @@ __global__ __launch_bounds__(64 * NW) void k_mfma_thin_bf16(const uint16_t* __re
       const int g = tid + u * NTH;
       u16x8 v;
       if (!TRANS) {
-        const int kk = g / (MT / 8), row = (g % (MT / 8)) * 8;
-        const int gr = r0 + row, gk = k0 + kk;
-        if (vecA && gk < K && gr + 7 < M_out) {
+        const int kk = g / (MT / 8), row = (g % (MT / 8)) * 8;  // eight rows within one half of a complex tile
+        const int gr = orow(row), gk = k0 + kk;
+        if (vecA && gk < K && ovalid(row + 7)) {
           v = avec(gr, gk);
         } else {
 #pragma unroll
-          for (int e = 0; e < 8; ++e) v[e] = (gk < K && gr + e < M_out) ? aval(gr + e, gk) : 0;
+          for (int e = 0; e < 8; ++e) v[e] = (gk < K && ovalid(row + e)) ? aval(gr + e, gk) : 0;
         }
       } else {
         const int row = g / (KC / 8), kk = (g % (KC / 8)) * 8;
-        const int gc = r0 + row, gk = k0 + kk;
-        if (vecA && gc < M_out && gk + 7 < K) {
+        const int gc = orow(row), gk = k0 + kk;
+        if (vecA && ovalid(row) && gk + 7 < K) {
           v = avec(gk, gc);
         } else {
 #pragma unroll
-          for (int e = 0; e < 8; ++e) v[e] = (gc < M_out && gk + e < K) ? aval(gk + e, gc) : 0;
+          for (int e = 0; e < 8; ++e) v[e] = (ovalid(row) && gk + e < K) ? aval(gk + e, gc) : 0;
         }
       }
       ra[u] = v;
@@ -190,33 +196,37 @@ __global__ __launch_bounds__(64 * NW) void k_mfma_thin_bf16(const uint16_t* __re
 
   double* S = reinterpret_cast<double*>(smem_raw);
   const int sp = LW + 1;
-  const int rows = min(MT, M_out - r0);
 #pragma unroll
   for (int b = 0; b < NB; ++b)
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
       const int i = 32 * wave + 8 * (r / 4) + 4 * (lane / 32) + (r % 4);
       const int c = 32 * b + (lane % 32);
-      S[i * sp + c] = (i < rows && c < l) ? (double)acc[b][r] : 0.0;
+      S[i * sp + c] = (ovalid(i) && c < l) ? (double)acc[b][r] : 0.0;
     }
   __syncthreads();
   for (int idx = tid; idx < MT * l; idx += NTH) {
     const int i = idx % MT, c = idx / MT;
-    if (i < rows) Yj[(r0 + i) + (int64_t)c * ldy] = (float)S[i * sp + c];
+    if (ovalid(i)) Yj[orow(i) + (int64_t)c * ldy] = (float)S[i * sp + c];
   }
-  if (gpart) tile_gram_mfma(S, sp, 1, rows, l, gpart + d.g1 + (int64_t)(r0 / kGramRows) * l * l);
+  if (gpart) {
+    if (CPLX)
+      tile_cgram_mfma(S, sp, 1, l, gpart + d.g1 + (int64_t)(r0 / kGramRows) * 2 * l * l);
+    else
+      tile_gram_mfma(S, sp, 1, min(MT, M_out - r0), l, gpart + d.g1 + (int64_t)(r0 / kGramRows) * l * l);
+  }
 }
 
-template <int NB, int NW, bool TRANS>
+template <int NB, int NW, bool TRANS, bool CPLX = false>
 int launch_thin_bf16(const uint16_t* A, const float* W, float* Y, const SliceDesc* sd, const int2* wk,
-                     const int2* items, int nitems, double* gpart, hipStream_t s) {
+                     const int2* items, int nitems, double* gpart, hipStream_t s, int wreal = 0) {
   using L = Bf16Lds<NB, NW>;
   if (nitems == 0) return HT_OK;
-  int rc = ensure_dynamic_lds((const void*)k_mfma_thin_bf16<NB, NW, TRANS>, L::BYTES);
+  int rc = ensure_dynamic_lds((const void*)k_mfma_thin_bf16<NB, NW, TRANS, CPLX>, L::BYTES);
   if (rc) return rc;
   const int aligned = (reinterpret_cast<uintptr_t>(A) % 16 == 0) && (reinterpret_cast<uintptr_t>(W) % 16 == 0);
-  hipLaunchKernelGGL((k_mfma_thin_bf16<NB, NW, TRANS>), dim3((unsigned)nitems), dim3(64 * NW), L::BYTES, s, A, W, Y,
-                     sd, wk, items, gpart, aligned);
+  hipLaunchKernelGGL((k_mfma_thin_bf16<NB, NW, TRANS, CPLX>), dim3((unsigned)nitems), dim3(64 * NW), L::BYTES, s, A,
+                     W, Y, sd, wk, items, gpart, aligned, wreal);
   HT_CHECK_LAUNCH();
   return HT_OK;
 }
@@ -240,6 +250,20 @@ int dispatch_bf16(const uint16_t* A, const float* W, float* Y, const SliceDesc* 
 int launch_bf16_nn(const uint16_t* A, const float* W, float* Y, const SliceDesc* sd, const int2* wk,
                    const int2* items, int nitems, int lmax, int rows, double* gpart, hipStream_t s) {
   return dispatch_bf16<false>(A, W, Y, sd, wk, items, nitems, lmax, rows, gpart, s);
+}
+
+int launch_bf16_cnn(const uint16_t* A, const float* W, float* Y, int wreal, const SliceDesc* sd, const int2* wk,
+                    const int2* items, int nitems, int lmax, double* gpart, hipStream_t s) {
+  if (lmax > kMaxComplexWidth) HT_FAIL(HT_ERR_UNSUPPORTED, "complex sketch width above 64");
+  if (lmax <= 32) return launch_thin_bf16<1, 4, false, true>(A, W, Y, sd, wk, items, nitems, gpart, s, wreal);
+  return launch_thin_bf16<2, 4, false, true>(A, W, Y, sd, wk, items, nitems, gpart, s, wreal);
+}
+
+int launch_bf16_ctn(const uint16_t* A, const float* Q, float* Z, const SliceDesc* sd, const int2* wk,
+                    const int2* items, int nitems, int lmax, double* gpart, hipStream_t s) {
+  if (lmax > kMaxComplexWidth) HT_FAIL(HT_ERR_UNSUPPORTED, "complex sketch width above 64");
+  if (lmax <= 32) return launch_thin_bf16<1, 4, true, true>(A, Q, Z, sd, wk, items, nitems, gpart, s);
+  return launch_thin_bf16<2, 4, true, true>(A, Q, Z, sd, wk, items, nitems, gpart, s);
 }
 
 int launch_bf16_tn(const uint16_t* A, const float* Q, float* Z, const SliceDesc* sd, const int2* wk,

@@ -6,7 +6,7 @@
 //   recon nn:   (Q1 K')_s (n1 x l) = Q1_s (n1 x l) K'_s (l x l)
 //   recon nt:   C_s (n1 x n2) = (Q1 K')_s Bt_s^T
 //
-// Every slice is a column-major block found through the slice table; one
+// Every (real) slice is a column-major block found through the slice table; one
 // workgroup per work item (slice, 64-row tile) stages a K-chunk of both
 // operands in LDS and accumulates in the storage precision.  One pass reads
 // every slice once.  Optionally the epilogue also writes, per output tile, the
@@ -66,7 +66,6 @@ __global__ __launch_bounds__(256) void k_gemm_nn(const T* __restrict__ Aall, con
   const T* Aj = Aall + (RECON ? d.y : d.a);
   const T* Wj = Wall + (RECON ? d.kq : d.z);
   T* Yj = Yall + d.y;
-  const int cplx = RECON ? 0 : d.cplx, n1o = d.n1 / 2, n2o = d.n2 / 2;
   const int tr = threadIdx.x % TM, tc = threadIdx.x / TM;
   T acc[CPT];
 #pragma unroll
@@ -76,11 +75,7 @@ __global__ __launch_bounds__(256) void k_gemm_nn(const T* __restrict__ Aall, con
       const int kk = idx / TM, rr = idx % TM;
       const int gr = row0 + rr, gk = k0 + kk;
       T v = T(0);
-      if (gr < m && gk < kd) {
-        bool neg;
-        v = Aj[embed_index(gr, gk, lda, cplx, n1o, n2o, neg)];
-        if (neg) v = -v;
-      }
+      if (gr < m && gk < kd) v = Aj[gr + (int64_t)gk * lda];
       As[kk][rr] = v;
     }
     for (int idx = threadIdx.x; idx < KC * LB; idx += 256) {
@@ -128,7 +123,6 @@ __global__ __launch_bounds__(256) void k_gemm_tn(const T* __restrict__ Aall, con
   const T* Aj = Aall + d.a;
   const T* Qj = Qall + d.y;
   T* Zj = Zall + d.z;
-  const int cplx = d.cplx, n1o = d.n1 / 2, n2o = d.n2 / 2;
   const int tcol = threadIdx.x % TM, tc = threadIdx.x / TM;
   T acc[CPT];
 #pragma unroll
@@ -138,11 +132,7 @@ __global__ __launch_bounds__(256) void k_gemm_tn(const T* __restrict__ Aall, con
       const int kk = idx % KC, cc = idx / KC;
       const int gk = k0 + kk, gc = col0 + cc;
       T v = T(0);
-      if (gk < m && gc < n) {
-        bool neg;
-        v = Aj[embed_index(gk, gc, lda, cplx, n1o, n2o, neg)];
-        if (neg) v = -v;
-      }
+      if (gk < m && gc < n) v = Aj[gk + (int64_t)gc * lda];
       As[kk][cc] = v;
     }
     for (int idx = threadIdx.x; idx < KC * LB; idx += 256) {
@@ -186,7 +176,7 @@ __global__ __launch_bounds__(256) void k_gemm_nt(const T* __restrict__ Xall, con
   const SliceDesc d = sd[s];
   const int l = slice_width(d, wk, s);
   if (l <= 0) return;  // slice not part of this pass
-  const int m = d.n1, n = d.nc;  // complex slices: the left block column [Re C; Im C]
+  const int m = d.n1, n = d.nc;
   const int nrt = (m + 63) / 64;
   const int row0 = (item.y % nrt) * 64, col0 = (item.y / nrt) * 64;
   const T* Xj = Xall + d.y;

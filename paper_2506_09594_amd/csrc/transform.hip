@@ -621,11 +621,8 @@ __global__ __launch_bounds__(256) void k_omega(T* __restrict__ om, double* __res
   const int s = blockIdx.x;
   const SliceDesc d = sd[s];
   const int64_t base = dense_stride > 0 ? (int64_t)s * dense_stride : d.z;
-  // complex slices: the real embedding of the real Gaussian Omega (n2o x lo)
-  // is blockdiag(Omega, Omega) (n2 x l = 2 n2o x 2 lo)
-  const int n2o = d.cplx ? d.n2 / 2 : d.n2;
-  const int lo = d.cplx ? slice_width(d, wk, s) / 2 : slice_width(d, wk, s);
-  const int64_t per_slice = (int64_t)n2o * lo;
+  // complex slices draw the same real Omega (n2 x l) as real ones
+  const int64_t per_slice = (int64_t)d.n2 * slice_width(d, wk, s);
   const uint32_t c = call_dev ? (uint32_t)(*call_dev) : call;
   const int64_t ngroups = (per_slice + 3) / 4;
   for (int64_t g = (int64_t)blockIdx.y * blockDim.x + threadIdx.x; g < ngroups; g += (int64_t)gridDim.y * blockDim.x) {
@@ -635,26 +632,8 @@ __global__ __launch_bounds__(256) void k_omega(T* __restrict__ om, double* __res
     for (int lane = 0; lane < 4; ++lane) {
       const int64_t e = 4 * g + lane;
       if (e < per_slice) {
-        if (!d.cplx) {
-          if (om) om[base + e] = (T)z[lane];
-          if (om64) om64[base + e] = z[lane];
-        } else {
-          const int64_t r = e % n2o, col = e / n2o, ld = 2 * (int64_t)n2o;
-          const int64_t i00 = r + col * ld, i11 = (r + n2o) + (col + lo) * ld;
-          const int64_t i10 = (r + n2o) + col * ld, i01 = r + (col + lo) * ld;
-          if (om) {
-            om[base + i00] = (T)z[lane];
-            om[base + i11] = (T)z[lane];
-            om[base + i10] = T(0);
-            om[base + i01] = T(0);
-          }
-          if (om64) {
-            om64[base + i00] = z[lane];
-            om64[base + i11] = z[lane];
-            om64[base + i10] = 0.0;
-            om64[base + i01] = 0.0;
-          }
-        }
+        if (om) om[base + e] = (T)z[lane];
+        if (om64) om64[base + e] = z[lane];
       }
     }
   }

@@ -2,11 +2,11 @@
 oracle's complex randomized t-SVT.
 
 Only one slice of each conjugate pair is sketched (the output of its partner
-is the conjugate, so the result is real); the sketch runs on the real
-embedding [[Re, -Im], [Im, Re]] of the complex slice with the embedded sketch
-matrix blockdiag(Omega, Omega), where Omega is the same real Gaussian draw the
-oracle uses (keyed by the canonical member of the pair).  Tolerances as for the
-real transforms: FP64 1e-10, FP32 1e-5, BF16-mixed 2e-2 (relative Frobenius).
+is the conjugate, so the result is real); the complex slice is sketched with
+the real Gaussian Omega the oracle uses (keyed by the canonical member of the
+pair), every product complex, CholeskyQR and the Hermitian eigensolver in
+complex FP64.  Tolerances as for the real transforms: FP64 1e-10, FP32 1e-5,
+BF16-mixed 2e-2 (relative Frobenius).
 """
 import numpy as np
 import pytest
@@ -50,6 +50,8 @@ def _case(ht, dims, rank, r, p, q, prec, tau, pen, seed=1, noise=1e-2):
     ((33, 20, 5), 4, 6, 4, 2),       # odd mode, ragged rows
     ((24, 64, 2, 2, 2), 3, 8, 8, 1), # order 5, all slices self-conjugate
     ((64, 48, 6), 10, 12, 6, 2),     # columns aligned for 16-byte loads
+    ((136, 100, 4, 2), 30, 40, 10, 2),  # width 50: three 64-row tiles with a ragged last one
+    ((64, 70, 3, 3), 20, 54, 10, 1),    # width 64, the largest complex width
 ])
 def test_tsvt_dft_matches_oracle(ht, prec, dims, rank, r, p, q):
     got, ref, plan = _case(ht, dims, rank, r, p, q, prec, 2.0, ("mcp", (30.0,)))
@@ -71,7 +73,7 @@ def test_dft_low_rank_recovered_exactly(ht):
     assert _rel(ht.from_device(out, dims), X) < 1e-11
 
 
-def test_dft_stats_come_in_pairs(ht):
+def test_dft_stats_are_the_complex_singular_values(ht):
     import torch
     dims, kinds = (40, 30, 5), ["dft"]
     X = synth.lowrank_tensor(dims, 6, kinds, seed=4, noise_std=1e-2)
@@ -79,13 +81,12 @@ def test_dft_stats_come_in_pairs(ht):
     out, sig, kept = plan.gnhtsvt(ht.to_device(X, torch.float64), 1.0, ("l1", ()), stats=True)
     torch.cuda.synchronize()
     sig = sig.cpu().numpy()
-    assert sig.shape[1] == 2 * 10
-    # singular values of the real embedding are the complex ones, each twice
-    assert np.allclose(sig[:, 0::2], sig[:, 1::2], rtol=1e-10, atol=1e-12)
+    assert plan.width == 10 and sig.shape[1] == 10
     LX = otr.to_slices(otr.forward(X, otr.build_transforms(dims, kinds)))
     s_true = np.linalg.svd(LX[:, :, 1], compute_uv=False)[:6]
     slot = sorted({otr.canonical_slice(j, dims, kinds) for j in range(5)}).index(1)
-    assert np.allclose(sig[slot, 0:12:2], s_true, rtol=1e-8)
+    assert np.allclose(sig[slot, :6], s_true, rtol=1e-8)
+    assert np.all(kept.cpu().numpy() == 6)
 
 
 def test_rpca_dft_matches_oracle(ht):
@@ -118,5 +119,7 @@ def test_rpca_dft_matches_oracle(ht):
 def test_dft_unsupported_combinations(ht):
     with pytest.raises(ht.HtError):  # mixed real and DFT modes
         ht.Plan((20, 20, 4, 4), ["dct2", "dft"], r=4, p=4)
-    with pytest.raises(ht.HtError):  # the embedding doubles the width: 2 l > HT_MAX_WIDTH
-        ht.Plan((100, 100, 4), ["dft"], r=30, p=10)
+    with pytest.raises(ht.HtError) as e:  # complex widths stop at 64
+        ht.Plan((100, 100, 4), ["dft"], r=60, p=10)
+    assert e.value.code == ht.ERR_UNSUPPORTED
+    ht.Plan((100, 100, 4), ["dft"], r=50, p=10)  # l = 60: the large robust-PCA width

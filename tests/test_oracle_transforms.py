@@ -35,6 +35,19 @@ def test_mode_product_matches_loops():
     assert np.allclose(Y, ref, atol=1e-13)
 
 
+@pytest.mark.parametrize("dims,kinds", [((5, 4, 6), ["dct2"]), ((3, 4, 4, 3), ["dft", "dft"]),
+                                        ((4, 3, 2, 3, 4), ["dct2", "dft_unnormalized", "dft"])])
+def test_forward_slice_matches_full_forward(dims, kinds):
+    """One transformed slice from the Kronecker coefficients equals that slice
+    of the mode-by-mode transform, for every slice index."""
+    rng = np.random.default_rng(7)
+    X = rng.standard_normal(dims)
+    T = tr.build_transforms(dims, kinds)
+    LX = tr.to_slices(tr.forward(X, T))
+    for j in range(LX.shape[2]):
+        assert np.allclose(tr.forward_slice(X, T, j), LX[:, :, j], atol=1e-13)
+
+
 def test_forward_matches_scipy_per_axis():
     rng = np.random.default_rng(1)
     X = rng.standard_normal((4, 3, 5, 6))
