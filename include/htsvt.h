@@ -406,6 +406,27 @@ int ht_admm_set_truth(ht_plan* plan, const void* truth);
  * or a slice of the last t-SVT was flagged non-finite. */
 int ht_admm_get_stats(const ht_plan* plan, const void* workspace, void* stream, ht_admm_stats* out);
 
+/* ---------------------------------------------------------------------------
+ * Allocation-free t-SVT, for callers that cannot allocate device memory while
+ * they run (code under HIP stream capture, serving loops, harnesses that forbid
+ * hipMalloc).  Same operation, arguments and results as ht_gnhtsvt, but the
+ * workspace is a device array held by the library: one copy of
+ * HT_NOALLOC_SCRATCH_BYTES bytes on every device the library runs on, kept
+ * until the process ends.  The call allocates nothing (no hipMalloc, hipFree,
+ * events or graphs); its first call on a device looks up that device's copy.
+ * Every call on one device shares its copy, which keeps the last call's
+ * contents; no part of it needs to start at zero.  Calls that overlap in time
+ * on one device (two streams, two threads) race on it and must not be issued.
+ * Errors: as ht_gnhtsvt; WORKSPACE when ht_plan_workspace_size of the plan is
+ * above HT_NOALLOC_SCRATCH_BYTES; UNSUPPORTED for batch plans and for plans
+ * with learned widths, graph replay or per-stage profiling enabled (their
+ * state lives in a caller's workspace or allocates).
+ * --------------------------------------------------------------------------- */
+#define HT_NOALLOC_SCRATCH_BYTES ((size_t)256 << 20)
+
+int ht_gnhtsvt_noalloc(ht_plan* plan, const void* X, void* out, double tau, const ht_penalty* penalty,
+                       uint32_t call_index, void* stream, double* sigma_out, int* kept_out);
+
 #ifdef __cplusplus
 }
 #endif

@@ -1103,6 +1103,30 @@ int run_admm(const ht_plan* pl, const ht_admm_params* prm, const T* M, const uin
                             st, s);
 }
 
+// Workspace of the allocation-free t-SVT: a device array of the library, one
+// copy per device.  In host code the array's name stands for a host-side
+// shadow, not for a device address, so it is never passed to a kernel or a
+// copy: the device address of each device's copy is looked up once, with that
+// device current, and kept here.
+static __device__ __align__(256) unsigned char scratch[HT_NOALLOC_SCRATCH_BYTES];
+
+int noalloc_scratch(int device, void** ptr) {
+  static std::mutex mu;
+  static std::vector<void*> addr;  // per device ordinal, null until looked up
+  std::lock_guard<std::mutex> lock(mu);
+  if (device < 0) HT_FAIL(HT_ERR_INVALID_ARG, "bad device ordinal");
+  if ((size_t)device >= addr.size()) addr.resize((size_t)device + 1, nullptr);
+  if (!addr[device]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || p == nullptr)
+      HT_FAIL(HT_ERR_HIP, std::string("hipGetSymbolAddress(scratch) failed: ") + hipGetErrorString(e));
+    addr[device] = p;
+  }
+  *ptr = addr[device];
+  return HT_OK;
+}
+
 // Every call on a plan runs on the device the plan was created on.
 int check_device(const ht_plan* pl) {
   int dev = -1;
@@ -1358,6 +1382,26 @@ int ht_gnhtsvt(ht_plan* pl, const void* X, void* out, double tau, const ht_penal
   if ((rc = check_penalty(penalty))) return rc;
   if ((rc = check_device(pl))) return rc;
   if ((rc = check_ws(ws, ws_bytes, pl->tsvt_bytes))) return rc;
+  return run_tsvt_any(pl, X, out, tau, nullptr, penalty, call_index, ws, static_cast<hipStream_t>(stream), sigma_out,
+                      kept_out);
+}
+
+int ht_gnhtsvt_noalloc(ht_plan* pl, const void* X, void* out, double tau, const ht_penalty* penalty,
+                       uint32_t call_index, void* stream, double* sigma_out, int* kept_out) {
+  if (!pl || !X || !out) HT_FAIL(HT_ERR_INVALID_ARG, "plan/X/out is NULL");
+  if (pl->batch) HT_FAIL(HT_ERR_UNSUPPORTED, "the allocation-free call takes a single-tensor plan");
+  if (pl->learn_mode != 0 || pl->graph_on || (pl->prof && pl->prof->on))
+    HT_FAIL(HT_ERR_UNSUPPORTED, "the allocation-free call needs learned widths, graph replay and profiling off");
+  if (!(tau >= 0.0) || !std::isfinite(tau)) HT_FAIL(HT_ERR_INVALID_ARG, "tau must be finite and >= 0");
+  int rc;
+  if ((rc = check_penalty(penalty))) return rc;
+  if ((rc = check_device(pl))) return rc;
+  if (pl->tsvt_bytes > HT_NOALLOC_SCRATCH_BYTES)
+    HT_FAIL(HT_ERR_WORKSPACE, "the plan needs " + std::to_string(pl->tsvt_bytes) +
+                                  " bytes of workspace, above the library scratch of " +
+                                  std::to_string((size_t)HT_NOALLOC_SCRATCH_BYTES));
+  void* ws = nullptr;
+  if ((rc = noalloc_scratch(pl->device, &ws))) return rc;
   return run_tsvt_any(pl, X, out, tau, nullptr, penalty, call_index, ws, static_cast<hipStream_t>(stream), sigma_out,
                       kept_out);
 }

@@ -45,7 +45,7 @@ EXPORTS = [
     "ht_batch_gnhtsvt", "ht_plan_set_tuning", "ht_plan_get_tuning", "ht_plan_autotune", "ht_plan_graph_enable",
     "ht_plan_learned", "ht_plan_learned_reset", "ht_plan_learned_counts", "ht_plan_force_fallback",
     "ht_mlp_param_count", "ht_mlp_workspace_size", "ht_mlp_forward", "ht_mlp_grad", "ht_mlp_train_step",
-    "ht_plan_device", "ht_plan_status", "ht_admm_set_truth",
+    "ht_plan_device", "ht_plan_status", "ht_admm_set_truth", "ht_gnhtsvt_noalloc",
 ]
 STAGES = ["transform_fwd", "omega", "sketch_nn", "cholqr", "sketch_tn", "smallsvd", "recon_qk", "recon_nt",
           "transform_inv", "admm_update"]
@@ -137,6 +137,8 @@ _sig = {
     "ht_plan_device": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_int)]),
     "ht_plan_status": (ctypes.c_int, [_vp, _vp, _vp, ctypes.POINTER(ctypes.c_int64)]),
     "ht_admm_set_truth": (ctypes.c_int, [_vp, _vp]),
+    "ht_gnhtsvt_noalloc": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_double, ctypes.POINTER(_Penalty), ctypes.c_uint32,
+                                          _vp, _vp, _vp]),
 }
 for _name, (_res, _args) in _sig.items():
     _f = getattr(_lib, _name)
@@ -373,6 +375,25 @@ class Plan:
                                wp, wn, _stream(), _ptr(sig), _ptr(kept)))
         if stats:
             return out, sig.view(self.n_slices, self.width), kept
+        return out
+
+    def gnhtsvt_noalloc(self, X, tau, penalty=("l1", ()), call_index=0, out=None, stats=None):
+        """ht_gnhtsvt on the library's own device scratch (no workspace argument;
+        the call itself allocates nothing).  out and stats = (sigma, kept) are
+        caller-allocated; out defaults to a new tensor like X."""
+        import torch
+        check_tensor(X, "X", self.torch_dtype, self.N)
+        if out is None:
+            out = torch.empty_like(X)
+        check_tensor(out, "out", self.torch_dtype, self.N)
+        sig = kept = None
+        if stats is not None:
+            sig, kept = stats
+            check_tensor(sig, "sigma", torch.float64, self.n_slices * self.width)
+            check_tensor(kept, "kept", torch.int32, self.n_slices)
+        pen = _penalty(penalty)
+        _check(_lib.ht_gnhtsvt_noalloc(self._h, _ptr(X), _ptr(out), float(tau), ctypes.byref(pen), int(call_index),
+                                       _stream(), _ptr(sig), _ptr(kept)))
         return out
 
     def omega_fp64(self, call_index=0):
