@@ -493,6 +493,7 @@ def main():
     dOut = torch.empty_like(dX)
     ws = plan.alloc_workspace()
     P_logical = int(np.prod(wl["dims"][2:]))
+    tuning, _ = plan.autotune(dX, workspace=ws, repeats=2)  # tile choices timed on this input
     for i in range(args.warmup):
         plan.gnhtsvt(dX, wl["tau"], wl["penalty"], call_index=i, out=dOut, workspace=ws)
     torch.cuda.synchronize()
@@ -544,7 +545,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": wl["name"], "dims": list(wl["dims"]), "r": wl["r"], "p": wl["p"], "q": wl["q"],
                    "transform": wl["transform"], "penalty": wl["penalty"][0], "slices_per_step": P_logical,
-                   "sketched_slices_per_step": plan.n_slices},
+                   "sketched_slices_per_step": plan.n_slices, "tuning": tuning},
         "roofline": roof,
         "stages": {k: {kk: round(vv, 5) for kk, vv in v.items()} for k, v in stages.items()},
     }

@@ -180,7 +180,9 @@ int ht_plan_info(const ht_plan* plan, int64_t* n_slices, int* width, int* kept);
  * learned widths: 14 widths of the redo pass, 15 widths used (l, k),
  * 16 singular values (P x l_max doubles), 17 kept counts (P ints),
  * 18 ||A_j||^2 (previous, current; P x 2 doubles), 19 features (P x 32
- * floats), 20 state (ints: history valid, predicted slices, redone slices).  Thin blocks of slice j start at
+ * floats), 20 state (ints: history valid, predicted slices, redone slices),
+ * 21 non-finite flags (P ints), 22 RSE partial sums, 23 squared group norms
+ * of the tube-wise / slice-wise solver update.  Thin blocks of slice j start at
  * j * align4(rows * l) elements (align4 rounds up to a multiple of 4).  A
  * complex slice keeps its real and imaginary parts stacked: A and C blocks of
  * 2 n1 x n2, thin blocks of 2 rows x l, K' of 2 l x l (column-major). */
@@ -355,21 +357,28 @@ int ht_profile_read(ht_plan* plan, double* ms_total, int* count, int n_stages);
 
 /* ---------------------------------------------------------------------------
  * Pure-L ADMM for completion (model = HT_COMPLETION) and robust completion
- * (model = HT_RPCA), one iteration per call:
+ * (model = HT_RPCA, HT_RPCA_TUBE, HT_RPCA_SLICE), one iteration per call:
  *   L   <- D_{Phi, 1/mu}(M - E + Y/mu)            (randomized t-SVT above)
  *   H   <- M - L + Y/mu
- *   E   <- mask ? (COMPLETION: 0 | RPCA: Prox_{psi, lambda/mu}(H)) : H
+ *   E   <- off the mask: H;  on the mask: COMPLETION 0, or the GNHTT of
+ *          P_mask(H) with Prox_{psi, lambda/mu} (Sec. IV-B):
+ *            RPCA        element-wise  Prox(H_i)
+ *            RPCA_TUBE   tube-wise     H_t / ||H_t|| Prox(||H_t||) for every tube
+ *                        t = (i1, i2) of P_mask(H) (the entries over modes 3..d)
+ *            RPCA_SLICE  slice-wise    H^<j> / ||H^<j>|| Prox(||H^<j>||) for
+ *                        every face slice j of P_mask(H)
+ *          (a group of norm 0 stays 0; group norms summed in FP64)
  *   Y   <- Y + mu (M - L - E)
  *   mu  <- min(mu_max, vartheta * mu)
  * and the stopping terms max|dL|, max|dE|, max|M - L - E| of the iteration.
  * --------------------------------------------------------------------------- */
-enum { HT_COMPLETION = 0, HT_RPCA = 1 };
+enum { HT_COMPLETION = 0, HT_RPCA = 1, HT_RPCA_TUBE = 2, HT_RPCA_SLICE = 3 };
 
 typedef struct {
   int model;
   ht_penalty phi;       /* low-rank penalty */
-  ht_penalty psi;       /* sparse penalty (RPCA only) */
-  double lambda;        /* weight of the sparse term (RPCA only) */
+  ht_penalty psi;       /* sparse penalty (robust models only) */
+  double lambda;        /* weight of the sparse term (robust models only) */
   double mu0, vartheta, mu_max;
 } ht_admm_params;
 

@@ -178,3 +178,40 @@ def prox_bruteforce(kind, v, mu, params=(), grid=20001):
     if _objective(kind, params, mu, a, 0.0) <= _objective(kind, params, mu, a, x):
         x = 0.0
     return (-1.0 if v < 0 else 1.0) * x
+
+
+def gnhtt(A, mu, kind, params=(), group="element", mask=None):
+    """GNHTT: the proximity operator of a penalty applied element-wise, tube-wise
+    or slice-wise (Sec. IV-B, the three solutions of the E-subproblem):
+      element  E_i = Prox(A_i)
+      tube     E_{i1 i2 :...:} = A_{i1 i2 :...:} / ||A_{i1 i2 :...:}||_F * Prox(||A_{i1 i2 :...:}||_F)
+      slice    E^<k> = A^<k> / ||A^<k>||_F * Prox(||A^<k>||_F)
+    with Prox = Prox_{phi, mu} and a zero group mapped to zero.  With a mask
+    (boolean, same shape) the groups are those of P_Omega(A): entries off the
+    mask count as zero in the norms and come out zero (the reading used for the
+    E-update on the observed set)."""
+    A = np.asarray(A, dtype=np.float64)
+    if mask is not None:
+        A = np.where(mask, A, 0.0)
+    if group == "element":
+        return prox(kind, A, mu, params)
+    n1, n2 = A.shape[:2]
+    P = int(np.prod(A.shape[2:])) if A.ndim > 2 else 1
+    S = A.reshape((n1, n2, P), order="F")
+    out = np.zeros_like(S)
+    if group == "tube":
+        for i in range(n1):
+            for j in range(n2):
+                v = S[i, j, :]
+                nrm = float(np.linalg.norm(v))
+                if nrm > 0.0:
+                    out[i, j, :] = v / nrm * prox_scalar(kind, nrm, mu, params)
+    elif group == "slice":
+        for k in range(P):
+            v = S[:, :, k]
+            nrm = float(np.linalg.norm(v))
+            if nrm > 0.0:
+                out[:, :, k] = v / nrm * prox_scalar(kind, nrm, mu, params)
+    else:
+        raise ValueError(group)
+    return out.reshape(A.shape, order="F")

@@ -11,7 +11,8 @@ the gradient directions removed, so the L-subproblem is the GNHTSVT problem with
 tau = 1/mu):
     L   <- D_{Phi, 1/mu}(M - E + Y/mu)
     H   <- M - L + Y/mu
-    E   <- on Omega:  0 (completion) or Prox_{psi, lambda/mu}(H) element-wise (robust)
+    E   <- on Omega:  0 (completion) or GNHTT_{psi, lambda/mu}(P_Omega(H)) (robust; element-wise
+                      "rpca", tube-wise "rpca_tube" or slice-wise "rpca_slice", Sec. IV-B)
            off Omega: H                          (the least-squares part)
     Y   <- Y + mu (M - L - E)
     mu  <- min(mu_max, vartheta * mu)
@@ -33,7 +34,8 @@ def admm(M, mask, model, penalty_L, penalty_E, lam, mu0, vartheta, mu_max, n_ite
     Returns (L, E, Ymul, history) with history a list of dicts holding the
     stopping terms and mu of every iteration.
     """
-    if model not in ("completion", "rpca"):
+    groups = {"rpca": "element", "rpca_tube": "tube", "rpca_slice": "slice"}
+    if model != "completion" and model not in groups:
         raise ValueError(model)
     M = np.asarray(M, dtype=np.float64)
     mask = np.asarray(mask, dtype=bool)
@@ -49,7 +51,7 @@ def admm(M, mask, model, penalty_L, penalty_E, lam, mu0, vartheta, mu_max, n_ite
             E_obs = np.zeros_like(H)
         else:
             kind, params = penalty_E
-            E_obs = proxmod.prox(kind, H, lam / mu, params)
+            E_obs = proxmod.gnhtt(H, lam / mu, kind, params, groups[model], mask)
         E_new = np.where(mask, E_obs, H)
         resid = M - L_new - E_new
         Ymul = Ymul + mu * resid

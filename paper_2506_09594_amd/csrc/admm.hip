@@ -1,6 +1,9 @@
-// Element-wise recovery update of the pure-L ADMM (Sec. V updates of E, the
-// multiplier and mu), fused with the stopping-term reductions and with the
-// formation of the next iteration's t-SVT input M - E + Y/mu.
+// Recovery update of the pure-L ADMM (Sec. V updates of E, the multiplier and
+// mu), fused with the stopping-term reductions and with the formation of the
+// next iteration's t-SVT input M - E + Y/mu.  The sparse part is shrunk
+// element-wise, or tube-wise / slice-wise (GNHTT, Sec. IV-B): then the squared
+// norm of every group of P_Omega(H) is formed first (FP64, fixed order) and
+// the update scales the group's observed entries by Prox(||g||) / ||g||.
 #include "kernels.hpp"
 
 namespace ht {
@@ -28,12 +31,50 @@ __global__ __launch_bounds__(256) void k_admm_input(const T* __restrict__ M, con
     Xin[i] = (T)((double)M[i] - (double)E[i] + (double)Y[i] * inv_mu);
 }
 
+// Squared norms of the groups of P_Omega(H), H = M - L_new + Y/mu: tube t
+// (tube-wise: one thread per tube position, the P entries at stride NT) or
+// slice j (slice-wise: one workgroup per slice, fixed-order tree reduction).
+template <typename T>
+__global__ __launch_bounds__(256) void k_group_sq(const T* __restrict__ M, const uint8_t* __restrict__ mask,
+                                                  const T* __restrict__ Lnew, const T* __restrict__ Y,
+                                                  const AdmmState* __restrict__ st, int64_t NT, int64_t P, int tube,
+                                                  double* __restrict__ gsq) {
+  const double inv_mu = 1.0 / st->mu;
+  auto hsq = [&](int64_t i) -> double {
+    if (!mask[i]) return 0.0;
+    const double h = (double)M[i] - (double)Lnew[i] + (double)Y[i] * inv_mu;
+    return h * h;
+  };
+  if (tube) {
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < NT; t += (int64_t)gridDim.x * blockDim.x) {
+      double acc = 0.0;
+      for (int64_t j = 0; j < P; ++j) acc += hsq(j * NT + t);
+      gsq[t] = acc;
+    }
+    return;
+  }
+  __shared__ double red[256];
+  for (int64_t j = blockIdx.x; j < P; j += gridDim.x) {
+    double acc = 0.0;
+    for (int64_t t = threadIdx.x; t < NT; t += blockDim.x) acc += hsq(j * NT + t);
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+      if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) gsq[j] = red[0];
+    __syncthreads();
+  }
+}
+
 template <typename T>
 __global__ __launch_bounds__(256) void k_admm_update(const T* __restrict__ M, const uint8_t* __restrict__ mask,
                                                      const T* __restrict__ Lnew, T* __restrict__ L,
                                                      T* __restrict__ E, T* __restrict__ Y, T* __restrict__ Xin,
                                                      AdmmState* __restrict__ st, int64_t N, int model, Penalty psi,
-                                                     double lambda, double vartheta, double mu_max) {
+                                                     double lambda, double vartheta, double mu_max,
+                                                     const double* __restrict__ gsq, int64_t NT) {
   const double mu = st->mu;
   const double inv_mu = 1.0 / mu;
   const double mu_next = fmin(mu_max, vartheta * mu);
@@ -45,10 +86,18 @@ __global__ __launch_bounds__(256) void k_admm_update(const T* __restrict__ M, co
     const double e = (double)E[i], y = (double)Y[i];
     const double h = m - ln + y * inv_mu;
     double en;
-    if (mask[i])
-      en = (model == HT_RPCA) ? prox_signed(psi, h, thr) : 0.0;
-    else
+    if (mask[i]) {
+      if (model == HT_RPCA) {
+        en = prox_signed(psi, h, thr);
+      } else if (model == HT_RPCA_TUBE || model == HT_RPCA_SLICE) {
+        const double nrm = sqrt(gsq[model == HT_RPCA_TUBE ? i % NT : i / NT]);
+        en = nrm > 0.0 ? h * (prox_pos(psi, nrm, thr) / nrm) : 0.0;
+      } else {
+        en = 0.0;
+      }
+    } else {
       en = h;
+    }
     const double r = m - ln - en;
     const double yn = y + mu * r;
     mdl = nan_max(mdl, fabs(ln - lo));
@@ -164,10 +213,17 @@ int launch_admm_input(const T* M, const T* E, const T* Y, const AdmmState* st, T
 
 template <typename T>
 int launch_admm_update(const T* M, const uint8_t* mask, const T* Lnew, T* L, T* E, T* Y, T* Xin, AdmmState* st,
-                       int64_t N, int model, Penalty psi, double lambda, double vartheta, double mu_max,
-                       hipStream_t s) {
+                       int64_t N, int model, Penalty psi, double lambda, double vartheta, double mu_max, double* gsq,
+                       int64_t NT, hipStream_t s) {
+  if (model == HT_RPCA_TUBE || model == HT_RPCA_SLICE) {
+    const int64_t P = N / NT;
+    const bool tube = model == HT_RPCA_TUBE;
+    const unsigned nb = tube ? elementwise_blocks(NT) : (unsigned)std::min<int64_t>(P, 4096);
+    hipLaunchKernelGGL(k_group_sq<T>, dim3(nb), dim3(256), 0, s, M, mask, Lnew, Y, st, NT, P, tube ? 1 : 0, gsq);
+    HT_CHECK_LAUNCH();
+  }
   hipLaunchKernelGGL(k_admm_update<T>, dim3(elementwise_blocks(N)), dim3(256), 0, s, M, mask, Lnew, L, E, Y, Xin, st,
-                     N, model, psi, lambda, vartheta, mu_max);
+                     N, model, psi, lambda, vartheta, mu_max, gsq, NT);
   HT_CHECK_LAUNCH();
   return HT_OK;
 }
@@ -207,9 +263,10 @@ template int launch_admm_input<float>(const float*, const float*, const float*, 
 template int launch_admm_input<double>(const double*, const double*, const double*, const AdmmState*, double*,
                                        int64_t, hipStream_t);
 template int launch_admm_update<float>(const float*, const uint8_t*, const float*, float*, float*, float*, float*,
-                                       AdmmState*, int64_t, int, Penalty, double, double, double, hipStream_t);
+                                       AdmmState*, int64_t, int, Penalty, double, double, double, double*, int64_t,
+                                       hipStream_t);
 template int launch_admm_update<double>(const double*, const uint8_t*, const double*, double*, double*, double*,
-                                        double*, AdmmState*, int64_t, int, Penalty, double, double, double,
-                                        hipStream_t);
+                                        double*, AdmmState*, int64_t, int, Penalty, double, double, double, double*,
+                                        int64_t, hipStream_t);
 
 }  // namespace ht

@@ -49,7 +49,7 @@ using namespace ht;
 
 // Named regions of the workspace (for introspection by the tests).
 enum { WS_A = 0, WS_OMEGA, WS_Y, WS_Z, WS_K, WS_QK, WS_C, WS_LNEW, WS_XIN, WS_STATE, WS_GP1, WS_GP2, WS_WK, WS_CALL,
-       WS_WK2, WS_WKF, WS_SIG, WS_KEPT, WS_ANORM, WS_FEAT, WS_LSTATE, WS_STATUS, WS_RED, WS_COUNT };
+       WS_WK2, WS_WKF, WS_SIG, WS_KEPT, WS_ANORM, WS_FEAT, WS_LSTATE, WS_STATUS, WS_RED, WS_GSQ, WS_COUNT };
 
 // Block partials of the RSE reduction of the solver (two doubles per block).
 constexpr int kRseBlocks = 1024;
@@ -147,6 +147,8 @@ struct ht_plan {
   float* table32;
   ItemList it_nn[2], it_tn[2], it_oy, it_oz, it_qk, it_nt, it_tf;  // [0]: 64-row tiles, [1]: 128-row tiles
   ItemList it_nns;  // nn items of the streaming product (256-row tiles)
+  ItemList it_cp[2];  // BF16 products of complex slices: nn, tn items of kCplxProdRows complex rows
+  ItemList it_cqk, it_cnt;  // complex reconstruction (strips x column-tile groups)
   ItemList it_t16;  // transform items when every tensor has two transformed modes of length 16 (else empty)
   // Width classes (bounds kClassBound) of plans whose slices differ in width:
   // orthonormalization items and small-SVD slices per class, so that each
@@ -383,6 +385,20 @@ std::vector<int2> row_items(const ht_plan* pl, bool over_n2, int rows, bool cost
   return xcd_grouped(groups, cost);
 }
 
+// Complex reconstruction items: strips of kCmulRows complex rows times groups
+// of kCmulGroup column tiles (QK = Q1 K': one group, its l <= 64 columns).
+std::vector<int2> cmul_items(const ht_plan* pl, bool full) {
+  std::vector<std::vector<int2>> groups(pl->Ptot);
+  std::vector<double> cost(pl->Ptot, 1.0);
+  for (int64_t s = 0; s < pl->Ptot; ++s) {
+    const SliceDesc& d = pl->h_slices[s];
+    const int ncg = full ? (int)ceil_div(ceil_div(d.n2, 64), kCmulGroup) : 1;
+    const int nstrips = (int)ceil_div(d.n1, kCmulRows);
+    for (int t = 0; t < nstrips * ncg; ++t) groups[s].push_back(make_int2((int)s, t));
+  }
+  return xcd_grouped(groups, cost);
+}
+
 std::vector<int2> nt_items(const ht_plan* pl) {
   std::vector<std::vector<int2>> groups(pl->Ptot);
   std::vector<double> cost(pl->Ptot, 1.0);
@@ -506,13 +522,18 @@ void layout(ht_plan* pl, int64_t nY, int64_t nZ, int64_t nK, int64_t nG1, int64_
   pl->size[WS_LSTATE] = 256;
   pl->size[WS_STATUS] = (size_t)pl->Ptot * sizeof(int);
   pl->size[WS_RED] = (size_t)kRseBlocks * 2 * sizeof(double);
+  {  // squared group norms of the tube-wise / slice-wise sparse update (single-tensor solvers)
+    int64_t g = 1;
+    for (const TensorHost& th : pl->tens) g = std::max<int64_t>(g, std::max<int64_t>(th.n1 * th.n2, th.P));
+    pl->size[WS_GSQ] = (size_t)g * sizeof(double);
+  }
   pl->size[WS_LNEW] = (size_t)pl->Ntot * es;
   pl->size[WS_XIN] = (size_t)pl->Ntot * es;
   pl->size[WS_STATE] = sizeof(AdmmState);
   // t-SVT regions first, then the solver-only regions
   const int order_[] = {WS_A,   WS_OMEGA, WS_Y,    WS_Z,    WS_K,     WS_QK,   WS_C,      WS_GP1,  WS_GP2,
                         WS_WK,  WS_CALL,  WS_WK2,  WS_WKF,  WS_SIG,   WS_KEPT, WS_ANORM,  WS_FEAT, WS_LSTATE,
-                        WS_STATUS, WS_LNEW, WS_XIN, WS_STATE, WS_RED};
+                        WS_STATUS, WS_LNEW, WS_XIN, WS_STATE, WS_RED, WS_GSQ};
   size_t o = 0;
   for (int r : order_) {
     pl->off[r] = o;
@@ -661,6 +682,10 @@ int build_plan(const ht_plan_desc* descs, int n, bool batch, ht_plan** out) {
   lists.push_back(row_items(pl, false, 64, false));  // recon QK
   lists.push_back(nt_items(pl));                     // recon C
   lists.push_back(row_items(pl, false, kStreamRows, true));  // nn, streaming product
+  lists.push_back(row_items(pl, false, kCplxProdRows, true));  // nn, complex BF16 products
+  lists.push_back(row_items(pl, true, kCplxProdRows, true));   // tn, complex BF16 products
+  lists.push_back(cmul_items(pl, false));                      // complex recon QK
+  lists.push_back(cmul_items(pl, true));                       // complex recon C
   // width classes: orthonormalization items (Y, Z) and small-SVD slices
   auto class_of = [&](int l) {
     int c = 0;
@@ -705,7 +730,7 @@ int build_plan(const ht_plan_desc* descs, int n, bool batch, ht_plan** out) {
   }
   pl->tf_capacity = (int)tfi.size();
   ItemList* dst[] = {&pl->it_nn[0], &pl->it_tn[0], &pl->it_nn[1], &pl->it_tn[1], &pl->it_oy, &pl->it_oz,
-                     &pl->it_qk, &pl->it_nt, &pl->it_nns,
+                     &pl->it_qk, &pl->it_nt, &pl->it_nns, &pl->it_cp[0], &pl->it_cp[1], &pl->it_cqk, &pl->it_cnt,
                      &pl->it_oyc[0], &pl->it_ozc[0], &pl->it_svc[0], &pl->it_oyc[1], &pl->it_ozc[1],
                      &pl->it_svc[1], &pl->it_oyc[2], &pl->it_ozc[2], &pl->it_svc[2], &pl->it_oyc[3],
                      &pl->it_ozc[3], &pl->it_svc[3], &pl->it_oyc[4], &pl->it_ozc[4], &pl->it_svc[4],
@@ -874,7 +899,8 @@ int run_tsvt(const ht_plan* pl, const T* X, T* out, double tau, const double* ta
       if (cplx) {  // items of 64 complex rows
         const ItemList& L = pl->it_nn[0];
         if (bf16)
-          return launch_bf16_cnn(Ah, (const float*)W, (float*)Y, W == Om, sd, wk, items(pl, L), L.n, lmax, gp1, s);
+          return launch_bf16_cnn(Ah, (const float*)W, (float*)Y, W == Om, sd, wk, items(pl, pl->it_cp[0]),
+                                 pl->it_cp[0].n, lmax, gp1, s);
         if (!fp64)
           return launch_mfma_cnn((const float*)A, (const float*)W, (float*)Y, W == Om, sd, wk, items(pl, L), L.n,
                                  lmax, gp1, s);
@@ -896,7 +922,9 @@ int run_tsvt(const ht_plan* pl, const T* X, T* out, double tau, const double* ta
     return timed(pl, ST_SKETCH_TN, s, [&] {
       if (cplx) {
         const ItemList& L = pl->it_tn[0];
-        if (bf16) return launch_bf16_ctn(Ah, (const float*)Y, (float*)Z, sd, wk, items(pl, L), L.n, lmax, gp1, s);
+        if (bf16)
+          return launch_bf16_ctn(Ah, (const float*)Y, (float*)Z, sd, wk, items(pl, pl->it_cp[1]), pl->it_cp[1].n,
+                                 lmax, gp1, s);
         if (!fp64)
           return launch_mfma_ctn((const float*)A, (const float*)Y, (float*)Z, sd, wk, items(pl, L), L.n, lmax, gp1,
                                  s);
@@ -989,8 +1017,8 @@ int run_tsvt(const ht_plan* pl, const T* X, T* out, double tau, const double* ta
   if ((rc = timed(pl, ST_RECON_QK, s, [&] {
          if (cplx) {
            if (!fp64)
-             return launch_mfma_cqk((const float*)Y, (const float*)K, (float*)QK, sd, wk_final, items(pl, pl->it_qk),
-                                    pl->it_qk.n, lmax, s);
+             return launch_mfma_cqk((const float*)Y, (const float*)K, (float*)QK, sd, wk_final, items(pl, pl->it_cqk),
+                                    pl->it_cqk.n, lmax, s);
            return launch_crecon<T>(Y, K, QK, 0, sd, wk_final, items(pl, pl->it_qk), pl->it_qk.n, s);
          }
          if (!fp64 && lmax <= 64)
@@ -1002,8 +1030,8 @@ int run_tsvt(const ht_plan* pl, const T* X, T* out, double tau, const double* ta
   if ((rc = timed(pl, ST_RECON_NT, s, [&] {
          if (cplx) {
            if (!fp64)
-             return launch_mfma_cnt((const float*)QK, (const float*)Z, (float*)C, sd, wk_final, items(pl, pl->it_nt),
-                                    pl->it_nt.n, lmax, s);
+             return launch_mfma_cnt((const float*)QK, (const float*)Z, (float*)C, sd, wk_final, items(pl, pl->it_cnt),
+                                    pl->it_cnt.n, lmax, s);
            return launch_crecon<T>(QK, Z, C, 1, sd, wk_final, items(pl, pl->it_nt), pl->it_nt.n, s);
          }
          if (!fp64)
@@ -1094,7 +1122,8 @@ int run_admm(const ht_plan* pl, const ht_admm_params* prm, const T* M, const uin
       return rc;
     if ((rc = timed(pl, ST_ADMM_UPDATE, s, [&] {
            return launch_admm_update<T>(M, mask, Lnew, L, E, Yv, Xin, st, pl->Ntot, prm->model, psi, prm->lambda,
-                                        prm->vartheta, prm->mu_max, s);
+                                        prm->vartheta, prm->mu_max, ws_ptr<double>(pl, ws, WS_GSQ),
+                                        pl->tens[0].n1 * pl->tens[0].n2, s);
          })))
       return rc;
     if ((rc = launch_admm_finalize(st, prm->vartheta, prm->mu_max, s))) return rc;
@@ -1139,10 +1168,10 @@ int check_device(const ht_plan* pl) {
 
 int check_admm_params(const ht_admm_params* prm) {
   if (!prm) HT_FAIL(HT_ERR_INVALID_ARG, "admm params are NULL");
-  if (prm->model != HT_COMPLETION && prm->model != HT_RPCA) HT_FAIL(HT_ERR_INVALID_ARG, "unknown model");
+  if (prm->model < HT_COMPLETION || prm->model > HT_RPCA_SLICE) HT_FAIL(HT_ERR_INVALID_ARG, "unknown model");
   int rc;
   if ((rc = check_penalty(&prm->phi))) return rc;
-  if (prm->model == HT_RPCA) {
+  if (prm->model != HT_COMPLETION) {
     if ((rc = check_penalty(&prm->psi))) return rc;
     if (!(prm->lambda >= 0.0) || !std::isfinite(prm->lambda)) HT_FAIL(HT_ERR_INVALID_ARG, "lambda must be >= 0");
   }

@@ -31,39 +31,62 @@ namespace {
 constexpr double kEps = 2.220446049250313e-16;
 
 // Sum of the complex Gram partials of a thin block (ntiles tiles, fixed
-// order): G = Gr + i Gi with Gr the summed real parts and Gi = M - M^T.
+// order): G = Gr + i Gi with Gr the summed real parts and Gi = M - M^T of the
+// summed M.  Every thread takes up to NE entries and issues the loads of four
+// tiles for all of them before adding, so that many loads are in flight; M is
+// summed into Gi and made antisymmetric after a barrier (each pair of entries
+// by one thread).  Ends with a barrier.
+template <int NE>
 __device__ inline void sum_cgram_partials(double* Gr, double* Gi, int gp, const double* __restrict__ part,
                                           int ntiles, int l) {
-  const int ll = l * l;
-  for (int idx = threadIdx.x; idx < ll; idx += blockDim.x) {
-    const int a = idx / l, b = idx % l;
-    double sr = 0.0, sm = 0.0, st = 0.0;
-    int t = 0;
-    for (; t + 4 <= ntiles; t += 4) {
-      double vr[4], vm[4], vt[4];
+  const int ll = l * l, nt = blockDim.x;
+  double sr[NE], sm[NE];
+  int o[NE];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const double* p = part + (int64_t)(t + u) * 2 * ll;
-        vr[u] = p[idx];
-        vm[u] = p[ll + a * l + b];
-        vt[u] = p[ll + b * l + a];
-      }
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        sr += vr[u];
-        sm += vm[u];
-        st += vt[u];
-      }
-    }
-    for (; t < ntiles; ++t) {
-      const double* p = part + (int64_t)t * 2 * ll;
-      sr += p[idx];
-      sm += p[ll + a * l + b];
-      st += p[ll + b * l + a];
-    }
-    Gr[a * gp + b] = sr;
-    Gi[a * gp + b] = sm - st;
+  for (int e = 0; e < NE; ++e) {
+    sr[e] = sm[e] = 0.0;
+    o[e] = min((int)threadIdx.x + e * nt, ll - 1);
   }
+  for (int t0 = 0; t0 < ntiles; t0 += 4) {
+    double vr[4][NE], vm[4][NE];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const double* p = part + (int64_t)min(t0 + u, ntiles - 1) * 2 * ll;
+#pragma unroll
+      for (int e = 0; e < NE; ++e) {
+        vr[u][e] = p[o[e]];
+        vm[u][e] = p[ll + o[e]];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      if (t0 + u < ntiles)
+#pragma unroll
+        for (int e = 0; e < NE; ++e) {
+          sr[e] += vr[u][e];
+          sm[e] += vm[u][e];
+        }
+  }
+#pragma unroll
+  for (int e = 0; e < NE; ++e) {
+    const int idx = (int)threadIdx.x + e * nt;
+    if (idx < ll) {
+      Gr[(idx / l) * gp + idx % l] = sr[e];
+      Gi[(idx / l) * gp + idx % l] = sm[e];
+    }
+  }
+  __syncthreads();
+  for (int idx = threadIdx.x; idx < ll; idx += nt) {
+    const int a = idx / l, b = idx % l;
+    if (a < b) {
+      const double x = Gi[a * gp + b], y = Gi[b * gp + a];
+      Gi[a * gp + b] = x - y;
+      Gi[b * gp + a] = y - x;
+    } else if (a == b) {
+      Gi[a * gp + a] = 0.0;
+    }
+  }
+  __syncthreads();
 }
 
 // Complex Cholesky with deflation, in place: on entry the upper triangle of
@@ -72,7 +95,10 @@ __device__ inline void sum_cgram_partials(double* Gr, double* Gi, int gp, const 
 // column, whose row of R is zero) and R[j][b] for b > j sits in the strict
 // lower triangle at (b, j).  A column is skipped when its Schur-complement
 // pivot is at most delta_rel * max_a G[a][a].  One barrier per column: the
-// trailing update reads the unscaled pivot row, which the column never writes.
+// trailing update reads only the unscaled pivot row, which the column never
+// writes, and its entries (a, b), j < a <= b, are spread over every thread of
+// the workgroup (entry e of the column-packed triangle is (a, b) with
+// e = b'(b' + 1)/2 + a', a' = a - j - 1, b' = b - j - 1).
 __device__ inline void cchol_deflate(double* Gr, double* Gi, double* dR, int gp, int l, double delta_rel,
                                      double* s_scr) {
   const int tid = threadIdx.x, nt = blockDim.x;
@@ -84,36 +110,47 @@ __device__ inline void cchol_deflate(double* Gr, double* Gi, double* dR, int gp,
   __syncthreads();
   const double maxdiag = *s_scr;
   const double delta = delta_rel * maxdiag;
-  constexpr int RB = 8;  // rows per batch of loads in the trailing update
+  constexpr int UE = 4;  // entries per thread per batch of loads
   for (int j = 0; j < l; ++j) {
     const double d = Gr[j * gp + j];
     const bool keep = d > delta && maxdiag > 0.0;
     const double inv_r = keep ? fast_rsqrt(d) : 0.0;
     const double inv_d = inv_r * inv_r;
-    for (int b = j + 1 + tid; b < l; b += nt) {
-      const double gbr = Gr[j * gp + b], gbi = Gi[j * gp + b];
-      const double fr = gbr * inv_d, fi = gbi * inv_d;
-      for (int a0 = j + 1; a0 <= b; a0 += RB) {
-        double jr[RB], ji[RB], xr[RB], xi[RB];
+    const int mrem = l - j - 1, ntri = mrem * (mrem + 1) / 2;
+    const double* pr = Gr + j * gp + j + 1;  // pivot row past the diagonal
+    const double* pi = Gi + j * gp + j + 1;
+    for (int e0 = tid; e0 < ntri; e0 += UE * nt) {
+      int ia[UE], ib[UE];
+      double jar[UE], jai[UE], jbr[UE], jbi[UE], xr[UE], xi[UE];
 #pragma unroll
-        for (int u = 0; u < RB; ++u) {
-          const int a = min(a0 + u, b);
-          jr[u] = Gr[j * gp + a];
-          ji[u] = Gi[j * gp + a];
-          xr[u] = Gr[a * gp + b];
-          xi[u] = Gi[a * gp + b];
-        }
+      for (int u = 0; u < UE; ++u) {
+        const int e = min(e0 + u * nt, ntri - 1);
+        int bb = (int)((sqrtf(8.0f * (float)e + 1.0f) - 1.0f) * 0.5f);
+        while ((bb + 1) * (bb + 2) / 2 <= e) ++bb;
+        while (bb * (bb + 1) / 2 > e) --bb;
+        const int aa = e - bb * (bb + 1) / 2;
+        ia[u] = aa;
+        ib[u] = bb;
+        jar[u] = pr[aa];
+        jai[u] = pi[aa];
+        jbr[u] = pr[bb];
+        jbi[u] = pi[bb];
+        xr[u] = Gr[(j + 1 + aa) * gp + j + 1 + bb];
+        xi[u] = Gi[(j + 1 + aa) * gp + j + 1 + bb];
+      }
 #pragma unroll
-        for (int u = 0; u < RB; ++u) {
-          const int a = a0 + u;
-          if (a <= b) {  // G[a][b] -= conj(G[j][a]) G[j][b] / d
-            Gr[a * gp + b] = xr[u] - fma(jr[u], fr, ji[u] * fi);
-            Gi[a * gp + b] = xi[u] - fma(jr[u], fi, -(ji[u] * fr));
-          }
+      for (int u = 0; u < UE; ++u) {
+        if (e0 + u * nt < ntri) {  // G[a][b] -= conj(G[j][a]) G[j][b] / d
+          const double fr = jbr[u] * inv_d, fi = jbi[u] * inv_d;
+          const int o = (j + 1 + ia[u]) * gp + j + 1 + ib[u];
+          Gr[o] = xr[u] - fma(jar[u], fr, jai[u] * fi);
+          Gi[o] = xi[u] - fma(jar[u], fi, -(jai[u] * fr));
         }
       }
-      Gr[b * gp + j] = gbr * inv_r;
-      Gi[b * gp + j] = gbi * inv_r;
+    }
+    for (int b = j + 1 + tid; b < l; b += nt) {
+      Gr[b * gp + j] = Gr[j * gp + b] * inv_r;
+      Gi[b * gp + j] = Gi[j * gp + b] * inv_r;
     }
     if (tid == 0) dR[j] = keep ? d * inv_r : 0.0;
     __syncthreads();
@@ -265,105 +302,124 @@ __global__ __launch_bounds__(kFactorThreads) void k_corth_factor(int which, cons
   double* Gi = Gr + (size_t)l * gp;
   double* dR = Gi + (size_t)l * gp;
   double* part = gin_all + d.g1;
-  sum_cgram_partials(Gr, Gi, gp, part, nparts, l);
-  __syncthreads();
+  sum_cgram_partials<(kMaxComplexWidth * kMaxComplexWidth + kFactorThreads - 1) / kFactorThreads>(Gr, Gi, gp, part,
+                                                                                                 nparts, l);
   cchol_deflate(Gr, Gi, dR, gp, l, 8.0 * (double)m * kEps, &s_scr);
   ctri_inverse_waves(Gr, Gi, dR, gp, l, part, part + ll, l);
 }
 
 size_t cfactor_lds_bytes(int l) { return (2 * (size_t)l * (l + 1) + (size_t)l + 1) * 8; }
 
-// Q = Y R^{-1} for 64 complex rows of one slice: lane i of every wavefront
-// holds row i of Y in registers; wavefront w forms the columns c = w, w + 4,
-// ... one at a time from R^{-1} in LDS (every lane of a wavefront reads the
-// same entry) and stores each at once.  Every wavefront loads its rows before
-// the barrier that follows the staging of R^{-1}, so no store overtakes a
-// load of the same row.  Optionally the complex Gram partial of the stored
-// rows is written for the next stage: the tile is read back into the LDS
-// that held R^{-1}.
+// Q = Y R^{-1} for 64 complex rows of one slice on the FP64 matrix cores, in
+// real form: [Qr, Qi] (64 x 2l) = [Yr, Yi] (64 x 2l) E with
+// E = [[Rr, Ri], [-Ri, Rr]] (2l x 2l) for R^{-1} = Rr + i Ri, whose four
+// quadrants are upper triangular.  Wavefront w owns rows 16w .. 16w + 15 and
+// every 16-column block of the result on v_mfma_f64_16x16x4f64 (lane t
+// supplies A[t % 16][t / 16] and B[t / 16][t % 16]; accumulator v of lane t
+// is D[4 v + t / 16][t % 16]); a (4-step, 16-column) pair whose entries of E
+// all lie below the diagonal of their quadrant is skipped.  R^{-1} sits in LDS
+// as two planes; the result goes through an LDS tile (real parts of the 64
+// rows, then their imaginary parts, FP32 as stored) for coalesced column
+// stores and, optionally, the complex Gram partial of the stored rows.
 template <typename T, int LB>
 __global__ __launch_bounds__(256) void k_corth_apply(T* __restrict__ Yall, int which, const SliceDesc* __restrict__ sd,
                                                      const int2* __restrict__ wk, const int2* __restrict__ items,
                                                      const double* __restrict__ gin_all,
                                                      double* __restrict__ gout_all) {
+  constexpr int NCB = LB / 8;     // 16-column blocks of the 2 l <= 2 LB result columns
+  constexpr int NST = LB / 2;     // 4-deep steps over the 2 l <= 2 LB reduction
+  constexpr int SP = LB + 1;      // pitch of the staging tile (storage type: the values as stored)
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int2 it = items[blockIdx.x];
   const int s = it.x, r0 = it.y;
   const SliceDesc d = sd[s];
   const int l = slice_width(d, wk, s);
   if (l <= 0) return;  // slice not part of this pass
-  const int m = which ? d.n2 : d.n1, ld = 2 * m, ll = l * l;
+  const int m = which ? d.n2 : d.n1, ld = 2 * m, ll = l * l, l2 = 2 * l;
   T* Y = Yall + (which ? d.z : d.y);
   const double* Rg = gin_all + d.g1;
-  double* Rr = reinterpret_cast<double*>(smem_raw);  // R^{-1}, row-major l x l, zero rows past l
-  double* Ri = Rr + LB * LB;
-  for (int idx0 = threadIdx.x; idx0 < LB * LB; idx0 += 4 * 256) {
-    double v[8];
+  double* Rr = reinterpret_cast<double*>(smem_raw);  // R^{-1}, row-major l x l (pitch l)
+  double* Ri = Rr + ll;
+  {  // both planes are contiguous in the parked area: every load issued at once
+    constexpr int NL = (2 * LB * LB + 255) / 256;
+    double v[NL];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int idx = min(idx0 + u * 256, ll - 1);
-      v[u] = Rg[idx];
-      v[4 + u] = Rg[ll + idx];
+    for (int u = 0; u < NL; ++u) v[u] = Rg[min((int)threadIdx.x + u * 256, 2 * ll - 1)];
+#pragma unroll
+    for (int u = 0; u < NL; ++u)
+      if ((int)threadIdx.x + u * 256 < 2 * ll) Rr[threadIdx.x + u * 256] = v[u];
+  }
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int li = lane & 15, lq = lane >> 4;
+  // A operand: row 16 w + li of the tile at k = 4 st + lq (k < l: Yr, k < 2l: Yi)
+  const int arow = r0 + 16 * w + li;
+  const int lrow = arow < m ? arow : m - 1;
+  double a[NST];
+#pragma unroll
+  for (int st = 0; st < NST; ++st) {
+    const int k = 4 * st + lq;
+    const int kk = k < l ? k : (k < l2 ? k - l : 0);
+    const T v = Y[(k < l ? 0 : m) + lrow + (int64_t)kk * ld];
+    a[st] = (k < l2 && arow < m) ? (double)v : 0.0;
+  }
+  __syncthreads();
+  typedef double d4 __attribute__((ext_vector_type(4)));
+  d4 acc[NCB];
+#pragma unroll
+  for (int cb = 0; cb < NCB; ++cb) acc[cb] = d4{0.0, 0.0, 0.0, 0.0};
+  // entry (k, c) of E: quadrant (k >= l, c >= l), position (k mod l, c mod l)
+  auto eval = [&](int k, int c) -> double {
+    if (k >= l2 || c >= l2) return 0.0;
+    const bool kh = k >= l, ch = c >= l;
+    const int kq = kh ? k - l : k, cq = ch ? c - l : c;
+    const int o = kq * l + cq;
+    return kh == ch ? Rr[o] : (ch ? Ri[o] : -Ri[o]);
+  };
+#pragma unroll
+  for (int st = 0; st < NST; ++st) {
+    if (4 * st >= l2) break;
+    const int k0 = 4 * st, k0q = k0 >= l ? k0 - l : k0;
+    const bool kstraddle = k0 < l && k0 + 3 >= l;
+    double b[NCB];
+    bool use[NCB];
+#pragma unroll
+    for (int cb = 0; cb < NCB; ++cb) {
+      // skip when every k of the step is past every c of the block within its quadrant;
+      // blocks and steps that straddle a quadrant boundary are always computed
+      const int c0 = 16 * cb, c1 = min(c0 + 15, l2 - 1);
+      const bool cstraddle = c0 < l && c1 >= l;
+      const int c1q = c1 >= l ? c1 - l : c1;
+      use[cb] = c0 < l2 && (cstraddle || kstraddle || k0q <= c1q);
+      b[cb] = use[cb] ? eval(k0 + lq, c0 + li) : 0.0;
     }
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int idx = idx0 + u * 256;
-      if (idx < LB * LB) {
-        Rr[idx] = idx < ll ? v[u] : 0.0;
-        Ri[idx] = idx < ll ? v[4 + u] : 0.0;
+    for (int cb = 0; cb < NCB; ++cb)
+      if (use[cb]) acc[cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[st], b[cb], acc[cb], 0, 0, 0);
+  }
+  __syncthreads();  // R^{-1} is no longer read: its LDS holds the result tile
+  T* S = reinterpret_cast<T*>(smem_raw);  // [part * 64 + row][column]
+#pragma unroll
+  for (int cb = 0; cb < NCB; ++cb)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int row = 16 * w + 4 * v + lq, c = 16 * cb + li;
+      if (c < l2) {
+        const bool part = c >= l;
+        S[((part ? 64 : 0) + row) * SP + (part ? c - l : c)] = (r0 + row < m) ? (T)acc[cb][v] : T(0);
       }
     }
-  }
-  const int i = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int row = r0 + i;
-  const bool valid = row < m;
-  const int lrow = valid ? row : m - 1;
-  T yr[LB], yi[LB];
-#pragma unroll
-  for (int a = 0; a < LB; ++a) {
-    const int ac = a < l ? a : l - 1;
-    yr[a] = Y[lrow + (int64_t)ac * ld];
-    yi[a] = Y[m + lrow + (int64_t)ac * ld];
-  }
-#pragma unroll
-  for (int a = 0; a < LB; ++a)
-    if (a >= l) yr[a] = yi[a] = T(0);
   __syncthreads();
-  // q_c = sum_a y_a R^{-1}[a][c]; rows a >= l of R^{-1} are zero in LDS
-#pragma unroll 1
-  for (int c = w; c < l; c += 4) {
-    double ar = 0.0, ai = 0.0, br = 0.0, bi = 0.0;
-#pragma unroll
-    for (int a = 0; a < LB; a += 2) {
-      const double r0r = Rr[a * l + c], r0i = Ri[a * l + c];
-      const double r1r = Rr[(a + 1) * l + c], r1i = Ri[(a + 1) * l + c];
-      const double y0r = (double)yr[a], y0i = (double)yi[a], y1r = (double)yr[a + 1], y1i = (double)yi[a + 1];
-      ar = fma(y0r, r0r, fma(-y0i, r0i, ar));
-      ai = fma(y0r, r0i, fma(y0i, r0r, ai));
-      br = fma(y1r, r1r, fma(-y1i, r1i, br));
-      bi = fma(y1r, r1i, fma(y1i, r1r, bi));
-    }
-    if (valid) {
-      Y[row + (int64_t)c * ld] = (T)(ar + br);
-      Y[m + row + (int64_t)c * ld] = (T)(ai + bi);
-    }
+  const int rows = min(64, m - r0);
+  for (int idx = threadIdx.x; idx < 2 * 64 * l; idx += 256) {
+    const int row = idx % 64, pc = idx / 64, part = pc / l, c = pc % l;
+    if (row < rows) Y[(part ? m : 0) + r0 + row + (int64_t)c * ld] = S[(part * 64 + row) * SP + c];
   }
-  if (gout_all) {
-    __syncthreads();  // R^{-1} is no longer read, and the tile is stored
-    double* S = reinterpret_cast<double*>(smem_raw);
-    constexpr int SP = LB + 1;
-    for (int c = w; c < l; c += 4) {
-      S[i * SP + c] = valid ? (double)Y[row + (int64_t)c * ld] : 0.0;
-      S[(64 + i) * SP + c] = valid ? (double)Y[m + row + (int64_t)c * ld] : 0.0;
-    }
-    __syncthreads();
-    tile_cgram_mfma(S, SP, 1, l, gout_all + d.g2 + (int64_t)(r0 / kGramRows) * 2 * ll);
-  }
+  if (gout_all) tile_cgram_mfma(S, SP, 1, l, gout_all + d.g2 + (int64_t)(r0 / kGramRows) * 2 * ll);
 }
 
-template <int LB>
+template <typename T, int LB>
 constexpr size_t capply_lds_bytes() {
-  constexpr size_t r = 2 * (size_t)LB * LB * 8, t = 128 * (size_t)(LB + 1) * 8;
+  constexpr size_t r = 2 * (size_t)LB * LB * 8, t = 128 * (size_t)(LB + 1) * sizeof(T);
   return r > t ? r : t;
 }
 
@@ -452,9 +508,9 @@ __global__ __launch_bounds__(kSvdThreads) void k_csvd(double* __restrict__ g2_al
   int* perm = reinterpret_cast<int*>(wv + LB);
   double* gq = g2_all + d.g2;  // partials of Q1; the first 2 l^2 doubles park R2^{-1}
 
-  sum_cgram_partials(Ar, Ai, gp, gq, nt_q, l);
-  sum_cgram_partials(Br, Bi, gp, gw_all + d.g1, nt_b, l);
-  __syncthreads();
+  constexpr int NE = (LB * LB + NT - 1) / NT;
+  sum_cgram_partials<NE>(Ar, Ai, gp, gq, nt_q, l);
+  sum_cgram_partials<NE>(Br, Bi, gp, gw_all + d.g1, nt_b, l);
   if (status && tid < 64) {  // a non-finite entry of the slice reaches a diagonal entry of the sums
     bool bad = false;
     for (int a = tid; a < l; a += 64) bad |= !isfinite(Ar[a * gp + a]) || !isfinite(Br[a * gp + a]);
@@ -933,8 +989,8 @@ int launch_corth(T* Y, int which, const SliceDesc* sd, const int2* wk, const int
     HT_CHECK_LAUNCH();
     return HT_OK;
   };
-  if (lmax <= 32) return apply(k_corth_apply<T, 32>, capply_lds_bytes<32>());
-  return apply(k_corth_apply<T, 64>, capply_lds_bytes<64>());
+  if (lmax <= 32) return apply(k_corth_apply<T, 32>, capply_lds_bytes<T, 32>());
+  return apply(k_corth_apply<T, 64>, capply_lds_bytes<T, 64>());
 }
 
 template <typename T>

@@ -19,6 +19,12 @@ constexpr int kGramRows = 64;
 // Largest sketch width of a complex slice (its l x l kernels hold two FP64
 // planes per matrix).
 constexpr int kMaxComplexWidth = 64;
+// Complex rows per work item of the BF16 products of complex slices (items
+// (slice, first complex row) with this step).
+constexpr int kCplxProdRows = 64;
+// Complex reconstruction items: strips of kCmulRows complex rows, groups of up
+// to kCmulGroup column tiles of 64 (item.y = strip * groups + group).
+constexpr int kCmulRows = 128, kCmulGroup = 4;
 
 // Work items.  Every per-slice launch takes an item list: item i of a product
 // or orthonormalization launch is (slice, first row of its tile); of the
@@ -113,9 +119,10 @@ int launch_bf16_tn(const uint16_t* A, const float* Q, float* Z, const SliceDesc*
                    const int2* items, int nitems, int lmax, int rows, double* gpart, hipStream_t s);
 
 // Complex slices (stacked layout) on the matrix cores, l <= kMaxComplexWidth,
-// items of 64 complex rows: nn Y = A W (wreal: W is the real Omega, n2 x l),
-// tn Z = A^H Q, with complex Gram partials; reconstruction QK = Q1 K' (items
-// of 64 complex rows) and C = QK Bt^H (64 x 64 tiles as launch_mfma_nt).
+// items of 64 complex rows (FP32) or kCplxProdRows (BF16): nn Y = A W (wreal:
+// W is the real Omega, n2 x l),
+// tn Z = A^H Q, with complex Gram partials; reconstruction QK = Q1 K' and
+// C = QK Bt^H (items of kCmulRows complex rows and column-tile groups).
 int launch_mfma_cnn(const float* A, const float* W, float* Y, int wreal, const SliceDesc* sd, const int2* wk,
                     const int2* items, int nitems, int lmax, double* gpart, hipStream_t s);
 int launch_mfma_ctn(const float* A, const float* Q, float* Z, const SliceDesc* sd, const int2* wk, const int2* items,
@@ -215,10 +222,12 @@ int launch_lstate_set(int* lstate, int valid, int clear_counts, hipStream_t s);
 // ADMM update (see htsvt.h) and the per-iteration scalar bookkeeping.
 template <typename T>
 int launch_admm_input(const T* M, const T* E, const T* Y, const AdmmState* st, T* Xin, int64_t N, hipStream_t s);
+// Models HT_RPCA_TUBE / HT_RPCA_SLICE first form the squared group norms into
+// gsq (NT or N / NT doubles; NT = n1 n2).
 template <typename T>
 int launch_admm_update(const T* M, const uint8_t* mask, const T* Lnew, T* L, T* E, T* Y, T* Xin,
                        AdmmState* st, int64_t N, int model, Penalty psi, double lambda, double vartheta,
-                       double mu_max, hipStream_t s);
+                       double mu_max, double* gsq, int64_t NT, hipStream_t s);
 int launch_admm_finalize(AdmmState* st, double vartheta, double mu_max, hipStream_t s);
 int launch_admm_reset(AdmmState* st, double mu0, hipStream_t s);
 // st->rse = ||L - truth||_F / ||truth||_F (FP64 block partials in part, 2 per

@@ -37,7 +37,7 @@ struct MfmaLds {
   static constexpr int A_WORDS = (KC * AP_NN > MT * AP_TN) ? KC * AP_NN : MT * AP_TN;
   static constexpr int B_WORDS = KC * BP;
   static constexpr int MAIN_BYTES = 2 * (A_WORDS + B_WORDS) * 4;
-  static constexpr int EPI_BYTES = MT * (32 * NB + 1) * 8;
+  static constexpr int EPI_BYTES = MT * (32 * NB + 1) * 4;  // FP32 tile (the values the products store)
   static constexpr int BYTES = MAIN_BYTES > EPI_BYTES ? MAIN_BYTES : EPI_BYTES;
 };
 
@@ -218,7 +218,7 @@ __global__ __launch_bounds__(64 * NW) void k_mfma_thin(const float* __restrict__
   }
 
   // ---- epilogue: tile to LDS (as double), coalesced store, Gram partial ----
-  double* S = reinterpret_cast<double*>(smem_raw);
+  float* S = reinterpret_cast<float*>(smem_raw);
   const int sp = LW + 1;
 #pragma unroll
   for (int b = 0; b < NB; ++b)
@@ -226,12 +226,12 @@ __global__ __launch_bounds__(64 * NW) void k_mfma_thin(const float* __restrict__
     for (int r = 0; r < 16; ++r) {
       const int i = 32 * wave + 8 * (r / 4) + 4 * (lane / 32) + (r % 4);
       const int c = 32 * b + (lane % 32);
-      S[i * sp + c] = (ovalid(i) && c < l) ? (double)acc[b][r] : 0.0;
+      S[i * sp + c] = (ovalid(i) && c < l) ? acc[b][r] : 0.0f;
     }
   __syncthreads();
   for (int idx = tid; idx < MT * l; idx += NTH) {
     const int i = idx % MT, c = idx / MT;
-    if (ovalid(i)) Yj[orow(i) + (int64_t)c * ldy] = (float)S[i * sp + c];
+    if (ovalid(i)) Yj[orow(i) + (int64_t)c * ldy] = S[i * sp + c];
   }
   if (gpart) {
     if (CPLX)
@@ -539,89 +539,162 @@ int launch_thin(const float* A, const float* W, float* Y, const SliceDesc* sd, c
 
 // Complex reconstruction on the matrix cores (FP32, complex slices in the
 // stacked layout, l <= 64):
-//   MODE 0: QK = Q1 K', a work item is 64 complex rows and all l columns;
-//   MODE 1: C = QK Bt^H, a work item is a 64 x 64 tile (complex rows; row tiles
-//           fastest, as the real reconstruction).
-// With the left factor X = Xr + i Xi and the right one B encoded as the real
-// 2 l x n matrix E = [Re B; -Im B], Re(X B) = [Xr, Xi] E and Im(X B) =
-// [Xi, -Xr] E.  Wavefront w computes the 32 x 32 block (rows 32 (w % 2),
-// columns 32 (w / 2)) of both parts on v_mfma_f32_32x32x2_f32: lane t supplies
-// row t % 32 of X and column t % 32 of E at k = 2 st + t / 32, every load
-// before the first step; the blocks go through LDS for coalesced stores.
+//   MODE 0: QK = Q1 K'   (n1 x l),  B = K' (l x l, stored as 2 l x l);
+//   MODE 1: C = QK Bt^H  (n1 x n2), B = Bt^H with Bt (n2 x l, stored as 2 n2 x l).
+// With X = Xr + i Xi:  Cr = Xr Br - Xi Bi,  Ci = Xi Br + Xr Bi.
+// A work item is a strip of 128 complex rows and a group of up to kCmulGroup
+// column tiles of 64 columns (item.y = strip * groups + group).  Wavefront w
+// keeps rows 32 w .. 32 w + 31 of Xr and Xi in registers for the whole item,
+// as the A operands of v_mfma_f32_32x32x2_f32 (lane t: row t % 32, k = 2 st +
+// t / 32; k past l reads zero).  Per column tile, Br and Bi (k x 64) go to LDS
+// with the two k of a step interleaved, so that the 64 lanes of a step read 64
+// consecutive floats; the next tile's loads are in flight in registers while
+// the matrix cores work on the current one.  The wavefront's 32 x 64 block of
+// both parts (2 column blocks x real / imaginary accumulators) is stored
+// straight from the accumulators: accumulators 4 j .. 4 j + 3 of lane t are
+// rows 8 j + 4 (t / 32) .. + 3 of column t % 32, one 16-byte segment.
+constexpr size_t kCmulLds = 2 * 32 * 64 * 2 * sizeof(float);  // [part][step][column][k parity]
+
 template <int MODE>
-__global__ __launch_bounds__(256) void k_mfma_cmul(const float* __restrict__ Xall, const float* __restrict__ Wall,
-                                                   float* __restrict__ Call, const SliceDesc* __restrict__ sd,
-                                                   const int2* __restrict__ wk, const int2* __restrict__ items) {
-  constexpr int TP = 68, NS = 64;  // staging pitch; steps for K = 2 l <= 128
-  __shared__ __align__(16) float Ts[2][64 * TP];  // [part][column][row]
+__global__ __launch_bounds__(256, 2) void k_cmul_strip(const float* __restrict__ Xall, const float* __restrict__ Wall,
+                                                    float* __restrict__ Call, const SliceDesc* __restrict__ sd,
+                                                    const int2* __restrict__ wk, const int2* __restrict__ items,
+                                                    int aligned) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  float* Es = reinterpret_cast<float*>(smem_raw);
   const int2 item = items[blockIdx.x];
   const int s = item.x;
   const SliceDesc d = sd[s];
   const int l = slice_width(d, wk, s);
   if (l <= 0) return;  // slice not part of this pass
-  const int n1 = d.n1, n2 = d.n2, ldx = 2 * n1, K2 = 2 * l;
-  const int nrt = (n1 + 63) / 64;
-  const int row0 = MODE == 0 ? item.y : (item.y % nrt) * 64;
-  const int col0 = MODE == 0 ? 0 : (item.y / nrt) * 64;
+  const int n1 = d.n1, n2 = d.n2, ldx = 2 * n1;
   const int ncols = MODE == 0 ? l : n2;
+  const int nct = (ncols + 63) / 64, ncg = (nct + kCmulGroup - 1) / kCmulGroup;
+  const int row0 = (item.y / ncg) * kCmulRows, cg = item.y % ncg;
+  const int ct_begin = cg * kCmulGroup, ct_end = min(nct, ct_begin + kCmulGroup);
+  const int half = (l + 1) / 2;  // steps: k = 2 st + parity < 2 half
   const float* X = Xall + d.y;                       // Q1 (MODE 0) or Q1 K' (MODE 1)
-  const float* W = Wall + (MODE == 0 ? d.kq : d.z);  // K' (2 l x l) or Bt (2 n2 x l)
-  float* C = Call + (MODE == 0 ? d.y : d.a);
-  const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
-  const int li = lane % 32, h = lane / 32;
-  const int br = 32 * (wave % 2), bc = 32 * (wave / 2);
-  const int gr = row0 + br + li, gc = col0 + bc + li;
-  const bool rok = gr < n1, cok = gc < ncols;
-  const int lr = rok ? gr : 0, lc = cok ? gc : 0;
-  float are[NS], aim[NS], bv[NS];
+  const float* W = Wall + (MODE == 0 ? d.kq : d.z);  // K' or Bt
+  const int64_t cbase = MODE == 0 ? d.y : d.a;
+  float* C = Call + cbase;
+  const int tid = threadIdx.x, wave = tid / 64, lane = tid % 64, li = lane % 32, h = lane / 32;
+  // ---- the strip's rows of X, in registers for every column tile ----
+  const int xrow = row0 + 32 * wave + li;
+  float xr[32], xi[32];
 #pragma unroll
-  for (int st = 0; st < NS; ++st) {
-    const int k = 2 * st + h;
-    const bool kh = k >= l;
-    const int kk = min(kh ? k - l : k, l - 1);
-    const float xr = X[lr + (int64_t)kk * ldx], xi = X[n1 + lr + (int64_t)kk * ldx];
-    float e;
-    if (MODE == 0) {
-      const float v = W[(kh ? l : 0) + kk + (int64_t)lc * K2];
-      e = kh ? -v : v;
-    } else {
-      e = W[(kh ? n2 : 0) + lc + (int64_t)kk * 2 * n2];
-    }
-    const bool ok = k < K2;
-    are[st] = (ok && rok) ? (kh ? xi : xr) : 0.0f;
-    aim[st] = (ok && rok) ? (kh ? -xr : xi) : 0.0f;
-    bv[st] = (ok && cok) ? e : 0.0f;
+  for (int st = 0; st < 32; ++st) {
+    const int kk = 2 * st + h;
+    const bool ok = st < half && kk < l && xrow < n1;
+    const float* src = X + (ok ? xrow + (int64_t)kk * ldx : 0);
+    xr[st] = ok ? src[0] : 0.0f;
+    xi[st] = ok ? src[n1] : 0.0f;
   }
-  f32x16 accr, acci;
+  // ---- staging of Br, Bi for one column tile: unit f = (part, step, column pair) ----
+  const bool vecw = MODE == 1 && aligned && n2 % 2 == 0 && d.z % 2 == 0;
+  f32x4 pre[8];
+  auto fetch = [&](int ct) {
+    const int col0 = 64 * ct;
 #pragma unroll
-  for (int r = 0; r < 16; ++r) accr[r] = acci[r] = 0.0f;
+    for (int u = 0; u < 8; ++u) {
+      const int f = tid + 256 * u;
+      const int cp = f % 32, st = (f / 32) % 32, part = f / 1024;
+      const int k0 = 2 * st, c0 = col0 + 2 * cp;
+      float v[4] = {0.0f, 0.0f, 0.0f, 0.0f};  // (k0, c0), (k0 + 1, c0), (k0, c0 + 1), (k0 + 1, c0 + 1)
+      if (st < half) {
+        if (MODE == 1) {
+          const float sg = part ? -1.0f : 1.0f;  // Bi = -Im Bt^T
+          const float* src = W + (part ? n2 : 0) + c0;
 #pragma unroll
-  for (int st = 0; st < NS; ++st)
-    if (2 * st < K2) {
-      accr = __builtin_amdgcn_mfma_f32_32x32x2f32(are[st], bv[st], accr, 0, 0, 0);
-      acci = __builtin_amdgcn_mfma_f32_32x32x2f32(aim[st], bv[st], acci, 0, 0, 0);
+          for (int e = 0; e < 2; ++e) {
+            const int kk = k0 + e;
+            if (kk < l) {
+              const float* p = src + (int64_t)kk * 2 * n2;
+              if (vecw && c0 + 1 < ncols) {
+                const float2 t = *reinterpret_cast<const float2*>(p);
+                v[e] = sg * t.x;
+                v[2 + e] = sg * t.y;
+              } else {
+                if (c0 < ncols) v[e] = sg * p[0];
+                if (c0 + 1 < ncols) v[2 + e] = sg * p[1];
+              }
+            }
+          }
+        } else {
+#pragma unroll
+          for (int e = 0; e < 2; ++e) {
+            const int kk = k0 + e;
+#pragma unroll
+            for (int q = 0; q < 2; ++q) {
+              const int c = c0 + q;
+              if (kk < l && c < ncols) v[2 * q + e] = W[(part ? l : 0) + kk + (int64_t)c * 2 * l];
+            }
+          }
+        }
+      }
+      pre[u] = f32x4{v[0], v[1], v[2], v[3]};
     }
+  };
+  auto stash = [&]() {
 #pragma unroll
-  for (int r = 0; r < 16; ++r) {
-    const int i = 8 * (r / 4) + 4 * h + (r % 4);
-    Ts[0][(bc + li) * TP + br + i] = accr[r];
-    Ts[1][(bc + li) * TP + br + i] = acci[r];
-  }
-  __syncthreads();
-  const int rows = min(64, n1 - row0), cols = min(64, ncols - col0);
-  const int64_t base = (MODE == 0 ? d.y : d.a);
-  const bool vec = (ldx % 4 == 0) && (n1 % 4 == 0) && (base % 4 == 0) && (row0 % 4 == 0);
-  for (int f = threadIdx.x; f < 2 * 64 * 16; f += 256) {
-    const int part = f / (64 * 16), g = f % (64 * 16);
-    const int c = g / 16, q = (g % 16) * 4;
-    if (c >= cols) continue;
-    float* dst = C + (part ? n1 : 0) + row0 + q + (int64_t)(col0 + c) * ldx;
-    const float* src = Ts[part] + c * TP + q;
-    if (vec && q + 3 < rows)
-      *reinterpret_cast<f32x4*>(dst) = *reinterpret_cast<const f32x4*>(src);
-    else
-      for (int e = 0; e < 4; ++e)
-        if (q + e < rows) dst[e] = src[e];
+    for (int u = 0; u < 8; ++u) {
+      const int f = tid + 256 * u;
+      const int cp = f % 32, st = (f / 32) % 32, part = f / 1024;
+      if (st < half) *reinterpret_cast<f32x4*>(Es + ((part * 32 + st) * 64 + 2 * cp) * 2) = pre[u];
+    }
+  };
+  const bool vecc = aligned && cbase % 4 == 0 && n1 % 4 == 0;
+  fetch(ct_begin);
+  for (int ct = ct_begin; ct < ct_end; ++ct) {
+    const int col0 = 64 * ct;
+    if (ct > ct_begin) __syncthreads();  // the previous tile's operands are no longer read
+    stash();
+    __syncthreads();
+    if (ct + 1 < ct_end) fetch(ct + 1);
+    const bool two = col0 + 32 < ncols;  // second column block
+    f32x16 ar0, ai0, ar1, ai1;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) ar0[r] = ai0[r] = ar1[r] = ai1[r] = 0.0f;
+#pragma unroll
+    for (int st = 0; st < 32; ++st) {
+      if (st < half) {
+        const float* e0 = Es + ((st * 64) + li) * 2 + h;
+        const float br0 = e0[0], bi0 = e0[32 * 64 * 2];
+        ar0 = __builtin_amdgcn_mfma_f32_32x32x2f32(xr[st], br0, ar0, 0, 0, 0);
+        ai0 = __builtin_amdgcn_mfma_f32_32x32x2f32(xi[st], br0, ai0, 0, 0, 0);
+        ar0 = __builtin_amdgcn_mfma_f32_32x32x2f32(xi[st], -bi0, ar0, 0, 0, 0);
+        ai0 = __builtin_amdgcn_mfma_f32_32x32x2f32(xr[st], bi0, ai0, 0, 0, 0);
+        if (two) {
+          const float br1 = e0[64], bi1 = e0[64 + 32 * 64 * 2];
+          ar1 = __builtin_amdgcn_mfma_f32_32x32x2f32(xr[st], br1, ar1, 0, 0, 0);
+          ai1 = __builtin_amdgcn_mfma_f32_32x32x2f32(xi[st], br1, ai1, 0, 0, 0);
+          ar1 = __builtin_amdgcn_mfma_f32_32x32x2f32(xi[st], -bi1, ar1, 0, 0, 0);
+          ai1 = __builtin_amdgcn_mfma_f32_32x32x2f32(xr[st], bi1, ai1, 0, 0, 0);
+        }
+      }
+    }
+    // ---- store: 16-byte column segments straight from the accumulators ----
+    auto put = [&](const f32x16& acc, int cb, int part) {
+      const int col = col0 + 32 * cb + li;
+      if (col >= ncols) return;
+      float* dst = C + (part ? n1 : 0) + (int64_t)col * ldx;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int rb = row0 + 32 * wave + 8 * j + 4 * h;
+        if (vecc && rb + 3 < n1) {
+          *reinterpret_cast<f32x4*>(dst + rb) = f32x4{acc[4 * j], acc[4 * j + 1], acc[4 * j + 2], acc[4 * j + 3]};
+        } else {
+#pragma unroll
+          for (int e = 0; e < 4; ++e)
+            if (rb + e < n1) dst[rb + e] = acc[4 * j + e];
+        }
+      }
+    };
+    put(ar0, 0, 0);
+    put(ai0, 0, 1);
+    if (two) {
+      put(ar1, 1, 0);
+      put(ai1, 1, 1);
+    }
   }
 }
 
@@ -706,22 +779,28 @@ int launch_mfma_ctn(const float* A, const float* Q, float* Z, const SliceDesc* s
   return launch_thin<2, 4, true, true>(A, Q, Z, sd, wk, items, nitems, gpart, s);
 }
 
-int launch_mfma_cqk(const float* Q, const float* K, float* QK, const SliceDesc* sd, const int2* wk, const int2* items,
-                    int nitems, int lmax, hipStream_t s) {
+template <int MODE>
+int launch_cmul(const float* X, const float* W, float* C, const SliceDesc* sd, const int2* wk, const int2* items,
+                int nitems, int lmax, hipStream_t s) {
   if (lmax > kMaxComplexWidth) HT_FAIL(HT_ERR_UNSUPPORTED, "complex sketch width above 64");
   if (nitems == 0) return HT_OK;
-  hipLaunchKernelGGL(k_mfma_cmul<0>, dim3((unsigned)nitems), dim3(256), 0, s, Q, K, QK, sd, wk, items);
+  int rc = ensure_dynamic_lds((const void*)k_cmul_strip<MODE>, kCmulLds);
+  if (rc) return rc;
+  const int aligned = (reinterpret_cast<uintptr_t>(W) % 8 == 0) && (reinterpret_cast<uintptr_t>(C) % 16 == 0);
+  hipLaunchKernelGGL(k_cmul_strip<MODE>, dim3((unsigned)nitems), dim3(256), kCmulLds, s, X, W, C, sd, wk, items,
+                     aligned);
   HT_CHECK_LAUNCH();
   return HT_OK;
 }
 
+int launch_mfma_cqk(const float* Q, const float* K, float* QK, const SliceDesc* sd, const int2* wk, const int2* items,
+                    int nitems, int lmax, hipStream_t s) {
+  return launch_cmul<0>(Q, K, QK, sd, wk, items, nitems, lmax, s);
+}
+
 int launch_mfma_cnt(const float* X, const float* W, float* C, const SliceDesc* sd, const int2* wk, const int2* items,
                     int nitems, int lmax, hipStream_t s) {
-  if (lmax > kMaxComplexWidth) HT_FAIL(HT_ERR_UNSUPPORTED, "complex sketch width above 64");
-  if (nitems == 0) return HT_OK;
-  hipLaunchKernelGGL(k_mfma_cmul<1>, dim3((unsigned)nitems), dim3(256), 0, s, X, W, C, sd, wk, items);
-  HT_CHECK_LAUNCH();
-  return HT_OK;
+  return launch_cmul<1>(X, W, C, sd, wk, items, nitems, lmax, s);
 }
 
 int launch_mfma_tn(const float* A, const float* Q, float* Z, const SliceDesc* sd, const int2* wk, const int2* items,

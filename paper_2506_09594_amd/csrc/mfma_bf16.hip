@@ -33,7 +33,7 @@ struct Bf16Lds {
   static constexpr int A_ELEMS = MT * KP;
   static constexpr int B_ELEMS = 32 * NB * KP;
   static constexpr int MAIN_BYTES = 2 * (A_ELEMS + B_ELEMS) * 2;
-  static constexpr int EPI_BYTES = MT * (32 * NB + 1) * 8;
+  static constexpr int EPI_BYTES = MT * (32 * NB + 1) * 4;  // FP32 tile (the values the products store)
   static constexpr int BYTES = MAIN_BYTES > EPI_BYTES ? MAIN_BYTES : EPI_BYTES;
 };
 
@@ -90,10 +90,10 @@ __global__ __launch_bounds__(64 * NW) void k_mfma_thin_bf16(const uint16_t* __re
   // A chunk: MT x 32 bf16 = 4 MT 16-byte groups of 8, two per thread.
   // nn: group = 8 consecutive rows of one column k;  tn: 8 consecutive k of one column.
   constexpr int NRA = MT * KC / 8 / NTH;
-  u16x8 ra[NRA];
   constexpr int NWB = (32 * NB * KC / 4 + NTH - 1) / NTH;  // float4 groups of the thin chunk per thread
-  f32x4 rw[NWB];
-  auto fetch = [&](int k0) {
+  u16x8 ra0[NRA], ra1[NRA];  // two chunks of loads in flight
+  f32x4 rw0[NWB], rw1[NWB];
+  auto fetch = [&](u16x8 (&ra)[NRA], f32x4 (&rw)[NWB], int k0) {
 #pragma unroll
     for (int u = 0; u < NRA; ++u) {
       const int g = tid + u * NTH;
@@ -134,7 +134,7 @@ __global__ __launch_bounds__(64 * NW) void k_mfma_thin_bf16(const uint16_t* __re
       rw[u] = v;
     }
   };
-  auto stash = [&](int buf) {
+  auto stash = [&](const u16x8 (&ra)[NRA], const f32x4 (&rw)[NWB], int buf) {
     uint16_t* As = lds_h + buf * L::A_ELEMS;
     uint16_t* Ws = lds_h + 2 * L::A_ELEMS + buf * L::B_ELEMS;
 #pragma unroll
@@ -168,14 +168,9 @@ __global__ __launch_bounds__(64 * NW) void k_mfma_thin_bf16(const uint16_t* __re
 
   const int nchunks = (K + KC - 1) / KC;
   const int nbl = (l + 31) / 32;
-  fetch(0);
-  stash(0);
-  __syncthreads();
   const int mrow = 32 * wave + (lane % 32);
   const int koff = 8 * (lane / 32);
-  for (int ch = 0; ch < nchunks; ++ch) {
-    const int buf = ch & 1;
-    if (ch + 1 < nchunks) fetch((ch + 1) * KC);
+  auto compute = [&](int buf) {
     const uint16_t* As = lds_h + buf * L::A_ELEMS;
     const uint16_t* Ws = lds_h + 2 * L::A_ELEMS + buf * L::B_ELEMS;
 #pragma unroll
@@ -190,11 +185,26 @@ __global__ __launch_bounds__(64 * NW) void k_mfma_thin_bf16(const uint16_t* __re
         }
       }
     }
-    if (ch + 1 < nchunks) stash(buf ^ 1);
+  };
+  // chunk c sits in LDS buffer c & 1 while chunks c + 1 and c + 2 load into
+  // the register sets (unrolled by two so that the sets are fixed)
+  fetch(ra0, rw0, 0);
+  if (nchunks > 1) fetch(ra1, rw1, KC);
+  stash(ra0, rw0, 0);
+  __syncthreads();
+  for (int ch = 0; ch < nchunks; ch += 2) {
+    if (ch + 2 < nchunks) fetch(ra0, rw0, (ch + 2) * KC);
+    compute(0);
+    if (ch + 1 < nchunks) stash(ra1, rw1, 1);
+    __syncthreads();
+    if (ch + 1 >= nchunks) break;
+    if (ch + 3 < nchunks) fetch(ra1, rw1, (ch + 3) * KC);
+    compute(1);
+    if (ch + 2 < nchunks) stash(ra0, rw0, 0);
     __syncthreads();
   }
 
-  double* S = reinterpret_cast<double*>(smem_raw);
+  float* S = reinterpret_cast<float*>(smem_raw);
   const int sp = LW + 1;
 #pragma unroll
   for (int b = 0; b < NB; ++b)
@@ -202,12 +212,12 @@ __global__ __launch_bounds__(64 * NW) void k_mfma_thin_bf16(const uint16_t* __re
     for (int r = 0; r < 16; ++r) {
       const int i = 32 * wave + 8 * (r / 4) + 4 * (lane / 32) + (r % 4);
       const int c = 32 * b + (lane % 32);
-      S[i * sp + c] = (ovalid(i) && c < l) ? (double)acc[b][r] : 0.0;
+      S[i * sp + c] = (ovalid(i) && c < l) ? acc[b][r] : 0.0f;
     }
   __syncthreads();
   for (int idx = tid; idx < MT * l; idx += NTH) {
     const int i = idx % MT, c = idx / MT;
-    if (ovalid(i)) Yj[orow(i) + (int64_t)c * ldy] = (float)S[i * sp + c];
+    if (ovalid(i)) Yj[orow(i) + (int64_t)c * ldy] = S[i * sp + c];
   }
   if (gpart) {
     if (CPLX)
@@ -215,6 +225,229 @@ __global__ __launch_bounds__(64 * NW) void k_mfma_thin_bf16(const uint16_t* __re
     else
       tile_gram_mfma(S, sp, 1, min(MT, M_out - r0), l, gpart + d.g1 + (int64_t)(r0 / kGramRows) * l * l);
   }
+}
+
+// Complex slices (stacked [Ar; Ai] blocks) in BF16: Y = A W (nn; W = [Wr; Wi]
+// stacked, or with wreal the real Omega) and Z = A^H Q (tn), each stored
+// element of A read once.  A work item is MT / 2 complex rows of the result
+// (MT / 64 groups of 64 complex rows, each held as 128 tile rows: its real
+// parts, then its imaginary parts) and all l <= 32 NB columns; wavefront w
+// owns tile rows 32 w .. 32 w + 31.  The reduction runs over the stored
+// columns (nn) or rows (tn) of A in chunks of 32: the chunk of Ar and Ai (MT x
+// 32 in LDS, k contiguous, rows in the tile's order) and the chunks of the
+// real and imaginary parts of the thin operand (rounded to BF16 while staged)
+// feed two passes of the MFMA loop,
+//   nn:  Yr = Ar Wr - Ai Wi,   Yi = Ai Wr + Ar Wi
+//   tn:  Zr = Ar^T Qr + Ai^T Qi,   Zi = -Ai^T Qr + Ar^T Qi
+// where the second pass takes the other half of the row's group (tile row
+// r ^ 64) and a sign flip is an XOR of the BF16 sign bits.  Two chunks of loads
+// are in flight in registers; the epilogue writes the tile and one complex
+// Gram partial per 64 complex rows.
+template <int NB, int MT, bool TRANS>
+__global__ __launch_bounds__(2 * MT) void k_cthin_bf16(const uint16_t* __restrict__ Aall,
+                                                       const float* __restrict__ Wall, float* __restrict__ Yall,
+                                                       const SliceDesc* __restrict__ sd, const int2* __restrict__ wk,
+                                                       const int2* __restrict__ items, double* __restrict__ gpart,
+                                                       int aligned, int wreal) {
+  constexpr int NTH = 2 * MT, LW = 32 * NB;
+  constexpr int A_ELEMS = MT * KP, B_ELEMS = LW * KP;  // one buffer: A chunk, then the two thin chunks
+  constexpr int BUF = A_ELEMS + 2 * B_ELEMS;
+  static_assert(MT % 128 == 0, "groups of 64 complex rows");
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  uint16_t* const lds_h = reinterpret_cast<uint16_t*>(smem_raw);
+  const int2 item = items[blockIdx.x];
+  const int s = item.x, r0 = item.y;
+  const SliceDesc d = sd[s];
+  const int l = slice_width(d, wk, s);
+  if (l <= 0) return;  // slice not part of this pass
+  const int n1 = d.n1, n2 = d.n2, lda = 2 * n1;
+  const int mo = TRANS ? n2 : n1;           // complex output rows
+  const int K = TRANS ? n1 : n2;            // stored reduction length
+  const int ldw = TRANS ? 2 * n1 : (wreal ? n2 : 2 * n2), wim = TRANS ? n1 : n2;
+  const bool two = TRANS || !wreal;         // the thin operand has an imaginary part
+  const int64_t woff = TRANS ? d.y : d.z, yoff = TRANS ? d.z : d.y;
+  const uint16_t* Aj = Aall + d.a;
+  const float* Wj = Wall + woff;
+  float* Yj = Yall + yoff;
+  const bool vecA = aligned && (d.a % 8 == 0) && (n1 % 8 == 0);
+  const bool vecW = aligned && (ldw % 4 == 0) && (woff % 4 == 0) && (wim % 4 == 0);
+  const int tid = threadIdx.x, wave = tid / 64, lane = tid % 64;
+  // complex row of tile row i, whether it holds an imaginary part, validity, stacked output row
+  auto crow = [&](int i) -> int { return r0 + 64 * (i >> 7) + (i & 63); };
+  auto ovalid = [&](int i) -> bool { return crow(i) < mo; };
+  auto orow = [&](int i) -> int { return ((i & 64) ? mo : 0) + crow(i); };
+
+  // A chunk: MT x 32 bf16 in groups of 8, MT / 128 per thread.
+  //   nn: group = 8 consecutive tile rows (of Ar or Ai) of one stored column k
+  //   tn: group = 8 consecutive k (stored rows of Ar or Ai) of one column
+  constexpr int NRA = MT * KC / 8 / NTH;
+  constexpr int NWB = (LW * KC / 4 + NTH - 1) / NTH;  // float4 groups of one thin chunk per thread
+  u16x8 ra0[NRA], ra1[NRA];
+  f32x4 rw0[2][NWB], rw1[2][NWB];
+  auto fetch = [&](u16x8 (&ra)[NRA], f32x4 (&rw)[2][NWB], int k0) {
+#pragma unroll
+    for (int u = 0; u < NRA; ++u) {
+      const int g = tid + u * NTH;
+      u16x8 v;
+      if (!TRANS) {
+        const int kk = g / (MT / 8), row = (g % (MT / 8)) * 8;
+        const int gk = k0 + kk, rr = crow(row);
+        const uint16_t* src = Aj + ((row & 64) ? n1 : 0) + rr + (int64_t)gk * lda;
+        if (vecA && gk < K && rr + 7 < n1) {
+          v = *reinterpret_cast<const u16x8*>(src);
+        } else {
+#pragma unroll
+          for (int e = 0; e < 8; ++e) v[e] = (gk < K && rr + e < n1) ? src[e] : 0;
+        }
+      } else {
+        const int row = g / (KC / 8), kk = (g % (KC / 8)) * 8;
+        const int c = crow(row), gk = k0 + kk;
+        const uint16_t* src = Aj + ((row & 64) ? n1 : 0) + gk + (int64_t)c * lda;
+        if (vecA && c < n2 && gk + 7 < K) {
+          v = *reinterpret_cast<const u16x8*>(src);
+        } else {
+#pragma unroll
+          for (int e = 0; e < 8; ++e) v[e] = (c < n2 && gk + e < K) ? src[e] : 0;
+        }
+      }
+      ra[u] = v;
+    }
+#pragma unroll
+    for (int part = 0; part < 2; ++part)
+#pragma unroll
+      for (int u = 0; u < NWB; ++u) {
+        const int f = tid + u * NTH;
+        const int c = f / (KC / 4), k4 = (f % (KC / 4)) * 4;
+        const int gk = k0 + k4;
+        const float* src = Wj + (part ? wim : 0) + gk + (int64_t)c * ldw;
+        const bool live = (part == 0 || two) && f < LW * KC / 4 && c < l;
+        f32x4 v;
+        if (vecW && live && gk + 3 < K) {
+          v = *reinterpret_cast<const f32x4*>(src);
+        } else {
+#pragma unroll
+          for (int e = 0; e < 4; ++e) v[e] = (live && gk + e < K) ? src[e] : 0.0f;
+        }
+        rw[part][u] = v;
+      }
+  };
+  auto stash = [&](const u16x8 (&ra)[NRA], const f32x4 (&rw)[2][NWB], int buf) {
+    uint16_t* As = lds_h + buf * BUF;
+#pragma unroll
+    for (int u = 0; u < NRA; ++u) {
+      const int g = tid + u * NTH;
+      if (!TRANS) {
+        const int kk = g / (MT / 8), row = (g % (MT / 8)) * 8;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) As[(row + e) * KP + kk] = ra[u][e];
+      } else {
+        const int row = g / (KC / 8), kk = (g % (KC / 8)) * 8;
+        *reinterpret_cast<u16x8*>(As + row * KP + kk) = ra[u];
+      }
+    }
+#pragma unroll
+    for (int part = 0; part < 2; ++part) {
+      uint16_t* Ws = As + A_ELEMS + part * B_ELEMS;
+#pragma unroll
+      for (int u = 0; u < NWB; ++u) {
+        const int f = tid + u * NTH;
+        if (f < LW * KC / 4) {
+          const int c = f / (KC / 4), k4 = (f % (KC / 4)) * 4;
+#pragma unroll
+          for (int e = 0; e < 4; ++e) Ws[c * KP + k4 + e] = f32_to_bf16_rne(rw[part][u][e]);
+        }
+      }
+    }
+  };
+
+  f32x16 acc[NB];
+#pragma unroll
+  for (int b = 0; b < NB; ++b)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) acc[b][r] = 0.0f;
+  const int nchunks = (K + KC - 1) / KC;
+  const int nbl = (l + 31) / 32;
+  const int mrow = 32 * wave + (lane % 32), koff = 8 * (lane / 32);
+  const bool top = (mrow & 64) == 0;  // this wavefront's rows are real parts
+  // sign flips of the two passes (see above)
+  const unsigned short flip1 = (TRANS && !top) ? 0x8000u : 0u;
+  const unsigned short flip2 = (!TRANS && top) ? 0x8000u : 0u;
+  auto compute = [&](int buf) {
+    const uint16_t* As = lds_h + buf * BUF;
+#pragma unroll
+    for (int part = 0; part < 2; ++part) {
+      if (part == 1 && !two) break;
+      const uint16_t* Ws = As + A_ELEMS + part * B_ELEMS;
+      const int arow = part ? (mrow ^ 64) : mrow;
+      const unsigned short flip = part ? flip2 : flip1;
+#pragma unroll
+      for (int kh = 0; kh < KC / 16; ++kh) {
+        u16x8 av = *reinterpret_cast<const u16x8*>(As + arow * KP + 16 * kh + koff);
+        av ^= flip;
+        const bf16x8 a = __builtin_bit_cast(bf16x8, av);
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+          if (b < nbl) {
+            const bf16x8 bv = __builtin_bit_cast(
+                bf16x8, *reinterpret_cast<const u16x8*>(Ws + (32 * b + (lane % 32)) * KP + 16 * kh + koff));
+            acc[b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bv, acc[b], 0, 0, 0);
+          }
+        }
+      }
+    }
+  };
+  fetch(ra0, rw0, 0);
+  if (nchunks > 1) fetch(ra1, rw1, KC);
+  stash(ra0, rw0, 0);
+  __syncthreads();
+  for (int ch = 0; ch < nchunks; ch += 2) {
+    if (ch + 2 < nchunks) fetch(ra0, rw0, (ch + 2) * KC);
+    compute(0);
+    if (ch + 1 < nchunks) stash(ra1, rw1, 1);
+    __syncthreads();
+    if (ch + 1 >= nchunks) break;
+    if (ch + 3 < nchunks) fetch(ra1, rw1, (ch + 3) * KC);
+    compute(1);
+    if (ch + 2 < nchunks) stash(ra0, rw0, 0);
+    __syncthreads();
+  }
+
+  float* S = reinterpret_cast<float*>(smem_raw);
+  const int sp = LW + 1;
+#pragma unroll
+  for (int b = 0; b < NB; ++b)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int i = 32 * wave + 8 * (r / 4) + 4 * (lane / 32) + (r % 4);
+      const int c = 32 * b + (lane % 32);
+      S[i * sp + c] = (ovalid(i) && c < l) ? acc[b][r] : 0.0f;
+    }
+  __syncthreads();
+  const int ldy = 2 * mo;
+  for (int idx = tid; idx < MT * l; idx += NTH) {
+    const int i = idx % MT, c = idx / MT;
+    if (ovalid(i)) Yj[orow(i) + (int64_t)c * ldy] = S[i * sp + c];
+  }
+  if (gpart)
+    for (int g = 0; g < MT / 128; ++g)
+      if (r0 + 64 * g < mo)
+        tile_cgram_mfma(S + 128 * g * sp, sp, 1, l, gpart + d.g1 + (int64_t)((r0 + 64 * g) / kGramRows) * 2 * l * l);
+}
+
+template <int NB, bool TRANS>
+int launch_cthin_bf16(const uint16_t* A, const float* W, float* Y, const SliceDesc* sd, const int2* wk,
+                      const int2* items, int nitems, double* gpart, hipStream_t s, int wreal) {
+  constexpr int MT = 2 * kCplxProdRows;
+  constexpr size_t main = 2 * (size_t)(MT * KP + 2 * 32 * NB * KP) * 2, epi = MT * (size_t)(32 * NB + 1) * 4;
+  constexpr size_t bytes = main > epi ? main : epi;
+  if (nitems == 0) return HT_OK;
+  int rc = ensure_dynamic_lds((const void*)k_cthin_bf16<NB, MT, TRANS>, bytes);
+  if (rc) return rc;
+  const int aligned = (reinterpret_cast<uintptr_t>(A) % 16 == 0) && (reinterpret_cast<uintptr_t>(W) % 16 == 0);
+  hipLaunchKernelGGL((k_cthin_bf16<NB, MT, TRANS>), dim3((unsigned)nitems), dim3(2 * MT), bytes, s, A, W, Y, sd, wk,
+                     items, gpart, aligned, wreal);
+  HT_CHECK_LAUNCH();
+  return HT_OK;
 }
 
 template <int NB, int NW, bool TRANS, bool CPLX = false>
@@ -255,15 +488,15 @@ int launch_bf16_nn(const uint16_t* A, const float* W, float* Y, const SliceDesc*
 int launch_bf16_cnn(const uint16_t* A, const float* W, float* Y, int wreal, const SliceDesc* sd, const int2* wk,
                     const int2* items, int nitems, int lmax, double* gpart, hipStream_t s) {
   if (lmax > kMaxComplexWidth) HT_FAIL(HT_ERR_UNSUPPORTED, "complex sketch width above 64");
-  if (lmax <= 32) return launch_thin_bf16<1, 4, false, true>(A, W, Y, sd, wk, items, nitems, gpart, s, wreal);
-  return launch_thin_bf16<2, 4, false, true>(A, W, Y, sd, wk, items, nitems, gpart, s, wreal);
+  if (lmax <= 32) return launch_cthin_bf16<1, false>(A, W, Y, sd, wk, items, nitems, gpart, s, wreal);
+  return launch_cthin_bf16<2, false>(A, W, Y, sd, wk, items, nitems, gpart, s, wreal);
 }
 
 int launch_bf16_ctn(const uint16_t* A, const float* Q, float* Z, const SliceDesc* sd, const int2* wk,
                     const int2* items, int nitems, int lmax, double* gpart, hipStream_t s) {
   if (lmax > kMaxComplexWidth) HT_FAIL(HT_ERR_UNSUPPORTED, "complex sketch width above 64");
-  if (lmax <= 32) return launch_thin_bf16<1, 4, true, true>(A, Q, Z, sd, wk, items, nitems, gpart, s);
-  return launch_thin_bf16<2, 4, true, true>(A, Q, Z, sd, wk, items, nitems, gpart, s);
+  if (lmax <= 32) return launch_cthin_bf16<1, true>(A, Q, Z, sd, wk, items, nitems, gpart, s, 0);
+  return launch_cthin_bf16<2, true>(A, Q, Z, sd, wk, items, nitems, gpart, s, 0);
 }
 
 int launch_bf16_tn(const uint16_t* A, const float* Q, float* Z, const SliceDesc* sd, const int2* wk,

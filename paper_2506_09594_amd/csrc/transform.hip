@@ -465,11 +465,72 @@ __device__ __forceinline__ void cplx_fiber(T* re, T* im, int base, int stride, i
   }
 }
 
+// The same product for a DFT mode of power-of-two length N, as an in-register
+// radix-2 fast Fourier transform (decimation in time, bit-reversed load,
+// natural-order result): M is the mode's DFT matrix s exp(-+ 2 pi i a b / N), so
+// its row 1 over its first entry gives the twiddles exp(-+ 2 pi i j / N) and
+// the first entry the scale s.  N log2 N / 2 butterflies instead of N^2
+// multiply-adds.
+template <int N>
+struct Log2 {
+  static constexpr int value = 1 + Log2<N / 2>::value;
+};
+template <>
+struct Log2<1> {
+  static constexpr int value = 0;
+};
+
+template <typename T, int N>
+__device__ __forceinline__ void fft_fiber(T* re, T* im, int base, int stride, const T* __restrict__ M) {
+  constexpr int LG = Log2<N>::value;
+  T xr[N], xi[N];
+#pragma unroll
+  for (int m = 0; m < N; ++m) {
+    int r = 0;
+#pragma unroll
+    for (int b = 0; b < LG; ++b) r |= ((m >> b) & 1) << (LG - 1 - b);
+    xr[r] = re[base + m * stride];
+    xi[r] = im[base + m * stride];
+  }
+  const T sc = M[0];
+  const T inv = T(1) / sc;
+  T wr[N / 2 > 0 ? N / 2 : 1], wi[N / 2 > 0 ? N / 2 : 1];
+#pragma unroll
+  for (int j = 0; j < N / 2; ++j) {
+    wr[j] = M[2 * (N + j)] * inv;
+    wi[j] = M[2 * (N + j) + 1] * inv;
+  }
+#pragma unroll
+  for (int len = 2; len <= N; len <<= 1) {
+    const int half = len / 2, step = N / len;
+#pragma unroll
+    for (int s0 = 0; s0 < N; s0 += len)
+#pragma unroll
+      for (int j = 0; j < half; ++j) {
+        const int a = s0 + j, b = s0 + j + half;
+        const T tr = wr[j * step] * xr[b] - wi[j * step] * xi[b];
+        const T ti = wr[j * step] * xi[b] + wi[j * step] * xr[b];
+        xr[b] = xr[a] - tr;
+        xi[b] = xi[a] - ti;
+        xr[a] += tr;
+        xi[a] += ti;
+      }
+  }
+#pragma unroll
+  for (int k = 0; k < N; ++k) {
+    re[base + k * stride] = xr[k] * sc;
+    im[base + k * stride] = xi[k] * sc;
+  }
+}
+
 template <typename T, typename TO>
 __global__ __launch_bounds__(256) void k_transform_cplx(const T* __restrict__ in_all, TO* __restrict__ out_all,
                                                         const TensorDesc* __restrict__ tds,
                                                         const int2* __restrict__ items, const T* __restrict__ table,
-                                                        const int32_t* __restrict__ cmap_all, int inverse) {
+                                                        const int32_t* __restrict__ cmap_all, int inverse, int aligned) {
+  constexpr int V = 16 / sizeof(T);  // elements per 16-byte access
+  constexpr int UNR = 8;             // accesses in flight per thread
+  using VT = __attribute__((ext_vector_type(V))) T;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int2 item = items[blockIdx.x];
   const TensorDesc* td = tds + item.x;
@@ -484,31 +545,83 @@ __global__ __launch_bounds__(256) void k_transform_cplx(const T* __restrict__ in
   const int64_t rem = NT - t0;
   const int tp = rem < TP ? (int)rem : TP;
   const int tid = threadIdx.x, nt = blockDim.x;
-  // ---- load --------------------------------------------------------------------
+  // V consecutive tube positions of one slice are V consecutive rows of one
+  // column of the slice (and of its slot) when these hold
+  const bool vec = aligned && TP % V == 0 && NT % V == 0 && n1 % V == 0 && td->x % V == 0 && td->a % V == 0;
+  const int nv = total / V;
+  // ---- load (every access of a batch issued before any LDS store) ------------
   if (!inverse) {
     const T* in = in_all + td->x;
-    for (int idx = tid; idx < total; idx += nt) {
-      const int j = idx >> lgTP, t = idx & (TP - 1);
-      re[idx] = (t < tp) ? in[(int64_t)j * NT + t0 + t] : T(0);
-      im[idx] = T(0);
+    if (vec) {
+      for (int v0 = tid; v0 < nv; v0 += UNR * nt) {
+        VT r[UNR];
+#pragma unroll
+        for (int u = 0; u < UNR; ++u) {
+          const int vi = v0 + u * nt, idx = vi * V;
+          const int j = idx >> lgTP, t = idx & (TP - 1);
+          r[u] = (vi < nv && t < tp) ? *reinterpret_cast<const VT*>(in + (int64_t)j * NT + t0 + t) : VT{};
+        }
+#pragma unroll
+        for (int u = 0; u < UNR; ++u) {
+          const int vi = v0 + u * nt;
+          if (vi < nv) {
+            *reinterpret_cast<VT*>(re + vi * V) = r[u];
+            *reinterpret_cast<VT*>(im + vi * V) = VT{};
+          }
+        }
+      }
+    } else {
+      for (int idx = tid; idx < total; idx += nt) {
+        const int j = idx >> lgTP, t = idx & (TP - 1);
+        re[idx] = (t < tp) ? in[(int64_t)j * NT + t0 + t] : T(0);
+        im[idx] = T(0);
+      }
     }
   } else {
     const T* C = in_all + td->a;  // slots [Re; Im], 2 NT each
-    for (int idx = tid; idx < total; idx += nt) {
-      const int j = idx >> lgTP, t = idx & (TP - 1);
-      T vr = T(0), vi = T(0);
-      if (t < tp) {
-        const int32_t code = cmap[j];
-        const int slot = code & 0x7fffffff;
-        const int64_t tt = t0 + t;
-        const int64_t i1 = tt % n1, i2 = tt / n1;
-        const T* S = C + (int64_t)slot * 2 * NT + i1 + i2 * 2 * n1;
-        vr = S[0];
-        vi = S[n1];
-        if (code < 0) vi = -vi;  // conjugate partner
+    if (vec) {
+      for (int v0 = tid; v0 < nv; v0 += UNR * nt) {
+        VT rr[UNR], ri[UNR];
+        bool cj[UNR];
+#pragma unroll
+        for (int u = 0; u < UNR; ++u) {
+          const int vi = v0 + u * nt, idx = vi * V;
+          const int j = idx >> lgTP, t = idx & (TP - 1);
+          const bool ok = vi < nv && t < tp;
+          const int32_t code = ok ? cmap[j] : 0;
+          const int64_t tt = t0 + t;
+          const int64_t i1 = tt % n1, i2 = tt / n1;
+          const T* S = C + (int64_t)(code & 0x7fffffff) * 2 * NT + i1 + i2 * 2 * n1;
+          rr[u] = ok ? *reinterpret_cast<const VT*>(S) : VT{};
+          ri[u] = ok ? *reinterpret_cast<const VT*>(S + n1) : VT{};
+          cj[u] = code < 0;  // conjugate partner
+        }
+#pragma unroll
+        for (int u = 0; u < UNR; ++u) {
+          const int vi = v0 + u * nt;
+          if (vi < nv) {
+            *reinterpret_cast<VT*>(re + vi * V) = rr[u];
+            *reinterpret_cast<VT*>(im + vi * V) = cj[u] ? -ri[u] : ri[u];
+          }
+        }
       }
-      re[idx] = vr;
-      im[idx] = vi;
+    } else {
+      for (int idx = tid; idx < total; idx += nt) {
+        const int j = idx >> lgTP, t = idx & (TP - 1);
+        T vr = T(0), vi = T(0);
+        if (t < tp) {
+          const int32_t code = cmap[j];
+          const int slot = code & 0x7fffffff;
+          const int64_t tt = t0 + t;
+          const int64_t i1 = tt % n1, i2 = tt / n1;
+          const T* S = C + (int64_t)slot * 2 * NT + i1 + i2 * 2 * n1;
+          vr = S[0];
+          vi = S[n1];
+          if (code < 0) vi = -vi;  // conjugate partner
+        }
+        re[idx] = vr;
+        im[idx] = vi;
+      }
     }
   }
   __syncthreads();
@@ -520,7 +633,17 @@ __global__ __launch_bounds__(256) void k_transform_cplx(const T* __restrict__ in
     const int nfib = total / n;
     for (int f = tid; f < nfib; f += nt) {
       const int base = fiber_base(f, TP, lgTP, s, n);
-      if (n <= 8)
+      if (n == 2)
+        fft_fiber<T, 2>(re, im, base, s * TP, M);
+      else if (n == 4)
+        fft_fiber<T, 4>(re, im, base, s * TP, M);
+      else if (n == 8)
+        fft_fiber<T, 8>(re, im, base, s * TP, M);
+      else if (n == 16)
+        fft_fiber<T, 16>(re, im, base, s * TP, M);
+      else if (n == 32)
+        fft_fiber<T, 32>(re, im, base, s * TP, M);
+      else if (n <= 8)
         cplx_fiber<T, 8>(re, im, base, s * TP, n, M);
       else if (n <= 16)
         cplx_fiber<T, 16>(re, im, base, s * TP, n, M);
@@ -534,27 +657,63 @@ __global__ __launch_bounds__(256) void k_transform_cplx(const T* __restrict__ in
   // ---- store ---------------------------------------------------------------------
   if (!inverse) {
     TO* A = out_all + td->a;
-    for (int idx = tid; idx < total; idx += nt) {
-      const int j = idx >> lgTP, t = idx & (TP - 1);
-      const int32_t code = cmap[j];
-      if (t < tp && code >= 0) {  // canonical member of its pair
-        const int64_t tt = t0 + t;
-        const int64_t i1 = tt % n1, i2 = tt / n1;
-        TO* S = A + (int64_t)code * 2 * NT + i1 + i2 * 2 * n1;
-        if constexpr (std::is_same<TO, T>::value) {
-          S[0] = re[idx];
-          S[n1] = im[idx];
-        } else {
-          S[0] = f32_to_bf16_rne((float)re[idx]);
-          S[n1] = f32_to_bf16_rne((float)im[idx]);
+    if (vec) {
+      for (int vi = tid; vi < nv; vi += nt) {
+        const int idx = vi * V;
+        const int j = idx >> lgTP, t = idx & (TP - 1);
+        const int32_t code = cmap[j];
+        if (t < tp && code >= 0) {  // canonical member of its pair
+          const int64_t tt = t0 + t;
+          const int64_t i1 = tt % n1, i2 = tt / n1;
+          TO* S = A + (int64_t)code * 2 * NT + i1 + i2 * 2 * n1;
+          const VT vr = *reinterpret_cast<const VT*>(re + idx), vi2 = *reinterpret_cast<const VT*>(im + idx);
+          if constexpr (std::is_same<TO, T>::value) {
+            *reinterpret_cast<VT*>(S) = vr;
+            *reinterpret_cast<VT*>(S + n1) = vi2;
+          } else {
+            typedef unsigned short us4 __attribute__((ext_vector_type(4)));
+            us4 hr, hi;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+              hr[e] = f32_to_bf16_rne((float)vr[e]);
+              hi[e] = f32_to_bf16_rne((float)vi2[e]);
+            }
+            *reinterpret_cast<us4*>(S) = hr;
+            *reinterpret_cast<us4*>(S + n1) = hi;
+          }
+        }
+      }
+    } else {
+      for (int idx = tid; idx < total; idx += nt) {
+        const int j = idx >> lgTP, t = idx & (TP - 1);
+        const int32_t code = cmap[j];
+        if (t < tp && code >= 0) {  // canonical member of its pair
+          const int64_t tt = t0 + t;
+          const int64_t i1 = tt % n1, i2 = tt / n1;
+          TO* S = A + (int64_t)code * 2 * NT + i1 + i2 * 2 * n1;
+          if constexpr (std::is_same<TO, T>::value) {
+            S[0] = re[idx];
+            S[n1] = im[idx];
+          } else {
+            S[0] = f32_to_bf16_rne((float)re[idx]);
+            S[n1] = f32_to_bf16_rne((float)im[idx]);
+          }
         }
       }
     }
   } else {
     TO* out = out_all + td->x;
-    for (int idx = tid; idx < total; idx += nt) {
-      const int j = idx >> lgTP, t = idx & (TP - 1);
-      if (t < tp) out[(int64_t)j * NT + t0 + t] = (TO)re[idx];
+    if (vec && std::is_same<TO, T>::value) {
+      for (int vi = tid; vi < nv; vi += nt) {
+        const int idx = vi * V;
+        const int j = idx >> lgTP, t = idx & (TP - 1);
+        if (t < tp) *reinterpret_cast<VT*>(out + (int64_t)j * NT + t0 + t) = *reinterpret_cast<const VT*>(re + idx);
+      }
+    } else {
+      for (int idx = tid; idx < total; idx += nt) {
+        const int j = idx >> lgTP, t = idx & (TP - 1);
+        if (t < tp) out[(int64_t)j * NT + t0 + t] = (TO)re[idx];
+      }
     }
   }
 }
@@ -566,8 +725,9 @@ int launch_transform_cplx(const T* in, TO* out, const TensorDesc* tds, const int
   if (lds > 160 * 1024) HT_FAIL(HT_ERR_UNSUPPORTED, "transform tile above the LDS size");
   int rc = ensure_dynamic_lds((const void*)k_transform_cplx<T, TO>, 160 * 1024);
   if (rc) return rc;
+  const int aligned = (reinterpret_cast<uintptr_t>(in) % 16 == 0) && (reinterpret_cast<uintptr_t>(out) % 16 == 0);
   hipLaunchKernelGGL((k_transform_cplx<T, TO>), dim3((unsigned)nitems), dim3(256), lds, stream, in, out, tds, items,
-                     table, cmap, inverse);
+                     table, cmap, inverse, aligned);
   HT_CHECK_LAUNCH();
   return HT_OK;
 }

@@ -31,10 +31,11 @@ OK, ERR_INVALID_ARG, ERR_UNSUPPORTED, ERR_NONFINITE, ERR_WORKSPACE, ERR_HIP, ERR
 TRANSFORMS = {"dct2": 0, "dft": 1, "custom": 2, "dft_unnormalized": 3}
 PRECISIONS = {"fp64": 0, "fp32": 1, "bf16": 2}
 PENALTIES = {"l1": 0, "mcp": 1, "scad": 2, "log": 3, "capped_l1": 4, "firm": 5}
-MODELS = {"completion": 0, "rpca": 1}
+MODELS = {"completion": 0, "rpca": 1, "rpca_tube": 2, "rpca_slice": 3}
 REGIONS = {"A": 0, "omega": 1, "Q": 2, "Bt": 3, "K": 4, "QK": 5, "C": 6, "Lnew": 7, "Xin": 8, "state": 9,
            "gram": 10, "gram_q": 11, "widths": 12, "call": 13, "widths_redo": 14, "widths_used": 15,
-           "sigma": 16, "kept": 17, "anorm": 18, "features": 19, "learn_state": 20, "status": 21, "rse_part": 22}
+           "sigma": 16, "kept": 17, "anorm": 18, "features": 19, "learn_state": 20, "status": 21, "rse_part": 22,
+           "group_sq": 23}
 
 # Symbols the header declares (checked by the CPU test suite).
 EXPORTS = [

@@ -140,3 +140,48 @@ def test_plan_records_its_device(ht):
     import torch
     plan = ht.Plan((20, 16, 3), ["dct2"], r=3, p=2, q=1, precision="fp32")
     assert plan.device() == torch.cuda.current_device()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("model", ["rpca_tube", "rpca_slice"])
+def test_group_sparse_models_match_oracle(ht, prec, model):
+    """Robust completion with tube-wise and slice-wise GNHTT on the sparse part
+    (structured outliers: whole corrupted tubes or slices), one and eight
+    iterations against the oracle at the per-iteration tolerances."""
+    import torch
+    dims, kinds, rank = (40, 30, 6, 4), ["dct2", "dct2"], 4
+    Lt = synth.lowrank_tensor(dims, rank, kinds, seed=5, noise_std=1e-3)
+    rng = np.random.default_rng(5)
+    S = np.zeros(dims)
+    if model == "rpca_tube":
+        for _ in range(60):  # corrupted tubes
+            S[rng.integers(dims[0]), rng.integers(dims[1]), :, :] = rng.uniform(-2, 2, dims[2:])
+    else:
+        for j in rng.choice(24, 3, replace=False):  # corrupted slices
+            S[:, :, j % 6, j // 6] = rng.uniform(-1, 1, dims[:2])
+    mask = synth.observation_mask(dims, 0.7, 5)
+    M = np.where(mask, Lt + S, 0.0).astype(np.float64 if prec == "fp64" else np.float32).astype(np.float64)
+    r, p, q, seed = 4, 4, 1, 31
+    mu0 = 1.0 / synth.max_slice_norm(M, kinds)
+    lam = 0.5 / np.sqrt(max(dims[0], dims[1]) * 24)
+    phi, psi = ("mcp", (40.0,)), ("l1", ())
+    plan = ht.Plan(dims, kinds, r=r, p=p, q=q, precision=prec, seed=seed)
+    dt = plan.torch_dtype
+    T = otr.build_transforms(dims, kinds)
+    for n_iter in (1, 8):
+        adm = ht.Admm(plan, model, phi=phi, psi=psi, lam=lam, mu0=mu0, vartheta=1.2, mu_max=1e10)
+        dL, dE, dY = (torch.empty(plan.N, dtype=dt, device="cuda") for _ in range(3))
+        ws = plan.alloc_workspace(admm=True)
+        adm.init(dL, dE, dY, ws)
+        adm.iterate(ht.to_device(M, dt), ht.to_device(mask.astype(np.uint8), torch.uint8), dL, dE, dY, n_iter, ws)
+        torch.cuda.synchronize()
+        rnd = lambda X, tau, t: otsvt.tsvt_randomized(
+            X, tau, phi, T, r, p, q,
+            otsvt.omegas(dims, kinds, r, p, seed=seed, call=t, round_to=None if prec == "fp64" else np.float32))
+        Lr, Er, Yr, _ = osolver.admm(M, mask, model, phi, psi, lam, mu0, 1.2, 1e10, n_iter, rnd)
+        # one iteration at the per-iteration tolerance; eight at ten times it (rounding of the
+        # storage type feeds the next iteration's sketch input)
+        tol = TOL[prec] * (1 if n_iter == 1 else 10)
+        for name, g, ref in (("L", dL, Lr), ("E", dE, Er), ("Y", dY, Yr)):
+            e = _rel(ht.from_device(g, dims), ref)
+            assert e < tol, f"{model} {prec} {n_iter} iterations: {name} rel err {e:.3e}"

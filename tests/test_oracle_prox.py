@@ -146,3 +146,54 @@ def test_zero_threshold_is_the_boundary_of_the_prox(kind, params, mu):
     surv = np.array([P.prox_scalar(kind, v, mu, params) > 0.0 for v in vs])
     first = vs[np.argmax(surv)]
     assert abs(first - t0) <= vs[1] - vs[0] + 1e-12
+
+
+# ---- GNHTT (group shrinkage) -------------------------------------------------
+
+@pytest.mark.parametrize("kind,params", [("l1", ()), ("mcp", (3.0,)), ("scad", (3.7, 1.0)), ("log", (0.5,))])
+def test_gnhtt_group_minimizes_its_objective(kind, params):
+    """Tube and slice GNHTT minimize mu * phi(||E_g||) + ||E_g - A_g||^2 / 2 group by
+    group: no random perturbation of a group's output lowers its objective."""
+    rng = np.random.default_rng(3)
+    A = rng.standard_normal((3, 2, 4)) * 1.5
+    mu = 0.8
+    for group, axes in (("tube", lambda E: [E[i, j, :] for i in range(3) for j in range(2)]),
+                        ("slice", lambda E: [E[:, :, k] for k in range(4)])):
+        E = P.gnhtt(A, mu, kind, params, group)
+        for eg, ag in zip(axes(E), axes(A)):
+            obj = lambda x: mu * P.phi(kind, np.linalg.norm(x), params) + 0.5 * np.sum((x - ag) ** 2)
+            f0 = obj(eg)
+            for _ in range(300):
+                d = rng.standard_normal(eg.shape) * rng.choice([1e-3, 1e-1, 1.0])
+                assert obj(eg + d) >= f0 - 1e-10
+
+
+def test_gnhtt_l1_tube_is_block_soft_threshold():
+    rng = np.random.default_rng(4)
+    A = rng.standard_normal((4, 3, 5))
+    mu = 1.1
+    E = P.gnhtt(A, mu, "l1", (), "tube")
+    nrm = np.linalg.norm(A, axis=2, keepdims=True)
+    ref = np.maximum(0.0, 1.0 - mu / nrm) * A
+    assert np.allclose(E, ref, atol=1e-14)
+
+
+def test_gnhtt_groups_of_one_are_element_wise():
+    """Tubes of length one (an order-2 tensor) and slices of one entry reduce to the
+    element-wise proximity operator."""
+    rng = np.random.default_rng(5)
+    A = rng.standard_normal((5, 4))
+    ref = P.prox("mcp", A, 0.7, (2.0,))
+    assert np.allclose(P.gnhtt(A, 0.7, "mcp", (2.0,), "tube"), ref, atol=1e-14)
+    B = rng.standard_normal((1, 1, 6))
+    assert np.allclose(P.gnhtt(B, 0.7, "mcp", (2.0,), "slice"), P.prox("mcp", B, 0.7, (2.0,)), atol=1e-14)
+
+
+def test_gnhtt_mask_zeroes_unobserved_entries():
+    rng = np.random.default_rng(6)
+    A = rng.standard_normal((4, 4, 3))
+    mask = rng.random(A.shape) < 0.5
+    E = P.gnhtt(A, 0.3, "l1", (), "slice", mask)
+    assert np.all(E[~mask] == 0.0)
+    Am = np.where(mask, A, 0.0)
+    assert np.allclose(E, P.gnhtt(Am, 0.3, "l1", (), "slice"), atol=1e-15)
