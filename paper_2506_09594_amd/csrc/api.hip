@@ -139,6 +139,7 @@ struct ht_plan {
   std::vector<SliceDesc> h_slices;
   int64_t Atot;   // elements of the A / C regions
   bool cplx;      // every tensor under the unitary DFT (complex slices)
+  int mode_nmax;  // longest transformed mode of the plan
   int32_t* d_cmap;
   TensorDesc* d_tens;
   SliceDesc* d_slices;
@@ -618,6 +619,9 @@ int build_plan(const ht_plan_desc* descs, int n, bool batch, ht_plan** out) {
     HT_FAIL(HT_ERR_UNSUPPORTED, "a batch mixes DFT and real transforms");
   }
   pl->cplx = ncplx > 0;
+  pl->mode_nmax = 1;
+  for (const TensorHost& th : pl->tens)
+    for (int m = 0; m < th.fwd.nmodes; ++m) pl->mode_nmax = std::max(pl->mode_nmax, th.fwd.n[m]);
   if (P > (int64_t)INT32_MAX / 64) {
     free_plan(pl);
     HT_FAIL(HT_ERR_UNSUPPORTED, "too many face slices in one plan");
@@ -869,9 +873,10 @@ int run_tsvt(const ht_plan* pl, const T* X, T* out, double tau, const double* ta
          if (pl->cplx) {
            if (bf16)
              return launch_transform_cplx<float, uint16_t>((const float*)X, (uint16_t*)A, pl->d_tens, it,
-                                                           pl->it_tf.n, pl->tf_lds, pl->table32, pl->d_cmap, 0, s);
+                                                           pl->it_tf.n, pl->tf_lds, pl->table32, pl->d_cmap, 0,
+                                                           pl->mode_nmax, s);
            return launch_transform_cplx<T, T>(X, A, pl->d_tens, it, pl->it_tf.n, pl->tf_lds, table<T>(pl),
-                                              pl->d_cmap, 0, s);
+                                              pl->d_cmap, 0, pl->mode_nmax, s);
          }
          if (bf16)
            return launch_transform<float, uint16_t>((const float*)X, (uint16_t*)A, pl->d_tens, it, pl->it_tf.n,
@@ -1046,7 +1051,7 @@ int run_tsvt(const ht_plan* pl, const T* X, T* out, double tau, const double* ta
                                        pl->table32, 1, s);
     if (pl->cplx)
       return launch_transform_cplx<T, T>(C, out, pl->d_tens, items(pl, pl->it_tf), pl->it_tf.n, pl->tf_lds,
-                                         table<T>(pl), pl->d_cmap, 1, s);
+                                         table<T>(pl), pl->d_cmap, 1, pl->mode_nmax, s);
     return launch_transform<T, T>(C, out, pl->d_tens, items(pl, pl->it_tf), pl->it_tf.n, pl->tf_lds, table<T>(pl), 1,
                                   s);
   });

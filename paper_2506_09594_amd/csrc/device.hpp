@@ -59,6 +59,14 @@ __device__ __forceinline__ uint16_t f32_to_bf16_rne(float f) {
   return (uint16_t)(u >> 16);
 }
 
+// Two FP32 values -> packed BF16 bits (low half: a), round to nearest even, on
+// the hardware conversion.
+__device__ __forceinline__ uint32_t f32x2_to_bf16x2(float a, float b) {
+  typedef float f2 __attribute__((ext_vector_type(2)));
+  typedef __bf16 h2 __attribute__((ext_vector_type(2)));
+  return __builtin_bit_cast(uint32_t, __builtin_convertvector(f2{a, b}, h2));
+}
+
 // ---------------------------------------------------------------------------
 // Penalties and their proximity operators, for v >= 0 (callers pass |v| and
 // restore the sign).  Prox_{phi,mu}(v) = argmin_x mu phi(x) + (x - v)^2 / 2.

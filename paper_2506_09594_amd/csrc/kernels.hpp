@@ -60,7 +60,7 @@ int launch_transform16(const float* in, TO* out, const TensorDesc* tds, const in
 // forward stores the canonical slots of A, inverse reads the slots of C.
 template <typename T, typename TO>
 int launch_transform_cplx(const T* in, TO* out, const TensorDesc* tds, const int2* items, int nitems, size_t lds,
-                          const T* table, const int32_t* cmap, int inverse, hipStream_t s);
+                          const T* table, const int32_t* cmap, int inverse, int nmax, hipStream_t s);
 
 // Gaussian sketch matrices of every slice (T storage and/or FP64 copy), at
 // the slices' Omega offsets, or densely at s * dense_stride when dense_stride > 0.

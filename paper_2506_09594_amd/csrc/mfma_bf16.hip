@@ -154,8 +154,8 @@ __global__ __launch_bounds__(64 * NW) void k_mfma_thin_bf16(const uint16_t* __re
       const int f = tid + u * NTH;
       if (f < LW * KC / 4) {
         const int c = f / (KC / 4), k4 = (f % (KC / 4)) * 4;
-#pragma unroll
-        for (int e = 0; e < 4; ++e) Ws[c * KP + k4 + e] = f32_to_bf16_rne(rw[u][e]);
+        *reinterpret_cast<uint2*>(Ws + c * KP + k4) =
+            make_uint2(f32x2_to_bf16x2(rw[u][0], rw[u][1]), f32x2_to_bf16x2(rw[u][2], rw[u][3]));
       }
     }
   };
@@ -353,8 +353,8 @@ __global__ __launch_bounds__(2 * MT) void k_cthin_bf16(const uint16_t* __restric
         const int f = tid + u * NTH;
         if (f < LW * KC / 4) {
           const int c = f / (KC / 4), k4 = (f % (KC / 4)) * 4;
-#pragma unroll
-          for (int e = 0; e < 4; ++e) Ws[c * KP + k4 + e] = f32_to_bf16_rne(rw[part][u][e]);
+          *reinterpret_cast<uint2*>(Ws + c * KP + k4) = make_uint2(f32x2_to_bf16x2(rw[part][u][0], rw[part][u][1]),
+                                                                   f32x2_to_bf16x2(rw[part][u][2], rw[part][u][3]));
         }
       }
     }

@@ -467,10 +467,12 @@ __device__ __forceinline__ void cplx_fiber(T* re, T* im, int base, int stride, i
 
 // The same product for a DFT mode of power-of-two length N, as an in-register
 // radix-2 fast Fourier transform (decimation in time, bit-reversed load,
-// natural-order result): M is the mode's DFT matrix s exp(-+ 2 pi i a b / N), so
-// its row 1 over its first entry gives the twiddles exp(-+ 2 pi i j / N) and
-// the first entry the scale s.  N log2 N / 2 butterflies instead of N^2
-// multiply-adds.
+// natural-order result) of the unscaled sums: the mode's matrix is
+// s exp(-+ 2 pi i a b / N) (minus forward, plus inverse), and its real scale s
+// (the first entry) is left to the caller, which applies the product of the
+// scales of all such modes once.  The twiddles exp(-+ 2 pi i k / N) are
+// compile-time constants: k = 0 and k = N / 4 (a multiply by -+ i) cost no
+// multiplications; N log2 N / 2 butterflies instead of N^2 multiply-adds.
 template <int N>
 struct Log2 {
   static constexpr int value = 1 + Log2<N / 2>::value;
@@ -480,9 +482,36 @@ struct Log2<1> {
   static constexpr int value = 0;
 };
 
-template <typename T, int N>
-__device__ __forceinline__ void fft_fiber(T* re, T* im, int base, int stride, const T* __restrict__ M) {
+// cos(2 pi k / n) and sin(2 pi k / n) by their Taylor series (evaluated by the
+// compiler; |angle| <= pi, 40 terms leave an error far below FP64 rounding)
+constexpr double ce_trig(int k, int n, bool want_sin) {
+  const double pi = 3.14159265358979323846264338327950288;
+  double x = 2.0 * pi * (double)k / (double)n;
+  if (x > pi) x -= 2.0 * pi;
+  double term = want_sin ? x : 1.0, sum = term;
+  for (int i = 0; i < 40; ++i) {
+    const double d1 = 2.0 * i + (want_sin ? 2.0 : 1.0), d2 = 2.0 * i + (want_sin ? 3.0 : 2.0);
+    term *= -x * x / (d1 * d2);
+    sum += term;
+  }
+  return sum;
+}
+
+template <typename T, int N, bool INV>
+struct Twiddles {
+  T re[N / 2 > 0 ? N / 2 : 1], im[N / 2 > 0 ? N / 2 : 1];
+  constexpr Twiddles() : re(), im() {
+    for (int k = 0; k < N / 2; ++k) {
+      re[k] = (T)ce_trig(k, N, false);
+      im[k] = (T)((INV ? 1.0 : -1.0) * ce_trig(k, N, true));
+    }
+  }
+};
+
+template <typename T, int N, bool INV>
+__device__ __forceinline__ void fft_fiber(T* re, T* im, int base, int stride) {
   constexpr int LG = Log2<N>::value;
+  constexpr Twiddles<T, N, INV> W{};
   T xr[N], xi[N];
 #pragma unroll
   for (int m = 0; m < N; ++m) {
@@ -492,14 +521,6 @@ __device__ __forceinline__ void fft_fiber(T* re, T* im, int base, int stride, co
     xr[r] = re[base + m * stride];
     xi[r] = im[base + m * stride];
   }
-  const T sc = M[0];
-  const T inv = T(1) / sc;
-  T wr[N / 2 > 0 ? N / 2 : 1], wi[N / 2 > 0 ? N / 2 : 1];
-#pragma unroll
-  for (int j = 0; j < N / 2; ++j) {
-    wr[j] = M[2 * (N + j)] * inv;
-    wi[j] = M[2 * (N + j) + 1] * inv;
-  }
 #pragma unroll
   for (int len = 2; len <= N; len <<= 1) {
     const int half = len / 2, step = N / len;
@@ -507,9 +528,18 @@ __device__ __forceinline__ void fft_fiber(T* re, T* im, int base, int stride, co
     for (int s0 = 0; s0 < N; s0 += len)
 #pragma unroll
       for (int j = 0; j < half; ++j) {
-        const int a = s0 + j, b = s0 + j + half;
-        const T tr = wr[j * step] * xr[b] - wi[j * step] * xi[b];
-        const T ti = wr[j * step] * xi[b] + wi[j * step] * xr[b];
+        const int a = s0 + j, b = s0 + j + half, k = j * step;
+        T tr, ti;
+        if (k == 0) {
+          tr = xr[b];
+          ti = xi[b];
+        } else if (4 * k == N) {  // exp(-+ i pi / 2) = -+ i
+          tr = INV ? -xi[b] : xi[b];
+          ti = INV ? xr[b] : -xr[b];
+        } else {
+          tr = W.re[k] * xr[b] - W.im[k] * xi[b];
+          ti = W.re[k] * xi[b] + W.im[k] * xr[b];
+        }
         xr[b] = xr[a] - tr;
         xi[b] = xi[a] - ti;
         xr[a] += tr;
@@ -518,226 +548,290 @@ __device__ __forceinline__ void fft_fiber(T* re, T* im, int base, int stride, co
   }
 #pragma unroll
   for (int k = 0; k < N; ++k) {
-    re[base + k * stride] = xr[k] * sc;
-    im[base + k * stride] = xi[k] * sc;
+    re[base + k * stride] = xr[k];
+    im[base + k * stride] = xi[k];
   }
 }
 
-template <typename T, typename TO>
-__global__ __launch_bounds__(256) void k_transform_cplx(const T* __restrict__ in_all, TO* __restrict__ out_all,
+template <typename T, typename TO, bool inverse, int NMAX>
+__global__ __launch_bounds__(256, sizeof(T) == 4 ? 2 : 1) void k_transform_cplx(const T* __restrict__ in_all, TO* __restrict__ out_all,
                                                         const TensorDesc* __restrict__ tds,
-                                                        const int2* __restrict__ items, const T* __restrict__ table,
-                                                        const int32_t* __restrict__ cmap_all, int inverse, int aligned) {
+                                                        const int2* __restrict__ items, int nitems,
+                                                        const T* __restrict__ table,
+                                                        const int32_t* __restrict__ cmap_all, int aligned) {
   constexpr int V = 16 / sizeof(T);  // elements per 16-byte access
-  constexpr int UNR = 8;             // accesses in flight per thread
+  constexpr int UNR = (inverse || NMAX > 32) ? 4 : 8;  // accesses in flight per thread (two per access when inverse)
   using VT = __attribute__((ext_vector_type(V))) T;
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  const int2 item = items[blockIdx.x];
-  const TensorDesc* td = tds + item.x;
-  const int64_t NT = td->NT;
-  const int P = td->P, TP = td->TP, lgTP = td->lgTP, n1 = td->n1;
-  const ModeTable* mt = inverse ? &td->inv : &td->fwd;
-  const int32_t* cmap = cmap_all + td->cmap;
   T* re = reinterpret_cast<T*>(smem_raw);
-  const int total = TP * P;
-  T* im = re + total;
-  const int64_t t0 = item.y;
-  const int64_t rem = NT - t0;
-  const int tp = rem < TP ? (int)rem : TP;
   const int tid = threadIdx.x, nt = blockDim.x;
-  // V consecutive tube positions of one slice are V consecutive rows of one
-  // column of the slice (and of its slot) when these hold
-  const bool vec = aligned && TP % V == 0 && NT % V == 0 && n1 % V == 0 && td->x % V == 0 && td->a % V == 0;
-  const int nv = total / V;
-  // ---- load (every access of a batch issued before any LDS store) ------------
-  if (!inverse) {
-    const T* in = in_all + td->x;
-    if (vec) {
-      for (int v0 = tid; v0 < nv; v0 += UNR * nt) {
-        VT r[UNR];
+  // The workgroup walks the items blockIdx.x, blockIdx.x + gridDim.x, ...; the
+  // first batch of loads of the next item is in flight while the current one
+  // is transformed and stored.
+  struct Tile {
+    const TensorDesc* td;
+    int64_t NT, t0;
+    int64_t sbase;  // offset in a stacked slot of the first tube position
+    int P, TP, lgTP, n1, tp, total, nv;
+    bool vec, onecol;  // onecol: the tile's tube positions share one slice column
+  };
+  // offset in a stacked slot [Re; Im] (2 n1 x n2) of tube position t0 + t
+  auto slot_off = [](const Tile& c, int t) -> int64_t {
+    if (c.onecol) return c.sbase + t;
+    const int64_t tt = c.t0 + t;
+    return tt % c.n1 + (tt / c.n1) * 2 * c.n1;
+  };
+  auto tile_of = [&](int it) -> Tile {
+    const int2 item = items[it];
+    Tile c;
+    c.td = tds + item.x;
+    c.NT = c.td->NT;
+    c.P = c.td->P;
+    c.TP = c.td->TP;
+    c.lgTP = c.td->lgTP;
+    c.n1 = c.td->n1;
+    c.t0 = item.y;
+    const int64_t rem = c.NT - c.t0;
+    c.tp = rem < c.TP ? (int)rem : c.TP;
+    c.total = c.TP * c.P;
+    c.nv = c.total / V;
+    // V consecutive tube positions of one slice are V consecutive rows of one
+    // column of the slice (and of its slot) when these hold
+    c.vec = aligned && c.TP % V == 0 && c.NT % V == 0 && c.n1 % V == 0 && c.td->x % V == 0 && c.td->a % V == 0;
+    const int64_t i1 = c.t0 % c.n1;
+    c.sbase = i1 + (c.t0 / c.n1) * 2 * c.n1;
+    c.onecol = i1 + c.TP <= c.n1;
+    return c;
+  };
+  VT rr[UNR], ri[inverse ? UNR : 1];
+  bool cj[inverse ? UNR : 1];
+  // one batch of vector loads (vector tiles only): the UNR accesses from v0
+  auto issue = [&](const Tile& c, int v0) {
+    const int32_t* cmap = cmap_all + c.td->cmap;
 #pragma unroll
-        for (int u = 0; u < UNR; ++u) {
-          const int vi = v0 + u * nt, idx = vi * V;
-          const int j = idx >> lgTP, t = idx & (TP - 1);
-          r[u] = (vi < nv && t < tp) ? *reinterpret_cast<const VT*>(in + (int64_t)j * NT + t0 + t) : VT{};
-        }
-#pragma unroll
-        for (int u = 0; u < UNR; ++u) {
-          const int vi = v0 + u * nt;
-          if (vi < nv) {
-            *reinterpret_cast<VT*>(re + vi * V) = r[u];
-            *reinterpret_cast<VT*>(im + vi * V) = VT{};
-          }
-        }
-      }
-    } else {
-      for (int idx = tid; idx < total; idx += nt) {
-        const int j = idx >> lgTP, t = idx & (TP - 1);
-        re[idx] = (t < tp) ? in[(int64_t)j * NT + t0 + t] : T(0);
-        im[idx] = T(0);
+    for (int u = 0; u < UNR; ++u) {
+      const int vi = v0 + u * nt, idx = vi * V;
+      const int j = idx >> c.lgTP, t = idx & (c.TP - 1);
+      const bool ok = vi < c.nv && t < c.tp;
+      if constexpr (!inverse) {
+        const T* in = in_all + c.td->x;
+        rr[u] = ok ? *reinterpret_cast<const VT*>(in + (int64_t)j * c.NT + c.t0 + t) : VT{};
+      } else {
+        const T* C = in_all + c.td->a;  // slots [Re; Im], 2 NT each
+        const int32_t code = ok ? cmap[j] : 0;
+        const T* S = C + (int64_t)(code & 0x7fffffff) * 2 * c.NT + slot_off(c, t);
+        rr[u] = ok ? *reinterpret_cast<const VT*>(S) : VT{};
+        ri[u] = ok ? *reinterpret_cast<const VT*>(S + c.n1) : VT{};
+        cj[u] = code < 0;  // conjugate partner
       }
     }
-  } else {
-    const T* C = in_all + td->a;  // slots [Re; Im], 2 NT each
-    if (vec) {
-      for (int v0 = tid; v0 < nv; v0 += UNR * nt) {
-        VT rr[UNR], ri[UNR];
-        bool cj[UNR];
+  };
+  auto stash = [&](const Tile& c, int v0) {
+    T* im = re + c.total;
 #pragma unroll
-        for (int u = 0; u < UNR; ++u) {
-          const int vi = v0 + u * nt, idx = vi * V;
-          const int j = idx >> lgTP, t = idx & (TP - 1);
-          const bool ok = vi < nv && t < tp;
-          const int32_t code = ok ? cmap[j] : 0;
-          const int64_t tt = t0 + t;
-          const int64_t i1 = tt % n1, i2 = tt / n1;
-          const T* S = C + (int64_t)(code & 0x7fffffff) * 2 * NT + i1 + i2 * 2 * n1;
-          rr[u] = ok ? *reinterpret_cast<const VT*>(S) : VT{};
-          ri[u] = ok ? *reinterpret_cast<const VT*>(S + n1) : VT{};
-          cj[u] = code < 0;  // conjugate partner
-        }
-#pragma unroll
-        for (int u = 0; u < UNR; ++u) {
-          const int vi = v0 + u * nt;
-          if (vi < nv) {
-            *reinterpret_cast<VT*>(re + vi * V) = rr[u];
-            *reinterpret_cast<VT*>(im + vi * V) = cj[u] ? -ri[u] : ri[u];
-          }
-        }
+    for (int u = 0; u < UNR; ++u) {
+      const int vi = v0 + u * nt;
+      if (vi < c.nv) {
+        *reinterpret_cast<VT*>(re + vi * V) = rr[u];
+        if constexpr (inverse)
+          *reinterpret_cast<VT*>(im + vi * V) = cj[u] ? -ri[u] : ri[u];
+        else
+          *reinterpret_cast<VT*>(im + vi * V) = VT{};
+      }
+    }
+  };
+  int it = blockIdx.x;
+  if (it >= nitems) return;
+  Tile cur = tile_of(it);
+  if (cur.vec) issue(cur, tid);
+  for (;;) {
+    T* im = re + cur.total;
+    const int32_t* cmap = cmap_all + cur.td->cmap;
+    // ---- load: the batch in flight, then any further batches ------------------
+    if (cur.vec) {
+      stash(cur, tid);
+      for (int v0 = tid + UNR * nt; v0 < cur.nv; v0 += UNR * nt) {
+        issue(cur, v0);
+        stash(cur, v0);
+      }
+    } else if constexpr (!inverse) {
+      const T* in = in_all + cur.td->x;
+      for (int idx = tid; idx < cur.total; idx += nt) {
+        const int j = idx >> cur.lgTP, t = idx & (cur.TP - 1);
+        re[idx] = (t < cur.tp) ? in[(int64_t)j * cur.NT + cur.t0 + t] : T(0);
+        im[idx] = T(0);
       }
     } else {
-      for (int idx = tid; idx < total; idx += nt) {
-        const int j = idx >> lgTP, t = idx & (TP - 1);
+      const T* C = in_all + cur.td->a;
+      for (int idx = tid; idx < cur.total; idx += nt) {
+        const int j = idx >> cur.lgTP, t = idx & (cur.TP - 1);
         T vr = T(0), vi = T(0);
-        if (t < tp) {
+        if (t < cur.tp) {
           const int32_t code = cmap[j];
           const int slot = code & 0x7fffffff;
-          const int64_t tt = t0 + t;
-          const int64_t i1 = tt % n1, i2 = tt / n1;
-          const T* S = C + (int64_t)slot * 2 * NT + i1 + i2 * 2 * n1;
+          const T* S = C + (int64_t)slot * 2 * cur.NT + slot_off(cur, t);
           vr = S[0];
-          vi = S[n1];
+          vi = S[cur.n1];
           if (code < 0) vi = -vi;  // conjugate partner
         }
         re[idx] = vr;
         im[idx] = vi;
       }
     }
-  }
-  __syncthreads();
-  // ---- modes ---------------------------------------------------------------------
-  for (int m = 0; m < mt->nmodes; ++m) {
-    const int n = mt->n[m];
-    const int s = mt->stride[m];
-    const T* M = table + mt->off[m];
-    const int nfib = total / n;
-    for (int f = tid; f < nfib; f += nt) {
-      const int base = fiber_base(f, TP, lgTP, s, n);
-      if (n == 2)
-        fft_fiber<T, 2>(re, im, base, s * TP, M);
-      else if (n == 4)
-        fft_fiber<T, 4>(re, im, base, s * TP, M);
-      else if (n == 8)
-        fft_fiber<T, 8>(re, im, base, s * TP, M);
-      else if (n == 16)
-        fft_fiber<T, 16>(re, im, base, s * TP, M);
-      else if (n == 32)
-        fft_fiber<T, 32>(re, im, base, s * TP, M);
-      else if (n <= 8)
-        cplx_fiber<T, 8>(re, im, base, s * TP, n, M);
-      else if (n <= 16)
-        cplx_fiber<T, 16>(re, im, base, s * TP, n, M);
-      else if (n <= 32)
-        cplx_fiber<T, 32>(re, im, base, s * TP, n, M);
-      else
-        cplx_fiber<T, 64>(re, im, base, s * TP, n, M);
-    }
     __syncthreads();
-  }
-  // ---- store ---------------------------------------------------------------------
-  if (!inverse) {
-    TO* A = out_all + td->a;
-    if (vec) {
-      for (int vi = tid; vi < nv; vi += nt) {
-        const int idx = vi * V;
-        const int j = idx >> lgTP, t = idx & (TP - 1);
-        const int32_t code = cmap[j];
-        if (t < tp && code >= 0) {  // canonical member of its pair
-          const int64_t tt = t0 + t;
-          const int64_t i1 = tt % n1, i2 = tt / n1;
-          TO* S = A + (int64_t)code * 2 * NT + i1 + i2 * 2 * n1;
-          const VT vr = *reinterpret_cast<const VT*>(re + idx), vi2 = *reinterpret_cast<const VT*>(im + idx);
-          if constexpr (std::is_same<TO, T>::value) {
-            *reinterpret_cast<VT*>(S) = vr;
-            *reinterpret_cast<VT*>(S + n1) = vi2;
-          } else {
-            typedef unsigned short us4 __attribute__((ext_vector_type(4)));
-            us4 hr, hi;
-#pragma unroll
-            for (int e = 0; e < 4; ++e) {
-              hr[e] = f32_to_bf16_rne((float)vr[e]);
-              hi[e] = f32_to_bf16_rne((float)vi2[e]);
+    const int nxt = it + gridDim.x;
+    Tile nc{};
+    if (nxt < nitems) {
+      nc = tile_of(nxt);
+      if (nc.vec) issue(nc, tid);
+    }
+    // ---- modes ---------------------------------------------------------------------
+    const ModeTable* mt = inverse ? &cur.td->inv : &cur.td->fwd;
+    T post = T(1);  // product of the scales the FFT modes leave out
+    for (int m = 0; m < mt->nmodes; ++m) {
+      const int n = mt->n[m];
+      const int s = mt->stride[m];
+      const T* M = table + mt->off[m];
+      const int nfib = cur.total / n;
+      if (n == 2 || n == 4 || n == 8 || (NMAX >= 16 && n == 16) || (NMAX >= 32 && n == 32)) post *= M[0];
+      for (int f = tid; f < nfib; f += nt) {
+        const int base = fiber_base(f, cur.TP, cur.lgTP, s, n);
+        const int st = s * cur.TP;
+        if (n == 2) {
+          fft_fiber<T, 2, inverse>(re, im, base, st);
+        } else if (n == 4) {
+          fft_fiber<T, 4, inverse>(re, im, base, st);
+        } else if (n == 8) {
+          fft_fiber<T, 8, inverse>(re, im, base, st);
+        } else if (n <= 8) {
+          cplx_fiber<T, 8>(re, im, base, st, n, M);
+        } else if constexpr (NMAX >= 16) {
+          if (n == 16) {
+            fft_fiber<T, 16, inverse>(re, im, base, st);
+          } else if (n <= 16) {
+            cplx_fiber<T, 16>(re, im, base, st, n, M);
+          } else if constexpr (NMAX >= 32) {
+            if (n == 32) {
+              fft_fiber<T, 32, inverse>(re, im, base, st);
+            } else if (n <= 32) {
+              cplx_fiber<T, 32>(re, im, base, st, n, M);
+            } else if constexpr (NMAX >= 64) {
+              cplx_fiber<T, 64>(re, im, base, st, n, M);
             }
-            *reinterpret_cast<us4*>(S) = hr;
-            *reinterpret_cast<us4*>(S + n1) = hi;
+          }
+        }
+      }
+      __syncthreads();
+    }
+    // ---- store ---------------------------------------------------------------------
+    const int64_t NT = cur.NT;
+    const int n1 = cur.n1, TP = cur.TP, lgTP = cur.lgTP, tp = cur.tp;
+    if (!inverse) {
+      TO* A = out_all + cur.td->a;
+      if (cur.vec) {
+        for (int vi = tid; vi < cur.nv; vi += nt) {
+          const int idx = vi * V;
+          const int j = idx >> lgTP, t = idx & (TP - 1);
+          const int32_t code = cmap[j];
+          if (t < tp && code >= 0) {  // canonical member of its pair
+            TO* S = A + (int64_t)code * 2 * NT + slot_off(cur, t);
+            const VT vr = *reinterpret_cast<const VT*>(re + idx) * post;
+            const VT vi2 = *reinterpret_cast<const VT*>(im + idx) * post;
+            if constexpr (std::is_same<TO, T>::value) {
+              *reinterpret_cast<VT*>(S) = vr;
+              *reinterpret_cast<VT*>(S + n1) = vi2;
+            } else {
+              typedef unsigned int u2 __attribute__((ext_vector_type(2)));
+              *reinterpret_cast<u2*>(S) = u2{f32x2_to_bf16x2(vr[0], vr[1]), f32x2_to_bf16x2(vr[2], vr[3])};
+              *reinterpret_cast<u2*>(S + n1) = u2{f32x2_to_bf16x2(vi2[0], vi2[1]), f32x2_to_bf16x2(vi2[2], vi2[3])};
+            }
+          }
+        }
+      } else {
+        for (int idx = tid; idx < cur.total; idx += nt) {
+          const int j = idx >> lgTP, t = idx & (TP - 1);
+          const int32_t code = cmap[j];
+          if (t < tp && code >= 0) {  // canonical member of its pair
+            TO* S = A + (int64_t)code * 2 * NT + slot_off(cur, t);
+            if constexpr (std::is_same<TO, T>::value) {
+              S[0] = re[idx] * post;
+              S[n1] = im[idx] * post;
+            } else {
+              S[0] = f32_to_bf16_rne((float)(re[idx] * post));
+              S[n1] = f32_to_bf16_rne((float)(im[idx] * post));
+            }
           }
         }
       }
     } else {
-      for (int idx = tid; idx < total; idx += nt) {
-        const int j = idx >> lgTP, t = idx & (TP - 1);
-        const int32_t code = cmap[j];
-        if (t < tp && code >= 0) {  // canonical member of its pair
-          const int64_t tt = t0 + t;
-          const int64_t i1 = tt % n1, i2 = tt / n1;
-          TO* S = A + (int64_t)code * 2 * NT + i1 + i2 * 2 * n1;
-          if constexpr (std::is_same<TO, T>::value) {
-            S[0] = re[idx];
-            S[n1] = im[idx];
-          } else {
-            S[0] = f32_to_bf16_rne((float)re[idx]);
-            S[n1] = f32_to_bf16_rne((float)im[idx]);
-          }
+      TO* out = out_all + cur.td->x;
+      if (cur.vec && std::is_same<TO, T>::value) {
+        for (int vi = tid; vi < cur.nv; vi += nt) {
+          const int idx = vi * V;
+          const int j = idx >> lgTP, t = idx & (TP - 1);
+          if (t < tp)
+            *reinterpret_cast<VT*>(out + (int64_t)j * NT + cur.t0 + t) = *reinterpret_cast<const VT*>(re + idx) * post;
+        }
+      } else {
+        for (int idx = tid; idx < cur.total; idx += nt) {
+          const int j = idx >> lgTP, t = idx & (TP - 1);
+          if (t < tp) out[(int64_t)j * NT + cur.t0 + t] = (TO)(re[idx] * post);
         }
       }
     }
-  } else {
-    TO* out = out_all + td->x;
-    if (vec && std::is_same<TO, T>::value) {
-      for (int vi = tid; vi < nv; vi += nt) {
-        const int idx = vi * V;
-        const int j = idx >> lgTP, t = idx & (TP - 1);
-        if (t < tp) *reinterpret_cast<VT*>(out + (int64_t)j * NT + t0 + t) = *reinterpret_cast<const VT*>(re + idx);
-      }
-    } else {
-      for (int idx = tid; idx < total; idx += nt) {
-        const int j = idx >> lgTP, t = idx & (TP - 1);
-        if (t < tp) out[(int64_t)j * NT + t0 + t] = (TO)re[idx];
-      }
-    }
+    if (nxt >= nitems) break;
+    __syncthreads();  // the tile's LDS is read by the stores above before the next stash
+    it = nxt;
+    cur = nc;
   }
 }
 
-template <typename T, typename TO>
-int launch_transform_cplx(const T* in, TO* out, const TensorDesc* tds, const int2* items, int nitems, size_t lds,
-                          const T* table, const int32_t* cmap, int inverse, hipStream_t stream) {
-  if (nitems == 0) return HT_OK;
-  if (lds > 160 * 1024) HT_FAIL(HT_ERR_UNSUPPORTED, "transform tile above the LDS size");
-  int rc = ensure_dynamic_lds((const void*)k_transform_cplx<T, TO>, 160 * 1024);
+template <typename T, typename TO, int NMAX>
+int launch_transform_cplx_n(const T* in, TO* out, const TensorDesc* tds, const int2* items, int nitems, size_t lds,
+                            const T* table, const int32_t* cmap, int inverse, hipStream_t stream) {
+  const void* kern = inverse ? (const void*)k_transform_cplx<T, TO, true, NMAX>
+                             : (const void*)k_transform_cplx<T, TO, false, NMAX>;
+  int rc = ensure_dynamic_lds(kern, 160 * 1024);
   if (rc) return rc;
+  // workgroups that stay resident for the whole launch, each walking its items
+  int per_cu = 0;
+  HT_CHECK_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, 256, lds));
+  int dev = 0, ncu = 0;
+  HT_CHECK_HIP(hipGetDevice(&dev));
+  HT_CHECK_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+  const int grid = std::max(1, std::min(nitems, std::max(per_cu, 1) * ncu));
   const int aligned = (reinterpret_cast<uintptr_t>(in) % 16 == 0) && (reinterpret_cast<uintptr_t>(out) % 16 == 0);
-  hipLaunchKernelGGL((k_transform_cplx<T, TO>), dim3((unsigned)nitems), dim3(256), lds, stream, in, out, tds, items,
-                     table, cmap, inverse, aligned);
+  if (inverse)
+    hipLaunchKernelGGL((k_transform_cplx<T, TO, true, NMAX>), dim3((unsigned)grid), dim3(256), lds, stream, in, out,
+                       tds, items, nitems, table, cmap, aligned);
+  else
+    hipLaunchKernelGGL((k_transform_cplx<T, TO, false, NMAX>), dim3((unsigned)grid), dim3(256), lds, stream, in, out,
+                       tds, items, nitems, table, cmap, aligned);
   HT_CHECK_LAUNCH();
   return HT_OK;
 }
 
+// nmax: the longest transformed mode (selects the fiber kernels compiled in)
+template <typename T, typename TO>
+int launch_transform_cplx(const T* in, TO* out, const TensorDesc* tds, const int2* items, int nitems, size_t lds,
+                          const T* table, const int32_t* cmap, int inverse, int nmax, hipStream_t stream) {
+  if (nitems == 0) return HT_OK;
+  if (lds > 160 * 1024) HT_FAIL(HT_ERR_UNSUPPORTED, "transform tile above the LDS size");
+  if (nmax > 64) HT_FAIL(HT_ERR_UNSUPPORTED, "DFT mode longer than 64");
+  if (nmax <= 8) return launch_transform_cplx_n<T, TO, 8>(in, out, tds, items, nitems, lds, table, cmap, inverse, stream);
+  if (nmax <= 16)
+    return launch_transform_cplx_n<T, TO, 16>(in, out, tds, items, nitems, lds, table, cmap, inverse, stream);
+  if (nmax <= 32)
+    return launch_transform_cplx_n<T, TO, 32>(in, out, tds, items, nitems, lds, table, cmap, inverse, stream);
+  return launch_transform_cplx_n<T, TO, 64>(in, out, tds, items, nitems, lds, table, cmap, inverse, stream);
+}
+
 template int launch_transform_cplx<float, float>(const float*, float*, const TensorDesc*, const int2*, int, size_t,
-                                                 const float*, const int32_t*, int, hipStream_t);
+                                                 const float*, const int32_t*, int, int, hipStream_t);
 template int launch_transform_cplx<double, double>(const double*, double*, const TensorDesc*, const int2*, int,
-                                                   size_t, const double*, const int32_t*, int, hipStream_t);
+                                                   size_t, const double*, const int32_t*, int, int, hipStream_t);
 template int launch_transform_cplx<float, uint16_t>(const float*, uint16_t*, const TensorDesc*, const int2*, int,
-                                                    size_t, const float*, const int32_t*, int, hipStream_t);
+                                                    size_t, const float*, const int32_t*, int, int, hipStream_t);
 
 int transform_tile_width(int64_t P, size_t elem_bytes, size_t budget) {
   int64_t tp = 256;

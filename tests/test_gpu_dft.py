@@ -52,6 +52,9 @@ def _case(ht, dims, rank, r, p, q, prec, tau, pen, seed=1, noise=1e-2):
     ((64, 48, 6), 10, 12, 6, 2),     # columns aligned for 16-byte loads
     ((136, 100, 4, 2), 30, 40, 10, 2),  # width 50: three 64-row tiles with a ragged last one
     ((64, 70, 3, 3), 20, 54, 10, 1),    # width 64, the largest complex width
+    ((48, 40, 8, 16), 6, 8, 4, 1),      # FFT modes of 8 and 16
+    ((36, 28, 32), 5, 8, 4, 1),         # FFT mode of 32
+    ((520, 512, 2, 2), 6, 8, 4, 1),     # more transform tiles than resident workgroups; tiles across columns
 ])
 def test_tsvt_dft_matches_oracle(ht, prec, dims, rank, r, p, q):
     got, ref, plan = _case(ht, dims, rank, r, p, q, prec, 2.0, ("mcp", (30.0,)))
