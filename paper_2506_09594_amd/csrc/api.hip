@@ -150,6 +150,7 @@ struct ht_plan {
   ItemList it_nns;  // nn items of the streaming product (256-row tiles)
   ItemList it_cp[2];  // BF16 products of complex slices: nn, tn items of kCplxProdRows complex rows
   ItemList it_cqk, it_cnt;  // complex reconstruction (strips x column-tile groups)
+  ItemList it_asy, it_asz;  // complex CholeskyQR apply: 64-row tiles of Y (n1 rows), Z (n2 rows) in slice order
   ItemList it_t16;  // transform items when every tensor has two transformed modes of length 16 (else empty)
   // Width classes (bounds kClassBound) of plans whose slices differ in width:
   // orthonormalization items and small-SVD slices per class, so that each
@@ -384,6 +385,17 @@ std::vector<int2> row_items(const ht_plan* pl, bool over_n2, int rows, bool cost
     cost[s] = cost_is_other_dim ? (double)(over_n2 ? d.n1 : d.n2) : 1.0;
   }
   return xcd_grouped(groups, cost);
+}
+
+// 64-row tiles over dimension n1 (or n2) of every slice, in slice order.
+std::vector<int2> slice_order_tiles(const ht_plan* pl, bool over_n2) {
+  std::vector<int2> items;
+  for (int64_t s = 0; s < pl->Ptot; ++s) {
+    const SliceDesc& d = pl->h_slices[s];
+    const int n = over_n2 ? d.n2 : d.n1;
+    for (int r0 = 0; r0 < n; r0 += 64) items.push_back(make_int2((int)s, r0));
+  }
+  return items;
 }
 
 // Complex reconstruction items: strips of kCmulRows complex rows times groups
@@ -690,6 +702,8 @@ int build_plan(const ht_plan_desc* descs, int n, bool batch, ht_plan** out) {
   lists.push_back(row_items(pl, true, kCplxProdRows, true));   // tn, complex BF16 products
   lists.push_back(cmul_items(pl, false));                      // complex recon QK
   lists.push_back(cmul_items(pl, true));                       // complex recon C
+  lists.push_back(slice_order_tiles(pl, false));  // complex orth apply tiles, Y
+  lists.push_back(slice_order_tiles(pl, true));   // complex orth apply tiles, Z
   // width classes: orthonormalization items (Y, Z) and small-SVD slices
   auto class_of = [&](int l) {
     int c = 0;
@@ -734,7 +748,7 @@ int build_plan(const ht_plan_desc* descs, int n, bool batch, ht_plan** out) {
   }
   pl->tf_capacity = (int)tfi.size();
   ItemList* dst[] = {&pl->it_nn[0], &pl->it_tn[0], &pl->it_nn[1], &pl->it_tn[1], &pl->it_oy, &pl->it_oz,
-                     &pl->it_qk, &pl->it_nt, &pl->it_nns, &pl->it_cp[0], &pl->it_cp[1], &pl->it_cqk, &pl->it_cnt,
+                     &pl->it_qk, &pl->it_nt, &pl->it_nns, &pl->it_cp[0], &pl->it_cp[1], &pl->it_cqk, &pl->it_cnt, &pl->it_asy, &pl->it_asz,
                      &pl->it_oyc[0], &pl->it_ozc[0], &pl->it_svc[0], &pl->it_oyc[1], &pl->it_ozc[1],
                      &pl->it_svc[1], &pl->it_oyc[2], &pl->it_ozc[2], &pl->it_svc[2], &pl->it_oyc[3],
                      &pl->it_ozc[3], &pl->it_svc[3], &pl->it_oyc[4], &pl->it_ozc[4], &pl->it_svc[4],
@@ -947,7 +961,9 @@ int run_tsvt(const ht_plan* pl, const T* X, T* out, double tau, const double* ta
     return timed(pl, ST_CHOLQR, s, [&] {
       if (cplx) {
         const ItemList& L = which ? pl->it_oz : pl->it_oy;
-        return launch_corth<T>(which ? Z : Y, which, sd, wk, items(pl, L), L.n, lmax, P, gp1, gout, s);
+        const ItemList& S = which ? pl->it_asz : pl->it_asy;
+        return launch_corth<T>(which ? Z : Y, which, sd, wk, items(pl, L), L.n, items(pl, S), S.n, lmax, P, gp1, gout,
+                               s);
       }
       if (wk == nullptr && pl->class_split) {  // one launch per width class
         for (int c = 0; c < kNumClasses; ++c) {

@@ -10,8 +10,8 @@
 
 namespace ht {
 
-// 1/x for x > 0 from the hardware estimate refined by two Newton steps
-// (relative error at the level of the FP64 rounding unit).
+// 1/x for x != 0 (finite, not denormal) from the hardware estimate refined by
+// two Newton steps (relative error at the level of the FP64 rounding unit).
 __device__ __forceinline__ double fast_rcp(double x) {
   double y = __builtin_amdgcn_rcp(x);
   y = y * (2.0 - x * y);

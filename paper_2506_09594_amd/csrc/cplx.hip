@@ -12,16 +12,12 @@
 // of the rows and M = Yr^T Yi, with Im(Y^H Y) = M - M^T (tile_cgram_mfma).
 //
 // This file holds the FP64 l x l stages of complex slices (CholeskyQR with
-// deflation, the Hermitian Jacobi eigensolver with the shrinkage) and the
-// vector-unit products that FP64 plans use; the FP32 and BF16 products run on
-// the matrix cores (mfma.hip, mfma_bf16.hip).
-//
-// Hermitian Jacobi.  For a pair (p, q) with W[p][q] = b = |b| e, the rotation
-// J = [[c, s e], [-s conj(e), c]] makes J^H W J diagonal on (p, q) when (c, s)
-// is the real rotation of [[W[p][p], |b|], [|b|, W[q][q]]]: the phase e turns
-// the block into that real symmetric one.  Steps apply l/2 disjoint rotations
-// (round-robin ordering) in place: one barrier after the rotations of the step
-// are computed from W, one after they are applied.
+// deflation, the Hermitian eigensolver with the shrinkage), the FP64 matrix-core
+// CholeskyQR apply and the vector-unit products that FP64 plans use; the FP32
+// and BF16 sketch products run on the matrix cores (mfma.hip, mfma_bf16.hip).
+#include <algorithm>
+#include <type_traits>
+
 #include "chol.hpp"
 
 namespace ht {
@@ -89,19 +85,38 @@ __device__ inline void sum_cgram_partials(double* Gr, double* Gi, int gp, const 
   __syncthreads();
 }
 
-// Complex Cholesky with deflation, in place: on entry the upper triangle of
-// the Hermitian G = Gr + i Gi (pitch gp); G = R^H R with R upper triangular
-// and a real positive diagonal.  On return dR[j] = R[j][j] (0 for a skipped
-// column, whose row of R is zero) and R[j][b] for b > j sits in the strict
-// lower triangle at (b, j).  A column is skipped when its Schur-complement
-// pivot is at most delta_rel * max_a G[a][a].  One barrier per column: the
-// trailing update reads only the unscaled pivot row, which the column never
-// writes, and its entries (a, b), j < a <= b, are spread over every thread of
-// the workgroup (entry e of the column-packed triangle is (a, b) with
-// e = b'(b' + 1)/2 + a', a' = a - j - 1, b' = b - j - 1).
+// Complex Cholesky with deflation: on entry the upper triangle of the
+// Hermitian G = Gr + i Gi (pitch gp); G = R^H R with R upper triangular and a
+// real positive diagonal.  On return dR[j] = R[j][j] (0 for a skipped column,
+// whose row of R is zero) and R[j][b] for b > j sits in the strict lower
+// triangle at (b, j).  A column is skipped when its Schur-complement pivot is
+// at most delta_rel * max_a G[a][a].  Each thread holds up to NE entries
+// (a <= b) of the triangle in registers for the whole factorization (entry
+// e = b (b + 1) / 2 + a, dealt out once).  Column j: the owners of row j
+// publish it to a row buffer (two, alternating, so that one barrier per column
+// suffices), then every thread updates its trailing entries,
+// G[a][b] -= conj(G[j][a]) G[j][b] / G[j][j] for j < a <= b, and the owners of
+// row j store it scaled by 1 / sqrt(G[j][j]).
+template <int NE>
 __device__ inline void cchol_deflate(double* Gr, double* Gi, double* dR, int gp, int l, double delta_rel,
                                      double* s_scr) {
+  __shared__ double rowr[2][kMaxComplexWidth], rowi[2][kMaxComplexWidth];
   const int tid = threadIdx.x, nt = blockDim.x;
+  const int ntri = l * (l + 1) / 2;
+  int ea[NE], eb[NE];
+  double vr[NE], vi[NE];
+#pragma unroll
+  for (int u = 0; u < NE; ++u) {
+    const int e = tid + u * nt;
+    int bb = (int)((sqrtf(8.0f * (float)e + 1.0f) - 1.0f) * 0.5f);
+    while ((bb + 1) * (bb + 2) / 2 <= e) ++bb;
+    while (bb * (bb + 1) / 2 > e) --bb;
+    const bool ok = e < ntri;
+    ea[u] = ok ? e - bb * (bb + 1) / 2 : l;  // a = l: no entry
+    eb[u] = ok ? bb : l;
+    vr[u] = ok ? Gr[ea[u] * gp + eb[u]] : 0.0;
+    vi[u] = ok ? Gi[ea[u] * gp + eb[u]] : 0.0;
+  }
   if (tid == 0) {
     double md = 0.0;
     for (int a = 0; a < l; ++a) md = fmax(md, Gr[a * gp + a]);
@@ -110,51 +125,38 @@ __device__ inline void cchol_deflate(double* Gr, double* Gi, double* dR, int gp,
   __syncthreads();
   const double maxdiag = *s_scr;
   const double delta = delta_rel * maxdiag;
-  constexpr int UE = 4;  // entries per thread per batch of loads
   for (int j = 0; j < l; ++j) {
-    const double d = Gr[j * gp + j];
+    const int buf = j & 1;
+#pragma unroll
+    for (int u = 0; u < NE; ++u)
+      if (ea[u] == j) {
+        rowr[buf][eb[u]] = vr[u];
+        rowi[buf][eb[u]] = vi[u];
+      }
+    __syncthreads();
+    const double d = rowr[buf][j];
     const bool keep = d > delta && maxdiag > 0.0;
     const double inv_r = keep ? fast_rsqrt(d) : 0.0;
     const double inv_d = inv_r * inv_r;
-    const int mrem = l - j - 1, ntri = mrem * (mrem + 1) / 2;
-    const double* pr = Gr + j * gp + j + 1;  // pivot row past the diagonal
-    const double* pi = Gi + j * gp + j + 1;
-    for (int e0 = tid; e0 < ntri; e0 += UE * nt) {
-      int ia[UE], ib[UE];
-      double jar[UE], jai[UE], jbr[UE], jbi[UE], xr[UE], xi[UE];
 #pragma unroll
-      for (int u = 0; u < UE; ++u) {
-        const int e = min(e0 + u * nt, ntri - 1);
-        int bb = (int)((sqrtf(8.0f * (float)e + 1.0f) - 1.0f) * 0.5f);
-        while ((bb + 1) * (bb + 2) / 2 <= e) ++bb;
-        while (bb * (bb + 1) / 2 > e) --bb;
-        const int aa = e - bb * (bb + 1) / 2;
-        ia[u] = aa;
-        ib[u] = bb;
-        jar[u] = pr[aa];
-        jai[u] = pi[aa];
-        jbr[u] = pr[bb];
-        jbi[u] = pi[bb];
-        xr[u] = Gr[(j + 1 + aa) * gp + j + 1 + bb];
-        xi[u] = Gi[(j + 1 + aa) * gp + j + 1 + bb];
-      }
-#pragma unroll
-      for (int u = 0; u < UE; ++u) {
-        if (e0 + u * nt < ntri) {  // G[a][b] -= conj(G[j][a]) G[j][b] / d
-          const double fr = jbr[u] * inv_d, fi = jbi[u] * inv_d;
-          const int o = (j + 1 + ia[u]) * gp + j + 1 + ib[u];
-          Gr[o] = xr[u] - fma(jar[u], fr, jai[u] * fi);
-          Gi[o] = xi[u] - fma(jar[u], fi, -(jai[u] * fr));
+    for (int u = 0; u < NE; ++u) {
+      const int a = ea[u], b = eb[u];
+      if (a < l && a > j) {
+        const double jar = rowr[buf][a], jai = rowi[buf][a];
+        const double fr = rowr[buf][b] * inv_d, fi = rowi[buf][b] * inv_d;
+        vr[u] -= fma(jar, fr, jai * fi);
+        vi[u] -= fma(jar, fi, -(jai * fr));
+      } else if (a == j) {
+        if (b > j) {
+          Gr[b * gp + j] = vr[u] * inv_r;
+          Gi[b * gp + j] = vi[u] * inv_r;
+        } else {
+          dR[j] = keep ? d * inv_r : 0.0;
         }
       }
     }
-    for (int b = j + 1 + tid; b < l; b += nt) {
-      Gr[b * gp + j] = Gr[j * gp + b] * inv_r;
-      Gi[b * gp + j] = Gi[j * gp + b] * inv_r;
-    }
-    if (tid == 0) dR[j] = keep ? d * inv_r : 0.0;
-    __syncthreads();
   }
+  __syncthreads();
 }
 
 // X = R^{-1} (upper triangular, zero below the diagonal and at skipped
@@ -304,7 +306,8 @@ __global__ __launch_bounds__(kFactorThreads) void k_corth_factor(int which, cons
   double* part = gin_all + d.g1;
   sum_cgram_partials<(kMaxComplexWidth * kMaxComplexWidth + kFactorThreads - 1) / kFactorThreads>(Gr, Gi, gp, part,
                                                                                                  nparts, l);
-  cchol_deflate(Gr, Gi, dR, gp, l, 8.0 * (double)m * kEps, &s_scr);
+  cchol_deflate<(kMaxComplexWidth * (kMaxComplexWidth + 1) / 2 + kFactorThreads - 1) / kFactorThreads>(
+      Gr, Gi, dR, gp, l, 8.0 * (double)m * kEps, &s_scr);
   ctri_inverse_waves(Gr, Gi, dR, gp, l, part, part + ll, l);
 }
 
@@ -417,6 +420,124 @@ __global__ __launch_bounds__(256) void k_corth_apply(T* __restrict__ Yall, int w
   if (gout_all) tile_cgram_mfma(S, SP, 1, l, gout_all + d.g2 + (int64_t)(r0 / kGramRows) * 2 * ll);
 }
 
+// The same product for FP32 blocks without Gram partials.  The 64-row tiles
+// of every slice, in slice order, are split into one contiguous range per
+// resident workgroup; R^{-1} is staged in LDS when the range enters a slice,
+// as two 64 x 64 planes with the quadrants padded to 64, so that every
+// (4-deep step, 16-column block) pair lies in one quadrant of E: its plane,
+// sign and triangular skip are uniform across the wavefront.  Wavefront w owns
+// rows 16 w .. 16 w + 15 of each tile and holds them as the A operands
+// (k = 4 st + t / 16: real parts for st < 16, imaginary parts after); the next
+// tile's rows load while the current one is multiplied, and the result goes
+// straight from the accumulators to Y (rows 4 v + t / 16 of column t % 16 in
+// accumulator v).  Each wavefront reads and then overwrites only its own rows.
+constexpr int kApplyPitch = 72;  // doubles per LDS row of a plane
+constexpr size_t kApplyLds = 2 * 64 * kApplyPitch * sizeof(double);
+
+__global__ __launch_bounds__(256, 2) void k_corth_apply_tiles(float* __restrict__ Yall, int which,
+                                                              const SliceDesc* __restrict__ sd,
+                                                              const int2* __restrict__ wk,
+                                                              const int2* __restrict__ tiles, int ntiles,
+                                                              const double* __restrict__ gin_all) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  double* Er = reinterpret_cast<double*>(smem_raw);  // Re R^{-1}, padded 64 x 64
+  double* Ei = Er + 64 * kApplyPitch;                // Im R^{-1}
+  const int t_begin = (int)((int64_t)blockIdx.x * ntiles / gridDim.x);
+  const int t_end = (int)((int64_t)(blockIdx.x + 1) * ntiles / gridDim.x);
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, w = tid >> 6, li = lane & 15, lq = lane >> 4;
+  // A operands of tile t: rows 16 w + li, k = 4 (st mod 16) + t / 16 of part st / 16
+  auto fetch = [&](int t, float (&dst)[32]) {
+    const int2 it = tiles[t];
+    const SliceDesc d = sd[it.x];
+    const int l = slice_width(d, wk, it.x);
+    const int m = which ? d.n2 : d.n1, ld = 2 * m;
+    const int row = it.y + 16 * w + li;
+    const bool okr = row < m && l > 0;
+    const float* src = Yall + (which ? d.z : d.y) + (okr ? row : 0);
+#pragma unroll
+    for (int st = 0; st < 32; ++st) {
+      const int kk = 4 * (st & 15) + lq;
+      const bool ok = okr && kk < l;
+      dst[st] = ok ? src[(st >= 16 ? m : 0) + (int64_t)kk * ld] : 0.0f;
+    }
+  };
+  float a[32], an[32];
+  if (t_begin < t_end) fetch(t_begin, a);
+  int cur = -1;
+  typedef double d4 __attribute__((ext_vector_type(4)));
+  for (int t = t_begin; t < t_end; ++t) {
+    const int2 it = tiles[t];
+    const int s = it.x, r0 = it.y;
+    const SliceDesc d = sd[s];
+    const int l = slice_width(d, wk, s);
+    if (s != cur) {  // stage this slice's R^{-1} (uniform branch)
+      if (cur >= 0) __syncthreads();
+      cur = s;
+      if (l > 0) {
+        const int ll = l * l;
+        const double* Rg = gin_all + d.g1;
+        double vr[16], vi[16];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+          const int idx = tid + 256 * u, a0 = idx / 64, b0 = idx % 64;
+          const bool ok = a0 < l && b0 < l;
+          const int o = ok ? a0 * l + b0 : 0;
+          vr[u] = Rg[o];
+          vi[u] = Rg[ll + o];
+          vr[u] = ok ? vr[u] : 0.0;
+          vi[u] = ok ? vi[u] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+          const int idx = tid + 256 * u, a0 = idx / 64, b0 = idx % 64;
+          Er[a0 * kApplyPitch + b0] = vr[u];
+          Ei[a0 * kApplyPitch + b0] = vi[u];
+        }
+      }
+      __syncthreads();
+    }
+    if (t + 1 < t_end) fetch(t + 1, an);
+    if (l > 0) {
+      const int m = which ? d.n2 : d.n1, ld = 2 * m;
+      float* Y = Yall + (which ? d.z : d.y);
+      d4 acc[8];
+#pragma unroll
+      for (int cb = 0; cb < 8; ++cb) acc[cb] = d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int st = 0; st < 32; ++st) {
+        const int kp = st >> 4, kq0 = 4 * (st & 15);
+        if (kq0 >= l) continue;
+        const double av = (double)a[st];
+#pragma unroll
+        for (int cb = 0; cb < 8; ++cb) {
+          const int cp = cb >> 2, cq0 = 16 * (cb & 3);
+          if (kq0 > cq0 + 15 || cq0 >= l) continue;  // zero block of the quadrant
+          // E = [[Rr, Ri], [-Ri, Rr]] by quadrant (k part, c part)
+          const double* P = kp == cp ? Er : Ei;
+          double b = P[(kq0 + lq) * kApplyPitch + cq0 + li];
+          if (kp == 1 && cp == 0) b = -b;
+          acc[cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, b, acc[cb], 0, 0, 0);
+        }
+      }
+      const int rb = r0 + 16 * w + lq;
+#pragma unroll
+      for (int cb = 0; cb < 8; ++cb) {
+        const int cp = cb >> 2, cq = 16 * (cb & 3) + li;
+        if (cq < l) {
+          float* dst = Y + (cp ? m : 0) + (int64_t)cq * ld;
+#pragma unroll
+          for (int v = 0; v < 4; ++v)
+            if (rb + 4 * v < m) dst[rb + 4 * v] = (float)acc[cb][v];
+        }
+      }
+    }
+    if (t + 1 < t_end)
+#pragma unroll
+      for (int st = 0; st < 32; ++st) a[st] = an[st];
+  }
+}
+
 template <typename T, int LB>
 constexpr size_t capply_lds_bytes() {
   constexpr size_t r = 2 * (size_t)LB * LB * 8, t = 128 * (size_t)(LB + 1) * sizeof(T);
@@ -427,48 +548,373 @@ constexpr size_t capply_lds_bytes() {
 // Small SVD and shrinkage of complex slices, FP64, one workgroup per slice.
 // With R2 = chol(Q1^H Q1) (from the Gram partials of Q1) and Wt = Bt^H Bt
 // (from those of Bt = A^H Q1): W = R2^{-H} Wt R2^{-1} = B B^H for
-// B = Q^H A, Q = Q1 R2^{-1}.  W = U diag(s^2) U^H by Hermitian Jacobi; with
+// B = Q^H A, Q = Q1 R2^{-1}.  W = U diag(s^2) U^H (heev_tridiag); with
 // the k = min(r, l) largest s shrunk,
 //   K' = R2^{-1} U diag(w) U^H R2^{-H},  w_i = prox(s_i) / s_i,
 // so that the reconstruction is C = Q1 K' Bt^H.
 // ---------------------------------------------------------------------------
-struct CRot {
-  double c, sr, si;  // rotation [[c, s], [-conj(s), c]] of pair (p, q)
-  int p, q;
-};
-
-__device__ __forceinline__ void rr_pair_c(int step, int t, int m, int& p, int& q) {
-  int a, b;
-  if (t == 0) {
-    a = m;
-    b = step;
-  } else {
-    a = step + t;
-    a = a >= m ? a - m : a;
-    b = step - t + m;
-    b = b >= m ? b - m : b;
-  }
-  p = min(a, b);
-  q = max(a, b);
-}
-
-// Real symmetric Schur rotation of [[app, apq], [apq, aqq]] (apq >= 0): the
-// identity when apq is at most tol or tol sqrt(app aqq).
-__device__ __forceinline__ bool schur_c(double app, double aqq, double apq, double tol, double& c, double& s) {
-  c = 1.0;
-  s = 0.0;
-  if (apq > tol && apq * apq > tol * tol * fabs(app * aqq)) {
-    const double dd = aqq - app;
-    const double h = sqrt(dd * dd + 4.0 * apq * apq);
-    const double t = 2.0 * apq * (dd >= 0.0 ? 1.0 : -1.0) * fast_rcp(fabs(dd) + h);
-    c = fast_rsqrt(1.0 + t * t);
-    s = t * c;
-    return true;
-  }
-  return false;
-}
-
 constexpr int kSvdThreads = 512;
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// Eigen-decomposition of a Hermitian W = Wr + i Wi (n x n, n <= 64, pitch gp,
+// full matrix) by a workgroup of 512 threads:
+//  1. Householder reduction W = Q T Q^H (T Hermitian tridiagonal), Q
+//     accumulated in (Vr, Vi), which hold the identity on entry.  Step k
+//     reflects x = W[k+1:n][k] to beta e1, beta = -(x0 / |x0|) |x|, with
+//     H = I - tau v v^H, v = x - beta e1, tau = 1 / (|x| (|x| + |x0|)); the
+//     trailing block becomes H W2 H = W2 - v w^H - w v^H with p = tau W2 v,
+//     w = p - (tau / 2)(v^H p) v, and Q2 <- Q2 - tau (Q2 v) v^H.  Every
+//     wavefront forms v itself (lane i holds v_i); the products W2 v and Q2 v
+//     are split over the wavefronts by columns (lane = row) and summed after a
+//     barrier; the rank-two update follows the same split.  Two barriers a step.
+//  2. The diagonal unitary D = diag(phi), phi_{k+1} = phi_k e_k / |e_k|, makes
+//     T' = D^H T D real with subdiagonal |e_k|.
+//  3. Eigenvalues of T' by bisection on Sturm counts (the number of negative
+//     pivots of T' - x I), nine-way: eight lanes per eigenvalue test eight
+//     points of its interval per round.
+//  4. Eigenvectors of T' from the twisted factorization of T' - lambda I: the
+//     forward and backward pivots d+ and d-, the twist r minimizing
+//     |d+_r + d-_r - (d_r - lambda)|, z_r = 1 and the two recurrences away
+//     from r; then the members of each cluster of eigenvalues closer than
+//     1e-3 ||T'|| are made orthogonal (below).  Only eigenpairs the caller
+//     uses need this: those with an eigenvalue above `thr` among the `keep`
+//     largest (the others may come out of a cluster non-orthogonal).
+//  5. U = Q D Z into (Vr, Vi); lam[i] ascending.
+// The planes (Wr, Wi) are scratch from step 3 on (they hold Z).
+__device__ inline void heev_tridiag(double* Wr, double* Wi, double* Vr, double* Vi, int gp, int n, double* lam,
+                                    double thr, int keep) {
+  __shared__ double s_part[8][4][64];  // per-wavefront partial sums: Re p, Im p, Re y, Im y
+  __shared__ double s_d[64], s_er[64], s_ei[64], s_eh[64], s_e2[64], s_phr[64], s_phi[64];
+  __shared__ int s_twist[64];
+  __shared__ double s_solve[5][64];  // elimination of T' - lambda I: multipliers, diagonals, right side
+  __shared__ double s_nrm;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  constexpr int NW = kSvdThreads / 64;
+  // ---- 1. Householder tridiagonalization ----
+  for (int k = 0; k + 2 < n; ++k) {
+    const int m = n - k - 1, c0 = k + 1;
+    const bool li = lane < m;
+    const double xr = li ? Wr[(c0 + lane) * gp + k] : 0.0, xi = li ? Wi[(c0 + lane) * gp + k] : 0.0;
+    const double alpha = sqrt(wave_sum(xr * xr + xi * xi));
+    const double x0r = readlane_d(xr, 0), x0i = readlane_d(xi, 0);
+    const double ax0 = sqrt(x0r * x0r + x0i * x0i);
+    const double phr = ax0 > 0.0 ? x0r / ax0 : 1.0, phi = ax0 > 0.0 ? x0i / ax0 : 0.0;
+    if (tid == 0) {
+      s_d[k] = Wr[k * gp + k];
+      s_er[k] = -phr * alpha;
+      s_ei[k] = -phi * alpha;
+    }
+    if (!(alpha > 0.0)) continue;  // nothing to reflect (uniform: every wavefront sums the same column)
+    const double tau = 1.0 / (alpha * (alpha + ax0));
+    const double vr = lane == 0 ? x0r + phr * alpha : xr, vi = lane == 0 ? x0i + phi * alpha : xi;
+    // partial products over this wavefront's columns j = wv, wv + 8, ...
+    double ppr = 0.0, ppi = 0.0, pyr = 0.0, pyi = 0.0;
+    for (int j = wv; j < m; j += NW) {
+      const double bjr = readlane_d(vr, j), bji = readlane_d(vi, j);
+      if (li) {
+        const double ar = Wr[(c0 + lane) * gp + c0 + j], ai = Wi[(c0 + lane) * gp + c0 + j];
+        ppr = fma(ar, bjr, fma(-ai, bji, ppr));
+        ppi = fma(ar, bji, fma(ai, bjr, ppi));
+      }
+      if (lane < n) {
+        const double qr = Vr[lane * gp + c0 + j], qi = Vi[lane * gp + c0 + j];
+        pyr = fma(qr, bjr, fma(-qi, bji, pyr));
+        pyi = fma(qr, bji, fma(qi, bjr, pyi));
+      }
+    }
+    s_part[wv][0][lane] = ppr;
+    s_part[wv][1][lane] = ppi;
+    s_part[wv][2][lane] = pyr;
+    s_part[wv][3][lane] = pyi;
+    __syncthreads();
+    double pr = 0.0, pi = 0.0, yr = 0.0, yi = 0.0;
+#pragma unroll
+    for (int w = 0; w < NW; ++w) {
+      pr += s_part[w][0][lane];
+      pi += s_part[w][1][lane];
+      yr += s_part[w][2][lane];
+      yi += s_part[w][3][lane];
+    }
+    pr *= tau;
+    pi *= tau;
+    // K = (tau / 2) v^H p (real), w = p - K v
+    const double K = 0.5 * tau * wave_sum(li ? vr * pr + vi * pi : 0.0);
+    const double wr = pr - K * vr, wi = pi - K * vi;
+    for (int j = wv; j < m; j += NW) {
+      const double bvr = readlane_d(vr, j), bvi = readlane_d(vi, j);
+      const double bwr = readlane_d(wr, j), bwi = readlane_d(wi, j);
+      if (li) {  // W2[i][j] -= v_i conj(w_j) + w_i conj(v_j)
+        const int o = (c0 + lane) * gp + c0 + j;
+        Wr[o] -= (vr * bwr + vi * bwi) + (wr * bvr + wi * bvi);
+        Wi[o] -= (vi * bwr - vr * bwi) + (wi * bvr - wr * bvi);
+      }
+      if (lane < n) {  // Q2[a][j] -= tau y_a conj(v_j)
+        const int o = lane * gp + c0 + j;
+        Vr[o] -= tau * (yr * bvr + yi * bvi);
+        Vi[o] -= tau * (yi * bvr - yr * bvi);
+      }
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    for (int k = (n >= 2 ? n - 2 : 0); k < n; ++k) s_d[k] = Wr[k * gp + k];
+    if (n >= 2) {
+      s_er[n - 2] = Wr[(n - 1) * gp + n - 2];
+      s_ei[n - 2] = Wi[(n - 1) * gp + n - 2];
+    }
+    // ---- 2. phases: T' = D^H T D real ----
+    double fr = 1.0, fi = 0.0;
+    s_phr[0] = 1.0;
+    s_phi[0] = 0.0;
+    for (int k = 0; k + 1 < n; ++k) {
+      const double er = s_er[k], ei = s_ei[k], ae = sqrt(er * er + ei * ei);
+      s_eh[k] = ae;
+      s_e2[k] = ae * ae;
+      if (ae > 0.0) {
+        const double ur = er / ae, ui = ei / ae;
+        const double nr = fr * ur - fi * ui, ni = fr * ui + fi * ur;
+        fr = nr;
+        fi = ni;
+      }
+      s_phr[k + 1] = fr;
+      s_phi[k + 1] = fi;
+    }
+    double nrm = 0.0;  // ||T'||_1
+    for (int k = 0; k < n; ++k)
+      nrm = fmax(nrm, fabs(s_d[k]) + (k > 0 ? s_eh[k - 1] : 0.0) + (k + 1 < n ? s_eh[k] : 0.0));
+    s_nrm = nrm;
+  }
+  __syncthreads();
+  const double tnorm = s_nrm;
+  double e2max = 0.0;
+  for (int k = 0; k + 1 < n; ++k) e2max = fmax(e2max, s_eh[k] * s_eh[k]);
+  const double pivmin = 2.2250738585072014e-308 * fmax(1.0, e2max);
+  // ---- 3. bisection: eigenvalue i = tid / 8, sub-point tid % 8 ----
+  {
+    const int i = tid >> 3, sub = tid & 7;
+    double lo = -tnorm - pivmin, hi = tnorm + pivmin;
+    for (int round = 0; round < 19; ++round) {
+      const double x = lo + (hi - lo) * (double)(sub + 1) / 9.0;
+      int cnt = 0;
+      if (i < n) {  // negative pivots of T' - x I (reciprocal refined to the FP64 rounding level)
+        double q = s_d[0] - x;
+        if (q <= pivmin) {
+          ++cnt;
+          q = fmin(q, -pivmin);
+        }
+#pragma unroll 4
+        for (int k = 1; k < n; ++k) {
+          q = (s_d[k] - x) - s_e2[k - 1] * fast_rcp(q);
+          if (q <= pivmin) {
+            ++cnt;
+            q = fmin(q, -pivmin);
+          }
+        }
+      }
+      // points with at most i eigenvalues below them form a prefix of the eight
+      const unsigned long long below = __ballot(cnt <= i);
+      const int t = __popcll((below >> (lane & ~7)) & 0xffull);
+      const double xlo = lo + (hi - lo) * (double)t / 9.0, xhi = lo + (hi - lo) * (double)(t + 1) / 9.0;
+      lo = t > 0 ? xlo : lo;
+      hi = t < 8 ? xhi : hi;
+    }
+    if (i < n && sub == 0) lam[i] = 0.5 * (lo + hi);
+  }
+  __syncthreads();
+  // ---- 4. eigenvectors of T' (thread e < n): Z row e at Wr + e * n ----
+  double* Z = Wr;
+  double* Dm = Wr + n * n;  // backward pivots
+  if (tid < n) {
+    const int e = tid;
+    const double lm = lam[e];
+    double* zp = Z + e * n;
+    double* dm = Dm + e * n;
+    auto guard = [&](double q) { return fabs(q) < pivmin ? (q < 0.0 ? -pivmin : pivmin) : q; };
+    double q = guard(s_d[n - 1] - lm);
+    dm[n - 1] = q;
+    for (int k = n - 2; k >= 0; --k) {
+      q = guard((s_d[k] - lm) - s_eh[k] * s_eh[k] / q);
+      dm[k] = q;
+    }
+    int r = 0;
+    double best = 0.0, qp = 0.0;
+    for (int k = 0; k < n; ++k) {
+      qp = guard(k == 0 ? s_d[0] - lm : (s_d[k] - lm) - s_eh[k - 1] * s_eh[k - 1] / qp);
+      zp[k] = qp;  // forward pivot d+_k
+      const double g = fabs(qp + dm[k] - (s_d[k] - lm));
+      if (k == 0 || g < best) {
+        best = g;
+        r = k;
+      }
+    }
+    double nz = 1.0, z = 1.0;
+    for (int k = r - 1; k >= 0; --k) {
+      z = -(s_eh[k] / zp[k]) * z;
+      zp[k] = z;
+      nz += z * z;
+    }
+    z = 1.0;
+    for (int k = r + 1; k < n; ++k) {
+      z = -(s_eh[k - 1] / dm[k]) * z;
+      zp[k] = z;
+      nz += z * z;
+    }
+    zp[r] = 1.0;
+    const double inv = 1.0 / sqrt(nz);
+    for (int k = 0; k < n; ++k) zp[k] *= inv;
+    s_twist[e] = r;
+  }
+  __syncthreads();
+  // Clusters of eigenvalues closer than 1e-3 ||T'|| (wavefront 0, lane =
+  // component): every member after the first is refined by three steps of
+  // inverse iteration, each preceded by Gram-Schmidt (twice) against the
+  // members before it, and orthogonalized once more at the end.  A vector
+  // that Gram-Schmidt annihilates restarts from a fixed dense vector.  The
+  // solves of T' - lambda I use Gaussian elimination with partial pivoting
+  // (lane 0; a zero pivot becomes eps ||T'||).
+  if (wv == 0) {
+    double* sdl = s_solve[0];  // subdiagonal multipliers, diagonal, first and second superdiagonals, right side
+    double* sdd = s_solve[1];
+    double* sdu = s_solve[2];
+    double* sdu2 = s_solve[3];
+    double* sx = s_solve[4];
+    const double ortol = 1e-3 * tnorm, tiny = 2.220446049250313e-16 * tnorm;
+    auto gs = [&](double x, int a, int e) {  // against members a + 1 .. e - 1
+      for (int pass = 0; pass < 2; ++pass)
+        for (int b = a + 1; b < e; ++b) {
+          const double zb = lane < n ? Z[b * n + lane] : 0.0;
+          x -= wave_sum(x * zb) * zb;
+        }
+      return x;
+    };
+    // first eigenpair the caller uses (eigenvalues ascend)
+    int i0 = max(0, n - keep);
+    while (i0 < n && !(lam[i0] > thr)) ++i0;
+    int c0 = 0;
+    for (int e = 1; e <= n; ++e) {
+      if (e < n && lam[e] - lam[e - 1] <= ortol) continue;
+      // cluster c0 .. e - 1: its largest member stays, the others (from the
+      // top) are refined against the members above them
+      for (int a = e - 2; a >= max(c0, i0); --a) {
+        double x = lane < n ? Z[a * n + lane] : 0.0;
+        for (int it = 0; it < 3; ++it) {
+          x = gs(x, a, e);
+          double nn = wave_sum(x * x);
+          if (!(nn > 1e-20)) {
+            x = lane < n ? 1.0 + 0.5 * sin(0.7 * lane + 1.3 * a) : 0.0;
+            x = gs(x, a, e);
+            nn = wave_sum(x * x);
+          }
+          x *= 1.0 / sqrt(nn);
+          if (lane < n) sx[lane] = x;
+          __threadfence_block();
+          if (lane == 0) {
+            const double lm = lam[a];
+            for (int k = 0; k < n; ++k) {
+              sdd[k] = s_d[k] - lm;
+              if (k + 1 < n) sdl[k] = sdu[k] = s_eh[k];
+              sdu2[k] = 0.0;
+            }
+            for (int i = 0; i + 1 < n; ++i) {
+              if (fabs(sdd[i]) >= fabs(sdl[i])) {  // no interchange
+                if (sdd[i] == 0.0) sdd[i] = tiny;
+                const double f = sdl[i] / sdd[i];
+                sdl[i] = f;
+                sdd[i + 1] -= f * sdu[i];
+                s_twist[i] = 0;
+              } else {  // rows i and i + 1 interchanged
+                const double f = sdd[i] / sdl[i];
+                sdd[i] = sdl[i];
+                sdl[i] = f;
+                const double t = sdu[i];
+                sdu[i] = sdd[i + 1];
+                sdd[i + 1] = t - f * sdd[i + 1];
+                if (i + 2 < n) {
+                  sdu2[i] = sdu[i + 1];
+                  sdu[i + 1] = -f * sdu[i + 1];
+                }
+                s_twist[i] = 1;
+              }
+            }
+            if (sdd[n - 1] == 0.0) sdd[n - 1] = tiny;
+            for (int i = 0; i + 1 < n; ++i) {
+              if (s_twist[i] == 0) {
+                sx[i + 1] -= sdl[i] * sx[i];
+              } else {
+                const double t = sx[i];
+                sx[i] = sx[i + 1];
+                sx[i + 1] = t - sdl[i] * sx[i];
+              }
+            }
+            sx[n - 1] /= sdd[n - 1];
+            if (n > 1) sx[n - 2] = (sx[n - 2] - sdu[n - 2] * sx[n - 1]) / sdd[n - 2];
+            for (int i = n - 3; i >= 0; --i) sx[i] = (sx[i] - sdu[i] * sx[i + 1] - sdu2[i] * sx[i + 2]) / sdd[i];
+          }
+          __threadfence_block();
+          x = lane < n ? sx[lane] : 0.0;
+          x *= 1.0 / sqrt(wave_sum(x * x));
+        }
+        x = gs(x, a, e);
+        x *= 1.0 / sqrt(wave_sum(x * x));
+        if (lane < n) Z[a * n + lane] = x;
+        __threadfence_block();
+      }
+      c0 = e;
+    }
+  }
+  __syncthreads();
+  // ---- 5. U = Q D Z into (Vr, Vi): 2 x 4 blocks per thread ----
+  {
+    const int nbc = (n + 3) / 4, nblk = ((n + 1) / 2) * nbc;
+    const bool act = tid < nblk;
+    const int a0 = act ? 2 * (tid / nbc) : 0, b0 = act ? 4 * (tid % nbc) : 0;
+    double ur[2][4], ui[2][4];
+#pragma unroll
+    for (int u = 0; u < 2; ++u)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) ur[u][v] = ui[u][v] = 0.0;
+    if (act) {
+      const int ra[2] = {min(a0, n - 1), min(a0 + 1, n - 1)};
+      const int cb[4] = {min(b0, n - 1), min(b0 + 1, n - 1), min(b0 + 2, n - 1), min(b0 + 3, n - 1)};
+      for (int k = 0; k < n; ++k) {
+        const double fr = s_phr[k], fi = s_phi[k];
+        double qr[2], qi[2];
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {  // (Q D)[a][k]
+          const double xr = Vr[ra[u] * gp + k], xi = Vi[ra[u] * gp + k];
+          qr[u] = xr * fr - xi * fi;
+          qi[u] = xr * fi + xi * fr;
+        }
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const double z = Z[cb[v] * n + k];
+#pragma unroll
+          for (int u = 0; u < 2; ++u) {
+            ur[u][v] = fma(qr[u], z, ur[u][v]);
+            ui[u][v] = fma(qi[u], z, ui[u][v]);
+          }
+        }
+      }
+    }
+    __syncthreads();
+    if (act)
+#pragma unroll
+      for (int u = 0; u < 2; ++u)
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+          if (a0 + u < n && b0 + v < n) {
+            Vr[(a0 + u) * gp + b0 + v] = ur[u][v];
+            Vi[(a0 + u) * gp + b0 + v] = ui[u][v];
+          }
+    __syncthreads();
+  }
+}
+
 
 template <int LB>
 size_t csvd_lds_bytes(int l) {
@@ -488,8 +934,7 @@ __global__ __launch_bounds__(kSvdThreads) void k_csvd(double* __restrict__ g2_al
   constexpr int NT = kSvdThreads;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   __shared__ double s_scr;
-  __shared__ int s_kept, s_cnt[3], s_open;
-  __shared__ CRot s_rot[2][LB / 2];
+  __shared__ int s_kept;
   const int j = slices ? slices[blockIdx.x].x : (int)blockIdx.x;
   const int tid = threadIdx.x;
   const SliceDesc d = sd[j];
@@ -517,7 +962,8 @@ __global__ __launch_bounds__(kSvdThreads) void k_csvd(double* __restrict__ g2_al
     const bool any_bad = __ballot(bad) != 0;
     if (tid == 0) status[j] = any_bad ? 1 : 0;
   }
-  cchol_deflate(Ar, Ai, dR, gp, l, 8.0 * (double)d.n1 * kEps, &s_scr);
+  cchol_deflate<(kMaxComplexWidth * (kMaxComplexWidth + 1) / 2 + NT - 1) / NT>(Ar, Ai, dR, gp, l,
+                                                                          8.0 * (double)d.n1 * kEps, &s_scr);
   ctri_inverse_waves(Ar, Ai, dR, gp, l, gq, gq + ll, l);
   __syncthreads();
   for (int idx = tid; idx < ll; idx += NT) {
@@ -564,156 +1010,13 @@ __global__ __launch_bounds__(kSvdThreads) void k_csvd(double* __restrict__ g2_al
     Br[a * gp + b] *= inv_scale;
     Bi[a * gp + b] *= inv_scale;
   }
-  if (tid < 3) s_cnt[tid] = 0;
   __syncthreads();
-  // A pair rotates only when |W[p][q]| is above tol and tol sqrt(W[p][p] W[q][q]):
-  // FP64 output 1e-15, FP32 output 1e-10 (as for real slices).
-  const double tol = std::is_same<T, double>::value ? 1e-15 : 1e-10;
-
-  // ---- parallel cyclic Jacobi, in place on W (B planes) and V (A planes) ----
-  const int half = L2 / 2, m = L2 - 1;
-  const int nblk = half * half, nvit = half * l;
-  constexpr int NBI = ((LB / 2) * (LB / 2) + NT - 1) / NT;
-  constexpr int NVI = ((LB / 2) * LB + NT - 1) / NT;
-  int step = 0, still = 0;
-  for (int g = 0; g < 30 * m; ++g) {
-    CRot* rot = s_rot[g & 1];
-    if (tid < half) {
-      int p, q;
-      rr_pair_c(step, tid, m, p, q);
-      const double br = Br[p * gp + q], bi = Bi[p * gp + q];
-      const double ab = sqrt(br * br + bi * bi);
-      double c, sn;
-      CRot r{1.0, 0.0, 0.0, p, q};
-      if (schur_c(Br[p * gp + p], Br[q * gp + q], ab, tol, c, sn)) {
-        const double inv_ab = 1.0 / ab;
-        r.c = c;
-        r.sr = sn * br * inv_ab;
-        r.si = sn * bi * inv_ab;
-        s_cnt[g % 3] = 1;
-      }
-      rot[tid] = r;
-    }
-    if (tid == 0) {
-      s_cnt[(g + 2) % 3] = 0;
-      s_open = 0;
-    }
-    __syncthreads();
-    if (s_cnt[g % 3] != 0) {
-      CRot ra[NBI], rb[NBI], rv[NVI];
-      int vx[NVI];
-      bool bok[NBI], vok[NVI];
-#pragma unroll
-      for (int u = 0; u < NBI; ++u) {
-        const int item = tid + u * NT;
-        bok[u] = item < nblk;
-        const int it2 = bok[u] ? item : 0;
-        ra[u] = rot[it2 / half];
-        rb[u] = rot[it2 % half];
-      }
-#pragma unroll
-      for (int u = 0; u < NVI; ++u) {
-        const int item = tid + u * NT;
-        vok[u] = item < nvit;
-        const int it2 = vok[u] ? item : 0;
-        rv[u] = rot[it2 / l];
-        vx[u] = it2 % l;
-      }
-      double wr[NBI][4], wi[NBI][4], vr[NVI][2], vi[NVI][2];
-#pragma unroll
-      for (int u = 0; u < NBI; ++u) {
-        const int o[4] = {ra[u].p * gp + rb[u].p, ra[u].p * gp + rb[u].q, ra[u].q * gp + rb[u].p,
-                          ra[u].q * gp + rb[u].q};
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          wr[u][e] = Br[o[e]];
-          wi[u][e] = Bi[o[e]];
-        }
-      }
-#pragma unroll
-      for (int u = 0; u < NVI; ++u) {
-        vr[u][0] = Ar[vx[u] * gp + rv[u].p];
-        vi[u][0] = Ai[vx[u] * gp + rv[u].p];
-        vr[u][1] = Ar[vx[u] * gp + rv[u].q];
-        vi[u][1] = Ai[vx[u] * gp + rv[u].q];
-      }
-#pragma unroll
-      for (int u = 0; u < NBI; ++u) {
-        // rows: J_s^H = [[c, -s], [conj(s), c]];  columns: J_t = [[c, s], [-conj(s), c]]
-        const double cs = ra[u].c, ssr = ra[u].sr, ssi = ra[u].si;
-        const double ct = rb[u].c, str = rb[u].sr, sti = rb[u].si;
-        double rr[4], ri[4];
-        // r0x = c w0x - s w1x ; r1x = conj(s) w0x + c w1x   (x = column 0, 1)
-#pragma unroll
-        for (int x = 0; x < 2; ++x) {
-          const double w0r = wr[u][x], w0i = wi[u][x], w1r = wr[u][2 + x], w1i = wi[u][2 + x];
-          rr[x] = cs * w0r - (ssr * w1r - ssi * w1i);
-          ri[x] = cs * w0i - (ssr * w1i + ssi * w1r);
-          rr[2 + x] = (ssr * w0r + ssi * w0i) + cs * w1r;
-          ri[2 + x] = (ssr * w0i - ssi * w0r) + cs * w1i;
-        }
-        double nr[4], ni[4];
-        // ny0 = c ry0 - conj(s) ry1 ; ny1 = s ry0 + c ry1   (y = row 0, 1)
-#pragma unroll
-        for (int y = 0; y < 2; ++y) {
-          const double a0r = rr[2 * y], a0i = ri[2 * y], a1r = rr[2 * y + 1], a1i = ri[2 * y + 1];
-          nr[2 * y] = ct * a0r - (str * a1r + sti * a1i);
-          ni[2 * y] = ct * a0i - (str * a1i - sti * a1r);
-          nr[2 * y + 1] = (str * a0r - sti * a0i) + ct * a1r;
-          ni[2 * y + 1] = (str * a0i + sti * a0r) + ct * a1i;
-        }
-        if (bok[u]) {
-          const bool diag = ra[u].p == rb[u].p;
-          if (diag) {  // the diagonal stays real; the annihilated pair is zero
-            ni[0] = 0.0;
-            ni[3] = 0.0;
-            if (ra[u].sr != 0.0 || ra[u].si != 0.0) nr[1] = ni[1] = nr[2] = ni[2] = 0.0;
-          }
-          const int o[4] = {ra[u].p * gp + rb[u].p, ra[u].p * gp + rb[u].q, ra[u].q * gp + rb[u].p,
-                            ra[u].q * gp + rb[u].q};
-#pragma unroll
-          for (int e = 0; e < 4; ++e) {
-            Br[o[e]] = nr[e];
-            Bi[o[e]] = ni[e];
-          }
-        }
-      }
-#pragma unroll
-      for (int u = 0; u < NVI; ++u) {
-        // V <- V J: col p = c Vp - conj(s) Vq ; col q = s Vp + c Vq
-        const double c = rv[u].c, sr = rv[u].sr, si = rv[u].si;
-        const double pr = vr[u][0], pi = vi[u][0], qr = vr[u][1], qi = vi[u][1];
-        const double npr = c * pr - (sr * qr + si * qi), npi = c * pi - (sr * qi - si * qr);
-        const double nqr = (sr * pr - si * pi) + c * qr, nqi = (sr * pi + si * pr) + c * qi;
-        if (vok[u]) {
-          Ar[vx[u] * gp + rv[u].p] = npr;
-          Ai[vx[u] * gp + rv[u].p] = npi;
-          Ar[vx[u] * gp + rv[u].q] = nqr;
-          Ai[vx[u] * gp + rv[u].q] = nqi;
-        }
-      }
-      __syncthreads();
-      still = 0;
-    } else if (++still >= m) {
-      break;
-    } else if (still == 1) {
-      // first quiet step: W changes from here on only if some pair passes the
-      // test, so testing every pair now decides the rest of the check
-      for (int idx = tid; idx < ll; idx += NT) {
-        const int p = idx / l, q = idx % l;
-        if (p < q) {
-          const double br = Br[p * gp + q], bi = Bi[p * gp + q];
-          const double ab = sqrt(br * br + bi * bi);
-          if (ab > tol && ab * ab > tol * tol * fabs(Br[p * gp + p] * Br[q * gp + q])) s_open = 1;
-        }
-      }
-      __syncthreads();
-      const bool open = s_open != 0;
-      __syncthreads();
-      if (!open) break;
-    }
-    step = (step + 1 == m) ? 0 : step + 1;
-  }
+  // ---- eigenvectors V and eigenvalues of W (tridiagonal route) ----
+  // eigenpairs whose singular value the shrinkage zeroes (or past the kept
+  // count) carry no weight in K': their refinement within clusters is skipped
+  const double t0 = prox_zero_threshold(pen, tau);
+  heev_tridiag(Br, Bi, Ar, Ai, gp, l, lam, 0.99 * t0 * t0 * inv_scale, kkeep);
+  for (int a = tid; a < l; a += NT) Br[a * gp + a] = lam[a];
   __syncthreads();
 
   // ---- order, shrink, K = U diag(w) U^H, K' = R2^{-1} K R2^{-H} ------------
@@ -973,8 +1276,8 @@ __global__ __launch_bounds__(256) void k_crecon(const T* __restrict__ Xall, cons
 }  // namespace
 
 template <typename T>
-int launch_corth(T* Y, int which, const SliceDesc* sd, const int2* wk, const int2* items, int nitems, int lmax,
-                 int nslices, double* gin, double* gout, hipStream_t s) {
+int launch_corth(T* Y, int which, const SliceDesc* sd, const int2* wk, const int2* items, int nitems,
+                 const int2* tiles, int ntiles, int lmax, int nslices, double* gin, double* gout, hipStream_t s) {
   if (lmax > kMaxComplexWidth) HT_FAIL(HT_ERR_UNSUPPORTED, "complex sketch width above 64");
   if (nitems == 0 || nslices == 0) return HT_OK;
   int rc = ensure_dynamic_lds((const void*)k_corth_factor, cfactor_lds_bytes(kMaxComplexWidth));
@@ -982,6 +1285,18 @@ int launch_corth(T* Y, int which, const SliceDesc* sd, const int2* wk, const int
   hipLaunchKernelGGL(k_corth_factor, dim3((unsigned)nslices), dim3(kFactorThreads), cfactor_lds_bytes(lmax), s,
                      which, sd, wk, gin);
   HT_CHECK_LAUNCH();
+  if (std::is_same<T, float>::value && gout == nullptr && tiles != nullptr && ntiles > 0) {
+    if ((rc = ensure_dynamic_lds((const void*)k_corth_apply_tiles, kApplyLds))) return rc;
+    int per_cu = 0, dev = 0, ncu = 0;
+    HT_CHECK_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)k_corth_apply_tiles, 256, kApplyLds));
+    HT_CHECK_HIP(hipGetDevice(&dev));
+    HT_CHECK_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+    const int grid = std::max(1, std::min(ntiles, std::max(per_cu, 1) * ncu));
+    hipLaunchKernelGGL(k_corth_apply_tiles, dim3((unsigned)grid), dim3(256), kApplyLds, s, reinterpret_cast<float*>(Y),
+                       which, sd, wk, tiles, ntiles, gin);
+    HT_CHECK_LAUNCH();
+    return HT_OK;
+  }
   auto apply = [&](auto kern, size_t lds) -> int {
     int r = ensure_dynamic_lds((const void*)kern, lds);
     if (r) return r;
@@ -1043,10 +1358,10 @@ int launch_crecon(const T* X, const T* W, T* C, int mode, const SliceDesc* sd, c
   return HT_OK;
 }
 
-template int launch_corth<float>(float*, int, const SliceDesc*, const int2*, const int2*, int, int, int, double*,
-                                 double*, hipStream_t);
-template int launch_corth<double>(double*, int, const SliceDesc*, const int2*, const int2*, int, int, int, double*,
-                                  double*, hipStream_t);
+template int launch_corth<float>(float*, int, const SliceDesc*, const int2*, const int2*, int, const int2*, int, int,
+                                 int, double*, double*, hipStream_t);
+template int launch_corth<double>(double*, int, const SliceDesc*, const int2*, const int2*, int, const int2*, int, int,
+                                  int, double*, double*, hipStream_t);
 template int launch_csvd<float>(double*, const double*, const SliceDesc*, const int2*, const int2*, int, int, int,
                                 double, const double*, const double*, Penalty, float*, double*, int*, int*,
                                 hipStream_t);

@@ -169,9 +169,11 @@ int launch_smallsvd(double* g2, const double* gw, const SliceDesc* sd, const int
 // CholeskyQR with deflation of the complex basis `which` (0: Y, 1: Z): one
 // factor launch per slice (R^{-1} parked over the first partial of gin), then
 // Q = Y R^{-1} per 64-complex-row item; gout as launch_orth_apply.
+// FP32 blocks without gout take `tiles` instead: the same 64-row items in slice
+// order, split into contiguous ranges over resident workgroups.
 template <typename T>
-int launch_corth(T* Y, int which, const SliceDesc* sd, const int2* wk, const int2* items, int nitems, int lmax,
-                 int nslices, double* gin, double* gout, hipStream_t s);
+int launch_corth(T* Y, int which, const SliceDesc* sd, const int2* wk, const int2* items, int nitems,
+                 const int2* tiles, int ntiles, int lmax, int nslices, double* gin, double* gout, hipStream_t s);
 // Small SVD and shrinkage of complex slices (arguments as launch_smallsvd;
 // K' is written stacked, 2 l x l).
 template <typename T>

@@ -44,6 +44,30 @@ def _case(ht, dims, rank, r, p, q, prec, tau, pen, seed=1, noise=1e-2):
     return ht.from_device(out, dims), ref, plan
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("noise", [0.0, 1e-6, 1e-3])
+def test_tsvt_dft_repeated_singular_values(ht, prec, noise):
+    """Every transformed slice of X = sum_i u_i v_i^T c (u, v orthonormal, c a
+    real tube) is c_hat_j U V^T: its nonzero singular values are |c_hat_j|,
+    repeated rank times.  Noise splits them into tight clusters (and fills
+    the zero ones).  All repeated values are kept (rank <= r)."""
+    import torch
+    dims, kinds, rank, r, p, q = (40, 36, 8, 2), ["dft", "dft"], 4, 6, 4, 1
+    rng = np.random.default_rng(5)
+    U = np.linalg.qr(rng.standard_normal((dims[0], rank)))[0]
+    V = np.linalg.qr(rng.standard_normal((dims[1], rank)))[0]
+    c = rng.standard_normal(dims[2:])
+    X = np.einsum("ar,br,jk->abjk", U, V, c) + noise * rng.standard_normal(dims)
+    Xs = X.astype(np.float64 if prec == "fp64" else np.float32).astype(np.float64)
+    plan = ht.Plan(dims, kinds, r=r, p=p, q=q, precision=prec, seed=61)
+    tau, pen = 0.05, ("mcp", (30.0,))
+    out = plan.gnhtsvt(ht.to_device(Xs, plan.torch_dtype), tau, pen, call_index=4)
+    torch.cuda.synchronize()
+    om = otsvt.omegas(dims, kinds, r, p, seed=61, call=4, round_to=None if prec == "fp64" else np.float32)
+    ref = otsvt.tsvt_randomized(Xs, tau, pen, otr.build_transforms(dims, kinds), r, p, q, om)
+    assert _rel(ht.from_device(out, dims), ref) < TOL[prec]
+
+
 @pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16"])
 @pytest.mark.parametrize("dims,rank,r,p,q", [
     ((40, 30, 4, 3), 5, 5, 5, 1),    # even mode: self-conjugate slices at index 0 and n/2
