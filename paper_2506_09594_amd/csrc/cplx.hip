@@ -555,10 +555,25 @@ constexpr size_t capply_lds_bytes() {
 // ---------------------------------------------------------------------------
 constexpr int kSvdThreads = 512;
 
+// Data-parallel move of a double across lanes (DPP control CTRL, every lane
+// active).
+template <int CTRL>
+__device__ __forceinline__ double mov_dpp_d(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_mov_dpp((int)(b & 0xffffffffll), CTRL, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), CTRL, 0xf, 0xf, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// Sum over the 64 lanes of a wavefront (every lane active), the same value in
+// every lane: butterflies within quads (quad_perm [1,0,3,2], [2,3,0,1]), then
+// rotations by 4 and 8 within rows of 16, then the four row sums.
 __device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-  return v;
+  v += mov_dpp_d<0xb1>(v);
+  v += mov_dpp_d<0x4e>(v);
+  v += mov_dpp_d<0x124>(v);
+  v += mov_dpp_d<0x128>(v);
+  return (readlane_d(v, 0) + readlane_d(v, 16)) + (readlane_d(v, 32) + readlane_d(v, 48));
 }
 
 // Eigen-decomposition of a Hermitian W = Wr + i Wi (n x n, n <= 64, pitch gp,
@@ -586,7 +601,7 @@ __device__ __forceinline__ double wave_sum(double v) {
 //     largest (the others may come out of a cluster non-orthogonal).
 //  5. U = Q D Z into (Vr, Vi); lam[i] ascending.
 // The planes (Wr, Wi) are scratch from step 3 on (they hold Z).
-__device__ inline void heev_tridiag(double* Wr, double* Wi, double* Vr, double* Vi, int gp, int n, double* lam,
+__device__ __forceinline__ void heev_tridiag(double* Wr, double* Wi, double* Vr, double* Vi, int gp, int n, double* lam,
                                     double thr, int keep) {
   __shared__ double s_part[8][4][64];  // per-wavefront partial sums: Re p, Im p, Re y, Im y
   __shared__ double s_d[64], s_er[64], s_ei[64], s_eh[64], s_e2[64], s_phr[64], s_phi[64];

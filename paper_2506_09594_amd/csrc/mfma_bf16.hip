@@ -26,6 +26,17 @@ typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
 
 constexpr int KC = 32;
 constexpr int KP = KC + 8;  // LDS pitch (bf16 elements) of a k-contiguous row: 80 bytes
+// Pitch of the complex kernel's rows: 88 bytes (22 banks), so that the four
+// row groups of a wavefront's transposing stores fall in disjoint bank ranges
+// and 32 consecutive rows read at one k cover every bank once; rows are 8-byte
+// aligned, read as two 8-byte halves.
+constexpr int KPC = KC + 12;
+
+__device__ __forceinline__ u16x8 lds_u16x8(const uint16_t* p) {
+  const uint2* q = reinterpret_cast<const uint2*>(p);
+  const uint2 lo = q[0], hi = q[1];
+  return __builtin_bit_cast(u16x8, make_uint4(lo.x, lo.y, hi.x, hi.y));
+}
 
 template <int NB, int NW>
 struct Bf16Lds {
@@ -250,7 +261,7 @@ __global__ __launch_bounds__(2 * MT) void k_cthin_bf16(const uint16_t* __restric
                                                        const int2* __restrict__ items, double* __restrict__ gpart,
                                                        int aligned, int wreal) {
   constexpr int NTH = 2 * MT, LW = 32 * NB;
-  constexpr int A_ELEMS = MT * KP, B_ELEMS = LW * KP;  // one buffer: A chunk, then the two thin chunks
+  constexpr int A_ELEMS = MT * KPC, B_ELEMS = LW * KPC;  // one buffer: A chunk, then the two thin chunks
   constexpr int BUF = A_ELEMS + 2 * B_ELEMS;
   static_assert(MT % 128 == 0, "groups of 64 complex rows");
   extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -277,21 +288,22 @@ __global__ __launch_bounds__(2 * MT) void k_cthin_bf16(const uint16_t* __restric
   auto ovalid = [&](int i) -> bool { return crow(i) < mo; };
   auto orow = [&](int i) -> int { return ((i & 64) ? mo : 0) + crow(i); };
 
-  // A chunk: MT x 32 bf16 in groups of 8, MT / 128 per thread.
-  //   nn: group = 8 consecutive tile rows (of Ar or Ai) of one stored column k
+  // A chunk: MT x 32 bf16, two groups of 8 per thread.
+  //   nn: thread t holds tile rows 8 (t / 16) .. + 7 of stored columns 2 (t % 16)
+  //       and 2 (t % 16) + 1 (stored to LDS as pairs: rows of a wavefront's
+  //       four row groups land in disjoint bank ranges with the pitch KPC)
   //   tn: group = 8 consecutive k (stored rows of Ar or Ai) of one column
   constexpr int NRA = MT * KC / 8 / NTH;
+  static_assert(NRA == 2, "two groups of eight per thread");
   constexpr int NWB = (LW * KC / 4 + NTH - 1) / NTH;  // float4 groups of one thin chunk per thread
   u16x8 ra0[NRA], ra1[NRA];
   f32x4 rw0[2][NWB], rw1[2][NWB];
   auto fetch = [&](u16x8 (&ra)[NRA], f32x4 (&rw)[2][NWB], int k0) {
 #pragma unroll
     for (int u = 0; u < NRA; ++u) {
-      const int g = tid + u * NTH;
       u16x8 v;
       if (!TRANS) {
-        const int kk = g / (MT / 8), row = (g % (MT / 8)) * 8;
-        const int gk = k0 + kk, rr = crow(row);
+        const int row = (tid / 16) * 8, gk = k0 + 2 * (tid % 16) + u, rr = crow(row);
         const uint16_t* src = Aj + ((row & 64) ? n1 : 0) + rr + (int64_t)gk * lda;
         if (vecA && gk < K && rr + 7 < n1) {
           v = *reinterpret_cast<const u16x8*>(src);
@@ -300,6 +312,7 @@ __global__ __launch_bounds__(2 * MT) void k_cthin_bf16(const uint16_t* __restric
           for (int e = 0; e < 8; ++e) v[e] = (gk < K && rr + e < n1) ? src[e] : 0;
         }
       } else {
+        const int g = tid + u * NTH;
         const int row = g / (KC / 8), kk = (g % (KC / 8)) * 8;
         const int c = crow(row), gk = k0 + kk;
         const uint16_t* src = Aj + ((row & 64) ? n1 : 0) + gk + (int64_t)c * lda;
@@ -333,16 +346,20 @@ __global__ __launch_bounds__(2 * MT) void k_cthin_bf16(const uint16_t* __restric
   };
   auto stash = [&](const u16x8 (&ra)[NRA], const f32x4 (&rw)[2][NWB], int buf) {
     uint16_t* As = lds_h + buf * BUF;
+    if (!TRANS) {
+      const int row = (tid / 16) * 8, kk = 2 * (tid % 16);
 #pragma unroll
-    for (int u = 0; u < NRA; ++u) {
-      const int g = tid + u * NTH;
-      if (!TRANS) {
-        const int kk = g / (MT / 8), row = (g % (MT / 8)) * 8;
+      for (int e = 0; e < 8; ++e)
+        *reinterpret_cast<uint32_t*>(As + (row + e) * KPC + kk) = (uint32_t)ra[0][e] | ((uint32_t)ra[1][e] << 16);
+    } else {
 #pragma unroll
-        for (int e = 0; e < 8; ++e) As[(row + e) * KP + kk] = ra[u][e];
-      } else {
+      for (int u = 0; u < NRA; ++u) {
+        const int g = tid + u * NTH;
         const int row = g / (KC / 8), kk = (g % (KC / 8)) * 8;
-        *reinterpret_cast<u16x8*>(As + row * KP + kk) = ra[u];
+        uint2* dst = reinterpret_cast<uint2*>(As + row * KPC + kk);
+        const uint4 w = __builtin_bit_cast(uint4, ra[u]);
+        dst[0] = make_uint2(w.x, w.y);
+        dst[1] = make_uint2(w.z, w.w);
       }
     }
 #pragma unroll
@@ -353,8 +370,8 @@ __global__ __launch_bounds__(2 * MT) void k_cthin_bf16(const uint16_t* __restric
         const int f = tid + u * NTH;
         if (f < LW * KC / 4) {
           const int c = f / (KC / 4), k4 = (f % (KC / 4)) * 4;
-          *reinterpret_cast<uint2*>(Ws + c * KP + k4) = make_uint2(f32x2_to_bf16x2(rw[part][u][0], rw[part][u][1]),
-                                                                   f32x2_to_bf16x2(rw[part][u][2], rw[part][u][3]));
+          *reinterpret_cast<uint2*>(Ws + c * KPC + k4) = make_uint2(f32x2_to_bf16x2(rw[part][u][0], rw[part][u][1]),
+                                                                    f32x2_to_bf16x2(rw[part][u][2], rw[part][u][3]));
         }
       }
     }
@@ -382,14 +399,14 @@ __global__ __launch_bounds__(2 * MT) void k_cthin_bf16(const uint16_t* __restric
       const unsigned short flip = part ? flip2 : flip1;
 #pragma unroll
       for (int kh = 0; kh < KC / 16; ++kh) {
-        u16x8 av = *reinterpret_cast<const u16x8*>(As + arow * KP + 16 * kh + koff);
+        u16x8 av = lds_u16x8(As + arow * KPC + 16 * kh + koff);
         av ^= flip;
         const bf16x8 a = __builtin_bit_cast(bf16x8, av);
 #pragma unroll
         for (int b = 0; b < NB; ++b) {
           if (b < nbl) {
-            const bf16x8 bv = __builtin_bit_cast(
-                bf16x8, *reinterpret_cast<const u16x8*>(Ws + (32 * b + (lane % 32)) * KP + 16 * kh + koff));
+            const bf16x8 bv =
+                __builtin_bit_cast(bf16x8, lds_u16x8(Ws + (32 * b + (lane % 32)) * KPC + 16 * kh + koff));
             acc[b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bv, acc[b], 0, 0, 0);
           }
         }
@@ -438,7 +455,7 @@ template <int NB, bool TRANS>
 int launch_cthin_bf16(const uint16_t* A, const float* W, float* Y, const SliceDesc* sd, const int2* wk,
                       const int2* items, int nitems, double* gpart, hipStream_t s, int wreal) {
   constexpr int MT = 2 * kCplxProdRows;
-  constexpr size_t main = 2 * (size_t)(MT * KP + 2 * 32 * NB * KP) * 2, epi = MT * (size_t)(32 * NB + 1) * 4;
+  constexpr size_t main = 2 * (size_t)(MT * KPC + 2 * 32 * NB * KPC) * 2, epi = MT * (size_t)(32 * NB + 1) * 4;
   constexpr size_t bytes = main > epi ? main : epi;
   if (nitems == 0) return HT_OK;
   int rc = ensure_dynamic_lds((const void*)k_cthin_bf16<NB, MT, TRANS>, bytes);
