@@ -1050,6 +1050,9 @@ int run_tsvt(const ht_plan* pl, const T* X, T* out, double tau, const double* ta
     return rc;
   if ((rc = timed(pl, ST_RECON_NT, s, [&] {
          if (cplx) {
+           if (bf16)
+             return launch_bf16x3_cnt((const float*)QK, (const float*)Z, (float*)C, sd, wk_final,
+                                      items(pl, pl->it_cnt), pl->it_cnt.n, lmax, s);
            if (!fp64)
              return launch_mfma_cnt((const float*)QK, (const float*)Z, (float*)C, sd, wk_final, items(pl, pl->it_cnt),
                                     pl->it_cnt.n, lmax, s);

@@ -133,6 +133,10 @@ int launch_bf16_ctn(const uint16_t* A, const float* Q, float* Z, const SliceDesc
                     const int2* items, int nitems, int lmax, double* gpart, hipStream_t s);
 int launch_mfma_cqk(const float* Q, const float* K, float* QK, const SliceDesc* sd, const int2* wk, const int2* items,
                     int nitems, int lmax, hipStream_t s);
+// C = QK Bt^H for BF16-mixed plans: split-BF16 operands (three BF16 products
+// per term), items as launch_mfma_cnt.
+int launch_bf16x3_cnt(const float* X, const float* W, float* C, const SliceDesc* sd, const int2* wk,
+                      const int2* items, int nitems, int lmax, hipStream_t s);
 int launch_mfma_cnt(const float* X, const float* W, float* C, const SliceDesc* sd, const int2* wk, const int2* items,
                     int nitems, int lmax, hipStream_t s);
 

@@ -467,6 +467,156 @@ int launch_cthin_bf16(const uint16_t* A, const float* W, float* Y, const SliceDe
   return HT_OK;
 }
 
+// Complex reconstruction C = X B, B = Bt^H (X = Q1 K', n1 x l; Bt, n2 x l;
+// both FP32 in the stacked layout), for BF16-mixed plans, on the BF16 matrix
+// cores with every operand split in two BF16 terms, x = xh + xl (xh = bf16(x),
+// xl = bf16(x - xh)): X B ~ Xh Bh + Xh Bl + Xl Bh, a relative error of a few
+// 2^-17 per product (the dropped Xl Bl and the split remainders).
+// Real form over K = 2 q (q = l rounded up to 8): Cr = [Xr, Xi] E1 and
+// Ci = [Xr, Xi] E2 with E1 = [Btr^T; Bti^T] and E2 = [-Bti^T; Btr^T], so E2 is
+// E1 with its halves exchanged and the first negated: one staged operand.
+// Work items as k_cmul_strip (strips of 128 complex rows, groups of up to four
+// 64-column tiles); wavefront w keeps rows 32 w .. 32 w + 31 of [Xr, Xi] as
+// split A operands (lane t: row t % 32, k = 16 s + 8 (t / 32) .. + 7); per
+// column tile E1 (split) goes to LDS column by column with k contiguous;
+// results are stored from the accumulators.
+constexpr int kXPitch = 136;  // bf16 per LDS column of E1: 2 q <= 128, 272 bytes
+constexpr size_t kX3Lds = 2 * 64 * kXPitch * sizeof(uint16_t);
+
+// Two FP32 values -> packed BF16 leading terms and packed BF16 remainders.
+__device__ __forceinline__ void split_bf16x2(float a, float b, uint32_t& hi, uint32_t& lo) {
+  hi = f32x2_to_bf16x2(a, b);
+  lo = f32x2_to_bf16x2(a - __uint_as_float(hi << 16), b - __uint_as_float(hi & 0xffff0000u));
+}
+
+__global__ __launch_bounds__(256, 1) void k_cmul_bf16x3(const float* __restrict__ Xall, const float* __restrict__ Wall,
+                                                        float* __restrict__ Call, const SliceDesc* __restrict__ sd,
+                                                        const int2* __restrict__ wk, const int2* __restrict__ items,
+                                                        int aligned) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  uint16_t* Eh = reinterpret_cast<uint16_t*>(smem_raw);  // [column][k]
+  uint16_t* El = Eh + 64 * kXPitch;
+  const int2 item = items[blockIdx.x];
+  const int s = item.x;
+  const SliceDesc d = sd[s];
+  const int l = slice_width(d, wk, s);
+  if (l <= 0) return;  // slice not part of this pass
+  const int n1 = d.n1, n2 = d.n2, ldx = 2 * n1;
+  const int nct = (n2 + 63) / 64, ncg = (nct + kCmulGroup - 1) / kCmulGroup;
+  const int row0 = (item.y / ncg) * kCmulRows, cg = item.y % ncg;
+  const int ct_begin = cg * kCmulGroup, ct_end = min(nct, ct_begin + kCmulGroup);
+  const int q = (l + 7) & ~7, nsteps = q / 8;  // K = 2 q in steps of 16
+  const float* X = Xall + d.y;
+  const float* W = Wall + d.z;
+  float* C = Call + d.a;
+  const int tid = threadIdx.x, wave = tid / 64, lane = tid % 64, li = lane % 32, h = lane / 32;
+  // ---- A operands: [Xr, Xi] rows of this wavefront, split ----
+  const int xrow = row0 + 32 * wave + li;
+  uint4 ah[8], al[8];  // eight BF16 per step, packed
+#pragma unroll
+  for (int st = 0; st < 8; ++st) {
+    float x[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const int k = 16 * st + 8 * h + e;  // < 2 q
+      const int part = k >= q, kk = part ? k - q : k;
+      const bool ok = st < nsteps && kk < l && xrow < n1;
+      x[e] = ok ? X[(part ? n1 : 0) + xrow + (int64_t)kk * ldx] : 0.0f;
+    }
+    split_bf16x2(x[0], x[1], ah[st].x, al[st].x);
+    split_bf16x2(x[2], x[3], ah[st].y, al[st].y);
+    split_bf16x2(x[4], x[5], ah[st].z, al[st].z);
+    split_bf16x2(x[6], x[7], ah[st].w, al[st].w);
+  }
+  // ---- staging of E1 for one column tile: unit = (column c, k group of 8) ----
+  // E1[k][c] = Btr(c, k) for k < q, Bti(c, k - q) after (zero past l)
+  auto stage = [&](int ct) {
+    const int col0 = 64 * ct;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int f = tid + 256 * u;
+      const int c = f % 64, g = f / 64;  // g < 16: k = 8 g .. 8 g + 7
+      const int gc = col0 + c;
+      float v[8];
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const int k = 8 * g + e, part = k >= q, kk = part ? k - q : k;
+        const bool ok = 8 * g < 2 * q && kk < l && gc < n2;
+        v[e] = ok ? W[(part ? n2 : 0) + gc + (int64_t)kk * 2 * n2] : 0.0f;
+      }
+      uint4 vh, vl;
+      split_bf16x2(v[0], v[1], vh.x, vl.x);
+      split_bf16x2(v[2], v[3], vh.y, vl.y);
+      split_bf16x2(v[4], v[5], vh.z, vl.z);
+      split_bf16x2(v[6], v[7], vh.w, vl.w);
+      *reinterpret_cast<uint4*>(Eh + c * kXPitch + 8 * g) = vh;
+      *reinterpret_cast<uint4*>(El + c * kXPitch + 8 * g) = vl;
+    }
+  };
+  const bool vecc = aligned && d.a % 4 == 0 && n1 % 4 == 0;
+  for (int ct = ct_begin; ct < ct_end; ++ct) {
+    const int col0 = 64 * ct;
+    if (ct > ct_begin) __syncthreads();  // the previous tile's operands are no longer read
+    stage(ct);
+    __syncthreads();
+    f32x16 acr[2], aci[2];
+#pragma unroll
+    for (int cb = 0; cb < 2; ++cb)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acr[cb][r] = aci[cb][r] = 0.0f;
+    const bool two = col0 + 32 < n2;
+#pragma unroll
+    for (int st = 0; st < 8; ++st) {
+      if (st >= nsteps) break;
+      const int k1 = 16 * st + 8 * h;  // this lane's k (E1), and its E2 source in the other half
+      const bool first = k1 < q;
+      const int k2 = first ? k1 + q : k1 - q;
+      const unsigned short flip = first ? 0x8000u : 0u;
+      const bf16x8 xa = __builtin_bit_cast(bf16x8, ah[st]), xb = __builtin_bit_cast(bf16x8, al[st]);
+#pragma unroll
+      for (int cb = 0; cb < 2; ++cb) {
+        if (cb == 1 && !two) break;
+        const int c = 32 * cb + li;
+        const bf16x8 e1h = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u16x8*>(Eh + c * kXPitch + k1));
+        const bf16x8 e1l = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u16x8*>(El + c * kXPitch + k1));
+        const bf16x8 e2h =
+            __builtin_bit_cast(bf16x8, *reinterpret_cast<const u16x8*>(Eh + c * kXPitch + k2) ^ flip);
+        const bf16x8 e2l =
+            __builtin_bit_cast(bf16x8, *reinterpret_cast<const u16x8*>(El + c * kXPitch + k2) ^ flip);
+        acr[cb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xa, e1h, acr[cb], 0, 0, 0);
+        aci[cb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xa, e2h, aci[cb], 0, 0, 0);
+        acr[cb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xa, e1l, acr[cb], 0, 0, 0);
+        aci[cb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xa, e2l, aci[cb], 0, 0, 0);
+        acr[cb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xb, e1h, acr[cb], 0, 0, 0);
+        aci[cb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xb, e2h, aci[cb], 0, 0, 0);
+      }
+    }
+    // ---- store: 16-byte column segments straight from the accumulators ----
+    auto put = [&](const f32x16& acc, int cb, int part) {
+      const int col = col0 + 32 * cb + li;
+      if (col >= n2) return;
+      float* dst = C + (part ? n1 : 0) + (int64_t)col * ldx;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int rb = row0 + 32 * wave + 8 * j + 4 * h;
+        if (vecc && rb + 3 < n1) {
+          *reinterpret_cast<f32x4*>(dst + rb) = f32x4{acc[4 * j], acc[4 * j + 1], acc[4 * j + 2], acc[4 * j + 3]};
+        } else {
+#pragma unroll
+          for (int e = 0; e < 4; ++e)
+            if (rb + e < n1) dst[rb + e] = acc[4 * j + e];
+        }
+      }
+    };
+    put(acr[0], 0, 0);
+    put(aci[0], 0, 1);
+    if (two) {
+      put(acr[1], 1, 0);
+      put(aci[1], 1, 1);
+    }
+  }
+}
+
 template <int NB, int NW, bool TRANS, bool CPLX = false>
 int launch_thin_bf16(const uint16_t* A, const float* W, float* Y, const SliceDesc* sd, const int2* wk,
                      const int2* items, int nitems, double* gpart, hipStream_t s, int wreal = 0) {
@@ -514,6 +664,18 @@ int launch_bf16_ctn(const uint16_t* A, const float* Q, float* Z, const SliceDesc
   if (lmax > kMaxComplexWidth) HT_FAIL(HT_ERR_UNSUPPORTED, "complex sketch width above 64");
   if (lmax <= 32) return launch_cthin_bf16<1, true>(A, Q, Z, sd, wk, items, nitems, gpart, s, 0);
   return launch_cthin_bf16<2, true>(A, Q, Z, sd, wk, items, nitems, gpart, s, 0);
+}
+
+int launch_bf16x3_cnt(const float* X, const float* W, float* C, const SliceDesc* sd, const int2* wk,
+                      const int2* items, int nitems, int lmax, hipStream_t s) {
+  if (lmax > kMaxComplexWidth) HT_FAIL(HT_ERR_UNSUPPORTED, "complex sketch width above 64");
+  if (nitems == 0) return HT_OK;
+  int rc = ensure_dynamic_lds((const void*)k_cmul_bf16x3, kX3Lds);
+  if (rc) return rc;
+  const int aligned = reinterpret_cast<uintptr_t>(C) % 16 == 0;
+  hipLaunchKernelGGL(k_cmul_bf16x3, dim3((unsigned)nitems), dim3(256), kX3Lds, s, X, W, C, sd, wk, items, aligned);
+  HT_CHECK_LAUNCH();
+  return HT_OK;
 }
 
 int launch_bf16_tn(const uint16_t* A, const float* Q, float* Z, const SliceDesc* sd, const int2* wk,
