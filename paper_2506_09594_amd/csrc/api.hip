@@ -480,6 +480,7 @@ int upload_tensors(ht_plan* pl, const std::vector<int>& tps) {
     d.cmap = th.cmap;
     d.cplx = th.cplx;
     d.n1 = (int32_t)th.n1;
+    d.nslots = (int32_t)th.nslots;
     d.P = (int32_t)th.P;
     d.TP = tps[t];
     int lg = 0;
@@ -598,7 +599,7 @@ int build_plan(const ht_plan_desc* descs, int n, bool batch, ht_plan** out) {
       // slot map: the canonical member of every conjugate pair (partner index =
       // every transform-domain index negated modulo n_k) gets a slot
       th.cmap = (int64_t)cmap.size();
-      cmap.resize(cmap.size() + th.P);
+      cmap.resize(cmap.size() + 3 * th.P);  // slot per slice, then (slice, partner) per slot
       int32_t* cm = cmap.data() + th.cmap;
       int64_t slots = 0;
       for (int64_t j = 0; j < th.P; ++j) {
@@ -610,12 +611,15 @@ int build_plan(const ht_plan_desc* descs, int n, bool batch, ht_plan** out) {
           stride *= nm;
         }
         if (pj >= j) {
+          cm[th.P + 2 * slots] = (int32_t)j;
+          cm[th.P + 2 * slots + 1] = pj == j ? -1 : (int32_t)pj;
           cm[j] = (int32_t)slots++;
         } else {
           cm[j] = (int32_t)(cm[pj] | (int32_t)0x80000000u);
         }
       }
       th.nslots = slots;
+      cmap.resize(th.cmap + th.P + 2 * slots);
     }
     th.a = Atot;
     Atot += th.nslots * f * th.n1 * th.n2;

@@ -40,6 +40,8 @@ struct TensorDesc {
   int32_t slice0; // index of its first slice in the slice table
   int32_t cplx;   // unitary DFT on every transformed mode (complex slices)
   int32_t n1;
+  int32_t nslots; // stored slots (complex: one per conjugate pair; the slot map
+                  // is followed by (canonical slice, partner or -1) per slot)
   ModeTable fwd, inv;  // complex matrices (interleaved re, im) when cplx
 };
 

@@ -573,6 +573,7 @@ __global__ __launch_bounds__(256, sizeof(T) == 4 ? 2 : 1) void k_transform_cplx(
     int64_t NT, t0;
     int64_t sbase;  // offset in a stacked slot of the first tube position
     int P, TP, lgTP, n1, tp, total, nv;
+    int nvl;           // vector accesses of the loads (inverse: over the stored slots)
     bool vec, onecol;  // onecol: the tile's tube positions share one slice column
   };
   // offset in a stacked slot [Re; Im] (2 n1 x n2) of tube position t0 + t
@@ -595,6 +596,7 @@ __global__ __launch_bounds__(256, sizeof(T) == 4 ? 2 : 1) void k_transform_cplx(
     c.tp = rem < c.TP ? (int)rem : c.TP;
     c.total = c.TP * c.P;
     c.nv = c.total / V;
+    c.nvl = (inverse ? c.TP * c.td->nslots : c.total) / V;
     // V consecutive tube positions of one slice are V consecutive rows of one
     // column of the slice (and of its slot) when these hold
     c.vec = aligned && c.TP % V == 0 && c.NT % V == 0 && c.n1 % V == 0 && c.td->x % V == 0 && c.td->a % V == 0;
@@ -604,25 +606,22 @@ __global__ __launch_bounds__(256, sizeof(T) == 4 ? 2 : 1) void k_transform_cplx(
     return c;
   };
   VT rr[UNR], ri[inverse ? UNR : 1];
-  bool cj[inverse ? UNR : 1];
-  // one batch of vector loads (vector tiles only): the UNR accesses from v0
+  // one batch of vector loads (vector tiles only): the UNR accesses from v0;
+  // inverse: access vi covers V tube positions of stored slot vi V / TP, read
+  // once and placed in the tile for both members of its conjugate pair
   auto issue = [&](const Tile& c, int v0) {
-    const int32_t* cmap = cmap_all + c.td->cmap;
 #pragma unroll
     for (int u = 0; u < UNR; ++u) {
       const int vi = v0 + u * nt, idx = vi * V;
       const int j = idx >> c.lgTP, t = idx & (c.TP - 1);
-      const bool ok = vi < c.nv && t < c.tp;
+      const bool ok = vi < c.nvl && t < c.tp;
       if constexpr (!inverse) {
         const T* in = in_all + c.td->x;
         rr[u] = ok ? *reinterpret_cast<const VT*>(in + (int64_t)j * c.NT + c.t0 + t) : VT{};
       } else {
-        const T* C = in_all + c.td->a;  // slots [Re; Im], 2 NT each
-        const int32_t code = ok ? cmap[j] : 0;
-        const T* S = C + (int64_t)(code & 0x7fffffff) * 2 * c.NT + slot_off(c, t);
+        const T* S = in_all + c.td->a + (int64_t)(ok ? j : 0) * 2 * c.NT + slot_off(c, t);  // slots [Re; Im]
         rr[u] = ok ? *reinterpret_cast<const VT*>(S) : VT{};
         ri[u] = ok ? *reinterpret_cast<const VT*>(S + c.n1) : VT{};
-        cj[u] = code < 0;  // conjugate partner
       }
     }
   };
@@ -631,12 +630,21 @@ __global__ __launch_bounds__(256, sizeof(T) == 4 ? 2 : 1) void k_transform_cplx(
 #pragma unroll
     for (int u = 0; u < UNR; ++u) {
       const int vi = v0 + u * nt;
-      if (vi < c.nv) {
-        *reinterpret_cast<VT*>(re + vi * V) = rr[u];
-        if constexpr (inverse)
-          *reinterpret_cast<VT*>(im + vi * V) = cj[u] ? -ri[u] : ri[u];
-        else
+      if (vi < c.nvl) {
+        if constexpr (inverse) {
+          const int idx = vi * V, slot = idx >> c.lgTP, t = idx & (c.TP - 1);
+          const int32_t* smap = cmap_all + c.td->cmap + c.P + 2 * slot;
+          const int j = smap[0], jp = smap[1];
+          *reinterpret_cast<VT*>(re + j * c.TP + t) = rr[u];
+          *reinterpret_cast<VT*>(im + j * c.TP + t) = ri[u];
+          if (jp >= 0) {  // the conjugate partner
+            *reinterpret_cast<VT*>(re + jp * c.TP + t) = rr[u];
+            *reinterpret_cast<VT*>(im + jp * c.TP + t) = -ri[u];
+          }
+        } else {
+          *reinterpret_cast<VT*>(re + vi * V) = rr[u];
           *reinterpret_cast<VT*>(im + vi * V) = VT{};
+        }
       }
     }
   };
@@ -650,7 +658,7 @@ __global__ __launch_bounds__(256, sizeof(T) == 4 ? 2 : 1) void k_transform_cplx(
     // ---- load: the batch in flight, then any further batches ------------------
     if (cur.vec) {
       stash(cur, tid);
-      for (int v0 = tid + UNR * nt; v0 < cur.nv; v0 += UNR * nt) {
+      for (int v0 = tid + UNR * nt; v0 < cur.nvl; v0 += UNR * nt) {
         issue(cur, v0);
         stash(cur, v0);
       }
