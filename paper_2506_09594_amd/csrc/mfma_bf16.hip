@@ -298,7 +298,37 @@ __global__ __launch_bounds__(2 * MT) void k_cthin_bf16(const uint16_t* __restric
   constexpr int NWB = (LW * KC / 4 + NTH - 1) / NTH;  // float4 groups of one thin chunk per thread
   u16x8 ra0[NRA], ra1[NRA];
   f32x4 rw0[2][NWB], rw1[2][NWB];
+  // interior chunks of a tile whose rows are all valid take plain loads
+  const bool rowsA = vecA && vecW && r0 + 64 <= mo;
   auto fetch = [&](u16x8 (&ra)[NRA], f32x4 (&rw)[2][NWB], int k0) {
+    if (rowsA && k0 + KC <= K) {
+#pragma unroll
+      for (int u = 0; u < NRA; ++u) {
+        const uint16_t* src;
+        if (!TRANS) {
+          const int row = (tid / 16) * 8;
+          src = Aj + ((row & 64) ? n1 : 0) + crow(row) + (int64_t)(k0 + 2 * (tid % 16) + u) * lda;
+        } else {
+          const int g = tid + u * NTH;
+          const int row = g / (KC / 8), kk = (g % (KC / 8)) * 8;
+          src = Aj + ((row & 64) ? n1 : 0) + k0 + kk + (int64_t)crow(row) * lda;
+        }
+        ra[u] = *reinterpret_cast<const u16x8*>(src);
+      }
+#pragma unroll
+      for (int part = 0; part < 2; ++part)
+#pragma unroll
+        for (int u = 0; u < NWB; ++u) {
+          const int f = tid + u * NTH;
+          const int c = f / (KC / 4), k4 = (f % (KC / 4)) * 4;
+          const bool live = (part == 0 || two) && f < LW * KC / 4 && c < l;
+          // a lane with nothing to load reads column 0 of the real part (always valid)
+          const float* src = Wj + (live && part ? wim : 0) + k0 + k4 + (int64_t)(live ? c : 0) * ldw;
+          const f32x4 v = *reinterpret_cast<const f32x4*>(src);
+          rw[part][u] = live ? v : f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+        }
+      return;
+    }
 #pragma unroll
     for (int u = 0; u < NRA; ++u) {
       u16x8 v;
