@@ -182,7 +182,10 @@ int ht_plan_info(const ht_plan* plan, int64_t* n_slices, int* width, int* kept);
  * 18 ||A_j||^2 (previous, current; P x 2 doubles), 19 features (P x 32
  * floats), 20 state (ints: history valid, predicted slices, redone slices),
  * 21 non-finite flags (P ints), 22 RSE partial sums, 23 squared group norms
- * of the tube-wise / slice-wise solver update.  Thin blocks of slice j start at
+ * of the tube-wise / slice-wise solver update, and, for BF16-mixed plans
+ * with complex slices only (zero bytes otherwise), BF16 copies of the thin
+ * operands of the complex products: 24 Omega, 25 the latest left basis Q,
+ * 26 the latest right basis (n2 x l per slice).  Thin blocks of slice j start at
  * j * align4(rows * l) elements (align4 rounds up to a multiple of 4).  A
  * complex slice keeps its real and imaginary parts stacked: A and C blocks of
  * 2 n1 x n2, thin blocks of 2 rows x l, K' of 2 l x l (column-major). */

@@ -49,7 +49,8 @@ using namespace ht;
 
 // Named regions of the workspace (for introspection by the tests).
 enum { WS_A = 0, WS_OMEGA, WS_Y, WS_Z, WS_K, WS_QK, WS_C, WS_LNEW, WS_XIN, WS_STATE, WS_GP1, WS_GP2, WS_WK, WS_CALL,
-       WS_WK2, WS_WKF, WS_SIG, WS_KEPT, WS_ANORM, WS_FEAT, WS_LSTATE, WS_STATUS, WS_RED, WS_GSQ, WS_COUNT };
+       WS_WK2, WS_WKF, WS_SIG, WS_KEPT, WS_ANORM, WS_FEAT, WS_LSTATE, WS_STATUS, WS_RED, WS_GSQ, WS_OMH, WS_YH,
+       WS_ZH, WS_COUNT };
 
 // Block partials of the RSE reduction of the solver (two doubles per block).
 constexpr int kRseBlocks = 1024;
@@ -541,13 +542,19 @@ void layout(ht_plan* pl, int64_t nY, int64_t nZ, int64_t nK, int64_t nG1, int64_
     for (const TensorHost& th : pl->tens) g = std::max<int64_t>(g, std::max<int64_t>(th.n1 * th.n2, th.P));
     pl->size[WS_GSQ] = (size_t)g * sizeof(double);
   }
+  {  // BF16 copies of the thin operands of the complex BF16 products (Omega, Q, Z)
+    const bool h = pl->cplx && pl->precision == HT_BF16_MIXED;
+    pl->size[WS_OMH] = h ? (size_t)nZ * 2 : 0;
+    pl->size[WS_YH] = h ? (size_t)nY * 2 : 0;
+    pl->size[WS_ZH] = h ? (size_t)nZ * 2 : 0;
+  }
   pl->size[WS_LNEW] = (size_t)pl->Ntot * es;
   pl->size[WS_XIN] = (size_t)pl->Ntot * es;
   pl->size[WS_STATE] = sizeof(AdmmState);
   // t-SVT regions first, then the solver-only regions
-  const int order_[] = {WS_A,   WS_OMEGA, WS_Y,    WS_Z,    WS_K,     WS_QK,   WS_C,      WS_GP1,  WS_GP2,
-                        WS_WK,  WS_CALL,  WS_WK2,  WS_WKF,  WS_SIG,   WS_KEPT, WS_ANORM,  WS_FEAT, WS_LSTATE,
-                        WS_STATUS, WS_LNEW, WS_XIN, WS_STATE, WS_RED, WS_GSQ};
+  const int order_[] = {WS_A,     WS_OMEGA, WS_Y,    WS_Z,    WS_K,     WS_QK,   WS_C,      WS_GP1,  WS_GP2,
+                        WS_WK,    WS_CALL,  WS_WK2,  WS_WKF,  WS_SIG,   WS_KEPT, WS_ANORM,  WS_FEAT, WS_LSTATE,
+                        WS_OMH,   WS_YH,    WS_ZH,   WS_STATUS, WS_LNEW, WS_XIN, WS_STATE, WS_RED, WS_GSQ};
   size_t o = 0;
   for (int r : order_) {
     pl->off[r] = o;
@@ -864,6 +871,10 @@ int run_tsvt(const ht_plan* pl, const T* X, T* out, double tau, const double* ta
   double* gp1 = ws_ptr<double>(pl, ws, WS_GP1);
   double* gp2 = ws_ptr<double>(pl, ws, WS_GP2);
   const bool bf16 = pl->precision == HT_BF16_MIXED;
+  // BF16 copies of the complex BF16 products' thin operands (null elsewhere)
+  uint16_t* Omh = (bf16 && pl->cplx) ? ws_ptr<uint16_t>(pl, ws, WS_OMH) : nullptr;
+  uint16_t* Yh = (bf16 && pl->cplx) ? ws_ptr<uint16_t>(pl, ws, WS_YH) : nullptr;
+  uint16_t* Zh = (bf16 && pl->cplx) ? ws_ptr<uint16_t>(pl, ws, WS_ZH) : nullptr;
   const bool fp64 = pl->precision == HT_FP64;
   const uint16_t* Ah = reinterpret_cast<const uint16_t*>(A);  // BF16 view of the transformed tensor
   const int rows = fp64 ? 64 : pl->prod_rows;
@@ -912,8 +923,8 @@ int run_tsvt(const ht_plan* pl, const T* X, T* out, double tau, const double* ta
   const OmegaKey okey{call, call_dev, pl->stream_id, pl->seed};
   const bool om_inline = !fp64 && pl->nn_stream;
   if (!om_inline && (rc = timed(pl, ST_OMEGA, s, [&] {
-                       return launch_omega<T>(Om, nullptr, sd, nullptr, P, pl->max_n2l, call, call_dev, pl->stream_id,
-                                              pl->seed, 0, s);
+                       return launch_omega<T>(Om, nullptr, Omh, sd, nullptr, P, pl->max_n2l, call, call_dev,
+                                              pl->stream_id, pl->seed, 0, s);
                      })))
     return rc;
   const bool cplx = pl->cplx;
@@ -922,7 +933,7 @@ int run_tsvt(const ht_plan* pl, const T* X, T* out, double tau, const double* ta
       if (cplx) {  // items of 64 complex rows
         const ItemList& L = pl->it_nn[0];
         if (bf16)
-          return launch_bf16_cnn(Ah, (const float*)W, (float*)Y, W == Om, sd, wk, items(pl, pl->it_cp[0]),
+          return launch_bf16_cnn(Ah, W == Om ? Omh : Zh, (float*)Y, W == Om, sd, wk, items(pl, pl->it_cp[0]),
                                  pl->it_cp[0].n, lmax, gp1, s);
         if (!fp64)
           return launch_mfma_cnn((const float*)A, (const float*)W, (float*)Y, W == Om, sd, wk, items(pl, L), L.n,
@@ -946,7 +957,7 @@ int run_tsvt(const ht_plan* pl, const T* X, T* out, double tau, const double* ta
       if (cplx) {
         const ItemList& L = pl->it_tn[0];
         if (bf16)
-          return launch_bf16_ctn(Ah, (const float*)Y, (float*)Z, sd, wk, items(pl, pl->it_cp[1]), pl->it_cp[1].n,
+          return launch_bf16_ctn(Ah, Yh, (float*)Z, sd, wk, items(pl, pl->it_cp[1]), pl->it_cp[1].n,
                                  lmax, gp1, s);
         if (!fp64)
           return launch_mfma_ctn((const float*)A, (const float*)Y, (float*)Z, sd, wk, items(pl, L), L.n, lmax, gp1,
@@ -966,8 +977,8 @@ int run_tsvt(const ht_plan* pl, const T* X, T* out, double tau, const double* ta
       if (cplx) {
         const ItemList& L = which ? pl->it_oz : pl->it_oy;
         const ItemList& S = which ? pl->it_asz : pl->it_asy;
-        return launch_corth<T>(which ? Z : Y, which, sd, wk, items(pl, L), L.n, items(pl, S), S.n, lmax, P, gp1, gout,
-                               s);
+        return launch_corth<T>(which ? Z : Y, which ? Zh : Yh, which, sd, wk, items(pl, L), L.n, items(pl, S), S.n,
+                               lmax, P, gp1, gout, s);
       }
       if (wk == nullptr && pl->class_split) {  // one launch per width class
         for (int c = 0; c < kNumClasses; ++c) {
@@ -1478,8 +1489,8 @@ int ht_omega_fp64(const ht_plan* pl, uint32_t call_index, double* dev_out, void*
   if (!pl || !dev_out) HT_FAIL(HT_ERR_INVALID_ARG, "plan/out is NULL");
   if (pl->batch || pl->cplx) HT_FAIL(HT_ERR_UNSUPPORTED, "ht_omega_fp64 takes a single-tensor real plan");
   const TensorHost& th = pl->tens[0];
-  return launch_omega<double>(nullptr, dev_out, pl->d_slices, nullptr, (int)pl->Ptot, pl->max_n2l, call_index, nullptr,
-                              pl->stream_id, pl->seed, th.n2 * th.l, static_cast<hipStream_t>(stream));
+  return launch_omega<double>(nullptr, dev_out, nullptr, pl->d_slices, nullptr, (int)pl->Ptot, pl->max_n2l, call_index,
+                              nullptr, pl->stream_id, pl->seed, th.n2 * th.l, static_cast<hipStream_t>(stream));
 }
 
 int ht_transform(const ht_plan* pl, const void* X, void* out, int inverse, void* stream) {

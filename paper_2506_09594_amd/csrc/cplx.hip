@@ -325,8 +325,9 @@ size_t cfactor_lds_bytes(int l) { return (2 * (size_t)l * (l + 1) + (size_t)l + 
 // rows, then their imaginary parts, FP32 as stored) for coalesced column
 // stores and, optionally, the complex Gram partial of the stored rows.
 template <typename T, int LB>
-__global__ __launch_bounds__(256) void k_corth_apply(T* __restrict__ Yall, int which, const SliceDesc* __restrict__ sd,
-                                                     const int2* __restrict__ wk, const int2* __restrict__ items,
+__global__ __launch_bounds__(256) void k_corth_apply(T* __restrict__ Yall, uint16_t* __restrict__ Yhall, int which,
+                                                     const SliceDesc* __restrict__ sd, const int2* __restrict__ wk,
+                                                     const int2* __restrict__ items,
                                                      const double* __restrict__ gin_all,
                                                      double* __restrict__ gout_all) {
   constexpr int NCB = LB / 8;     // 16-column blocks of the 2 l <= 2 LB result columns
@@ -415,7 +416,12 @@ __global__ __launch_bounds__(256) void k_corth_apply(T* __restrict__ Yall, int w
   const int rows = min(64, m - r0);
   for (int idx = threadIdx.x; idx < 2 * 64 * l; idx += 256) {
     const int row = idx % 64, pc = idx / 64, part = pc / l, c = pc % l;
-    if (row < rows) Y[(part ? m : 0) + r0 + row + (int64_t)c * ld] = S[(part * 64 + row) * SP + c];
+    if (row < rows) {
+      const int64_t o = (part ? m : 0) + r0 + row + (int64_t)c * ld;
+      Y[o] = S[(part * 64 + row) * SP + c];
+      if (Yhall)
+        Yhall[(which ? d.z : d.y) + o] = (uint16_t)(f32x2_to_bf16x2((float)S[(part * 64 + row) * SP + c], 0.0f) & 0xffffu);
+    }
   }
   if (gout_all) tile_cgram_mfma(S, SP, 1, l, gout_all + d.g2 + (int64_t)(r0 / kGramRows) * 2 * ll);
 }
@@ -428,14 +434,18 @@ __global__ __launch_bounds__(256) void k_corth_apply(T* __restrict__ Yall, int w
 // sign and triangular skip are uniform across the wavefront.  Wavefront w owns
 // rows 16 w .. 16 w + 15 of each tile and holds them as the A operands
 // (k = 4 st + t / 16: real parts for st < 16, imaginary parts after); the next
-// tile's rows load while the current one is multiplied, and the result goes
-// straight from the accumulators to Y (rows 4 v + t / 16 of column t % 16 in
-// accumulator v).  Each wavefront reads and then overwrites only its own rows.
+// tile's rows load while the current one is multiplied.  The product is
+// taken transposed (E block as the A operand, the rows as the B operand), so
+// accumulator v of lane t holds row t % 16 of column 4 v + t / 16 of its
+// block: the result goes straight from the accumulators to Y as runs of 16
+// consecutive rows per column, and an optional BF16 copy as pairs of rows
+// joined across neighbouring lanes.  Each wavefront reads and then overwrites
+// only its own rows.
 constexpr int kApplyPitch = 72;  // doubles per LDS row of a plane
 constexpr size_t kApplyLds = 2 * 64 * kApplyPitch * sizeof(double);
 
-__global__ __launch_bounds__(256, 2) void k_corth_apply_tiles(float* __restrict__ Yall, int which,
-                                                              const SliceDesc* __restrict__ sd,
+__global__ __launch_bounds__(256, 2) void k_corth_apply_tiles(float* __restrict__ Yall, uint16_t* __restrict__ Yhall,
+                                                              int which, const SliceDesc* __restrict__ sd,
                                                               const int2* __restrict__ wk,
                                                               const int2* __restrict__ tiles, int ntiles,
                                                               const double* __restrict__ gin_all) {
@@ -446,7 +456,7 @@ __global__ __launch_bounds__(256, 2) void k_corth_apply_tiles(float* __restrict_
   const int t_end = (int)((int64_t)(blockIdx.x + 1) * ntiles / gridDim.x);
   const int tid = threadIdx.x;
   const int lane = tid & 63, w = tid >> 6, li = lane & 15, lq = lane >> 4;
-  // A operands of tile t: rows 16 w + li, k = 4 (st mod 16) + t / 16 of part st / 16
+  // B operands of tile t: rows 16 w + li, k = 4 (st mod 16) + t / 16 of part st / 16
   auto fetch = [&](int t, float (&dst)[32]) {
     const int2 it = tiles[t];
     const SliceDesc d = sd[it.x];
@@ -500,7 +510,6 @@ __global__ __launch_bounds__(256, 2) void k_corth_apply_tiles(float* __restrict_
     if (t + 1 < t_end) fetch(t + 1, an);
     if (l > 0) {
       const int m = which ? d.n2 : d.n1, ld = 2 * m;
-      float* Y = Yall + (which ? d.z : d.y);
       d4 acc[8];
 #pragma unroll
       for (int cb = 0; cb < 8; ++cb) acc[cb] = d4{0.0, 0.0, 0.0, 0.0};
@@ -517,18 +526,33 @@ __global__ __launch_bounds__(256, 2) void k_corth_apply_tiles(float* __restrict_
           const double* P = kp == cp ? Er : Ei;
           double b = P[(kq0 + lq) * kApplyPitch + cq0 + li];
           if (kp == 1 && cp == 0) b = -b;
-          acc[cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, b, acc[cb], 0, 0, 0);
+          acc[cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(b, av, acc[cb], 0, 0, 0);
         }
       }
-      const int rb = r0 + 16 * w + lq;
+      const int row = r0 + 16 * w + li;
+      const bool pairs = (m & 1) == 0;  // row pairs (2 j, 2 j + 1) are 4-byte aligned in the BF16 copy
 #pragma unroll
       for (int cb = 0; cb < 8; ++cb) {
-        const int cp = cb >> 2, cq = 16 * (cb & 3) + li;
-        if (cq < l) {
-          float* dst = Y + (cp ? m : 0) + (int64_t)cq * ld;
+        const int cp = cb >> 2, cq0 = 16 * (cb & 3);
+        if (cq0 >= l) continue;  // uniform
 #pragma unroll
-          for (int v = 0; v < 4; ++v)
-            if (rb + 4 * v < m) dst[rb + 4 * v] = (float)acc[cb][v];
+        for (int v = 0; v < 4; ++v) {
+          const int cq = cq0 + 4 * v + lq;
+          const int64_t o = (which ? d.z : d.y) + (cp ? m : 0) + (int64_t)cq * ld + row;
+          const float q = (float)acc[cb][v];
+          const bool ok = cq < l && row < m;
+          if (ok) Yall[o] = q;
+          if (Yhall) {
+            // every lane takes part in the exchange; even lanes store the pair
+            const float qn = __int_as_float(
+                __builtin_amdgcn_mov_dpp(__float_as_int(q), 0xb1, 0xf, 0xf, false));
+            if (pairs) {
+              if (ok && (li & 1) == 0)
+                *reinterpret_cast<uint32_t*>(Yhall + o) = f32x2_to_bf16x2(q, qn);
+            } else if (ok) {
+              Yhall[o] = (uint16_t)(f32x2_to_bf16x2(q, 0.0f) & 0xffffu);
+            }
+          }
         }
       }
     }
@@ -1291,7 +1315,7 @@ __global__ __launch_bounds__(256) void k_crecon(const T* __restrict__ Xall, cons
 }  // namespace
 
 template <typename T>
-int launch_corth(T* Y, int which, const SliceDesc* sd, const int2* wk, const int2* items, int nitems,
+int launch_corth(T* Y, uint16_t* Yh, int which, const SliceDesc* sd, const int2* wk, const int2* items, int nitems,
                  const int2* tiles, int ntiles, int lmax, int nslices, double* gin, double* gout, hipStream_t s) {
   if (lmax > kMaxComplexWidth) HT_FAIL(HT_ERR_UNSUPPORTED, "complex sketch width above 64");
   if (nitems == 0 || nslices == 0) return HT_OK;
@@ -1308,14 +1332,14 @@ int launch_corth(T* Y, int which, const SliceDesc* sd, const int2* wk, const int
     HT_CHECK_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
     const int grid = std::max(1, std::min(ntiles, std::max(per_cu, 1) * ncu));
     hipLaunchKernelGGL(k_corth_apply_tiles, dim3((unsigned)grid), dim3(256), kApplyLds, s, reinterpret_cast<float*>(Y),
-                       which, sd, wk, tiles, ntiles, gin);
+                       Yh, which, sd, wk, tiles, ntiles, gin);
     HT_CHECK_LAUNCH();
     return HT_OK;
   }
   auto apply = [&](auto kern, size_t lds) -> int {
     int r = ensure_dynamic_lds((const void*)kern, lds);
     if (r) return r;
-    hipLaunchKernelGGL(kern, dim3((unsigned)nitems), dim3(256), lds, s, Y, which, sd, wk, items, gin, gout);
+    hipLaunchKernelGGL(kern, dim3((unsigned)nitems), dim3(256), lds, s, Y, Yh, which, sd, wk, items, gin, gout);
     HT_CHECK_LAUNCH();
     return HT_OK;
   };
@@ -1373,10 +1397,10 @@ int launch_crecon(const T* X, const T* W, T* C, int mode, const SliceDesc* sd, c
   return HT_OK;
 }
 
-template int launch_corth<float>(float*, int, const SliceDesc*, const int2*, const int2*, int, const int2*, int, int,
-                                 int, double*, double*, hipStream_t);
-template int launch_corth<double>(double*, int, const SliceDesc*, const int2*, const int2*, int, const int2*, int, int,
-                                  int, double*, double*, hipStream_t);
+template int launch_corth<float>(float*, uint16_t*, int, const SliceDesc*, const int2*, const int2*, int, const int2*,
+                                 int, int, int, double*, double*, hipStream_t);
+template int launch_corth<double>(double*, uint16_t*, int, const SliceDesc*, const int2*, const int2*, int,
+                                  const int2*, int, int, int, double*, double*, hipStream_t);
 template int launch_csvd<float>(double*, const double*, const SliceDesc*, const int2*, const int2*, int, int, int,
                                 double, const double*, const double*, Penalty, float*, double*, int*, int*,
                                 hipStream_t);

@@ -62,12 +62,13 @@ template <typename T, typename TO>
 int launch_transform_cplx(const T* in, TO* out, const TensorDesc* tds, const int2* items, int nitems, size_t lds,
                           const T* table, const int32_t* cmap, int inverse, int nmax, hipStream_t s);
 
-// Gaussian sketch matrices of every slice (T storage and/or FP64 copy), at
-// the slices' Omega offsets, or densely at s * dense_stride when dense_stride > 0.
+// Gaussian sketch matrices of every slice (T storage, FP64 copy and/or the
+// BF16 rounding of the T values), at the slices' Omega offsets, or densely at
+// s * dense_stride when dense_stride > 0.
 template <typename T>
-int launch_omega(T* om, double* om64, const SliceDesc* sd, const int2* wk, int nslices, int64_t max_per_slice,
-                 uint32_t call, const int32_t* call_dev, uint32_t stream_base, uint64_t seed, int64_t dense_stride,
-                 hipStream_t s);
+int launch_omega(T* om, double* om64, uint16_t* omh, const SliceDesc* sd, const int2* wk, int nslices,
+                 int64_t max_per_slice, uint32_t call, const int32_t* call_dev, uint32_t stream_base, uint64_t seed,
+                 int64_t dense_stride, hipStream_t s);
 
 // Thin products on the vector ALUs (64-row tiles; Gram partials per tile).
 //   sketch nn: Y = A Omega or A Z;  tn: Z = A^T Q;  recon: QK = Q1 K', C = QK Bt^T.
@@ -127,9 +128,9 @@ int launch_mfma_cnn(const float* A, const float* W, float* Y, int wreal, const S
                     const int2* items, int nitems, int lmax, double* gpart, hipStream_t s);
 int launch_mfma_ctn(const float* A, const float* Q, float* Z, const SliceDesc* sd, const int2* wk, const int2* items,
                     int nitems, int lmax, double* gpart, hipStream_t s);
-int launch_bf16_cnn(const uint16_t* A, const float* W, float* Y, int wreal, const SliceDesc* sd, const int2* wk,
+int launch_bf16_cnn(const uint16_t* A, const uint16_t* W, float* Y, int wreal, const SliceDesc* sd, const int2* wk,
                     const int2* items, int nitems, int lmax, double* gpart, hipStream_t s);
-int launch_bf16_ctn(const uint16_t* A, const float* Q, float* Z, const SliceDesc* sd, const int2* wk,
+int launch_bf16_ctn(const uint16_t* A, const uint16_t* Q, float* Z, const SliceDesc* sd, const int2* wk,
                     const int2* items, int nitems, int lmax, double* gpart, hipStream_t s);
 int launch_mfma_cqk(const float* Q, const float* K, float* QK, const SliceDesc* sd, const int2* wk, const int2* items,
                     int nitems, int lmax, hipStream_t s);
@@ -174,9 +175,11 @@ int launch_smallsvd(double* g2, const double* gw, const SliceDesc* sd, const int
 // factor launch per slice (R^{-1} parked over the first partial of gin), then
 // Q = Y R^{-1} per 64-complex-row item; gout as launch_orth_apply.
 // FP32 blocks without gout take `tiles` instead: the same 64-row items in slice
-// order, split into contiguous ranges over resident workgroups.
+// order, split into contiguous ranges over resident workgroups.  Yh (nullable):
+// a BF16 copy of the result at the same element offsets (the operand of the
+// BF16 products that follow).
 template <typename T>
-int launch_corth(T* Y, int which, const SliceDesc* sd, const int2* wk, const int2* items, int nitems,
+int launch_corth(T* Y, uint16_t* Yh, int which, const SliceDesc* sd, const int2* wk, const int2* items, int nitems,
                  const int2* tiles, int ntiles, int lmax, int nslices, double* gin, double* gout, hipStream_t s);
 // Small SVD and shrinkage of complex slices (arguments as launch_smallsvd;
 // K' is written stacked, 2 l x l).

@@ -256,7 +256,7 @@ __global__ __launch_bounds__(64 * NW) void k_mfma_thin_bf16(const uint16_t* __re
 // Gram partial per 64 complex rows.
 template <int NB, int MT, bool TRANS>
 __global__ __launch_bounds__(2 * MT) void k_cthin_bf16(const uint16_t* __restrict__ Aall,
-                                                       const float* __restrict__ Wall, float* __restrict__ Yall,
+                                                       const uint16_t* __restrict__ Wall, float* __restrict__ Yall,
                                                        const SliceDesc* __restrict__ sd, const int2* __restrict__ wk,
                                                        const int2* __restrict__ items, double* __restrict__ gpart,
                                                        int aligned, int wreal) {
@@ -278,10 +278,10 @@ __global__ __launch_bounds__(2 * MT) void k_cthin_bf16(const uint16_t* __restric
   const bool two = TRANS || !wreal;         // the thin operand has an imaginary part
   const int64_t woff = TRANS ? d.y : d.z, yoff = TRANS ? d.z : d.y;
   const uint16_t* Aj = Aall + d.a;
-  const float* Wj = Wall + woff;
+  const uint16_t* Wj = Wall + woff;  // the thin operand as BF16 (rounded by its producer)
   float* Yj = Yall + yoff;
   const bool vecA = aligned && (d.a % 8 == 0) && (n1 % 8 == 0);
-  const bool vecW = aligned && (ldw % 4 == 0) && (woff % 4 == 0) && (wim % 4 == 0);
+  const bool vecW = aligned && (ldw % 8 == 0) && (woff % 8 == 0) && (wim % 8 == 0);
   const int tid = threadIdx.x, wave = tid / 64, lane = tid % 64;
   // complex row of tile row i, whether it holds an imaginary part, validity, stacked output row
   auto crow = [&](int i) -> int { return r0 + 64 * (i >> 7) + (i & 63); };
@@ -295,12 +295,12 @@ __global__ __launch_bounds__(2 * MT) void k_cthin_bf16(const uint16_t* __restric
   //   tn: group = 8 consecutive k (stored rows of Ar or Ai) of one column
   constexpr int NRA = MT * KC / 8 / NTH;
   static_assert(NRA == 2, "two groups of eight per thread");
-  constexpr int NWB = (LW * KC / 4 + NTH - 1) / NTH;  // float4 groups of one thin chunk per thread
+  constexpr int NWB = (LW * KC / 8 + NTH - 1) / NTH;  // groups of 8 BF16 of one thin chunk per thread
   u16x8 ra0[NRA], ra1[NRA];
-  f32x4 rw0[2][NWB], rw1[2][NWB];
+  u16x8 rw0[2][NWB], rw1[2][NWB];
   // interior chunks of a tile whose rows are all valid take plain loads
   const bool rowsA = vecA && vecW && r0 + 64 <= mo;
-  auto fetch = [&](u16x8 (&ra)[NRA], f32x4 (&rw)[2][NWB], int k0) {
+  auto fetch = [&](u16x8 (&ra)[NRA], u16x8 (&rw)[2][NWB], int k0) {
     if (rowsA && k0 + KC <= K) {
 #pragma unroll
       for (int u = 0; u < NRA; ++u) {
@@ -320,12 +320,12 @@ __global__ __launch_bounds__(2 * MT) void k_cthin_bf16(const uint16_t* __restric
 #pragma unroll
         for (int u = 0; u < NWB; ++u) {
           const int f = tid + u * NTH;
-          const int c = f / (KC / 4), k4 = (f % (KC / 4)) * 4;
-          const bool live = (part == 0 || two) && f < LW * KC / 4 && c < l;
+          const int c = f / (KC / 8), k8 = (f % (KC / 8)) * 8;
+          const bool live = (part == 0 || two) && f < LW * KC / 8 && c < l;
           // a lane with nothing to load reads column 0 of the real part (always valid)
-          const float* src = Wj + (live && part ? wim : 0) + k0 + k4 + (int64_t)(live ? c : 0) * ldw;
-          const f32x4 v = *reinterpret_cast<const f32x4*>(src);
-          rw[part][u] = live ? v : f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+          const uint16_t* src = Wj + (live && part ? wim : 0) + k0 + k8 + (int64_t)(live ? c : 0) * ldw;
+          const u16x8 v = *reinterpret_cast<const u16x8*>(src);
+          rw[part][u] = live ? v : u16x8{0, 0, 0, 0, 0, 0, 0, 0};
         }
       return;
     }
@@ -360,21 +360,21 @@ __global__ __launch_bounds__(2 * MT) void k_cthin_bf16(const uint16_t* __restric
 #pragma unroll
       for (int u = 0; u < NWB; ++u) {
         const int f = tid + u * NTH;
-        const int c = f / (KC / 4), k4 = (f % (KC / 4)) * 4;
-        const int gk = k0 + k4;
-        const float* src = Wj + (part ? wim : 0) + gk + (int64_t)c * ldw;
-        const bool live = (part == 0 || two) && f < LW * KC / 4 && c < l;
-        f32x4 v;
-        if (vecW && live && gk + 3 < K) {
-          v = *reinterpret_cast<const f32x4*>(src);
+        const int c = f / (KC / 8), k8 = (f % (KC / 8)) * 8;
+        const int gk = k0 + k8;
+        const uint16_t* src = Wj + (part ? wim : 0) + gk + (int64_t)c * ldw;
+        const bool live = (part == 0 || two) && f < LW * KC / 8 && c < l;
+        u16x8 v;
+        if (vecW && live && gk + 7 < K) {
+          v = *reinterpret_cast<const u16x8*>(src);
         } else {
 #pragma unroll
-          for (int e = 0; e < 4; ++e) v[e] = (live && gk + e < K) ? src[e] : 0.0f;
+          for (int e = 0; e < 8; ++e) v[e] = (live && gk + e < K) ? src[e] : (unsigned short)0;
         }
         rw[part][u] = v;
       }
   };
-  auto stash = [&](const u16x8 (&ra)[NRA], const f32x4 (&rw)[2][NWB], int buf) {
+  auto stash = [&](const u16x8 (&ra)[NRA], const u16x8 (&rw)[2][NWB], int buf) {
     uint16_t* As = lds_h + buf * BUF;
     if (!TRANS) {
       const int row = (tid / 16) * 8, kk = 2 * (tid % 16);
@@ -398,10 +398,12 @@ __global__ __launch_bounds__(2 * MT) void k_cthin_bf16(const uint16_t* __restric
 #pragma unroll
       for (int u = 0; u < NWB; ++u) {
         const int f = tid + u * NTH;
-        if (f < LW * KC / 4) {
-          const int c = f / (KC / 4), k4 = (f % (KC / 4)) * 4;
-          *reinterpret_cast<uint2*>(Ws + c * KPC + k4) = make_uint2(f32x2_to_bf16x2(rw[part][u][0], rw[part][u][1]),
-                                                                    f32x2_to_bf16x2(rw[part][u][2], rw[part][u][3]));
+        if (f < LW * KC / 8) {
+          const int c = f / (KC / 8), k8 = (f % (KC / 8)) * 8;
+          uint2* dst = reinterpret_cast<uint2*>(Ws + c * KPC + k8);
+          const uint4 w = __builtin_bit_cast(uint4, rw[part][u]);
+          dst[0] = make_uint2(w.x, w.y);
+          dst[1] = make_uint2(w.z, w.w);
         }
       }
     }
@@ -482,7 +484,7 @@ __global__ __launch_bounds__(2 * MT) void k_cthin_bf16(const uint16_t* __restric
 }
 
 template <int NB, bool TRANS>
-int launch_cthin_bf16(const uint16_t* A, const float* W, float* Y, const SliceDesc* sd, const int2* wk,
+int launch_cthin_bf16(const uint16_t* A, const uint16_t* W, float* Y, const SliceDesc* sd, const int2* wk,
                       const int2* items, int nitems, double* gpart, hipStream_t s, int wreal) {
   constexpr int MT = 2 * kCplxProdRows;
   constexpr size_t main = 2 * (size_t)(MT * KPC + 2 * 32 * NB * KPC) * 2, epi = MT * (size_t)(32 * NB + 1) * 4;
@@ -682,14 +684,14 @@ int launch_bf16_nn(const uint16_t* A, const float* W, float* Y, const SliceDesc*
   return dispatch_bf16<false>(A, W, Y, sd, wk, items, nitems, lmax, rows, gpart, s);
 }
 
-int launch_bf16_cnn(const uint16_t* A, const float* W, float* Y, int wreal, const SliceDesc* sd, const int2* wk,
+int launch_bf16_cnn(const uint16_t* A, const uint16_t* W, float* Y, int wreal, const SliceDesc* sd, const int2* wk,
                     const int2* items, int nitems, int lmax, double* gpart, hipStream_t s) {
   if (lmax > kMaxComplexWidth) HT_FAIL(HT_ERR_UNSUPPORTED, "complex sketch width above 64");
   if (lmax <= 32) return launch_cthin_bf16<1, false>(A, W, Y, sd, wk, items, nitems, gpart, s, wreal);
   return launch_cthin_bf16<2, false>(A, W, Y, sd, wk, items, nitems, gpart, s, wreal);
 }
 
-int launch_bf16_ctn(const uint16_t* A, const float* Q, float* Z, const SliceDesc* sd, const int2* wk,
+int launch_bf16_ctn(const uint16_t* A, const uint16_t* Q, float* Z, const SliceDesc* sd, const int2* wk,
                     const int2* items, int nitems, int lmax, double* gpart, hipStream_t s) {
   if (lmax > kMaxComplexWidth) HT_FAIL(HT_ERR_UNSUPPORTED, "complex sketch width above 64");
   if (lmax <= 32) return launch_cthin_bf16<1, true>(A, Q, Z, sd, wk, items, nitems, gpart, s, 0);

@@ -877,9 +877,10 @@ template int launch_transform<float, uint16_t>(const float*, uint16_t*, const Te
 // ---------------------------------------------------------------------------
 template <typename T>
 __global__ __launch_bounds__(256) void k_omega(T* __restrict__ om, double* __restrict__ om64,
-                                               const SliceDesc* __restrict__ sd, const int2* __restrict__ wk,
-                                               uint32_t call, const int32_t* __restrict__ call_dev,
-                                               uint32_t stream_base, uint64_t seed, int64_t dense_stride) {
+                                               uint16_t* __restrict__ omh, const SliceDesc* __restrict__ sd,
+                                               const int2* __restrict__ wk, uint32_t call,
+                                               const int32_t* __restrict__ call_dev, uint32_t stream_base,
+                                               uint64_t seed, int64_t dense_stride) {
   const int s = blockIdx.x;
   const SliceDesc d = sd[s];
   const int64_t base = dense_stride > 0 ? (int64_t)s * dense_stride : d.z;
@@ -896,27 +897,28 @@ __global__ __launch_bounds__(256) void k_omega(T* __restrict__ om, double* __res
       if (e < per_slice) {
         if (om) om[base + e] = (T)z[lane];
         if (om64) om64[base + e] = z[lane];
+        if (omh) omh[base + e] = (uint16_t)(f32x2_to_bf16x2((float)(T)z[lane], 0.0f) & 0xffffu);
       }
     }
   }
 }
 
 template <typename T>
-int launch_omega(T* om, double* om64, const SliceDesc* sd, const int2* wk, int nslices, int64_t max_per_slice,
+int launch_omega(T* om, double* om64, uint16_t* omh, const SliceDesc* sd, const int2* wk, int nslices, int64_t max_per_slice,
                  uint32_t call, const int32_t* call_dev, uint32_t stream_base, uint64_t seed, int64_t dense_stride,
                  hipStream_t stream) {
   if (nslices == 0) return HT_OK;
   const int64_t ngroups = (max_per_slice + 3) / 4;
   const unsigned gy = (unsigned)std::max<int64_t>(1, std::min<int64_t>(ceil_div(ngroups, 256), 64));
-  hipLaunchKernelGGL(k_omega<T>, dim3((unsigned)nslices, gy), dim3(256), 0, stream, om, om64, sd, wk, call, call_dev,
-                     stream_base, seed, dense_stride);
+  hipLaunchKernelGGL(k_omega<T>, dim3((unsigned)nslices, gy), dim3(256), 0, stream, om, om64, omh, sd, wk, call,
+                     call_dev, stream_base, seed, dense_stride);
   HT_CHECK_LAUNCH();
   return HT_OK;
 }
 
-template int launch_omega<float>(float*, double*, const SliceDesc*, const int2*, int, int64_t, uint32_t,
+template int launch_omega<float>(float*, double*, uint16_t*, const SliceDesc*, const int2*, int, int64_t, uint32_t,
                                  const int32_t*, uint32_t, uint64_t, int64_t, hipStream_t);
-template int launch_omega<double>(double*, double*, const SliceDesc*, const int2*, int, int64_t, uint32_t,
+template int launch_omega<double>(double*, double*, uint16_t*, const SliceDesc*, const int2*, int, int64_t, uint32_t,
                                   const int32_t*, uint32_t, uint64_t, int64_t, hipStream_t);
 
 }  // namespace ht

@@ -35,7 +35,7 @@ MODELS = {"completion": 0, "rpca": 1, "rpca_tube": 2, "rpca_slice": 3}
 REGIONS = {"A": 0, "omega": 1, "Q": 2, "Bt": 3, "K": 4, "QK": 5, "C": 6, "Lnew": 7, "Xin": 8, "state": 9,
            "gram": 10, "gram_q": 11, "widths": 12, "call": 13, "widths_redo": 14, "widths_used": 15,
            "sigma": 16, "kept": 17, "anorm": 18, "features": 19, "learn_state": 20, "status": 21, "rse_part": 22,
-           "group_sq": 23}
+           "group_sq": 23, "omega_bf16": 24, "Q_bf16": 25, "Bt_bf16": 26}
 
 # Symbols the header declares (checked by the CPU test suite).
 EXPORTS = [

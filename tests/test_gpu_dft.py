@@ -72,6 +72,7 @@ def test_tsvt_dft_repeated_singular_values(ht, prec, noise):
 @pytest.mark.parametrize("dims,rank,r,p,q", [
     ((40, 30, 4, 3), 5, 5, 5, 1),    # even mode: self-conjugate slices at index 0 and n/2
     ((33, 20, 5), 4, 6, 4, 2),       # odd mode, ragged rows
+    ((35, 27, 6), 4, 6, 4, 2),       # odd row and column counts in both thin blocks
     ((24, 64, 2, 2, 2), 3, 8, 8, 1), # order 5, all slices self-conjugate
     ((64, 48, 6), 10, 12, 6, 2),     # columns aligned for 16-byte loads
     ((136, 100, 4, 2), 30, 40, 10, 2),  # width 50: three 64-row tiles with a ragged last one
