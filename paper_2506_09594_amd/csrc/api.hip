@@ -137,6 +137,8 @@ struct ht_plan {
   int prod_rows;     // output rows per product workgroup (64 or 128)
   size_t tf_budget;  // LDS bytes of one transform tile
   size_t tf_lds;
+  int tf_nf;      // first-mode length of the fused DFT transform, shared by every tensor (0: general form)
+  size_t tf_map;  // LDS bytes of the slot map the fused DFT transform keeps next to its tile
   std::vector<SliceDesc> h_slices;
   int64_t Atot;   // elements of the A / C regions
   bool cplx;      // every tensor under the unitary DFT (complex slices)
@@ -469,8 +471,32 @@ int tf_items(ht_plan* pl, size_t budget, std::vector<int2>& items, std::vector<i
   return HT_OK;
 }
 
+// Modes of the fused DFT transform of a mode table: the shortest mode goes
+// first (length <= 8), the longest last, and every mode must have a
+// power-of-two length <= 32; otherwise -1 (general form).
+void pick_fused_modes(ModeTable& mt) {
+  mt.first = mt.last = -1;
+  if (mt.nmodes < 2) return;
+  auto pow2 = [](int n) { return n >= 2 && (n & (n - 1)) == 0; };
+  int f = 0, l = 0;
+  for (int m = 0; m < mt.nmodes; ++m) {
+    if (!pow2(mt.n[m])) return;
+    if (mt.n[m] < mt.n[f]) f = m;
+  }
+  l = f == 0 ? 1 : 0;
+  for (int m = 0; m < mt.nmodes; ++m)
+    if (m != f && mt.n[m] > mt.n[l]) l = m;
+  if (mt.n[f] > 8 || mt.n[l] > 32) return;
+  mt.first = f;
+  mt.last = l;
+}
+
 int upload_tensors(ht_plan* pl, const std::vector<int>& tps) {
   std::vector<TensorDesc> td(pl->tens.size());
+  const int64_t V = 16 / (int64_t)elem_bytes(pl->precision);  // elements per 16-byte access
+  pl->tf_nf = 0;
+  pl->tf_map = 0;
+  bool fused = pl->cplx;
   for (size_t t = 0; t < pl->tens.size(); ++t) {
     const TensorHost& th = pl->tens[t];
     TensorDesc& d = td[t];
@@ -490,7 +516,21 @@ int upload_tensors(ht_plan* pl, const std::vector<int>& tps) {
     d.slice0 = (int32_t)th.slice0;
     d.fwd = th.fwd;
     d.inv = th.inv;
+    pick_fused_modes(d.fwd);
+    pick_fused_modes(d.inv);
+    // 16-byte tile loads need V consecutive tube positions in one column of every slice and slot
+    const bool vec = d.TP % V == 0 && d.NT % V == 0 && d.n1 % V == 0 && d.x % V == 0 && d.a % V == 0;
+    if (d.fwd.first < 0 || d.inv.first < 0 || !vec) {
+      fused = false;
+    } else {
+      const int nf = d.fwd.n[d.fwd.first];
+      if (d.inv.n[d.inv.first] != nf || (pl->tf_nf != 0 && pl->tf_nf != nf)) fused = false;
+      pl->tf_nf = nf;
+      pl->tf_map = std::max(pl->tf_map, (size_t)align4(d.P) * sizeof(int32_t));
+    }
   }
+  if (!fused) pl->tf_nf = 0;
+  if (!fused) pl->tf_map = 0;
   HT_CHECK_HIP(hipMemcpy(pl->d_tens, td.data(), td.size() * sizeof(TensorDesc), hipMemcpyHostToDevice));
   return HT_OK;
 }
@@ -900,12 +940,13 @@ int run_tsvt(const ht_plan* pl, const T* X, T* out, double tau, const double* ta
          }
          const int2* it = items(pl, pl->it_tf);
          if (pl->cplx) {
+           const size_t lds = pl->tf_lds + pl->tf_map;
            if (bf16)
              return launch_transform_cplx<float, uint16_t>((const float*)X, (uint16_t*)A, pl->d_tens, it,
-                                                           pl->it_tf.n, pl->tf_lds, pl->table32, pl->d_cmap, 0,
-                                                           pl->mode_nmax, s);
-           return launch_transform_cplx<T, T>(X, A, pl->d_tens, it, pl->it_tf.n, pl->tf_lds, table<T>(pl),
-                                              pl->d_cmap, 0, pl->mode_nmax, s);
+                                                           pl->it_tf.n, lds, pl->table32, pl->d_cmap, 0,
+                                                           pl->mode_nmax, pl->tf_nf, s);
+           return launch_transform_cplx<T, T>(X, A, pl->d_tens, it, pl->it_tf.n, lds, table<T>(pl), pl->d_cmap, 0,
+                                              pl->mode_nmax, pl->tf_nf, s);
          }
          if (bf16)
            return launch_transform<float, uint16_t>((const float*)X, (uint16_t*)A, pl->d_tens, it, pl->it_tf.n,
@@ -1084,8 +1125,9 @@ int run_tsvt(const ht_plan* pl, const T* X, T* out, double tau, const double* ta
       return launch_transform16<float>((const float*)C, (float*)out, pl->d_tens, items(pl, pl->it_t16), pl->it_t16.n,
                                        pl->table32, 1, s);
     if (pl->cplx)
-      return launch_transform_cplx<T, T>(C, out, pl->d_tens, items(pl, pl->it_tf), pl->it_tf.n, pl->tf_lds,
-                                         table<T>(pl), pl->d_cmap, 1, pl->mode_nmax, s);
+      return launch_transform_cplx<T, T>(C, out, pl->d_tens, items(pl, pl->it_tf), pl->it_tf.n,
+                                         pl->tf_lds + pl->tf_map, table<T>(pl), pl->d_cmap, 1, pl->mode_nmax,
+                                         pl->tf_nf, s);
     return launch_transform<T, T>(C, out, pl->d_tens, items(pl, pl->it_tf), pl->it_tf.n, pl->tf_lds, table<T>(pl), 1,
                                   s);
   });

@@ -58,9 +58,11 @@ int launch_transform16(const float* in, TO* out, const TensorDesc* tds, const in
 
 // Same for tensors under the unitary DFT (complex slices, see TensorDesc):
 // forward stores the canonical slots of A, inverse reads the slots of C.
+// nf > 0 selects the fused form (every tensor's first fused mode has length
+// nf, 16-byte tile accesses; see ModeTable::first), nf = 0 the general one.
 template <typename T, typename TO>
 int launch_transform_cplx(const T* in, TO* out, const TensorDesc* tds, const int2* items, int nitems, size_t lds,
-                          const T* table, const int32_t* cmap, int inverse, int nmax, hipStream_t s);
+                          const T* table, const int32_t* cmap, int inverse, int nmax, int nf, hipStream_t s);
 
 // Gaussian sketch matrices of every slice (T storage, FP64 copy and/or the
 // BF16 rounding of the T values), at the slices' Omega offsets, or densely at

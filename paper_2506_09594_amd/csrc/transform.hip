@@ -508,18 +508,21 @@ struct Twiddles {
   }
 };
 
+// In-register form: xr, xi hold the N values in natural order on entry and
+// their transform in natural order on return (the bit-reversed placement is
+// resolved at compile time).
 template <typename T, int N, bool INV>
-__device__ __forceinline__ void fft_fiber(T* re, T* im, int base, int stride) {
+__device__ __forceinline__ void fft_regs(T (&xr)[N], T (&xi)[N]) {
   constexpr int LG = Log2<N>::value;
   constexpr Twiddles<T, N, INV> W{};
-  T xr[N], xi[N];
+  T yr[N], yi[N];
 #pragma unroll
   for (int m = 0; m < N; ++m) {
     int r = 0;
 #pragma unroll
     for (int b = 0; b < LG; ++b) r |= ((m >> b) & 1) << (LG - 1 - b);
-    xr[r] = re[base + m * stride];
-    xi[r] = im[base + m * stride];
+    yr[r] = xr[m];
+    yi[r] = xi[m];
   }
 #pragma unroll
   for (int len = 2; len <= N; len <<= 1) {
@@ -531,21 +534,37 @@ __device__ __forceinline__ void fft_fiber(T* re, T* im, int base, int stride) {
         const int a = s0 + j, b = s0 + j + half, k = j * step;
         T tr, ti;
         if (k == 0) {
-          tr = xr[b];
-          ti = xi[b];
+          tr = yr[b];
+          ti = yi[b];
         } else if (4 * k == N) {  // exp(-+ i pi / 2) = -+ i
-          tr = INV ? -xi[b] : xi[b];
-          ti = INV ? xr[b] : -xr[b];
+          tr = INV ? -yi[b] : yi[b];
+          ti = INV ? yr[b] : -yr[b];
         } else {
-          tr = W.re[k] * xr[b] - W.im[k] * xi[b];
-          ti = W.re[k] * xi[b] + W.im[k] * xr[b];
+          tr = W.re[k] * yr[b] - W.im[k] * yi[b];
+          ti = W.re[k] * yi[b] + W.im[k] * yr[b];
         }
-        xr[b] = xr[a] - tr;
-        xi[b] = xi[a] - ti;
-        xr[a] += tr;
-        xi[a] += ti;
+        yr[b] = yr[a] - tr;
+        yi[b] = yi[a] - ti;
+        yr[a] += tr;
+        yi[a] += ti;
       }
   }
+#pragma unroll
+  for (int m = 0; m < N; ++m) {
+    xr[m] = yr[m];
+    xi[m] = yi[m];
+  }
+}
+
+template <typename T, int N, bool INV>
+__device__ __forceinline__ void fft_fiber(T* re, T* im, int base, int stride) {
+  T xr[N], xi[N];
+#pragma unroll
+  for (int m = 0; m < N; ++m) {
+    xr[m] = re[base + m * stride];
+    xi[m] = im[base + m * stride];
+  }
+  fft_regs<T, N, INV>(xr, xi);
 #pragma unroll
   for (int k = 0; k < N; ++k) {
     re[base + k * stride] = xr[k];
@@ -794,21 +813,279 @@ __global__ __launch_bounds__(256, sizeof(T) == 4 ? 2 : 1) void k_transform_cplx(
   }
 }
 
+// ---------------------------------------------------------------------------
+// Fused form of the same transform, for tensors with at least two transformed
+// modes whose tiles take 16-byte accesses (ModeTable::first / last name the
+// modes).  The first mode (power-of-two length NF <= 8, slice stride sf) is
+// applied in registers while the tile is loaded: a thread takes V consecutive
+// tube positions of the NF slices j0 + k sf of one fiber of that mode (one
+// 16-byte load per slice and plane; the inverse reads each slice's slot,
+// conjugated for a partner), transforms the V fibers and writes them to the
+// LDS tile.  Modes in between run in place in LDS as in the general form.  The
+// last mode (a power of two <= 32) is applied in registers while the tile is
+// stored: a thread reads one fiber of it from LDS, transforms it and stores
+// each value straight to its slot (forward: canonical members only, rounded
+// to TO) or to its slice (inverse: the real part).  The tile thus crosses LDS
+// once; the slot map of the tile's tensor is copied next to it so that no
+// global load of the map waits behind the next tile's loads, which are in
+// flight while the current tile is transformed and stored.
+// ---------------------------------------------------------------------------
+template <typename T, typename TO, bool inverse, int N>
+__device__ __forceinline__ void dft_last_fiber(const T* re, const T* im, int base, int stride, int j0, int sl, int t,
+                                               bool live, T post, TO* __restrict__ dst, int64_t NT, int n1,
+                                               int64_t t0, int64_t soff, const int32_t* smap) {
+  T xr[N], xi[N];
+#pragma unroll
+  for (int k = 0; k < N; ++k) {
+    xr[k] = re[base + k * stride];
+    xi[k] = im[base + k * stride];
+  }
+  fft_regs<T, N, inverse>(xr, xi);
+  if (!live) return;
+#pragma unroll
+  for (int k = 0; k < N; ++k) {
+    const int j = j0 + k * sl;
+    if constexpr (inverse) {
+      dst[(int64_t)j * NT + t0 + t] = (TO)(xr[k] * post);
+    } else {
+      const int32_t code = smap[j];
+      if (code >= 0) {  // canonical member of its pair
+        TO* S = dst + (int64_t)code * 2 * NT + soff;
+        if constexpr (std::is_same<TO, T>::value) {
+          S[0] = xr[k] * post;
+          S[n1] = xi[k] * post;
+        } else {
+          S[0] = f32_to_bf16_rne((float)(xr[k] * post));
+          S[n1] = f32_to_bf16_rne((float)(xi[k] * post));
+        }
+      }
+    }
+  }
+}
+
+template <typename T, typename TO, bool inverse, int NF>
+__global__ __launch_bounds__(256, sizeof(T) == 4 ? 2 : 1) void k_transform_dft(
+    const T* __restrict__ in_all, TO* __restrict__ out_all, const TensorDesc* __restrict__ tds,
+    const int2* __restrict__ items, int nitems, const T* __restrict__ table, const int32_t* __restrict__ cmap_all) {
+  constexpr int V = 16 / sizeof(T);  // elements per 16-byte access
+  using VT = __attribute__((ext_vector_type(V))) T;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T* re = reinterpret_cast<T*>(smem_raw);
+  const int tid = threadIdx.x, nt = blockDim.x;
+  struct Tile {
+    const TensorDesc* td;
+    const ModeTable* mt;
+    int64_t NT, t0;
+    int P, TP, lgTP, n1, tp, total;
+    int nu;    // load units: TP / V tube vectors x P / NF fibers of the first mode
+    int lgTV;  // log2(TP / V)
+    int sf;    // slice stride of the first mode
+  };
+  auto tile_of = [&](int it) -> Tile {
+    const int2 item = items[it];
+    Tile c;
+    c.td = tds + item.x;
+    c.mt = inverse ? &c.td->inv : &c.td->fwd;
+    c.NT = c.td->NT;
+    c.P = c.td->P;
+    c.TP = c.td->TP;
+    c.lgTP = c.td->lgTP;
+    c.n1 = c.td->n1;
+    c.t0 = item.y;
+    const int64_t rem = c.NT - c.t0;
+    c.tp = rem < c.TP ? (int)rem : c.TP;
+    c.total = c.TP * c.P;
+    c.lgTV = c.lgTP - Log2<V>::value;
+    c.nu = c.total / (V * NF);
+    c.sf = c.mt->stride[c.mt->first];
+    return c;
+  };
+  // offset in a stacked slot [Re; Im] (2 n1 x n2) of tube position t0 + t
+  auto slot_off = [](const Tile& c, int t) -> int64_t {
+    const int64_t tt = c.t0 + t;
+    return tt % c.n1 + (tt / c.n1) * 2 * c.n1;
+  };
+  // load unit u: tube positions t .. t + V - 1 of the slices j0 + k sf, k < NF
+  auto unit = [](const Tile& c, int u, int& t, int& j0) {
+    const int tv = u & ((1 << c.lgTV) - 1), rest = u >> c.lgTV;
+    t = tv * V;
+    j0 = rest % c.sf + (rest / c.sf) * c.sf * NF;
+  };
+  VT lr[NF], li[inverse ? NF : 1];
+  unsigned neg = 0;  // inverse: slices read conjugated (partners), one bit per k
+  // the loads of unit u; the inverse takes the slot map from LDS (lmap) or global memory (gmap)
+  auto issue = [&](const Tile& c, int u, const int32_t* lmap, const int32_t* __restrict__ gmap) {
+    int t, j0;
+    unit(c, u, t, j0);
+    const bool ok = u < c.nu && t < c.tp;
+    neg = 0;
+#pragma unroll
+    for (int k = 0; k < NF; ++k) {
+      const int j = j0 + k * c.sf;
+      if constexpr (!inverse) {
+        const T* src = in_all + c.td->x + (ok ? (int64_t)j * c.NT + c.t0 + t : 0);
+        lr[k] = ok ? *reinterpret_cast<const VT*>(src) : VT{};
+      } else {
+        const int32_t code = !ok ? 0 : (lmap ? lmap[j] : gmap[j]);
+        const T* S = in_all + c.td->a + (int64_t)(code & 0x7fffffff) * 2 * c.NT + (ok ? slot_off(c, t) : 0);
+        lr[k] = ok ? *reinterpret_cast<const VT*>(S) : VT{};
+        li[k] = ok ? *reinterpret_cast<const VT*>(S + c.n1) : VT{};
+        neg |= (code < 0 ? 1u : 0u) << k;
+      }
+    }
+  };
+  // the first mode of unit u (loads in lr / li) into the LDS tile
+  auto first_mode = [&](const Tile& c, int u) {
+    if (u >= c.nu) return;
+    int t, j0;
+    unit(c, u, t, j0);
+    T* im = re + c.total;
+    VT orr[NF], oii[NF];
+#pragma unroll
+    for (int e = 0; e < V; ++e) {
+      T xr[NF], xi[NF];
+#pragma unroll
+      for (int k = 0; k < NF; ++k) {
+        xr[k] = lr[k][e];
+        if constexpr (inverse)
+          xi[k] = ((neg >> k) & 1u) ? -li[k][e] : li[k][e];
+        else
+          xi[k] = T(0);
+      }
+      fft_regs<T, NF, inverse>(xr, xi);
+#pragma unroll
+      for (int k = 0; k < NF; ++k) {
+        orr[k][e] = xr[k];
+        oii[k][e] = xi[k];
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < NF; ++k) {
+      const int o = (j0 + k * c.sf) * c.TP + t;
+      *reinterpret_cast<VT*>(re + o) = orr[k];
+      *reinterpret_cast<VT*>(im + o) = oii[k];
+    }
+  };
+  int it = blockIdx.x;
+  if (it >= nitems) return;
+  Tile cur = tile_of(it);
+  issue(cur, tid, nullptr, cmap_all + cur.td->cmap);
+  for (;;) {
+    T* im = re + cur.total;
+    int32_t* smap = reinterpret_cast<int32_t*>(re + 2 * cur.total);
+    const int32_t* gmap = cmap_all + cur.td->cmap;
+    // ---- load with the first mode ------------------------------------------------
+    for (int j = tid; j < cur.P; j += nt) smap[j] = gmap[j];
+    first_mode(cur, tid);
+    for (int u = tid + nt; u < cur.nu; u += nt) {
+      issue(cur, u, nullptr, gmap);
+      first_mode(cur, u);
+    }
+    __syncthreads();
+    const int nxt = it + gridDim.x;
+    Tile nc{};
+    if (nxt < nitems) {
+      nc = tile_of(nxt);
+      if (nc.td == cur.td)
+        issue(nc, tid, smap, nullptr);
+      else
+        issue(nc, tid, nullptr, cmap_all + nc.td->cmap);
+    }
+    // ---- modes between ---------------------------------------------------------------
+    const ModeTable* mt = cur.mt;
+    T post = table[mt->off[mt->first]] * table[mt->off[mt->last]];  // scales the FFTs leave out
+    for (int m = 0; m < mt->nmodes; ++m) {
+      if (m == mt->first || m == mt->last) continue;
+      const int n = mt->n[m];  // a power of two <= 32 (ModeTable::first)
+      const int s = mt->stride[m];
+      post *= table[mt->off[m]];
+      const int nfib = cur.total / n, st = s * cur.TP;
+      for (int f = tid; f < nfib; f += nt) {
+        const int base = fiber_base(f, cur.TP, cur.lgTP, s, n);
+        if (n == 2)
+          fft_fiber<T, 2, inverse>(re, im, base, st);
+        else if (n == 4)
+          fft_fiber<T, 4, inverse>(re, im, base, st);
+        else if (n == 8)
+          fft_fiber<T, 8, inverse>(re, im, base, st);
+        else if (n == 16)
+          fft_fiber<T, 16, inverse>(re, im, base, st);
+        else if (n == 32)
+          fft_fiber<T, 32, inverse>(re, im, base, st);
+      }
+      __syncthreads();
+    }
+    // ---- last mode with the store --------------------------------------------------
+    {
+      const int nl = mt->n[mt->last], sl = mt->stride[mt->last];
+      const int nfib = cur.total / nl, st = sl * cur.TP;
+      TO* dst = out_all + (inverse ? cur.td->x : cur.td->a);
+      for (int f = tid; f < nfib; f += nt) {
+        const int base = fiber_base(f, cur.TP, cur.lgTP, sl, nl);
+        const int t = f & (cur.TP - 1), j0 = base >> cur.lgTP;
+        const bool live = t < cur.tp;
+        const int64_t soff = inverse ? 0 : slot_off(cur, t);
+#define HT_LAST(N) \
+  dft_last_fiber<T, TO, inverse, N>(re, im, base, st, j0, sl, t, live, post, dst, cur.NT, cur.n1, cur.t0, soff, smap)
+        if (nl == 2)
+          HT_LAST(2);
+        else if (nl == 4)
+          HT_LAST(4);
+        else if (nl == 8)
+          HT_LAST(8);
+        else if (nl == 16)
+          HT_LAST(16);
+        else if (nl == 32)
+          HT_LAST(32);
+#undef HT_LAST
+      }
+    }
+    if (nxt >= nitems) break;
+    __syncthreads();  // the tile and its map are read above before the next tile replaces them
+    it = nxt;
+    cur = nc;
+  }
+}
+
+// workgroups that stay resident for the whole launch, each walking its items
+int resident_grid(const void* kern, size_t lds, int nitems) {
+  int per_cu = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, 256, lds) != hipSuccess) return -1;
+  int dev = 0, ncu = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return -1;
+  if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return -1;
+  return std::max(1, std::min(nitems, std::max(per_cu, 1) * ncu));
+}
+
+template <typename T, typename TO, int NF>
+int launch_transform_dft(const T* in, TO* out, const TensorDesc* tds, const int2* items, int nitems, size_t lds,
+                         const T* table, const int32_t* cmap, int inverse, hipStream_t stream) {
+  const void* kern = inverse ? (const void*)k_transform_dft<T, TO, true, NF>
+                             : (const void*)k_transform_dft<T, TO, false, NF>;
+  int rc = ensure_dynamic_lds(kern, 160 * 1024);
+  if (rc) return rc;
+  const int grid = resident_grid(kern, lds, nitems);
+  if (grid < 0) HT_FAIL(HT_ERR_HIP, "occupancy query failed");
+  if (inverse)
+    hipLaunchKernelGGL((k_transform_dft<T, TO, true, NF>), dim3((unsigned)grid), dim3(256), lds, stream, in,
+                       out, tds, items, nitems, table, cmap);
+  else
+    hipLaunchKernelGGL((k_transform_dft<T, TO, false, NF>), dim3((unsigned)grid), dim3(256), lds, stream, in,
+                       out, tds, items, nitems, table, cmap);
+  HT_CHECK_LAUNCH();
+  return HT_OK;
+}
+
 template <typename T, typename TO, int NMAX>
 int launch_transform_cplx_n(const T* in, TO* out, const TensorDesc* tds, const int2* items, int nitems, size_t lds,
                             const T* table, const int32_t* cmap, int inverse, hipStream_t stream) {
+  const int aligned = (reinterpret_cast<uintptr_t>(in) % 16 == 0) && (reinterpret_cast<uintptr_t>(out) % 16 == 0);
   const void* kern = inverse ? (const void*)k_transform_cplx<T, TO, true, NMAX>
                              : (const void*)k_transform_cplx<T, TO, false, NMAX>;
   int rc = ensure_dynamic_lds(kern, 160 * 1024);
   if (rc) return rc;
-  // workgroups that stay resident for the whole launch, each walking its items
-  int per_cu = 0;
-  HT_CHECK_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, 256, lds));
-  int dev = 0, ncu = 0;
-  HT_CHECK_HIP(hipGetDevice(&dev));
-  HT_CHECK_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
-  const int grid = std::max(1, std::min(nitems, std::max(per_cu, 1) * ncu));
-  const int aligned = (reinterpret_cast<uintptr_t>(in) % 16 == 0) && (reinterpret_cast<uintptr_t>(out) % 16 == 0);
+  const int grid = resident_grid(kern, lds, nitems);
+  if (grid < 0) HT_FAIL(HT_ERR_HIP, "occupancy query failed");
   if (inverse)
     hipLaunchKernelGGL((k_transform_cplx<T, TO, true, NMAX>), dim3((unsigned)grid), dim3(256), lds, stream, in, out,
                        tds, items, nitems, table, cmap, aligned);
@@ -822,11 +1099,19 @@ int launch_transform_cplx_n(const T* in, TO* out, const TensorDesc* tds, const i
 // nmax: the longest transformed mode (selects the fiber kernels compiled in)
 template <typename T, typename TO>
 int launch_transform_cplx(const T* in, TO* out, const TensorDesc* tds, const int2* items, int nitems, size_t lds,
-                          const T* table, const int32_t* cmap, int inverse, int nmax, hipStream_t stream) {
+                          const T* table, const int32_t* cmap, int inverse, int nmax, int nf, hipStream_t stream) {
   if (nitems == 0) return HT_OK;
   if (lds > 160 * 1024) HT_FAIL(HT_ERR_UNSUPPORTED, "transform tile above the LDS size");
   if (nmax > 64) HT_FAIL(HT_ERR_UNSUPPORTED, "DFT mode longer than 64");
-  if (nmax <= 8) return launch_transform_cplx_n<T, TO, 8>(in, out, tds, items, nitems, lds, table, cmap, inverse, stream);
+  const bool aligned = reinterpret_cast<uintptr_t>(in) % 16 == 0 && reinterpret_cast<uintptr_t>(out) % 16 == 0;
+  if (nf > 0 && aligned) {
+    if (nf == 2) return launch_transform_dft<T, TO, 2>(in, out, tds, items, nitems, lds, table, cmap, inverse, stream);
+    if (nf == 4) return launch_transform_dft<T, TO, 4>(in, out, tds, items, nitems, lds, table, cmap, inverse, stream);
+    if (nf == 8) return launch_transform_dft<T, TO, 8>(in, out, tds, items, nitems, lds, table, cmap, inverse, stream);
+    HT_FAIL(HT_ERR_UNSUPPORTED, "fused DFT transform: first mode longer than 8");
+  }
+  if (nmax <= 8)
+    return launch_transform_cplx_n<T, TO, 8>(in, out, tds, items, nitems, lds, table, cmap, inverse, stream);
   if (nmax <= 16)
     return launch_transform_cplx_n<T, TO, 16>(in, out, tds, items, nitems, lds, table, cmap, inverse, stream);
   if (nmax <= 32)
@@ -835,11 +1120,12 @@ int launch_transform_cplx(const T* in, TO* out, const TensorDesc* tds, const int
 }
 
 template int launch_transform_cplx<float, float>(const float*, float*, const TensorDesc*, const int2*, int, size_t,
-                                                 const float*, const int32_t*, int, int, hipStream_t);
+                                                 const float*, const int32_t*, int, int, int, hipStream_t);
 template int launch_transform_cplx<double, double>(const double*, double*, const TensorDesc*, const int2*, int,
-                                                   size_t, const double*, const int32_t*, int, int, hipStream_t);
+                                                   size_t, const double*, const int32_t*, int, int, int, hipStream_t);
 template int launch_transform_cplx<float, uint16_t>(const float*, uint16_t*, const TensorDesc*, const int2*, int,
-                                                    size_t, const float*, const int32_t*, int, int, hipStream_t);
+                                                    size_t, const float*, const int32_t*, int, int, int,
+                                                    hipStream_t);
 
 int transform_tile_width(int64_t P, size_t elem_bytes, size_t budget) {
   int64_t tp = 256;

@@ -74,6 +74,7 @@ def test_tsvt_dft_repeated_singular_values(ht, prec, noise):
     ((33, 20, 5), 4, 6, 4, 2),       # odd mode, ragged rows
     ((35, 27, 6), 4, 6, 4, 2),       # odd row and column counts in both thin blocks
     ((24, 64, 2, 2, 2), 3, 8, 8, 1), # order 5, all slices self-conjugate
+    ((40, 36, 4, 16, 2), 5, 6, 4, 1),  # order 5: first mode 2, last 16, a mode of 4 between
     ((64, 48, 6), 10, 12, 6, 2),     # columns aligned for 16-byte loads
     ((136, 100, 4, 2), 30, 40, 10, 2),  # width 50: three 64-row tiles with a ragged last one
     ((64, 70, 3, 3), 20, 54, 10, 1),    # width 64, the largest complex width
