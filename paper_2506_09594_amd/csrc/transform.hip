@@ -510,12 +510,13 @@ struct Twiddles {
 
 // In-register form: xr, xi hold the N values in natural order on entry and
 // their transform in natural order on return (the bit-reversed placement is
-// resolved at compile time).
-template <typename T, int N, bool INV>
-__device__ __forceinline__ void fft_regs(T (&xr)[N], T (&xi)[N]) {
+// resolved at compile time).  E is T, or a vector of T holding independent
+// transforms in its lanes.
+template <typename T, int N, bool INV, typename E = T>
+__device__ __forceinline__ void fft_regs(E (&xr)[N], E (&xi)[N]) {
   constexpr int LG = Log2<N>::value;
   constexpr Twiddles<T, N, INV> W{};
-  T yr[N], yi[N];
+  E yr[N], yi[N];
 #pragma unroll
   for (int m = 0; m < N; ++m) {
     int r = 0;
@@ -532,7 +533,7 @@ __device__ __forceinline__ void fft_regs(T (&xr)[N], T (&xi)[N]) {
 #pragma unroll
       for (int j = 0; j < half; ++j) {
         const int a = s0 + j, b = s0 + j + half, k = j * step;
-        T tr, ti;
+        E tr, ti;
         if (k == 0) {
           tr = yr[b];
           ti = yi[b];
@@ -815,52 +816,39 @@ __global__ __launch_bounds__(256, sizeof(T) == 4 ? 2 : 1) void k_transform_cplx(
 
 // ---------------------------------------------------------------------------
 // Fused form of the same transform, for tensors with at least two transformed
-// modes whose tiles take 16-byte accesses (ModeTable::first / last name the
-// modes).  The first mode (power-of-two length NF <= 8, slice stride sf) is
-// applied in registers while the tile is loaded: a thread takes V consecutive
-// tube positions of the NF slices j0 + k sf of one fiber of that mode (one
-// 16-byte load per slice and plane; the inverse reads each slice's slot,
-// conjugated for a partner), transforms the V fibers and writes them to the
-// LDS tile.  Modes in between run in place in LDS as in the general form.  The
-// last mode (a power of two <= 32) is applied in registers while the tile is
-// stored: a thread reads one fiber of it from LDS, transforms it and stores
-// each value straight to its slot (forward: canonical members only, rounded
-// to TO) or to its slice (inverse: the real part).  The tile thus crosses LDS
-// once; the slot map of the tile's tensor is copied next to it so that no
-// global load of the map waits behind the next tile's loads, which are in
-// flight while the current tile is transformed and stored.
+// modes, all of power-of-two length <= 32, whose tiles take 16-byte accesses
+// (ModeTable::first names the shortest mode).  The first mode (length
+// NF <= 8, slice stride sf) is applied in registers while the tile is loaded:
+// a thread takes V consecutive tube positions of the NF slices j0 + k sf of
+// one fiber of that mode (one 16-byte load per slice and plane; the inverse
+// reads each slice's slot, conjugated for a partner), transforms the V fibers
+// and writes them to the LDS tile.  The other modes run in place in LDS; the
+// forward tile leaves with 16-byte stores (8 BF16 or V values of a canonical
+// slot); the inverse applies its last mode in registers as it stores the real
+// parts (dft_last_inverse), which measured faster than a further LDS pass
+// with 16-byte stores.  The slot map of the tile's tensor is copied next to
+// the tile so that no global load of the map waits behind the next tile's
+// loads, which are in flight while the current tile is transformed and
+// stored.
 // ---------------------------------------------------------------------------
-template <typename T, typename TO, bool inverse, int N>
-__device__ __forceinline__ void dft_last_fiber(const T* re, const T* im, int base, int stride, int j0, int sl, int t,
-                                               bool live, T post, TO* __restrict__ dst, int64_t NT, int n1,
-                                               int64_t t0, int64_t soff, const int32_t* smap) {
+// Last mode of the inverse in registers: fiber (tube position t, slices
+// j0 + k sl) from the LDS tile, transformed, and the real parts stored
+// straight to the output slices (consecutive lanes hold consecutive
+// positions, so each store covers runs of the slice's row).
+template <typename T, int N>
+__device__ __forceinline__ void dft_last_inverse(const T* re, const T* im, int base, int stride, int j0, int sl,
+                                                 int t, bool live, T post, T* __restrict__ out, int64_t NT,
+                                                 int64_t t0) {
   T xr[N], xi[N];
 #pragma unroll
   for (int k = 0; k < N; ++k) {
     xr[k] = re[base + k * stride];
     xi[k] = im[base + k * stride];
   }
-  fft_regs<T, N, inverse>(xr, xi);
+  fft_regs<T, N, true>(xr, xi);
   if (!live) return;
 #pragma unroll
-  for (int k = 0; k < N; ++k) {
-    const int j = j0 + k * sl;
-    if constexpr (inverse) {
-      dst[(int64_t)j * NT + t0 + t] = (TO)(xr[k] * post);
-    } else {
-      const int32_t code = smap[j];
-      if (code >= 0) {  // canonical member of its pair
-        TO* S = dst + (int64_t)code * 2 * NT + soff;
-        if constexpr (std::is_same<TO, T>::value) {
-          S[0] = xr[k] * post;
-          S[n1] = xi[k] * post;
-        } else {
-          S[0] = f32_to_bf16_rne((float)(xr[k] * post));
-          S[n1] = f32_to_bf16_rne((float)(xi[k] * post));
-        }
-      }
-    }
-  }
+  for (int k = 0; k < N; ++k) out[(int64_t)(j0 + k * sl) * NT + t0 + t] = xr[k] * post;
 }
 
 template <typename T, typename TO, bool inverse, int NF>
@@ -905,16 +893,20 @@ __global__ __launch_bounds__(256, sizeof(T) == 4 ? 2 : 1) void k_transform_dft(
     const int64_t tt = c.t0 + t;
     return tt % c.n1 + (tt / c.n1) * 2 * c.n1;
   };
-  // load unit u: tube positions t .. t + V - 1 of the slices j0 + k sf, k < NF
+  // LDS copy of the slot map of tile c's tensor
+  auto lds_map = [&](const Tile& c) { return reinterpret_cast<int32_t*>(re + 2 * c.total); };
+  // unit u: tube positions t .. t + V - 1 (t = V (u mod TP / V)) of the slices
+  // j0 + k sf, k < NF, of fiber u / (TP / V) of the first mode
   auto unit = [](const Tile& c, int u, int& t, int& j0) {
-    const int tv = u & ((1 << c.lgTV) - 1), rest = u >> c.lgTV;
-    t = tv * V;
-    j0 = rest % c.sf + (rest / c.sf) * c.sf * NF;
+    const int f = u >> c.lgTV;
+    t = (u & ((1 << c.lgTV) - 1)) * V;
+    j0 = f % c.sf + (f / c.sf) * c.sf * NF;
   };
   VT lr[NF], li[inverse ? NF : 1];
   unsigned neg = 0;  // inverse: slices read conjugated (partners), one bit per k
-  // the loads of unit u; the inverse takes the slot map from LDS (lmap) or global memory (gmap)
-  auto issue = [&](const Tile& c, int u, const int32_t* lmap, const int32_t* __restrict__ gmap) {
+  // the loads of unit u, with the slot map of its tensor from LDS (FROM_LDS) or global memory
+  auto issue = [&](const Tile& c, int u, auto from_lds) {
+    constexpr bool L = decltype(from_lds)::value;
     int t, j0;
     unit(c, u, t, j0);
     const bool ok = u < c.nu && t < c.tp;
@@ -926,7 +918,8 @@ __global__ __launch_bounds__(256, sizeof(T) == 4 ? 2 : 1) void k_transform_dft(
         const T* src = in_all + c.td->x + (ok ? (int64_t)j * c.NT + c.t0 + t : 0);
         lr[k] = ok ? *reinterpret_cast<const VT*>(src) : VT{};
       } else {
-        const int32_t code = !ok ? 0 : (lmap ? lmap[j] : gmap[j]);
+        const int32_t* mp = L ? lds_map(c) : cmap_all + c.td->cmap;
+        const int32_t code = ok ? mp[j] : 0;
         const T* S = in_all + c.td->a + (int64_t)(code & 0x7fffffff) * 2 * c.NT + (ok ? slot_off(c, t) : 0);
         lr[k] = ok ? *reinterpret_cast<const VT*>(S) : VT{};
         li[k] = ok ? *reinterpret_cast<const VT*>(S + c.n1) : VT{};
@@ -940,25 +933,16 @@ __global__ __launch_bounds__(256, sizeof(T) == 4 ? 2 : 1) void k_transform_dft(
     int t, j0;
     unit(c, u, t, j0);
     T* im = re + c.total;
-    VT orr[NF], oii[NF];
+    VT orr[NF], oii[NF];  // V transforms at once, one per vector lane
 #pragma unroll
-    for (int e = 0; e < V; ++e) {
-      T xr[NF], xi[NF];
-#pragma unroll
-      for (int k = 0; k < NF; ++k) {
-        xr[k] = lr[k][e];
-        if constexpr (inverse)
-          xi[k] = ((neg >> k) & 1u) ? -li[k][e] : li[k][e];
-        else
-          xi[k] = T(0);
-      }
-      fft_regs<T, NF, inverse>(xr, xi);
-#pragma unroll
-      for (int k = 0; k < NF; ++k) {
-        orr[k][e] = xr[k];
-        oii[k][e] = xi[k];
-      }
+    for (int k = 0; k < NF; ++k) {
+      orr[k] = lr[k];
+      if constexpr (inverse)
+        oii[k] = ((neg >> k) & 1u) ? -li[k] : li[k];
+      else
+        oii[k] = VT{};
     }
+    fft_regs<T, NF, inverse, VT>(orr, oii);
 #pragma unroll
     for (int k = 0; k < NF; ++k) {
       const int o = (j0 + k * c.sf) * c.TP + t;
@@ -969,16 +953,18 @@ __global__ __launch_bounds__(256, sizeof(T) == 4 ? 2 : 1) void k_transform_dft(
   int it = blockIdx.x;
   if (it >= nitems) return;
   Tile cur = tile_of(it);
-  issue(cur, tid, nullptr, cmap_all + cur.td->cmap);
+  issue(cur, tid, std::false_type{});
   for (;;) {
     T* im = re + cur.total;
-    int32_t* smap = reinterpret_cast<int32_t*>(re + 2 * cur.total);
-    const int32_t* gmap = cmap_all + cur.td->cmap;
+    int32_t* smap = lds_map(cur);
     // ---- load with the first mode ------------------------------------------------
-    for (int j = tid; j < cur.P; j += nt) smap[j] = gmap[j];
+    {
+      const int32_t* gmap = cmap_all + cur.td->cmap;
+      for (int j = tid; j < cur.P; j += nt) smap[j] = gmap[j];
+    }
     first_mode(cur, tid);
     for (int u = tid + nt; u < cur.nu; u += nt) {
-      issue(cur, u, nullptr, gmap);
+      issue(cur, u, std::false_type{});
       first_mode(cur, u);
     }
     __syncthreads();
@@ -987,15 +973,15 @@ __global__ __launch_bounds__(256, sizeof(T) == 4 ? 2 : 1) void k_transform_dft(
     if (nxt < nitems) {
       nc = tile_of(nxt);
       if (nc.td == cur.td)
-        issue(nc, tid, smap, nullptr);
+        issue(nc, tid, std::true_type{});
       else
-        issue(nc, tid, nullptr, cmap_all + nc.td->cmap);
+        issue(nc, tid, std::false_type{});
     }
-    // ---- modes between ---------------------------------------------------------------
+    // ---- the other modes -----------------------------------------------------------
     const ModeTable* mt = cur.mt;
-    T post = table[mt->off[mt->first]] * table[mt->off[mt->last]];  // scales the FFTs leave out
+    T post = table[mt->off[mt->first]];  // scales the FFTs leave out
     for (int m = 0; m < mt->nmodes; ++m) {
-      if (m == mt->first || m == mt->last) continue;
+      if (m == mt->first || (inverse && m == mt->last)) continue;  // inverse: last mode with the store
       const int n = mt->n[m];  // a power of two <= 32 (ModeTable::first)
       const int s = mt->stride[m];
       post *= table[mt->off[m]];
@@ -1015,29 +1001,70 @@ __global__ __launch_bounds__(256, sizeof(T) == 4 ? 2 : 1) void k_transform_dft(
       }
       __syncthreads();
     }
-    // ---- last mode with the store --------------------------------------------------
-    {
-      const int nl = mt->n[mt->last], sl = mt->stride[mt->last];
-      const int nfib = cur.total / nl, st = sl * cur.TP;
-      TO* dst = out_all + (inverse ? cur.td->x : cur.td->a);
+    // ---- store ---------------------------------------------------------------------
+    const int64_t NT = cur.NT;
+    const int n1 = cur.n1, TP = cur.TP, lgTP = cur.lgTP, tp = cur.tp;
+    if constexpr (!inverse) {
+      TO* A = out_all + cur.td->a;
+      bool wide = false;  // 8 BF16 (16 bytes) per store
+      if constexpr (!std::is_same<TO, T>::value)
+        wide = n1 % 8 == 0 && NT % 8 == 0 && cur.td->a % 8 == 0 && TP % 8 == 0;
+      if constexpr (!std::is_same<TO, T>::value) {
+        if (wide) {
+          typedef unsigned int u4 __attribute__((ext_vector_type(4)));
+          auto pack = [&](const T* p) {
+            const VT a = *reinterpret_cast<const VT*>(p) * post, b = *reinterpret_cast<const VT*>(p + 4) * post;
+            return u4{f32x2_to_bf16x2(a[0], a[1]), f32x2_to_bf16x2(a[2], a[3]), f32x2_to_bf16x2(b[0], b[1]),
+                      f32x2_to_bf16x2(b[2], b[3])};
+          };
+          for (int vi = tid; vi < cur.total / 8; vi += nt) {
+            const int idx = vi * 8, j = idx >> lgTP, t = idx & (TP - 1);
+            const int32_t code = smap[j];
+            if (t < tp && code >= 0) {  // canonical member of its pair
+              TO* S = A + (int64_t)code * 2 * NT + slot_off(cur, t);
+              *reinterpret_cast<u4*>(S) = pack(re + idx);
+              *reinterpret_cast<u4*>(S + n1) = pack(im + idx);
+            }
+          }
+        }
+      }
+      if (!wide) {
+        for (int vi = tid; vi < cur.total / V; vi += nt) {
+          const int idx = vi * V, j = idx >> lgTP, t = idx & (TP - 1);
+          const int32_t code = smap[j];
+          if (t < tp && code >= 0) {
+            TO* S = A + (int64_t)code * 2 * NT + slot_off(cur, t);
+            const VT vr = *reinterpret_cast<const VT*>(re + idx) * post;
+            const VT vi2 = *reinterpret_cast<const VT*>(im + idx) * post;
+            if constexpr (std::is_same<TO, T>::value) {
+              *reinterpret_cast<VT*>(S) = vr;
+              *reinterpret_cast<VT*>(S + n1) = vi2;
+            } else {
+              typedef unsigned int u2 __attribute__((ext_vector_type(2)));
+              *reinterpret_cast<u2*>(S) = u2{f32x2_to_bf16x2(vr[0], vr[1]), f32x2_to_bf16x2(vr[2], vr[3])};
+              *reinterpret_cast<u2*>(S + n1) = u2{f32x2_to_bf16x2(vi2[0], vi2[1]), f32x2_to_bf16x2(vi2[2], vi2[3])};
+            }
+          }
+        }
+      }
+    } else {
+      post *= table[mt->off[mt->last]];
+      const int nl = mt->n[mt->last], sl = mt->stride[mt->last], nfib = cur.total / nl, st = sl * TP;
+      T* out = reinterpret_cast<T*>(out_all) + cur.td->x;
       for (int f = tid; f < nfib; f += nt) {
-        const int base = fiber_base(f, cur.TP, cur.lgTP, sl, nl);
-        const int t = f & (cur.TP - 1), j0 = base >> cur.lgTP;
-        const bool live = t < cur.tp;
-        const int64_t soff = inverse ? 0 : slot_off(cur, t);
-#define HT_LAST(N) \
-  dft_last_fiber<T, TO, inverse, N>(re, im, base, st, j0, sl, t, live, post, dst, cur.NT, cur.n1, cur.t0, soff, smap)
+        const int base = fiber_base(f, TP, lgTP, sl, nl);
+        const int t = f & (TP - 1), j0 = base >> lgTP;
+        const bool live = t < tp;
         if (nl == 2)
-          HT_LAST(2);
+          dft_last_inverse<T, 2>(re, im, base, st, j0, sl, t, live, post, out, NT, cur.t0);
         else if (nl == 4)
-          HT_LAST(4);
+          dft_last_inverse<T, 4>(re, im, base, st, j0, sl, t, live, post, out, NT, cur.t0);
         else if (nl == 8)
-          HT_LAST(8);
+          dft_last_inverse<T, 8>(re, im, base, st, j0, sl, t, live, post, out, NT, cur.t0);
         else if (nl == 16)
-          HT_LAST(16);
+          dft_last_inverse<T, 16>(re, im, base, st, j0, sl, t, live, post, out, NT, cur.t0);
         else if (nl == 32)
-          HT_LAST(32);
-#undef HT_LAST
+          dft_last_inverse<T, 32>(re, im, base, st, j0, sl, t, live, post, out, NT, cur.t0);
       }
     }
     if (nxt >= nitems) break;
