@@ -561,36 +561,71 @@ __global__ __launch_bounds__(256, 1) void k_cmul_bf16x3(const float* __restrict_
     split_bf16x2(x[6], x[7], ah[st].w, al[st].w);
   }
   // ---- staging of E1 for one column tile: unit = (column c, k group of 8) ----
-  // E1[k][c] = Btr(c, k) for k < q, Bti(c, k - q) after (zero past l)
-  auto stage = [&](int ct) {
+  // E1[k][c] = Btr(c, k) for k < q, Bti(c, k - q) after (zero past l).  The
+  // next tile's loads (stage_load) are issued before the current tile's
+  // products and split (stage_split) after them, before its stores: their
+  // wait then covers only the previous tile's stores, which drained during
+  // the products; the split terms go to LDS (stage_store) after a barrier.
+  float pv[4][8];
+  uint4 sh[4], sl[4];
+  // loads from clamped (always valid) addresses, unconditionally, so that no
+  // path leaves a load pending; entries past the operand are zeroed at the split
+  auto stage_load = [&](int ct) {
     const int col0 = 64 * ct;
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
       const int f = tid + 256 * u;
       const int c = f % 64, g = f / 64;  // g < 16: k = 8 g .. 8 g + 7
-      const int gc = col0 + c;
+      const int gc = min(col0 + c, n2 - 1);
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const int k = 8 * g + e, part = k >= q, kk = min(part ? k - q : k, l - 1);
+        pv[u][e] = W[(part ? n2 : 0) + gc + (int64_t)kk * 2 * n2];
+      }
+    }
+  };
+  auto stage_split = [&](int ct) {
+    const int col0 = 64 * ct;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int f = tid + 256 * u;
+      const int c = f % 64, g = f / 64;
       float v[8];
 #pragma unroll
       for (int e = 0; e < 8; ++e) {
         const int k = 8 * g + e, part = k >= q, kk = part ? k - q : k;
-        const bool ok = 8 * g < 2 * q && kk < l && gc < n2;
-        v[e] = ok ? W[(part ? n2 : 0) + gc + (int64_t)kk * 2 * n2] : 0.0f;
+        v[e] = (8 * g < 2 * q && kk < l && col0 + c < n2) ? pv[u][e] : 0.0f;
       }
-      uint4 vh, vl;
-      split_bf16x2(v[0], v[1], vh.x, vl.x);
-      split_bf16x2(v[2], v[3], vh.y, vl.y);
-      split_bf16x2(v[4], v[5], vh.z, vl.z);
-      split_bf16x2(v[6], v[7], vh.w, vl.w);
-      *reinterpret_cast<uint4*>(Eh + c * kXPitch + 8 * g) = vh;
-      *reinterpret_cast<uint4*>(El + c * kXPitch + 8 * g) = vl;
+      split_bf16x2(v[0], v[1], sh[u].x, sl[u].x);
+      split_bf16x2(v[2], v[3], sh[u].y, sl[u].y);
+      split_bf16x2(v[4], v[5], sh[u].z, sl[u].z);
+      split_bf16x2(v[6], v[7], sh[u].w, sl[u].w);
+      // the split happens here, before the stores that follow (not sunk to its LDS store)
+      asm volatile("" ::"v"(sh[u].x), "v"(sh[u].y), "v"(sh[u].z), "v"(sh[u].w), "v"(sl[u].x), "v"(sl[u].y),
+                   "v"(sl[u].z), "v"(sl[u].w)
+                   : "memory");
     }
   };
-  const bool vecc = aligned && d.a % 4 == 0 && n1 % 4 == 0;
+  auto stage_store = [&]() {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int f = tid + 256 * u;
+      const int c = f % 64, g = f / 64;
+      *reinterpret_cast<uint4*>(Eh + c * kXPitch + 8 * g) = sh[u];
+      *reinterpret_cast<uint4*>(El + c * kXPitch + 8 * g) = sl[u];
+    }
+  };
+  // every row of the strip in range and 16-byte aligned column segments: vector stores only
+  const bool full = aligned && d.a % 4 == 0 && n1 % 4 == 0 && row0 + kCmulRows <= n1;
+  stage_load(ct_begin);
+  stage_split(ct_begin);
+  stage_store();
+  __syncthreads();
   for (int ct = ct_begin; ct < ct_end; ++ct) {
     const int col0 = 64 * ct;
-    if (ct > ct_begin) __syncthreads();  // the previous tile's operands are no longer read
-    stage(ct);
-    __syncthreads();
+    const bool more = ct + 1 < ct_end;  // uniform
+    const int cn = more ? ct + 1 : ct;  // the last tile reloads itself (cached, unused)
+    stage_load(cn);
     f32x16 acr[2], aci[2];
 #pragma unroll
     for (int cb = 0; cb < 2; ++cb)
@@ -623,17 +658,22 @@ __global__ __launch_bounds__(256, 1) void k_cmul_bf16x3(const float* __restrict_
         aci[cb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xb, e2h, aci[cb], 0, 0, 0);
       }
     }
+    stage_split(cn);
     // ---- store: 16-byte column segments straight from the accumulators ----
     auto put = [&](const f32x16& acc, int cb, int part) {
       const int col = col0 + 32 * cb + li;
       if (col >= n2) return;
       float* dst = C + (part ? n1 : 0) + (int64_t)col * ldx;
+      if (full) {
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const int rb = row0 + 32 * wave + 8 * j + 4 * h;
-        if (vecc && rb + 3 < n1) {
+        for (int j = 0; j < 4; ++j) {
+          const int rb = row0 + 32 * wave + 8 * j + 4 * h;
           *reinterpret_cast<f32x4*>(dst + rb) = f32x4{acc[4 * j], acc[4 * j + 1], acc[4 * j + 2], acc[4 * j + 3]};
-        } else {
+        }
+      } else {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int rb = row0 + 32 * wave + 8 * j + 4 * h;
 #pragma unroll
           for (int e = 0; e < 4; ++e)
             if (rb + e < n1) dst[rb + e] = acc[4 * j + e];
@@ -645,6 +685,11 @@ __global__ __launch_bounds__(256, 1) void k_cmul_bf16x3(const float* __restrict_
     if (two) {
       put(acr[1], 1, 0);
       put(aci[1], 1, 1);
+    }
+    if (more) {
+      __syncthreads();  // every wavefront is done reading this tile's operands
+      stage_store();
+      __syncthreads();
     }
   }
 }
