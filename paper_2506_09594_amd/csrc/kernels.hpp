@@ -24,7 +24,7 @@ constexpr int kMaxComplexWidth = 64;
 constexpr int kCplxProdRows = 64;
 // Complex reconstruction items: strips of kCmulRows complex rows, groups of up
 // to kCmulGroup column tiles of 64 (item.y = strip * groups + group).
-constexpr int kCmulRows = 128, kCmulGroup = 4;
+constexpr int kCmulRows = 128, kCmulGroup = 8;
 
 // Work items.  Every per-slice launch takes an item list: item i of a product
 // or orthonormalization launch is (slice, first row of its tile); of the
