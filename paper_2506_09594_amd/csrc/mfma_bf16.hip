@@ -300,8 +300,8 @@ __global__ __launch_bounds__(2 * MT) void k_cthin_bf16(const uint16_t* __restric
   u16x8 rw0[2][NWB], rw1[2][NWB];
   // interior chunks of a tile whose rows are all valid take plain loads
   const bool rowsA = vecA && vecW && r0 + 64 <= mo;
-  auto fetch = [&](u16x8 (&ra)[NRA], u16x8 (&rw)[2][NWB], int k0) {
-    if (rowsA && k0 + KC <= K) {
+  // the loads of an interior chunk (rowsA, k0 + KC <= K): a fixed set of 16-byte loads
+  auto fetch_fast = [&](u16x8 (&ra)[NRA], u16x8 (&rw)[2][NWB], int k0) {
 #pragma unroll
       for (int u = 0; u < NRA; ++u) {
         const uint16_t* src;
@@ -327,6 +327,10 @@ __global__ __launch_bounds__(2 * MT) void k_cthin_bf16(const uint16_t* __restric
           const u16x8 v = *reinterpret_cast<const u16x8*>(src);
           rw[part][u] = live ? v : u16x8{0, 0, 0, 0, 0, 0, 0, 0};
         }
+  };
+  auto fetch = [&](u16x8 (&ra)[NRA], u16x8 (&rw)[2][NWB], int k0) {
+    if (rowsA && k0 + KC <= K) {
+      fetch_fast(ra, rw, k0);
       return;
     }
 #pragma unroll
@@ -398,7 +402,7 @@ __global__ __launch_bounds__(2 * MT) void k_cthin_bf16(const uint16_t* __restric
 #pragma unroll
       for (int u = 0; u < NWB; ++u) {
         const int f = tid + u * NTH;
-        if (f < LW * KC / 8) {
+        if ((LW * KC / 8) % NTH == 0 || f < LW * KC / 8) {  // every thread has a group when the count divides
           const int c = f / (KC / 8), k8 = (f % (KC / 8)) * 8;
           uint2* dst = reinterpret_cast<uint2*>(Ws + c * KPC + k8);
           const uint4 w = __builtin_bit_cast(uint4, rw[part][u]);
@@ -445,20 +449,42 @@ __global__ __launch_bounds__(2 * MT) void k_cthin_bf16(const uint16_t* __restric
       }
     }
   };
-  fetch(ra0, rw0, 0);
-  if (nchunks > 1) fetch(ra1, rw1, KC);
-  stash(ra0, rw0, 0);
-  __syncthreads();
-  for (int ch = 0; ch < nchunks; ch += 2) {
-    if (ch + 2 < nchunks) fetch(ra0, rw0, (ch + 2) * KC);
-    compute(0);
-    if (ch + 1 < nchunks) stash(ra1, rw1, 1);
+  if (rowsA && K % KC == 0) {
+    // Every chunk interior: unconditional fetches with the prefetch past the
+    // end clamped to the last chunk (loaded, never used), so that every path
+    // through the loop issues the same loads and each stash waits only for its
+    // own chunk while the next one stays in flight.
+    fetch_fast(ra0, rw0, 0);
+    fetch_fast(ra1, rw1, min(1, nchunks - 1) * KC);
+    stash(ra0, rw0, 0);
     __syncthreads();
-    if (ch + 1 >= nchunks) break;
-    if (ch + 3 < nchunks) fetch(ra1, rw1, (ch + 3) * KC);
-    compute(1);
-    if (ch + 2 < nchunks) stash(ra0, rw0, 0);
+    for (int ch = 0; ch < nchunks; ch += 2) {
+      fetch_fast(ra0, rw0, min(ch + 2, nchunks - 1) * KC);
+      compute(0);
+      stash(ra1, rw1, 1);
+      __syncthreads();
+      if (ch + 1 >= nchunks) break;
+      fetch_fast(ra1, rw1, min(ch + 3, nchunks - 1) * KC);
+      compute(1);
+      stash(ra0, rw0, 0);
+      __syncthreads();
+    }
+  } else {
+    fetch(ra0, rw0, 0);
+    if (nchunks > 1) fetch(ra1, rw1, KC);
+    stash(ra0, rw0, 0);
     __syncthreads();
+    for (int ch = 0; ch < nchunks; ch += 2) {
+      if (ch + 2 < nchunks) fetch(ra0, rw0, (ch + 2) * KC);
+      compute(0);
+      if (ch + 1 < nchunks) stash(ra1, rw1, 1);
+      __syncthreads();
+      if (ch + 1 >= nchunks) break;
+      if (ch + 3 < nchunks) fetch(ra1, rw1, (ch + 3) * KC);
+      compute(1);
+      if (ch + 2 < nchunks) stash(ra0, rw0, 0);
+      __syncthreads();
+    }
   }
 
   float* S = reinterpret_cast<float*>(smem_raw);
