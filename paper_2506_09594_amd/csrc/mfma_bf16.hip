@@ -454,19 +454,28 @@ __global__ __launch_bounds__(2 * MT) void k_cthin_bf16(const uint16_t* __restric
     // end clamped to the last chunk (loaded, never used), so that every path
     // through the loop issues the same loads and each stash waits only for its
     // own chunk while the next one stays in flight.
+    // Three register slots: step c refills the slot of chunk c (already in
+    // LDS) with chunk c + 3, multiplies chunk c and stashes chunk c + 1.
+    u16x8 ra2[NRA], rw2[2][NWB];
     fetch_fast(ra0, rw0, 0);
     fetch_fast(ra1, rw1, min(1, nchunks - 1) * KC);
+    fetch_fast(ra2, rw2, min(2, nchunks - 1) * KC);
     stash(ra0, rw0, 0);
     __syncthreads();
-    for (int ch = 0; ch < nchunks; ch += 2) {
-      fetch_fast(ra0, rw0, min(ch + 2, nchunks - 1) * KC);
-      compute(0);
-      stash(ra1, rw1, 1);
+    for (int ch = 0; ch < nchunks; ch += 3) {
+      fetch_fast(ra0, rw0, min(ch + 3, nchunks - 1) * KC);
+      compute(ch & 1);
+      stash(ra1, rw1, (ch + 1) & 1);
       __syncthreads();
       if (ch + 1 >= nchunks) break;
-      fetch_fast(ra1, rw1, min(ch + 3, nchunks - 1) * KC);
-      compute(1);
-      stash(ra0, rw0, 0);
+      fetch_fast(ra1, rw1, min(ch + 4, nchunks - 1) * KC);
+      compute((ch + 1) & 1);
+      stash(ra2, rw2, (ch + 2) & 1);
+      __syncthreads();
+      if (ch + 2 >= nchunks) break;
+      fetch_fast(ra2, rw2, min(ch + 5, nchunks - 1) * KC);
+      compute((ch + 2) & 1);
+      stash(ra0, rw0, (ch + 3) & 1);
       __syncthreads();
     }
   } else {
