@@ -52,9 +52,11 @@ WORKLOADS = {
 
 def stage_bytes(stage, plan, es, cplx):
     """Algorithmic HBM bytes of one launch of a stage (read once, write once).
-    The transformed tensor is 2 bytes per entry in the BF16-mixed path.  Complex
-    slices (DFT) count their real and imaginary parts (stacked blocks of
-    2 n1 x n2 and 2 n x l); only the sketched (canonical) slices are stored."""
+    The transformed tensor is 2 bytes per entry in the BF16-mixed path, and
+    complex BF16-mixed products read their thin operand as the BF16 copy its
+    producer wrote (output FP32).  Complex slices (DFT) count their real and
+    imaginary parts (stacked blocks of 2 n1 x n2 and 2 n x l); only the
+    sketched (canonical) slices are stored."""
     n1, n2 = plan.dims[0], plan.dims[1]
     P, l, N = plan.n_slices, plan.width, plan.N
     ea = 2 if plan.precision == "bf16" else es
@@ -64,13 +66,15 @@ def stage_bytes(stage, plan, es, cplx):
     if stage == "transform_inv":
         return P * f * n1 * n2 * es + N * es
     if stage in ("sketch_nn", "sketch_tn"):
-        return P * f * (n1 * n2 * ea + (n1 + n2) * l * es)
+        m_in, m_out = (n2, n1) if stage == "sketch_nn" else (n1, n2)
+        ew = 2 if (cplx and plan.precision == "bf16") else es
+        return P * f * (n1 * n2 * ea + m_in * l * ew + m_out * l * es)
     if stage == "recon_nt":
         return P * f * (n1 * n2 + (n1 + n2) * l) * es
     if stage == "recon_qk":
         return P * f * (2 * n1 * l + f * l * l) * es
     if stage == "omega":
-        return P * n2 * l * es
+        return P * n2 * l * (es + (2 if (cplx and plan.precision == "bf16") else 0))
     return None
 
 
