@@ -562,6 +562,36 @@ __global__ __launch_bounds__(256, 2) void k_corth_apply_tiles(float* __restrict_
   }
 }
 
+// Complex Gram partials of a stored basis, one workgroup per 64-row tile
+// (the items of the apply): the tile's values as stored go to LDS as 128 real
+// rows (real parts of the 64 rows, then their imaginary parts; zeros past the
+// slice and past l) and tile_cgram_mfma forms the partial.  Follows the
+// resident tile apply for the final basis, which then needs no per-tile
+// restaging of R^-1.
+template <typename T, int LB>
+__global__ __launch_bounds__(256) void k_cgram_tiles(const T* __restrict__ Yall, int which,
+                                                     const SliceDesc* __restrict__ sd, const int2* __restrict__ wk,
+                                                     const int2* __restrict__ items, double* __restrict__ gout_all) {
+  constexpr int SP = LB + 1;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T* S = reinterpret_cast<T*>(smem_raw);  // [part * 64 + row][column]
+  const int2 it = items[blockIdx.x];
+  const int s = it.x, r0 = it.y;
+  const SliceDesc d = sd[s];
+  const int l = slice_width(d, wk, s);
+  if (l <= 0) return;  // slice not part of this pass
+  const int m = which ? d.n2 : d.n1, ld = 2 * m, rows = min(64, m - r0);
+  const T* Y = Yall + (which ? d.z : d.y);
+  for (int idx = threadIdx.x; idx < 2 * 64 * LB; idx += 256) {
+    const int row = idx % 64, pc = idx / 64, part = pc / LB, c = pc % LB;
+    const bool ok = row < rows && c < l;
+    const T v = Y[ok ? (part ? m : 0) + r0 + row + (int64_t)c * ld : 0];
+    S[(part * 64 + row) * SP + c] = ok ? v : T(0);
+  }
+  __syncthreads();
+  tile_cgram_mfma(S, SP, 1, l, gout_all + d.g2 + (int64_t)(r0 / kGramRows) * 2 * l * l);
+}
+
 template <typename T, int LB>
 constexpr size_t capply_lds_bytes() {
   constexpr size_t r = 2 * (size_t)LB * LB * 8, t = 128 * (size_t)(LB + 1) * sizeof(T);
@@ -1324,7 +1354,7 @@ int launch_corth(T* Y, uint16_t* Yh, int which, const SliceDesc* sd, const int2*
   hipLaunchKernelGGL(k_corth_factor, dim3((unsigned)nslices), dim3(kFactorThreads), cfactor_lds_bytes(lmax), s,
                      which, sd, wk, gin);
   HT_CHECK_LAUNCH();
-  if (std::is_same<T, float>::value && gout == nullptr && tiles != nullptr && ntiles > 0) {
+  if (std::is_same<T, float>::value && tiles != nullptr && ntiles > 0) {
     if ((rc = ensure_dynamic_lds((const void*)k_corth_apply_tiles, kApplyLds))) return rc;
     int per_cu = 0, dev = 0, ncu = 0;
     HT_CHECK_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)k_corth_apply_tiles, 256, kApplyLds));
@@ -1334,7 +1364,17 @@ int launch_corth(T* Y, uint16_t* Yh, int which, const SliceDesc* sd, const int2*
     hipLaunchKernelGGL(k_corth_apply_tiles, dim3((unsigned)grid), dim3(256), kApplyLds, s, reinterpret_cast<float*>(Y),
                        Yh, which, sd, wk, tiles, ntiles, gin);
     HT_CHECK_LAUNCH();
-    return HT_OK;
+    if (gout == nullptr) return HT_OK;
+    // the final basis: Gram partials of the stored tiles
+    auto gram = [&](auto kern, size_t lds) -> int {
+      int r = ensure_dynamic_lds((const void*)kern, lds);
+      if (r) return r;
+      hipLaunchKernelGGL(kern, dim3((unsigned)nitems), dim3(256), lds, s, Y, which, sd, wk, items, gout);
+      HT_CHECK_LAUNCH();
+      return HT_OK;
+    };
+    if (lmax <= 32) return gram(k_cgram_tiles<T, 32>, 128 * 33 * sizeof(T));
+    return gram(k_cgram_tiles<T, 64>, 128 * 65 * sizeof(T));
   }
   auto apply = [&](auto kern, size_t lds) -> int {
     int r = ensure_dynamic_lds((const void*)kern, lds);
