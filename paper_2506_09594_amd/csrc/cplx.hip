@@ -582,11 +582,18 @@ __global__ __launch_bounds__(256) void k_cgram_tiles(const T* __restrict__ Yall,
   if (l <= 0) return;  // slice not part of this pass
   const int m = which ? d.n2 : d.n1, ld = 2 * m, rows = min(64, m - r0);
   const T* Y = Yall + (which ? d.z : d.y);
-  for (int idx = threadIdx.x; idx < 2 * 64 * LB; idx += 256) {
-    const int row = idx % 64, pc = idx / 64, part = pc / LB, c = pc % LB;
+  constexpr int NL = 2 * 64 * LB / 256;  // loads per thread, all issued before the first LDS store
+  T v[NL];
+#pragma unroll
+  for (int u = 0; u < NL; ++u) {
+    const int idx = threadIdx.x + 256 * u, row = idx % 64, pc = idx / 64, part = pc / LB, c = pc % LB;
     const bool ok = row < rows && c < l;
-    const T v = Y[ok ? (part ? m : 0) + r0 + row + (int64_t)c * ld : 0];
-    S[(part * 64 + row) * SP + c] = ok ? v : T(0);
+    v[u] = Y[ok ? (part ? m : 0) + r0 + row + (int64_t)c * ld : 0];
+  }
+#pragma unroll
+  for (int u = 0; u < NL; ++u) {
+    const int idx = threadIdx.x + 256 * u, row = idx % 64, pc = idx / 64, part = pc / LB, c = pc % LB;
+    S[(part * 64 + row) * SP + c] = (row < rows && c < l) ? v[u] : T(0);
   }
   __syncthreads();
   tile_cgram_mfma(S, SP, 1, l, gout_all + d.g2 + (int64_t)(r0 / kGramRows) * 2 * l * l);
