@@ -848,7 +848,7 @@ __device__ __forceinline__ void dft_last_inverse(const T* re, const T* im, int b
   fft_regs<T, N, true>(xr, xi);
   if (!live) return;
 #pragma unroll
-  for (int k = 0; k < N; ++k) out[(int64_t)(j0 + k * sl) * NT + t0 + t] = xr[k] * post;
+  for (int k = 0; k < N; ++k) __builtin_nontemporal_store(xr[k] * post, out + (int64_t)(j0 + k * sl) * NT + t0 + t);
 }
 
 template <typename T, typename TO, bool inverse, int NF>
