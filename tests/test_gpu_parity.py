@@ -321,6 +321,43 @@ def test_admm_matches_oracle(ht, prec, model):
     assert st["resid"] == pytest.approx(hist[-1]["resid"], rel=1e-6 if prec == "fp64" else 1e-2)
 
 
+@pytest.mark.parametrize("model", ["completion", "rpca"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_admm_one_iteration_matches_oracle(ht, prec, model):
+    """One recovery iteration (t-SVT of the current input, then the E / Y / mu
+    updates of Sec. V) at the per-operator bounds: 1e-10 (FP64), 1e-5 (FP32)."""
+    import torch
+    dims, kinds, rank = (60, 50, 20), ["dct2"], 5
+    L = synth.lowrank_tensor(dims, rank, kinds, seed=6, noise_std=1e-3)
+    mask = synth.observation_mask(dims, 0.3 if model == "completion" else 0.5, 6)
+    S = synth.outliers(dims, 0.05, 6) * 3.0 if model == "rpca" else 0.0
+    M = np.where(mask, L + S, 0.0).astype(_np_dtype(prec)).astype(np.float64)
+    r, p, q, seed = 5, 5, 1, 31
+    # tau = 1 / mu0 = a quarter of the largest transformed-slice norm: the first
+    # t-SVT keeps part of the spectrum (at 1 / max norm it would zero all of L)
+    mu0 = 4.0 / synth.max_slice_norm(M, kinds)
+    lam = 2.0 / np.sqrt(max(dims[0], dims[1]) * dims[2])
+    vartheta, mu_max = 1.2, 1e10
+    pen = PEN["mcp"] if model == "completion" else PEN["l1"]
+    plan = ht.Plan(dims, kinds, r=r, p=p, q=q, precision=prec, seed=seed)
+    adm = ht.Admm(plan, model, phi=pen, psi=PEN["l1"], lam=lam, mu0=mu0, vartheta=vartheta, mu_max=mu_max)
+    dt = plan.torch_dtype
+    dM, dmask = ht.to_device(M, dt), ht.to_device(mask.astype(np.uint8), torch.uint8)
+    dL, dE, dY = (torch.empty(plan.N, dtype=dt, device="cuda") for _ in range(3))
+    ws = plan.alloc_workspace(admm=True)
+    adm.init(dL, dE, dY, ws)
+    adm.iterate(dM, dmask, dL, dE, dY, 1, ws)
+    T = otr.build_transforms(dims, kinds)
+    rnd = lambda X, tau, t: otsvt.tsvt_randomized(
+        X, tau, pen, T, r, p, q,
+        otsvt.omegas(dims, kinds, r, p, seed=seed, call=t, round_to=_np_dtype(prec) if prec != "fp64" else None))
+    Lr, Er, Yr, _ = osolver.admm(M, mask, model, pen, PEN["l1"], lam, mu0, vartheta, mu_max, 1, rnd)
+    tol = TOL[prec]
+    assert _rel(ht.from_device(dL, dims), Lr) < tol
+    assert _rel(ht.from_device(dE, dims), Er) < tol
+    assert _rel(ht.from_device(dY, dims), Yr) < tol
+
+
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 def test_tsvt_wide_sketch_with_deflation(ht, prec):
     """Sketch width 70 (> 64: the factor-once orthonormalization path) on
