@@ -170,7 +170,8 @@ int ht_plan_info(const ht_plan* plan, int64_t* n_slices, int* width, int* kept);
  * inspecting intermediate results after a call: 0 transformed tensor A,
  * 1 sketch matrices Omega (left unwritten by FP32 plans whose slices are all
  * real with n1 >= 192, n1 a multiple of 4, n2 <= 512 and l <= 64: there the
- * first product draws Omega in place),
+ * first product draws Omega in place; and by BF16-mixed plans with complex
+ * slices, which write only region 24),
  * 2 basis Q1 of the last CholeskyQR pass (n1 x l per
  * slice; the final R2 correction is applied in the l x l space),
  * 3 B^T = A^T Q1 (n2 x l per slice), 4 K' = R2^{-1} U diag(w) U^T R2^{-T}

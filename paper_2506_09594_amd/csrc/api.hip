@@ -963,9 +963,10 @@ int run_tsvt(const ht_plan* pl, const T* X, T* out, double tau, const double* ta
   // the streaming product draws Omega itself; every other path reads it
   const OmegaKey okey{call, call_dev, pl->stream_id, pl->seed};
   const bool om_inline = !fp64 && pl->nn_stream;
+  // complex BF16-mixed plans read only the BF16 copy of Omega
   if (!om_inline && (rc = timed(pl, ST_OMEGA, s, [&] {
-                       return launch_omega<T>(Om, nullptr, Omh, sd, nullptr, P, pl->max_n2l, call, call_dev,
-                                              pl->stream_id, pl->seed, 0, s);
+                       return launch_omega<T>(Omh ? nullptr : Om, nullptr, Omh, sd, nullptr, P, pl->max_n2l, call,
+                                              call_dev, pl->stream_id, pl->seed, 0, s);
                      })))
     return rc;
   const bool cplx = pl->cplx;
