@@ -152,3 +152,29 @@ def test_dft_unsupported_combinations(ht):
         ht.Plan((100, 100, 4), ["dft"], r=60, p=10)
     assert e.value.code == ht.ERR_UNSUPPORTED
     ht.Plan((100, 100, 4), ["dft"], r=50, p=10)  # l = 60: the large robust-PCA width
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+@pytest.mark.parametrize("shapes", [
+    [(40, 32, 8, 4), (36, 24, 4, 8), (24, 20, 4, 4, 4)],  # one first-mode length: fused transform across tensors
+    [(40, 32, 8, 4), (30, 20, 6)],                         # mixed mode lengths: the general transform
+])
+def test_batch_of_dft_tensors_matches_oracle(ht, prec, shapes):
+    """Uneven DFT tensors in one batched plan (Philox stream stream_id + t for
+    tensor t) against the oracle tensor by tensor."""
+    import torch
+    n = len(shapes)
+    ranks, ps, taus = [4, 5, 3][:n], [4, 3, 5][:n], [2.0, 1.5, 1.0][:n]
+    q, seed, sid = 1, 99, 3
+    kinds = [["dft"] * (len(s) - 2) for s in shapes]
+    xs = [synth.lowrank_tensor(s, ranks[t], kinds[t], seed=20 + t, noise_std=1e-2).astype(np.float32)
+          .astype(np.float64) for t, s in enumerate(shapes)]
+    plan = ht.BatchPlan(shapes, transforms=kinds, r=ranks, p=ps, q=q, precision=prec, seed=seed, stream_id=sid)
+    out = plan.gnhtsvt(plan.pack(xs), taus, ("mcp", (30.0,)), call_index=2)
+    torch.cuda.synchronize()
+    got = plan.unpack(out)
+    for t, s in enumerate(shapes):
+        om = otsvt.omegas(s, kinds[t], ranks[t], ps[t], seed=seed, call=2, stream=sid + t, round_to=np.float32)
+        ref = otsvt.tsvt_randomized(xs[t], taus[t], ("mcp", (30.0,)), otr.build_transforms(s, kinds[t]), ranks[t],
+                                    ps[t], q, om)
+        assert _rel(got[t], ref) < TOL[prec], f"tensor {t} shape {s}"
