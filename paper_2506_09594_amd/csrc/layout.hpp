@@ -19,9 +19,10 @@ struct ModeTable {
   int n[HT_MAX_ORDER];
   int stride[HT_MAX_ORDER];  // stride of mode m in the face-slice index
   int off[HT_MAX_ORDER];     // offset of the n x n row-major matrix in the table
-  // DFT tensors: the modes the fused transform applies while loading (the
-  // shortest, length <= 8) and while storing (the longest), every mode a power
-  // of two <= 32; -1 when the tensor takes the general form
+  // DFT tensors, fused transform: first, the shortest mode (length <= 8),
+  // applied while the tile loads; last, the longest, which the inverse applies
+  // while the tile is stored; every mode a power of two <= 32.  -1 when the
+  // tensor takes the general form
   int first, last;
 };
 

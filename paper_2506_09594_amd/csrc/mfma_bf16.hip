@@ -246,14 +246,14 @@ __global__ __launch_bounds__(64 * NW) void k_mfma_thin_bf16(const uint16_t* __re
 // owns tile rows 32 w .. 32 w + 31.  The reduction runs over the stored
 // columns (nn) or rows (tn) of A in chunks of 32: the chunk of Ar and Ai (MT x
 // 32 in LDS, k contiguous, rows in the tile's order) and the chunks of the
-// real and imaginary parts of the thin operand (rounded to BF16 while staged)
-// feed two passes of the MFMA loop,
+// real and imaginary parts of the thin operand (the BF16 copy its producer
+// wrote) feed two passes of the MFMA loop,
 //   nn:  Yr = Ar Wr - Ai Wi,   Yi = Ai Wr + Ar Wi
 //   tn:  Zr = Ar^T Qr + Ai^T Qi,   Zi = -Ai^T Qr + Ar^T Qi
 // where the second pass takes the other half of the row's group (tile row
 // r ^ 64) and a sign flip is an XOR of the BF16 sign bits.  Two chunks of loads
-// are in flight in registers; the epilogue writes the tile and one complex
-// Gram partial per 64 complex rows.
+// are in flight in registers (three when every chunk of the tile is interior);
+// the epilogue writes the tile and one complex Gram partial per 64 complex rows.
 template <int NB, int MT, bool TRANS>
 __global__ __launch_bounds__(2 * MT) void k_cthin_bf16(const uint16_t* __restrict__ Aall,
                                                        const uint16_t* __restrict__ Wall, float* __restrict__ Yall,

@@ -824,9 +824,9 @@ __global__ __launch_bounds__(256, sizeof(T) == 4 ? 2 : 1) void k_transform_cplx(
 // reads each slice's slot, conjugated for a partner), transforms the V fibers
 // and writes them to the LDS tile.  The other modes run in place in LDS; the
 // forward tile leaves with 16-byte stores (8 BF16 or V values of a canonical
-// slot); the inverse applies its last mode in registers as it stores the real
-// parts (dft_last_inverse), which measured faster than a further LDS pass
-// with 16-byte stores.  The slot map of the tile's tensor is copied next to
+// slot); the inverse applies its last mode (ModeTable::last) in registers as
+// it stores the real parts (dft_last_inverse), which measured faster than a
+// further LDS pass with 16-byte stores.  The slot map of the tile's tensor is copied next to
 // the tile so that no global load of the map waits behind the next tile's
 // loads, which are in flight while the current tile is transformed and
 // stored.
